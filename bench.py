@@ -1,0 +1,228 @@
+"""Throughput of the electrode-charge step on one MI355X.
+
+A step is one pass of the hot path over one batch of synthetic frames:
+cpm_rhs (b = chi - b_sol for F electrolyte frames) followed by cpm_solve
+(warm start, block CG, electroneutrality projection) for those F frames,
+with E assembled once beforehand (its assembly is timed and reported
+separately as GFLOP/s). Inputs are resident in HBM before the timed region.
+
+Prints one JSON line. Default workload: two 3-layer AB-graphite electrodes,
+N = 4608 electrode atoms, 16 frames of 2000 random +-1 e ions, a = 1.979 /A,
+beta = 0.3 /A, rcut = 12 A, k-space accuracy 1e-6, 1 V.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--tol", type=float, default=1e-11)
+    ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--warm", default="auto", choices=["auto", "zero", "chi", "mlp"])
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2111_06704_amd", "weights",
+                                                      "warmstart_cfg2.npz"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    return ap.parse_args()
+
+
+def cpu_baseline(geo, ipos, iq, chi, nframes, q_gpu):
+    """The FP64 oracle on the host: E and its Cholesky factor once, then per
+    frame b and the two-step solve. Returns the baseline record and the
+    charge error of the GPU result on the sampled frames."""
+    from oracle import cpm as ocpm
+    from oracle import ewald as ew
+    from paper_2111_06704_amd import workloads as wl
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    km = ew.kmax_from_eps(wl.EWALD_SPLIT, wl.KSPACE_EPS)
+    t0 = time.perf_counter()
+    E = ew.ewald_matrix(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, km)
+    fac = ocpm.cholesky(E)
+    _, d, _ = ocpm.neutralising_vector(fac, geo.n)
+    t1 = time.perf_counter()
+    b, qs = ew.rhs(geo.pos, wl.GAUSS_INV_WIDTH, ipos[:nframes], iq[:nframes], chi, geo.box,
+                   wl.EWALD_SPLIT, wl.RCUT, km)
+    q = ocpm.two_step(fac, b, qs, d)
+    t2 = time.perf_counter()
+    r2, rm = ocpm.rel_errors(q_gpu[:nframes], q)
+    rec = {"value": nframes / (t2 - t1), "unit": "solves/s", "cores": cores, "kind": "oracle",
+           "sample": f"{nframes} frames of the same workload: b (direct Ewald) + Cholesky solve + "
+                     f"two-step projection per frame; E assembly and its factorisation once "
+                     f"({t1 - t0:.1f} s, not in the rate)",
+           "setup_s": t1 - t0}
+    return rec, float(r2.max()), float(rm.max())
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        sys.exit(2)
+    import torch
+    from paper_2111_06704_amd import cpm, workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = args.workload
+    geo, ipos, iq, chi = wl.workload(cfg)
+    nf, m = ipos.shape[0], ipos.shape[1]
+    log(f"workload {cfg}: N={geo.n} frames={nf} ions={m}")
+
+    store = ("f32", "bf16") if cfg < 3 else (("f32",) if args.precision == "f32" else ("bf16",))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, wl.KSPACE_EPS,
+                   store=store, profile_build=True)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    prof_build = S.profile_read()[3]
+    desc = S.describe()
+    asm_gflops = prof_build["work"] / (prof_build["ms"] * 1e-3) / 1e9 if prof_build["ms"] > 0 else None
+    log(f"E built in {build_s:.3f} s; contraction {prof_build['ms']:.2f} ms, "
+        f"{asm_gflops:.1f} GFLOP/s; n_kvec={desc['n_kvec']}")
+
+    t_ipos = torch.tensor(ipos, device=dev)
+    t_iq = torch.tensor(iq, device=dev)
+    t_chi = torch.tensor(chi, device=dev)
+    b = torch.empty((nf, geo.n), dtype=torch.float64, device=dev)
+    qsol = torch.empty((nf,), dtype=torch.float64, device=dev)
+    q = torch.empty_like(b)
+
+    prec = {"f64": cpm.PREC_F64, "f32": cpm.PREC_F32, "bf16": cpm.PREC_BF16}[args.precision]
+    warm = args.warm
+    if warm == "auto":
+        warm = "mlp" if (os.path.exists(args.weights) and cfg in (1, 2)) else "chi"
+    if warm == "chi":
+        S.set_warm_chi(t_chi)
+        wmode = cpm.WARM_CHI
+    elif warm == "mlp":
+        from paper_2111_06704_amd import warmstart
+        warmstart.load_into(S, geo, args.weights)
+        wmode = cpm.WARM_MLP
+    else:
+        wmode = cpm.WARM_ZERO
+
+    def step(precision, wm, qout):
+        S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
+        return S.solve(b, qsol, tol=args.tol, precision=precision, warm_start=wm, inner_tol=1e-2,
+                       check_every=8, q_out=qout)
+
+    # reference: plain FP64 CG from zero at the same tolerance
+    q64 = torch.empty_like(b)
+    for _ in range(max(1, args.warmup)):
+        step(cpm.PREC_F64, cpm.WARM_ZERO, q64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n64 = max(3, args.steps // 2)
+    for _ in range(n64):
+        _, st64 = step(cpm.PREC_F64, cpm.WARM_ZERO, q64)
+    torch.cuda.synchronize()
+    fp64_ms = (time.perf_counter() - t0) / n64 * 1e3
+
+    # every precision mode once (same tolerance), for the record
+    modes = {}
+    for name, pm, wm in (("f64_zero", cpm.PREC_F64, cpm.WARM_ZERO), ("f32_zero", cpm.PREC_F32, cpm.WARM_ZERO),
+                         ("bf16_zero", cpm.PREC_BF16, cpm.WARM_ZERO), (f"f32_{warm}", cpm.PREC_F32, wmode),
+                         (f"bf16_{warm}", cpm.PREC_BF16, wmode)):
+        if (pm == cpm.PREC_F32 and "f32" not in store) or (pm == cpm.PREC_BF16 and "bf16" not in store):
+            continue
+        step(pm, wm, q)
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        _, sm = step(pm, wm, q)
+        torch.cuda.synchronize()
+        modes[name] = {"solves_per_s": nf / (time.perf_counter() - tm), "iterations": sm["iterations"],
+                       "true_residual_updates": sm["outer"], "initial_rel_resid": sm["initial_rel_resid"]}
+        log(name, modes[name])
+
+    for _ in range(args.warmup):
+        step(prec, wmode, q)
+    torch.cuda.synchronize()
+    S.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = step(prec, wmode, q)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = S.profile_read()
+    S.profile_enable(False)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = nf * args.steps / elapsed
+
+    # dominant kernel of the timed region: the block matrix product with the most time
+    kinds = ["matvec_f64", "matvec_f32", "matvec_bf16"]
+    k = int(np.argmax([prof[i]["ms"] for i in range(3)]))
+    avg_ms = prof[k]["ms"] / max(1, prof[k]["launches"])
+    bytes_per_launch = prof[k]["work"] / max(1, prof[k]["launches"])
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kinds[k],
+                "avg_launch_us": avg_ms * 1e3, "launches": prof[k]["launches"],
+                "bytes_per_launch": bytes_per_launch,
+                "kernel_share_of_step": prof[k]["ms"] / (elapsed * 1e3)}
+
+    qg = q.cpu().numpy()
+    q64g = q64.cpu().numpy()
+    rel_vs_fp64 = float(np.max(np.linalg.norm(qg - q64g, axis=1) / np.linalg.norm(q64g, axis=1)))
+
+    out = {
+        "metric": "charge solves/sec to 1e-8 rel (mixed+warm vs FP64 CG); E-assembly GFLOP/s",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == cpm.PREC_F64 else f"{args.precision}+f64",
+        "data": "synthetic",
+        "config": {"workload": f"workload {cfg}: two graphite electrodes, N={geo.n}, "
+                               f"{nf} frames x {m} ions",
+                   "n_electrode": geo.n, "frames_per_step": nf, "ions": m,
+                   "n_kvec": desc["n_kvec"], "tol": args.tol, "precision": args.precision,
+                   "warm_start": warm},
+        "fp64_cg_solves_per_s": nf / (fp64_ms * 1e-3),
+        "fp64_cg_iterations": st64["iterations"],
+        "speedup_vs_fp64_cg": value / (nf / (fp64_ms * 1e-3)),
+        "iterations": st["iterations"], "true_residual_updates": st["outer"], "modes": modes,
+        "initial_rel_resid": st["initial_rel_resid"], "max_rel_resid": st["max_rel_resid"],
+        "max_abs_sum_q": st["max_abs_sum_q"],
+        "charge_rel_err_vs_fp64_gpu": rel_vs_fp64,
+        "e_assembly_gflops": asm_gflops, "e_assembly_ms": prof_build["ms"],
+        "e_assembly_frac_fp64_peak": (asm_gflops / 1e3 / FP64_PEAK_TFLOPS) if asm_gflops else None,
+        "e_build_s": build_s,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        rec, r2, rm = cpu_baseline(geo, ipos, iq, chi, args.cpu_frames, qg)
+        out["cpu_baseline"] = rec
+        out["charge_rel2_vs_oracle"] = r2
+        out["charge_relmax_vs_oracle"] = rm
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,265 @@
+/* cpm.h - C ABI of the constant-potential electrode-charge library (gfx950).
+ *
+ * The library computes electrode charges of the Gaussian-charge constant
+ * potential method (SR-CPM) of Li, Wang, Liu, Jiang, arXiv 2111.06704:
+ *
+ *   cpm_build_E  assembles the dense Gaussian Ewald interaction matrix E over
+ *                the N electrode atoms (Sec. II.C, Eq. 22-23) and the
+ *                neutralising vector d' = E^-1 1 (Supplementary Eq. S8-S9);
+ *   cpm_rhs      forms b = chi - b_sol for F electrolyte frames, where b_sol
+ *                is the potential of the electrolyte point charges on the
+ *                Gaussian electrode charges (Sec. III.A, Eq. 25);
+ *   cpm_solve    solves E q_b = b by block conjugate gradients and enforces
+ *                electroneutrality sum(q) = -Q_sol with the two-step
+ *                post-treatment q = q_b - (1^T q_b + Q_sol) d (Eq. 34-35);
+ *   cpm_mlp_*    a per-atom network that predicts a CG starting point.
+ *
+ * Conventions (all entry points):
+ *   - Units: lengths in Angstrom, charges in e, applied potentials chi in
+ *     volts. E is in Gaussian units (1/Angstrom); b is in e/Angstrom
+ *     (chi is divided by k_e = 14.3996454784 V A / e inside cpm_rhs).
+ *   - "Gaussian inverse width" a_i is the paper's alpha_i (Eq. 4); the Ewald
+ *     splitting parameter beta is the paper's eta (Eq. 12-13).
+ *   - Arrays are row-major, FP64 unless stated. Pointers named *_dev are
+ *     device pointers (HBM of the current HIP device), *_host are host
+ *     pointers. The caller owns every buffer it passes; the library copies
+ *     what it keeps. A cpm_system owns its device memory until cpm_free.
+ *   - Work is enqueued on the stream given to cpm_build_E (or cpm_set_stream).
+ *     Calls that return host-side results (info structs, losses)
+ *     synchronise that stream.
+ *   - Atom order in and out is the caller's order.
+ *   - No exception or abort crosses the ABI. On failure a call returns a
+ *     negative cpm_status and cpm_last_error() describes it (thread-local).
+ */
+#ifndef CPM_H
+#define CPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CPM_OK = 0,
+  CPM_EINVAL = -1,    /* invalid argument (NaN/Inf, sizes, coincident atoms, ...) */
+  CPM_ENOMEM = -2,    /* a device allocation failed; the system is unchanged      */
+  CPM_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed              */
+  CPM_ENOTSPD = -4,   /* CG breakdown p^T E p <= 0: E is not positive definite   */
+  CPM_ENOTCONV = -5,  /* tolerance not reached within max_iter; outputs hold the
+                         last projected iterate                                   */
+  CPM_ESTATE = -6     /* call out of order (e.g. no network loaded)             */
+} cpm_status;
+
+typedef struct cpm_system cpm_system;   /* opaque */
+
+/* Storage precisions of E. FP64 is always kept: it defines the residual.
+   CPM_PROFILE_BUILD additionally times the assembly contraction (see
+   cpm_profile_read). */
+enum { CPM_STORE_F32 = 1u, CPM_STORE_BF16 = 2u, CPM_PROFILE_BUILD = 4u };
+
+typedef struct {
+  /* Gaussian inverse width a_i of each electrode charge in 1/A (Eq. 4).
+     Either a pointer to N host values (gauss_inv_width_per_atom) or, when it
+     is NULL, the single value gauss_inv_width for every atom. Mixing
+     a_ij = (a_i^-2 + a_j^-2)^-1/2 (Eq. 5); a_ii = a_i / sqrt 2 (Eq. 6). */
+  double gauss_inv_width;
+  const double *gauss_inv_width_per_atom;
+  double ewald_split;    /* beta > 0 in 1/A (the paper's eta, Eq. 12-13)         */
+  double rcut;           /* real-space cutoff in A: images with d < rcut count  */
+  double kspace_eps;     /* reciprocal cutoff K_max = 2 beta sqrt(ln(1/eps))     */
+  double kmax_override;  /* > 0: use this K_max (1/A) instead of kspace_eps      */
+  unsigned store_mask;   /* CPM_STORE_F32 | CPM_STORE_BF16: extra copies of E   */
+} cpm_params;
+
+/* Assemble E for n electrode atoms. The neutralising vector d' = E^-1 1
+ * (S9) is solved on first use by cpm_solve / cpm_get_dprime /
+ * cpm_set_warm_chi, which return its CPM_ENOTSPD / CPM_ENOTCONV (E of point
+ * charges alone, a = inf, is in general not positive definite).
+ *   pos_host  (n, 3) positions in an orthorhombic box [0, box_d); values
+ *             outside are wrapped.
+ *   box_host  (3,) box edges in A, > 0. The box is 3D periodic (tinfoil,
+ *             Sec. II.B after Eq. 14).
+ *   stream    hipStream_t (may be NULL for the default stream).
+ * E_ij (i != j) = sum over images n with d = |r_ij + n L| < rcut of
+ *   [erfc(beta d) - erfc(a_ij d)] / d
+ *   + sum_{K != 0, |K| <= K_max} (4 pi / V) exp(-K^2 / 4 beta^2) / K^2 cos(K.r_ij)
+ *   - pi / (V beta^2);
+ * E_ii adds -2 beta / sqrt(pi) + 2 a_ii / sqrt(pi) and takes n != 0 images
+ * only (Eq. 22-23, with the reciprocal prefactor of Eq. 13).
+ * Errors: CPM_EINVAL for n < 1, non-finite input, box <= 0, beta <= 0,
+ * a_i <= 0, rcut <= 0, eps outside (0, 1), two atoms closer than 1e-6 A
+ * (minimum image); CPM_ENOMEM.
+ * On error *out is set to NULL and nothing is leaked. */
+cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host,
+                       const cpm_params *params, void *stream, cpm_system **out);
+
+/* Release every device and host resource of s (NULL is a no-op). */
+void cpm_free(cpm_system *s);
+
+/* Change the stream later calls enqueue on. */
+cpm_status cpm_set_stream(cpm_system *s, void *stream);
+
+/* Problem facts: n atoms, number of half-space k-vectors, K_max used, memory
+   held on the device (bytes). Any pointer may be NULL. */
+cpm_status cpm_describe(const cpm_system *s, int64_t *n, int64_t *n_kvec, double *kmax,
+                        int64_t *device_bytes);
+
+/* Right-hand side for f electrolyte frames of m point charges each (Eq. 25):
+ *   b[f, i] = chi_i / k_e - sum_I q_fI e_iI(a_i),   Q_sol[f] = sum_I q_fI,
+ * where e_iI is Eq. 22 between Gaussian electrode charge i (width a_i) and
+ * point charge I (mixing width a_iI = a_i, Sec. II.A).
+ *   ion_pos_dev (f, m, 3), ion_q_dev (f, m), chi_dev (n,) in volts,
+ *   b_out_dev (f, n), qsol_out_dev (f,) - all device pointers.
+ * m may be 0 (then b = chi / k_e and Q_sol = 0). An ion exactly on an
+ * electrode site uses the limit 2 (a_i - beta) / sqrt(pi) of the real-space
+ * term. Errors: CPM_EINVAL for NULL pointers, f < 1, m < 0. */
+cpm_status cpm_rhs(cpm_system *s, const double *ion_pos_dev, const double *ion_q_dev,
+                   int64_t m, int64_t f, const double *chi_dev, double *b_out_dev,
+                   double *qsol_out_dev);
+
+enum { CPM_PREC_F64 = 0, CPM_PREC_F32 = 1, CPM_PREC_BF16 = 2 };
+enum { CPM_WARM_ZERO = 0, CPM_WARM_CHI = 1, CPM_WARM_MLP = 2 };
+
+typedef struct {
+  double tol;          /* stop when |b - E q_b|_2 <= tol |b|_2 (true FP64 residual) */
+  int max_iter;        /* total CG iterations (inner iterations for mixed)          */
+  int precision;       /* CPM_PREC_*: storage of E in the CG matvec. F32/BF16 run
+                          iterative refinement: inner FP32 CG on the rounded E,
+                          FP64 residual b - E q on the FP64 E                      */
+  int warm_start;      /* CPM_WARM_*: zero, the no-electrolyte solution q_chi, or
+                          the network prediction                                   */
+  double inner_tol;    /* relative tolerance of each inner solve (mixed), e.g. 1e-3 */
+  int check_every;     /* host convergence check period in iterations (>= 1)       */
+} cpm_solve_opts;
+
+typedef struct {
+  int iterations;      /* CG iterations (max over frames; inner for mixed)         */
+  int outer;           /* refinement steps (mixed) / true-residual restarts (F64)  */
+  double max_rel_resid;/* max over frames of |b - E q_b| / |b| at exit             */
+  double initial_rel_resid; /* max over frames of the relative residual at start   */
+  double max_abs_sum_q;/* max over frames of |sum(q) + Q_sol| after projection     */
+  double warm_ms;      /* time of the warm start (network + shift)                 */
+  double solve_ms;     /* wall time of the whole call                              */
+  int fell_back;       /* 1 if the warm start was rejected (|r0| >= |b|)           */
+  /* optional per-frame outputs (host arrays of length f, may be NULL) */
+  int *frame_iters;
+  double *frame_rel_resid;
+} cpm_solve_info;
+
+/* Electrode charges for f right-hand sides.
+ *   b_dev (f, n), qsol_dev (f,), q_out_dev (f, n): device pointers.
+ * q_out[f] = q_b - (1^T q_b + Q_sol[f]) d with E q_b = b[f] (Eq. 35),
+ * d = d' / 1^T d'. Errors: CPM_EINVAL (pointers, f < 1, tol <= 0, unknown
+ * precision, precision not stored), CPM_ESTATE (CPM_WARM_MLP without a
+ * network), CPM_ENOTSPD (breakdown), CPM_ENOTCONV (q_out then holds the
+ * projected last iterate). info may be NULL. */
+cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
+                     const cpm_solve_opts *opts, double *q_out_dev, cpm_solve_info *info);
+
+/* Copy E (caller's atom order) into dst_dev with leading dimension ld >= n,
+   in the requested precision (FP64 double, FP32 float, BF16 uint16 bits).
+   CPM_EINVAL if that precision is not stored. */
+cpm_status cpm_get_E(const cpm_system *s, int precision, void *dst_dev, int64_t ld);
+
+/* Copy d' = E^-1 1 (S9) into dst_dev (n,) and return C_ele = 1^T d'. */
+cpm_status cpm_get_dprime(cpm_system *s, double *dst_dev, double *c_ele);
+
+/* Block matrix product V = E P for f vectors, P and V (f, n) row-major
+   device arrays (one vector per row), E in the requested precision (FP32/BF16 products accumulate
+   in FP32 and are returned widened to FP64). The CG's own matvec. */
+cpm_status cpm_matvec(cpm_system *s, int precision, const double *p_dev, int64_t f,
+                      double *v_dev);
+
+/* ---- learned warm start --------------------------------------------------
+ * A per-atom multilayer perceptron 26 -> 64 -> 64 -> 1 with SiLU activations
+ * predicts each atom's charge from its own b_i - mean(b), its layer index and
+ * its 12 nearest electrode neighbours' (b_j - mean(b), r_ij). Neighbours are
+ * ordered by distance, then azimuth about +z from +x, then index, using the
+ * minimum image; distances and angles are compared after rounding to 1e-6.
+ * The prediction is shifted to sum(q0) = -Q_sol, and the CG start is
+ * q_b0 = q0 + mu0 d' with mu0 = mean(b - E q0) (the Lagrange shift of
+ * Eq. 29-31). A start whose residual is not below |b| is discarded (zero
+ * start). Feature layout per atom: [b_i - mean, layer/(L-1),
+ * 12 x (b_j - mean), 12 x r_ij], with b scaled by 1/b_scale and r by 1/r_scale;
+ * the output is multiplied by q_scale. */
+#define CPM_MLP_IN 26
+#define CPM_MLP_HIDDEN 64
+#define CPM_MLP_NPARAM (CPM_MLP_IN * CPM_MLP_HIDDEN + CPM_MLP_HIDDEN + \
+                        CPM_MLP_HIDDEN * CPM_MLP_HIDDEN + CPM_MLP_HIDDEN + CPM_MLP_HIDDEN + 1)
+
+/* Parameter vector layout (float32, CPM_MLP_NPARAM values):
+   W1 (26 x 64, row-major: input-major), b1 (64), W2 (64 x 64), b2 (64),
+   W3 (64), b3 (1). Layer: h = silu(x W + b). */
+
+/* Set the 12-neighbour list from the geometry given at build (computed on
+   the host) and the layer index of each atom (n ints, host; n_layers >= 1). */
+cpm_status cpm_mlp_init(cpm_system *s, const int32_t *layer_host, int32_t n_layers,
+                        float b_scale, float r_scale, float q_scale);
+
+/* Copy the neighbour list (n, 12) int32 to host (for tests). */
+cpm_status cpm_mlp_neighbours(const cpm_system *s, int32_t *nbr_host);
+
+/* Load / read parameters (host float32, CPM_MLP_NPARAM values). Setting
+   resets the Adam moments. */
+cpm_status cpm_mlp_set_params(cpm_system *s, const float *params_host);
+cpm_status cpm_mlp_get_params(const cpm_system *s, float *params_host);
+
+/* Features (f*n, 26) float32 of f frames of b (device) into feat_out_dev. */
+cpm_status cpm_mlp_features(cpm_system *s, const double *b_dev, int64_t f, float *feat_out_dev);
+
+/* Network output y (rows,) float32 for feature rows (rows, 26) (device). */
+cpm_status cpm_mlp_forward(cpm_system *s, const float *feat_dev, int64_t rows, float *y_out_dev);
+
+/* Loss and gradient of the mean squared error L = mean((y - t)^2) over rows
+   (device features and targets, targets already divided by q_scale); the
+   gradient (CPM_MLP_NPARAM floats) goes to grad_out_dev, the loss to *loss. */
+cpm_status cpm_mlp_loss_grad(cpm_system *s, const float *feat_dev, const float *target_dev,
+                             int64_t rows, float *grad_out_dev, double *loss);
+
+/* One Adam step (Kingma & Ba 2015; beta1, beta2, eps, bias correction) with
+   learning rate lr on the loss of one mini-batch; returns the batch loss
+   before the step. */
+cpm_status cpm_mlp_train_step(cpm_system *s, const float *feat_dev, const float *target_dev,
+                              int64_t rows, float lr, float beta1, float beta2, float eps,
+                              double *loss);
+
+/* One pass over f frames of (b, q) pairs (device, (f, n) each; q is the
+   solver's neutral charge): rows are visited in the order perm_dev (f*n
+   int64 row ids, row = frame * n + atom), batch rows per Adam step. Features
+   and targets (q / q_scale) are gathered on the device. mean_loss receives
+   the mean of the batch losses. */
+cpm_status cpm_mlp_train_epoch(cpm_system *s, const double *b_dev, const double *q_dev, int64_t f,
+                               const int64_t *perm_dev, int64_t batch, float lr, float beta1,
+                               float beta2, float eps, double *mean_loss);
+
+/* Precompute q_chi, the neutral solution without electrolyte (b = chi / k_e,
+   Q_sol = 0), used by CPM_WARM_CHI. chi_dev (n,) volts; opts as cpm_solve. */
+cpm_status cpm_set_warm_chi(cpm_system *s, const double *chi_dev, const cpm_solve_opts *opts);
+
+/* ---- live kernel timing ----------------------------------------------------
+ * While enabled, the library brackets every launch of the block matrix
+ * product (per storage precision of E) and of the assembly contraction with
+ * HIP events on its stream and records each launch's algorithmic work:
+ *   matvec: bytes s*n*n (E) + 2 * s_v * n * cols (P read, V written),
+ *           s = 8/4/2 for FP64/FP32/BF16 E, s_v = 8 (FP64) or 4 (FP32 vectors);
+ *   assembly: flops 4 * n_k * n (n + 1) / 2 for a chunk of n_k k-vectors.
+ * cpm_profile_enable(s, 1) starts a new window (clears earlier records);
+ * cpm_profile_read synchronises the stream and sums each kind. */
+typedef struct {
+  int64_t launches[4];   /* index: CPM_PREC_F64, CPM_PREC_F32, CPM_PREC_BF16, 3 = assembly */
+  double ms[4];          /* summed kernel time (ms) between the events                    */
+  double work[4];        /* summed algorithmic bytes (matvec) or flops (assembly)         */
+} cpm_profile_info;
+
+cpm_status cpm_profile_enable(cpm_system *s, int on);
+cpm_status cpm_profile_read(cpm_system *s, cpm_profile_info *out);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+const char *cpm_status_str(cpm_status st);
+const char *cpm_last_error(void);   /* thread-local message of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPM_H */

@@ -1,0 +1,966 @@
+// Block conjugate gradients on the dense Ewald matrix and the two-step
+// electroneutrality post-treatment (Sec. III.A, Eq. 31-35; Sec. III.B.2).
+//
+// Up to 64 right-hand sides run as independent CG recurrences that share
+// one matrix product V = E P per iteration (E streamed once for all of
+// them). Vectors are stored frame-major: column c of a block is a
+// contiguous array of ld values; rows >= n stay zero (E's padded columns
+// are zero, and 0 * NaN would not be).
+//
+// One iteration is three kernels:
+//   block_matvec_kernel  v = E p. A workgroup owns 16*RT rows; its 16/NG waves
+//     split the k range, each accumulating 16x16 MFMA blocks
+//     (v_mfma_f64_16x16x4f64 for FP64 E, v_mfma_f32_16x16x4f32 for FP32 and
+//     BF16 E, products accumulated in FP32). Lane l supplies A[l % 16][l / 16]
+//     and B[l / 16][l % 16]; the k slots of the MFMA are mapped to 32
+//     contiguous bytes of an E row per lane, so E and P are read with wide,
+//     coalesced loads. The waves' partial tiles are summed in LDS in a fixed
+//     order, v is written, and the block's share of p.v is reduced.
+//   cg_update_kernel     alpha = r.z / p.v; x += alpha p; r -= alpha v;
+//                        z = M^-1 r (Jacobi, M = diag E); partial r.r, r.z.
+//   cg_direction_kernel  beta = r'.z' / r.z; p = z + beta p.
+// All dots are FP64 and reduced in a fixed order (bitwise reproducible).
+//
+// Precision: x, r, z are FP64 in every mode. FP64 mode streams the FP64 E.
+// FP32 / BF16 modes stream the rounded E (p and v in FP32) and use true-
+// residual updates: whenever the recursive residual has fallen by the factor
+// inner_tol below the last true residual (or meets the tolerance), r is
+// replaced by the true FP64 residual b - E x computed on the FP64 E. FP32
+// continues with the same search direction (a reliable update); BF16
+// restarts it from the new residual, i.e. iterative refinement with an
+// inner CG on the BF16 matrix. Convergence is always decided on the true
+// FP64 residual.
+#include "cpm_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace cpm {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int RED_THREADS = 256;
+constexpr int MAX_COLS = 64;
+constexpr int64_t CHUNK = 1024;   // rows per block of the vector kernels
+
+// scalar fields (struct of arrays, cols entries each)
+enum { S_RZ0 = 0, S_RZ1 = 1, S_RR = 2, S_BN2 = 3, S_ACT = 4, S_NFIELDS = 5 };
+
+template <typename T> struct Mv;
+template <> struct Mv<double> {
+  using VT = double;
+  using Acc = d4;
+  static constexpr int VEC = 4;
+  static constexpr int RT = 1;
+  __device__ static inline Acc mfma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  struct Raw { double v[VEC]; };
+  __device__ static inline void load(const double *p, Raw &o) {
+    const double4 v = *reinterpret_cast<const double4 *>(p);
+    o.v[0] = v.x; o.v[1] = v.y; o.v[2] = v.z; o.v[3] = v.w;
+  }
+  __device__ static inline double elem(const Raw &o, int t) { return o.v[t]; }
+  // output row of register v in lane group g: D[4v + g][lane % 16]
+  __device__ static inline int out_row(int g, int v) { return 4 * v + g; }
+};
+template <> struct Mv<float> {
+  using VT = float;
+  using Acc = f4;
+  static constexpr int VEC = 8;
+  static constexpr int RT = 2;
+  __device__ static inline Acc mfma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  struct Raw { float v[VEC]; };
+  __device__ static inline void load(const float *p, Raw &o) {
+    const float4 v0 = *reinterpret_cast<const float4 *>(p);
+    const float4 v1 = *reinterpret_cast<const float4 *>(p + 4);
+    o.v[0] = v0.x; o.v[1] = v0.y; o.v[2] = v0.z; o.v[3] = v0.w;
+    o.v[4] = v1.x; o.v[5] = v1.y; o.v[6] = v1.z; o.v[7] = v1.w;
+  }
+  __device__ static inline float elem(const Raw &o, int t) { return o.v[t]; }
+  // output row of register v in lane group g: D[4g + v][lane % 16]
+  __device__ static inline int out_row(int g, int v) { return 4 * g + v; }
+};
+template <> struct Mv<uint16_t> {   // bf16 storage, widened to FP32
+  using VT = float;
+  using Acc = f4;
+  static constexpr int VEC = 16;
+  static constexpr int RT = 2;
+  __device__ static inline Acc mfma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // raw bf16 pairs stay packed in registers until the MFMA needs them
+  struct Raw { uint32_t w[8]; };
+  __device__ static inline void load(const uint16_t *p, Raw &o) {
+    const uint4 v0 = *reinterpret_cast<const uint4 *>(p);
+    const uint4 v1 = *reinterpret_cast<const uint4 *>(p + 8);
+    o.w[0] = v0.x; o.w[1] = v0.y; o.w[2] = v0.z; o.w[3] = v0.w;
+    o.w[4] = v1.x; o.w[5] = v1.y; o.w[6] = v1.z; o.w[7] = v1.w;
+  }
+  __device__ static inline float elem(const Raw &o, int t) {
+    const uint32_t w = o.w[t >> 1];
+    return __uint_as_float((t & 1) ? (w & 0xffff0000u) : (w << 16));
+  }
+  __device__ static inline int out_row(int g, int v) { return 4 * g + v; }
+};
+
+template <typename VT, int VEC> __device__ inline void load_vec(const VT *p, VT (&o)[VEC]) {
+#pragma unroll
+  for (int q = 0; q < VEC; q += 4) {
+    if constexpr (sizeof(VT) == 8) {
+      const double4 v = *reinterpret_cast<const double4 *>(p + q);
+      o[q] = v.x; o[q + 1] = v.y; o[q + 2] = v.z; o[q + 3] = v.w;
+    } else {
+      const float4 v = *reinterpret_cast<const float4 *>(p + q);
+      o[q] = v.x; o[q + 1] = v.y; o[q + 2] = v.z; o[q + 3] = v.w;
+    }
+  }
+}
+
+// Waves per workgroup of the block product: 16 / NG, so that the LDS
+// reduction buffer stays at 32 KB and the grid keeps ~16 waves per 16*RT rows.
+template <int NG> constexpr int mv_waves() { return 16 / NG; }
+
+// Load stages kept in flight per wave (register budget: <= 128 VGPRs at
+// 1024 threads per workgroup).
+template <typename T, int NG> constexpr int mv_stages() {
+  return sizeof(T) == 8 ? (NG == 1 ? 4 : (NG == 2 ? 2 : 1)) : (NG == 1 ? 2 : 1);
+}
+
+// V[c][row] = sum_k E[row][k] P[c][k] for the block's 16*RT rows; optionally
+// pv_part[block][c] = sum over those rows of P[c][row] V[c][row]. The
+// workgroup's waves split the k range; each wave keeps two independent
+// accumulator chains per output tile (even / odd k slot) so that consecutive
+// MFMAs do not wait on each other.
+template <typename T, int NG>
+__global__ __launch_bounds__(64 * mv_waves<NG>()) void block_matvec_kernel(
+    const T *__restrict__ E, int64_t ld, const typename Mv<T>::VT *__restrict__ P,
+    typename Mv<T>::VT *__restrict__ V, int64_t kq, double *__restrict__ pv_part) {
+  using M = Mv<T>;
+  using VT = typename M::VT;
+  using Acc = typename M::Acc;
+  constexpr int W = mv_waves<NG>();
+  constexpr int NT = 64 * W;
+  constexpr int VEC = M::VEC;
+  constexpr int KB = 4 * VEC;
+  constexpr int RT = M::RT;
+  constexpr int ROWS = 16 * RT;
+  constexpr int COLS = 16 * NG;
+  __shared__ VT red[W][ROWS][COLS + 1];
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+  const int64_t kbeg = (int64_t)wave * kq;
+  const int64_t kend = min(ld, kbeg + kq);
+
+  Acc acc[2][RT][NG];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) acc[h][a][g] = Acc{0, 0, 0, 0};
+
+  const T *erow[RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a) erow[a] = E + (r0 + a * 16 + lr) * ld + lg * VEC;
+  const VT *pcol[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) pcol[g] = P + (int64_t)(g * 16 + lr) * ld + lg * VEC;
+
+  // software pipeline: U stages of E / P loads are in flight while the
+  // MFMAs of the oldest stage run
+  constexpr int U = mv_stages<T, NG>();
+  typename M::Raw ea[U][RT];
+  VT pb[U][NG][VEC];
+  const int64_t nsteps = kend > kbeg ? (kend - kbeg) / KB : 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (u < nsteps) {
+      const int64_t kb = kbeg + u * KB;
+#pragma unroll
+      for (int a = 0; a < RT; ++a) M::load(erow[a] + kb, ea[u][a]);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) load_vec<VT, VEC>(pcol[g] + kb, pb[u][g]);
+    }
+  }
+  for (int64_t st0 = 0; st0 < nsteps; st0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (st0 + u < nsteps) {
+#pragma unroll
+        for (int t = 0; t < VEC; ++t)
+#pragma unroll
+          for (int a = 0; a < RT; ++a)
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+              acc[t & 1][a][g] = M::mfma(M::elem(ea[u][a], t), pb[u][g][t], acc[t & 1][a][g]);
+        const int64_t nxt = st0 + u + U;
+        if (nxt < nsteps) {
+          const int64_t kb = kbeg + nxt * KB;
+#pragma unroll
+          for (int a = 0; a < RT; ++a) M::load(erow[a] + kb, ea[u][a]);
+#pragma unroll
+          for (int g = 0; g < NG; ++g) load_vec<VT, VEC>(pcol[g] + kb, pb[u][g]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        red[wave][a * 16 + M::out_row(lg, v)][g * 16 + lr] = acc[0][a][g][v] + acc[1][a][g][v];
+  __syncthreads();
+
+  // thread -> (row, column group); the ROWS threads of a group are adjacent lanes
+  constexpr int TPR = NT / ROWS;
+  const int row = threadIdx.x % ROWS, cg0 = threadIdx.x / ROWS;
+  for (int c = cg0; c < COLS; c += TPR) {
+    VT s = red[0][row][c];
+#pragma unroll
+    for (int w = 1; w < W; ++w) s += red[w][row][c];
+    const int64_t idx = (int64_t)c * ld + r0 + row;
+    V[idx] = s;
+    if (pv_part) {
+      double pv = (double)P[idx] * (double)s;
+#pragma unroll
+      for (int off = ROWS / 2; off > 0; off >>= 1) pv += __shfl_xor(pv, off, ROWS);
+      if (row == 0) pv_part[(int64_t)blockIdx.x * COLS + c] = pv;
+    }
+  }
+}
+
+__device__ inline double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// r = b - v (v = E x from the FP64 product); partial[blk][c][0] = |r|^2.
+__global__ __launch_bounds__(RED_THREADS) void residual_kernel(
+    const double *__restrict__ v, const double *__restrict__ b, double *__restrict__ r,
+    int64_t ld, int64_t n, int cols, double *__restrict__ partial) {
+  __shared__ double red[RED_THREADS];
+  const int c = blockIdx.y;
+  const int blk = blockIdx.x;
+  const int64_t i0 = (int64_t)blk * CHUNK;
+  const int64_t i1 = min(n, i0 + CHUNK);
+  double acc = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) {
+    const int64_t idx = (int64_t)c * ld + i;
+    const double ri = b[idx] - v[idx];
+    r[idx] = ri;
+    acc += ri * ri;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[((int64_t)blk * cols + c) * 2] = acc;
+}
+
+// partial[blk][c][0] = sum of squares of a over the block's rows
+__global__ __launch_bounds__(RED_THREADS) void sumsq_kernel(const double *__restrict__ a,
+                                                            int64_t ld, int64_t n, int cols,
+                                                            double *__restrict__ partial) {
+  __shared__ double red[RED_THREADS];
+  const int c = blockIdx.y;
+  const int blk = blockIdx.x;
+  const int64_t i0 = (int64_t)blk * CHUNK;
+  const int64_t i1 = min(n, i0 + CHUNK);
+  double acc = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) {
+    const double ai = a[(int64_t)c * ld + i];
+    acc += ai * ai;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[((int64_t)blk * cols + c) * 2] = acc;
+}
+
+// scal[field][c] = sum over blocks of partial[blk][c][0]
+__global__ void sum_partials_kernel(const double *__restrict__ partial, int nblk, int cols,
+                                    double *__restrict__ scal, int field) {
+  const int c = threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[((int64_t)b * cols + c) * 2];
+  scal[field * cols + c] = s;
+}
+
+// z = M^-1 r; if set_p, p = z; partial r.r and r.z (active columns only).
+template <typename VT>
+__global__ __launch_bounds__(RED_THREADS) void cg_refresh_kernel(
+    const double *__restrict__ r, double *__restrict__ z, VT *__restrict__ p,
+    const double *__restrict__ dinv, int64_t ld, int64_t n, int cols,
+    const double *__restrict__ scal, double *__restrict__ partial, int set_p) {
+  __shared__ double red[RED_THREADS];
+  const int c = blockIdx.y;
+  const int blk = blockIdx.x;
+  const bool act = scal[S_ACT * cols + c] != 0.0;
+  double arr = 0.0, arz = 0.0;
+  if (act) {
+    const int64_t i0 = (int64_t)blk * CHUNK;
+    const int64_t i1 = min(n, i0 + CHUNK);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) {
+      const int64_t idx = (int64_t)c * ld + i;
+      const double ri = r[idx];
+      const double zi = ri * dinv[i];
+      z[idx] = zi;
+      if (set_p) p[idx] = (VT)zi;
+      arr += ri * ri;
+      arz += ri * zi;
+    }
+  }
+  arr = block_sum(arr, red);
+  arz = block_sum(arz, red);
+  if (threadIdx.x == 0) {
+    partial[((int64_t)blk * cols + c) * 2] = arr;
+    partial[((int64_t)blk * cols + c) * 2 + 1] = arz;
+  }
+}
+
+// Reduce (rr, rz) partials into the scalars of active columns.
+__global__ void set_scalars_kernel(const double *__restrict__ partial, int nblk, int cols,
+                                   double *__restrict__ scal, int slot) {
+  const int c = threadIdx.x;
+  if (c >= cols) return;
+  if (scal[S_ACT * cols + c] == 0.0) return;
+  double rr = 0.0, rz = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    rr += partial[((int64_t)b * cols + c) * 2];
+    rz += partial[((int64_t)b * cols + c) * 2 + 1];
+  }
+  scal[S_RR * cols + c] = rr;
+  scal[(S_RZ0 + slot) * cols + c] = rz;
+}
+
+// alpha = rz / p.v; x += alpha p; r -= alpha v; z = M^-1 r; partial rr, rz.
+template <typename VT>
+__global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
+    double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
+    const VT *__restrict__ p, const VT *__restrict__ v, const double *__restrict__ dinv,
+    int64_t ld, int64_t n, int cols, int npv, const double *__restrict__ pv_part,
+    const double *__restrict__ scal, int slot, double *__restrict__ partial,
+    int *__restrict__ flags) {
+  __shared__ double red[RED_THREADS];
+  const int c = blockIdx.y;
+  const int blk = blockIdx.x;
+  const bool act = scal[S_ACT * cols + c] != 0.0;
+  double arr = 0.0, arz = 0.0;
+  if (act) {
+    double pv = 0.0;
+    for (int b = threadIdx.x; b < npv; b += RED_THREADS) pv += pv_part[(int64_t)b * cols + c];
+    pv = block_sum(pv, red);
+    const double rz = scal[(S_RZ0 + slot) * cols + c];
+    double alpha = 0.0;
+    if (pv > 0.0 && isfinite(pv)) {
+      alpha = rz / pv;
+    } else if (blk == 0 && threadIdx.x == 0) {
+      flags[0] = 1;   // breakdown: p^T E p <= 0
+      flags[1] = c;
+      double *dbg = reinterpret_cast<double *>(flags + 2);
+      dbg[0] = pv;
+      dbg[1] = rz;
+    }
+    const int64_t i0 = (int64_t)blk * CHUNK;
+    const int64_t i1 = min(n, i0 + CHUNK);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) {
+      const int64_t idx = (int64_t)c * ld + i;
+      x[idx] += alpha * (double)p[idx];
+      const double ri = r[idx] - alpha * (double)v[idx];
+      r[idx] = ri;
+      const double zi = ri * dinv[i];
+      z[idx] = zi;
+      arr += ri * ri;
+      arz += ri * zi;
+    }
+  }
+  arr = block_sum(arr, red);
+  arz = block_sum(arz, red);
+  if (threadIdx.x == 0) {
+    partial[((int64_t)blk * cols + c) * 2] = arr;
+    partial[((int64_t)blk * cols + c) * 2 + 1] = arz;
+  }
+}
+
+// beta = rz' / rz; p = z + beta p; block 0 stores rz' in the other slot and rr.
+template <typename VT>
+__global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
+    VT *__restrict__ p, const double *__restrict__ z, int64_t ld, int64_t n, int cols, int nblk,
+    const double *__restrict__ partial, double *__restrict__ scal, int slot) {
+  const int c = blockIdx.y;
+  const int blk = blockIdx.x;
+  if (scal[S_ACT * cols + c] == 0.0) return;
+  double rr = 0.0, rzn = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    rr += partial[((int64_t)b * cols + c) * 2];
+    rzn += partial[((int64_t)b * cols + c) * 2 + 1];
+  }
+  const double rz = scal[(S_RZ0 + slot) * cols + c];
+  const double beta = (rz != 0.0) ? rzn / rz : 0.0;
+  const int64_t i0 = (int64_t)blk * CHUNK;
+  const int64_t i1 = min(n, i0 + CHUNK);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) {
+    const int64_t idx = (int64_t)c * ld + i;
+    p[idx] = (VT)(z[idx] + beta * (double)p[idx]);
+  }
+  if (blk == 0 && threadIdx.x == 0) {
+    scal[(S_RZ0 + (slot ^ 1)) * cols + c] = rzn;
+    scal[S_RR * cols + c] = rr;
+  }
+}
+
+__global__ void f64_to_f32_kernel(const double *__restrict__ a, float *__restrict__ b,
+                                  int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) b[i] = (float)a[i];
+}
+
+__global__ void f32_to_f64_kernel(const float *__restrict__ a, double *__restrict__ b,
+                                  int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) b[i] = (double)a[i];
+}
+
+__global__ void zero_kernel(double *__restrict__ a, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) a[i] = 0.0;
+}
+
+// Copy rows of a frame-major (f, n) array into (cols, ld) with zero padding.
+__global__ void pack_kernel(const double *__restrict__ src, int64_t n, int64_t f,
+                            double *__restrict__ dst, int64_t ld, int64_t cols) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (i >= ld || c >= cols) return;
+  dst[c * ld + i] = (c < f && i < n) ? src[c * n + i] : 0.0;
+}
+
+// Two-step neutralisation (Eq. 35): q = x - (sum(x) + Q_sol) d, one block per
+// frame; also reports |sum(q) + Q_sol|.
+__global__ __launch_bounds__(RED_THREADS) void project_kernel(
+    const double *__restrict__ x, int64_t ld, int64_t n, const double *__restrict__ d,
+    const double *__restrict__ qsol, double *__restrict__ q, double *__restrict__ sum_err) {
+  __shared__ double red[RED_THREADS];
+  const int64_t f = blockIdx.x;
+  const double *xf = x + f * ld;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) s += xf[i];
+  s = block_sum(s, red);
+  const double shift = s + qsol[f];
+  double t = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) {
+    const double qi = xf[i] - shift * d[i];
+    q[f * n + i] = qi;
+    t += qi;
+  }
+  t = block_sum(t, red);
+  if (threadIdx.x == 0) sum_err[f] = fabs(t + qsol[f]);
+}
+
+__global__ void diag_inverse_kernel(const double *__restrict__ E, int64_t n, int64_t ld,
+                                    double *__restrict__ dinv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ld) dinv[i] = (i < n) ? 1.0 / E[i * ld + i] : 0.0;
+}
+
+// ------------------------------------------------------------------ host side
+
+dim3 elem_grid(int64_t count) { return dim3((unsigned)((count + 255) / 256)); }
+
+// profiling context of the current call (set by the drivers below)
+thread_local Profile *t_prof = nullptr;
+thread_local int64_t t_n = 0;
+
+template <typename T> constexpr int prec_of() {
+  return sizeof(T) == 8 ? CPM_PREC_F64 : (sizeof(T) == 4 ? CPM_PREC_F32 : CPM_PREC_BF16);
+}
+
+// number of row blocks of the block product for storage type T
+template <typename T> int64_t matvec_blocks(int64_t ld) { return ld / (16 * Mv<T>::RT); }
+
+template <typename T, int NG>
+hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typename Mv<T>::VT *P,
+                           typename Mv<T>::VT *V, double *pv_part) {
+  constexpr int KB = 4 * Mv<T>::VEC;
+  constexpr int W = mv_waves<NG>();
+  const int64_t kq = ((ld + W - 1) / W + KB - 1) / KB * KB;
+  const int64_t blocks = matvec_blocks<T>(ld);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (t_prof && t_prof->enabled) {
+    // algorithmic traffic: E (n x n) once, the n x cols block P read and V written
+    const double n = (double)t_n;
+    const double work = sizeof(T) * n * n + 2.0 * sizeof(typename Mv<T>::VT) * n * (NG * 16);
+    Profile::Rec &r = t_prof->add(prec_of<T>(), work);
+    ea = r.a;
+    eb = r.b;
+  }
+  hipExtLaunchKernelGGL((block_matvec_kernel<T, NG>), dim3((unsigned)blocks), dim3(64 * W), 0,
+                        st, ea, eb, 0, E, ld, P, V, kq, pv_part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_matvec(hipStream_t st, const T *E, int64_t ld, int64_t cols,
+                         const typename Mv<T>::VT *P, typename Mv<T>::VT *V, double *pv_part) {
+  switch (cols / 16) {
+    case 1: return launch_matvec_t<T, 1>(st, E, ld, P, V, pv_part);
+    case 2: return launch_matvec_t<T, 2>(st, E, ld, P, V, pv_part);
+    case 3: return launch_matvec_t<T, 3>(st, E, ld, P, V, pv_part);
+    case 4: return launch_matvec_t<T, 4>(st, E, ld, P, V, pv_part);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+void free_workspace(Workspace &w) {
+  void *ptrs[] = {w.x, w.r, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.bx, w.bres, w.flags,
+                  w.xf, w.rf, w.pf, w.zf, w.vf};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  w = Workspace();
+}
+
+cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
+  Workspace &w = s->ws;
+  if (w.cols >= cols) return CPM_OK;
+  s->device_bytes -= (int64_t)w.bytes;
+  free_workspace(w);
+  const int64_t ld = s->ld;
+  const size_t vec = sizeof(double) * (size_t)ld * (size_t)cols;
+  const int64_t nblk = (s->n + CHUNK - 1) / CHUNK;
+  const int64_t npv = ld / 16;   // most row blocks of the block product (FP64)
+  size_t total = 0;
+  auto alloc = [&](void **p, size_t bytes) -> bool {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    total += bytes;
+    return true;
+  };
+  // x, r, z, b, v (FP64); p (FP64) and pf, vf (FP32) for the mixed modes
+  bool ok = alloc(&w.x, vec) && alloc(&w.r, vec) && alloc(&w.p, vec) && alloc(&w.z, vec) &&
+            alloc(&w.v, vec) && alloc((void **)&w.bx, vec) && alloc((void **)&w.bres, vec) &&
+            alloc(&w.pf, vec / 2) && alloc(&w.vf, vec / 2) &&
+            alloc((void **)&w.partial, sizeof(double) * 2 * (size_t)(nblk + npv) * cols) &&
+            alloc((void **)&w.scal, sizeof(double) * S_NFIELDS * cols) &&
+            alloc((void **)&w.flags, sizeof(int) * 8);
+  if (!ok) {
+    free_workspace(w);
+    set_error("workspace allocation failed");
+    return CPM_ENOMEM;
+  }
+  void *zs[] = {w.x, w.r, w.p, w.z, w.v, w.bx, w.bres};
+  for (void *q : zs)
+    if (hipMemset(q, 0, vec) != hipSuccess) {
+      set_error("workspace memset failed");
+      return CPM_EDEVICE;
+    }
+  void *zf[] = {w.pf, w.vf};
+  for (void *q : zf)
+    if (hipMemset(q, 0, vec / 2) != hipSuccess) {
+      set_error("workspace memset failed");
+      return CPM_EDEVICE;
+    }
+  w.cols = cols;
+  w.bytes = total;
+  s->device_bytes += (int64_t)total;
+  return CPM_OK;
+}
+
+struct HostScal {
+  std::vector<double> v;
+  int cols = 0;
+  double rr(int c) const { return v[S_RR * cols + c]; }
+  double bn2(int c) const { return v[S_BN2 * cols + c]; }
+};
+
+cpm_status read_scal(cpm_system *s, int cols, HostScal &h, int *flag) {
+  h.cols = cols;
+  h.v.resize(S_NFIELDS * cols);
+  CPM_HIP_CHECK(hipMemcpyAsync(h.v.data(), s->ws.scal, sizeof(double) * S_NFIELDS * cols,
+                               hipMemcpyDeviceToHost, s->stream));
+  if (flag)
+    CPM_HIP_CHECK(hipMemcpyAsync(flag, s->ws.flags, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return CPM_OK;
+}
+
+cpm_status write_active(cpm_system *s, int cols, const std::vector<double> &act) {
+  CPM_HIP_CHECK(hipMemcpyAsync(s->ws.scal + S_ACT * cols, act.data(), sizeof(double) * cols,
+                               hipMemcpyHostToDevice, s->stream));
+  return CPM_OK;
+}
+
+// The solver over one block of cols columns. VT is the vector type of p and
+// v (double for FP64 E, float for FP32 / BF16 E); x, r, z, b are FP64.
+template <typename T> struct Solver {
+  using VT = typename Mv<T>::VT;
+  cpm_system *s;
+  hipStream_t st;
+  const T *E;
+  int64_t n, ld, cols;
+  int nblk, npv;
+  double *x, *r, *z, *b, *v64, *partial, *pvp, *scal;
+  VT *p, *v;
+  int *flags;
+  int slot = 0;
+
+  Solver(cpm_system *s_, const T *E_, int64_t cols_) : s(s_), st(s_->stream), E(E_) {
+    n = s->n;
+    ld = s->ld;
+    cols = cols_;
+    nblk = (int)((n + CHUNK - 1) / CHUNK);
+    npv = (int)matvec_blocks<T>(ld);
+    Workspace &w = s->ws;
+    x = (double *)w.x; r = (double *)w.r; z = (double *)w.z; b = w.bx; v64 = (double *)w.v;
+    partial = w.partial;
+    pvp = w.partial + 2 * (int64_t)nblk * cols;
+    scal = w.scal;
+    flags = w.flags;
+    if constexpr (sizeof(VT) == 8) {
+      p = (VT *)w.p;
+      v = (VT *)w.v;
+    } else {
+      p = (VT *)w.pf;
+      v = (VT *)w.vf;
+    }
+  }
+  dim3 grid() const { return dim3((unsigned)nblk, (unsigned)cols); }
+
+  // r = b - E64 x for all columns; scal RR = |r|^2
+  hipError_t true_residual() {
+    hipError_t e = launch_matvec<double>(st, s->E64, ld, cols, x, v64, nullptr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(residual_kernel, grid(), dim3(RED_THREADS), 0, st, v64, b, r, ld, n,
+                       (int)cols, partial);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, partial, nblk,
+                       (int)cols, scal, (int)S_RR);
+    return hipGetLastError();
+  }
+
+  // z = M^-1 r (and p = z when restarting); rz into the current slot
+  hipError_t refresh(bool set_p) {
+    hipLaunchKernelGGL(cg_refresh_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, r, z, p, s->dinv,
+                       ld, n, (int)cols, scal, partial, set_p ? 1 : 0);
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(MAX_COLS), 0, st, partial, nblk,
+                       (int)cols, scal, slot);
+    return hipGetLastError();
+  }
+
+  hipError_t iterate() {
+    hipError_t e = launch_matvec<T>(st, E, ld, cols, p, v, pvp);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cg_update_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, x, r, z, p, v,
+                       s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial, flags);
+    hipLaunchKernelGGL(cg_direction_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, p, z, ld, n,
+                       (int)cols, nblk, partial, scal, slot);
+    slot ^= 1;
+    return hipGetLastError();
+  }
+};
+
+cpm_status breakdown_error(cpm_system *s, int it_done, int cols, const HostScal &h) {
+  int fl[8] = {0};
+  CPM_HIP_CHECK(hipMemcpy(fl, s->ws.flags, sizeof(fl), hipMemcpyDeviceToHost));
+  double dbg[2];
+  std::memcpy(dbg, fl + 2, sizeof(dbg));
+  const int c = fl[1];
+  set_error("CG breakdown: p^T E p <= 0 (E is not positive definite); column " +
+            std::to_string(c) + " after " + std::to_string(it_done) + " iterations, p.Ep=" +
+            std::to_string(dbg[0]) + " r.z=" + std::to_string(dbg[1]) +
+            " |r|^2=" + std::to_string(c >= 0 && c < cols ? h.rr(c) : -1.0));
+  return CPM_ENOTSPD;
+}
+
+// CG with reliable updates on columns [0, fc) of the workspace block: b in
+// ws.bx, start in ws.x (x_zero: it is zero). On return ws.x holds q_b.
+template <typename T>
+cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o,
+                      cpm_solve_info *info, std::vector<int> &frame_iters,
+                      std::vector<double> &frame_res, bool x_zero) {
+  const int64_t cols = round_up(fc, kColGroup);
+  Solver<T> sv(s, E, cols);
+  hipStream_t st = s->stream;
+  const bool f64 = sizeof(T) == 8;
+  // reliable-update factor: the recursive residual may fall this far below
+  // the last true residual before it is replaced (FP64: only at the end)
+  const double ru = f64 ? 0.0 : std::min(0.5, std::max(1e-8, o.inner_tol));
+  const bool restart = sizeof(T) == 2;
+  const double tol = o.tol;
+  std::vector<double> act(cols, 0.0);
+  for (int c = 0; c < fc; ++c) act[c] = 1.0;
+  cpm_status stt = write_active(s, (int)cols, act);
+  if (stt != CPM_OK) return stt;
+  CPM_HIP_CHECK(hipMemsetAsync(sv.flags, 0, sizeof(int) * 8, st));
+
+  // |b|^2
+  hipLaunchKernelGGL(sumsq_kernel, sv.grid(), dim3(RED_THREADS), 0, st, sv.b, sv.ld, sv.n,
+                     (int)cols, sv.partial);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.partial, sv.nblk,
+                     (int)cols, sv.scal, (int)S_BN2);
+  // start residual
+  if (x_zero) {
+    CPM_HIP_CHECK(hipMemcpyAsync(sv.r, sv.b, sizeof(double) * sv.ld * cols,
+                                 hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(sumsq_kernel, sv.grid(), dim3(RED_THREADS), 0, st, sv.r, sv.ld, sv.n,
+                       (int)cols, sv.partial);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.partial, sv.nblk,
+                       (int)cols, sv.scal, (int)S_RR);
+  } else {
+    CPM_HIP_CHECK(sv.true_residual());
+  }
+  HostScal h;
+  if ((stt = read_scal(s, (int)cols, h, nullptr)) != CPM_OK) return stt;
+  std::vector<double> bn(cols, 0.0), rtrue(cols, 0.0);
+  double init_res = 0.0;
+  for (int c = 0; c < fc; ++c) {
+    bn[c] = std::sqrt(h.bn2(c));
+    double rn = std::sqrt(h.rr(c));
+    if (bn[c] == 0.0) {   // b = 0: q_b = 0
+      act[c] = 0.0;
+      continue;
+    }
+    if (!x_zero && !(rn < bn[c])) {
+      // a start no better than zero (or non-finite): discard it
+      CPM_HIP_CHECK(hipMemsetAsync(sv.x + c * sv.ld, 0, sizeof(double) * sv.ld, st));
+      CPM_HIP_CHECK(hipMemcpyAsync(sv.r + c * sv.ld, sv.b + c * sv.ld, sizeof(double) * sv.ld,
+                                   hipMemcpyDeviceToDevice, st));
+      rn = bn[c];
+      if (info) info->fell_back = 1;
+    }
+    rtrue[c] = rn;
+    init_res = std::max(init_res, rn / bn[c]);
+    if (rn <= tol * bn[c]) act[c] = 0.0;
+    frame_res[c] = rn / bn[c];
+  }
+  if (info) info->initial_rel_resid = std::max(info->initial_rel_resid, init_res);
+  if ((stt = write_active(s, (int)cols, act)) != CPM_OK) return stt;
+  sv.slot = 0;
+  CPM_HIP_CHECK(sv.refresh(true));
+
+  auto any_active = [&]() {
+    for (int c = 0; c < fc; ++c)
+      if (act[c] != 0.0) return true;
+    return false;
+  };
+  const int check = std::max(1, o.check_every);
+  int it = 0, updates = 0;
+  int flag = 0;
+  while (any_active() && it < o.max_iter) {
+    const int todo = std::min(check, o.max_iter - it);
+    for (int k = 0; k < todo; ++k) CPM_HIP_CHECK(sv.iterate());
+    for (int c = 0; c < fc; ++c)
+      if (act[c] != 0.0) frame_iters[c] += todo;
+    it += todo;
+    if ((stt = read_scal(s, (int)cols, h, &flag)) != CPM_OK) return stt;
+    if (flag) return breakdown_error(s, it, (int)cols, h);
+    bool need = it >= o.max_iter;
+    for (int c = 0; c < fc && !need; ++c) {
+      if (act[c] == 0.0) continue;
+      const double rn = std::sqrt(h.rr(c));
+      if (!std::isfinite(rn)) {
+        set_error("CG produced a non-finite residual");
+        return CPM_ENOTSPD;
+      }
+      if (rn <= 0.5 * tol * bn[c] || (ru > 0.0 && rn <= ru * rtrue[c])) need = true;
+    }
+    if (!need) continue;
+    // reliable update: true FP64 residual of every column
+    CPM_HIP_CHECK(sv.true_residual());
+    if ((stt = read_scal(s, (int)cols, h, nullptr)) != CPM_OK) return stt;
+    ++updates;
+    for (int c = 0; c < fc; ++c) {
+      if (bn[c] == 0.0) continue;
+      const double rn = std::sqrt(h.rr(c));
+      frame_res[c] = rn / bn[c];
+      if (act[c] == 0.0) continue;
+      rtrue[c] = rn;
+      if (rn <= tol * bn[c]) act[c] = 0.0;
+    }
+    if ((stt = write_active(s, (int)cols, act)) != CPM_OK) return stt;
+    // FP32: keep the search direction (reliable update). BF16: its matrix
+    // error (~2^-9 per entry) is too large for the old direction to stay
+    // conjugate, so the iteration restarts from the true residual.
+    if (any_active()) CPM_HIP_CHECK(sv.refresh(restart));
+  }
+  if (info) {
+    info->iterations = std::max(info->iterations, it);
+    info->outer = std::max(info->outer, updates);
+    for (int c = 0; c < fc; ++c) info->max_rel_resid = std::max(info->max_rel_resid, frame_res[c]);
+  }
+  for (int c = 0; c < fc; ++c)
+    if (frame_res[c] > tol) {
+      set_error("CG did not reach the tolerance within max_iter");
+      return CPM_ENOTCONV;
+    }
+  return CPM_OK;
+}
+
+cpm_status solve_columns(cpm_system *s, int fc, const cpm_solve_opts &o, cpm_solve_info *info,
+                         std::vector<int> &frame_iters, std::vector<double> &frame_res,
+                         bool x_zero) {
+  switch (o.precision) {
+    case CPM_PREC_F64:
+      return run_solver<double>(s, s->E64, fc, o, info, frame_iters, frame_res, x_zero);
+    case CPM_PREC_F32:
+      return run_solver<float>(s, s->E32, fc, o, info, frame_iters, frame_res, x_zero);
+    default:
+      return run_solver<uint16_t>(s, s->E16, fc, o, info, frame_iters, frame_res, x_zero);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_diag_inverse(hipStream_t st, const double *E, int64_t n, int64_t ld,
+                               double *dinv) {
+  hipLaunchKernelGGL(diag_inverse_kernel, elem_grid(ld), dim3(256), 0, st, E, n, ld, dinv);
+  return hipGetLastError();
+}
+
+cpm_status solve_dprime(cpm_system *s, double tol, int max_iter) {
+  t_prof = &s->prof;
+  t_n = s->n;
+  cpm_status stt = ensure_workspace(s, kColGroup);
+  if (stt != CPM_OK) return stt;
+  const int64_t ld = s->ld;
+  // b = 1 on the n atoms (column 0), zero elsewhere
+  std::vector<double> ones(ld * kColGroup, 0.0);
+  for (int64_t i = 0; i < s->n; ++i) ones[i] = 1.0;
+  CPM_HIP_CHECK(hipMemcpyAsync(s->ws.bx, ones.data(), sizeof(double) * ones.size(),
+                               hipMemcpyHostToDevice, s->stream));
+  CPM_HIP_CHECK(hipMemsetAsync(s->ws.x, 0, sizeof(double) * ld * kColGroup, s->stream));
+  cpm_solve_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.tol = tol;
+  o.max_iter = max_iter;
+  o.precision = CPM_PREC_F64;
+  o.check_every = 16;
+  std::vector<int> it(kColGroup, 0);
+  std::vector<double> res(kColGroup, 0.0);
+  stt = solve_columns(s, 1, o, nullptr, it, res, true);
+  if (stt != CPM_OK) return stt;
+  CPM_HIP_CHECK(hipMemcpyAsync(s->dprime, s->ws.x, sizeof(double) * ld, hipMemcpyDeviceToDevice,
+                               s->stream));
+  std::vector<double> dp(s->n);
+  CPM_HIP_CHECK(hipMemcpyAsync(dp.data(), s->dprime, sizeof(double) * s->n, hipMemcpyDeviceToHost,
+                               s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  double c = 0.0;
+  for (double v : dp) c += v;
+  if (!(c > 0.0) || !std::isfinite(c)) {
+    set_error("neutralising vector: 1^T E^-1 1 is not positive");
+    return CPM_ENOTSPD;
+  }
+  s->c_ele = c;
+  for (double &v : dp) v /= c;
+  dp.resize(ld, 0.0);
+  CPM_HIP_CHECK(hipMemcpyAsync(s->dvec, dp.data(), sizeof(double) * ld, hipMemcpyHostToDevice,
+                               s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return CPM_OK;
+}
+
+cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
+                       const cpm_solve_opts &o, double *q_out_dev, cpm_solve_info *info,
+                       const double *x0_dev) {
+  t_prof = &s->prof;
+  t_n = s->n;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t ld = s->ld, n = s->n;
+  hipStream_t st = s->stream;
+  cpm_status result = CPM_OK;
+  std::vector<double> sum_err(MAX_COLS);
+  double *sum_err_dev = nullptr;
+  CPM_HIP_CHECK(hipMallocAsync((void **)&sum_err_dev, sizeof(double) * MAX_COLS, st));
+  for (int64_t f0 = 0; f0 < f; f0 += MAX_COLS) {
+    const int fc = (int)std::min<int64_t>(MAX_COLS, f - f0);
+    const int64_t cols = round_up(fc, kColGroup);
+    cpm_status stt = ensure_workspace(s, cols);
+    if (stt != CPM_OK) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)cols), dim3(256),
+                       0, st, b_dev + f0 * n, n, (int64_t)fc, s->ws.bx, ld, cols);
+    if (x0_dev) {
+      hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)cols),
+                         dim3(256), 0, st, x0_dev + f0 * n, n, (int64_t)fc, (double *)s->ws.x, ld,
+                         cols);
+    } else {
+      hipLaunchKernelGGL(zero_kernel, elem_grid(ld * cols), dim3(256), 0, st, (double *)s->ws.x,
+                         ld * cols);
+    }
+    std::vector<int> fit(cols, 0);
+    std::vector<double> fres(cols, 0.0);
+    stt = solve_columns(s, fc, o, info, fit, fres, x0_dev == nullptr);
+    if (stt != CPM_OK && stt != CPM_ENOTCONV) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
+    if (stt == CPM_ENOTCONV) result = CPM_ENOTCONV;
+    hipLaunchKernelGGL(project_kernel, dim3((unsigned)fc), dim3(RED_THREADS), 0, st,
+                       (const double *)s->ws.x, ld, n, s->dvec, qsol_dev + f0, q_out_dev + f0 * n,
+                       sum_err_dev);
+    CPM_HIP_CHECK(hipMemcpyAsync(sum_err.data(), sum_err_dev, sizeof(double) * fc,
+                                 hipMemcpyDeviceToHost, st));
+    CPM_HIP_CHECK(hipStreamSynchronize(st));
+    if (info) {
+      for (int c = 0; c < fc; ++c) {
+        info->max_abs_sum_q = std::max(info->max_abs_sum_q, sum_err[c]);
+        if (info->frame_iters) info->frame_iters[f0 + c] = fit[c];
+        if (info->frame_rel_resid) info->frame_rel_resid[f0 + c] = fres[c];
+      }
+    }
+  }
+  (void)hipFreeAsync(sum_err_dev, st);
+  CPM_HIP_CHECK(hipStreamSynchronize(st));
+  if (info)
+    info->solve_ms +=
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return result;
+}
+
+cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_t f,
+                       double *v_dev) {
+  t_prof = &s->prof;
+  t_n = s->n;
+  hipStream_t st = s->stream;
+  const int64_t ld = s->ld, n = s->n;
+  for (int64_t f0 = 0; f0 < f; f0 += MAX_COLS) {
+    const int fc = (int)std::min<int64_t>(MAX_COLS, f - f0);
+    const int64_t cols = round_up(fc, kColGroup);
+    cpm_status stt = ensure_workspace(s, cols);
+    if (stt != CPM_OK) return stt;
+    double *in = s->ws.bres;   // packed input (double)
+    double *out = (double *)s->ws.v;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)cols), dim3(256),
+                       0, st, p_dev + f0 * n, n, (int64_t)fc, in, ld, cols);
+    if (precision == CPM_PREC_F64) {
+      CPM_HIP_CHECK(launch_matvec<double>(st, s->E64, ld, cols, in, out, nullptr));
+    } else {
+      float *pf = (float *)s->ws.pf, *vf = (float *)s->ws.vf;
+      hipLaunchKernelGGL(f64_to_f32_kernel, elem_grid(ld * cols), dim3(256), 0, st, in, pf,
+                         ld * cols);
+      if (precision == CPM_PREC_F32)
+        CPM_HIP_CHECK(launch_matvec<float>(st, s->E32, ld, cols, pf, vf, nullptr));
+      else
+        CPM_HIP_CHECK(launch_matvec<uint16_t>(st, s->E16, ld, cols, pf, vf, nullptr));
+      hipLaunchKernelGGL(f32_to_f64_kernel, elem_grid(ld * cols), dim3(256), 0, st, vf, out,
+                         ld * cols);
+    }
+    CPM_HIP_CHECK(hipMemcpy2DAsync(v_dev + f0 * n, sizeof(double) * n, out, sizeof(double) * ld,
+                                   sizeof(double) * n, fc, hipMemcpyDeviceToDevice, st));
+  }
+  CPM_HIP_CHECK(hipGetLastError());
+  return CPM_OK;
+}
+
+}  // namespace cpm

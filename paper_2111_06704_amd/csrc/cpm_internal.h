@@ -1,0 +1,166 @@
+// Internal declarations shared by the HIP translation units of libcpm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_ext.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cpm.h"
+
+namespace cpm {
+
+constexpr int kColGroup = 16;  // CG works on column groups of 16 right-hand sides
+constexpr double kCoulombVA = 14.3996454784;   // e^2/(4 pi eps0) in V*A/e
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// thread-local error message
+void set_error(const std::string &msg);
+const char *last_error();
+
+struct Kset {
+  int64_t nk = 0;              // number of half-space vectors
+  int nmax[3] = {0, 0, 0};
+  std::vector<int32_t> n;      // nk*3 integer triplets
+  std::vector<double> w;       // nk weights 2 (4 pi / V) exp(-K^2/4 beta^2) / K^2
+};
+
+// Half-space reciprocal vectors with |K| <= kmax, K != 0 (host).
+Kset make_kset(const double box[3], double beta, double kmax);
+
+struct Workspace {            // CG scratch, grown on demand
+  int64_t cols = 0;           // padded number of columns the buffers hold
+  int splits = 0;
+  void *x = nullptr, *r = nullptr, *p = nullptr, *z = nullptr, *v = nullptr;  // n_pad*cols (double)
+  void *vpart = nullptr;      // splits*n_pad*cols (double)
+  // FP32 vectors of the inner CG, separate from the FP64 ones so that their
+  // padding rows (>= n) are always zero
+  void *xf = nullptr, *rf = nullptr, *pf = nullptr, *zf = nullptr, *vf = nullptr;
+  double *partial = nullptr;  // dot partial sums: 2*nblk*cols
+  double *scal = nullptr;     // per-column scalars, see cg.hip
+  double *bx = nullptr;       // n_pad*cols double: right-hand sides / outer iterate
+  double *bres = nullptr;     // n_pad*cols double: outer residual
+  int *flags = nullptr;       // device flags
+  size_t bytes = 0;
+};
+
+struct Mlp {
+  bool ready = false;
+  int32_t *nbr = nullptr;     // n*12
+  float *nbr_r = nullptr;     // n*12 distances
+  int32_t *layer = nullptr;   // n
+  int32_t n_layers = 1;
+  float b_scale = 1.f, r_scale = 1.f, q_scale = 1.f;
+  float *params = nullptr;    // CPM_MLP_NPARAM
+  float *adam_m = nullptr, *adam_v = nullptr;
+  float *grad = nullptr;      // CPM_MLP_NPARAM
+  float *gpart = nullptr;     // per-tile gradient partials
+  int64_t gpart_tiles = 0;
+  double *loss = nullptr;     // device loss scalar(s)
+  int64_t step = 0;
+  float *feat = nullptr;      // feature scratch for the warm start
+  float *yout = nullptr;
+  int64_t feat_rows = 0;
+  bool params_set = false;
+};
+
+// Live kernel timing: HIP events around every launch of the profiled
+// kernels (block matrix product per storage precision, and the assembly
+// contraction), enabled per system.
+struct Profile {
+  bool enabled = false;
+  struct Rec {
+    int kind;              // 0..2: matvec FP64/FP32/BF16, 3: assembly contraction
+    double work;           // algorithmic bytes (matvec) or flops (assembly) of the launch
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  // new record; its events are passed to hipExtLaunchKernelGGL, which
+  // stamps them as part of the kernel dispatch (no extra queue packets)
+  Rec &add(int kind, double work);
+  void reset();
+};
+
+}  // namespace cpm
+
+struct cpm_system {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t n = 0, ld = 0;      // ld = padded leading dimension (multiple of 128)
+  double box[3] = {0, 0, 0};
+  double vol = 0, beta = 0, rcut = 0, kmax = 0;
+  cpm::Kset kset;
+  double *pos = nullptr;      // n*3 device
+  double *width = nullptr;    // n device (Gaussian inverse widths)
+  int32_t *kn = nullptr;      // nk*3 device
+  double *kw = nullptr;       // nk device
+  double *E64 = nullptr;      // ld*ld device (rows >= n and cols >= n are zero)
+  float *E32 = nullptr;
+  uint16_t *E16 = nullptr;
+  double *dinv = nullptr;     // ld: 1/E_ii (zero in padding)
+  double *dprime = nullptr;   // ld: E^-1 1
+  double *dvec = nullptr;     // ld: d' / C_ele
+  double c_ele = 0;
+  bool dprime_ready = false;
+  double *qchi = nullptr;     // ld: neutral charges without electrolyte (warm start)
+  bool qchi_ready = false;
+  double *rhs_S = nullptr;    // structure-factor scratch
+  int64_t rhs_S_elems = 0;
+  std::vector<double> pos_host;   // n*3 wrapped positions (host copy)
+  cpm::Workspace ws;
+  cpm::Mlp mlp;
+  cpm::Profile prof;
+  int64_t device_bytes = 0;
+};
+
+namespace cpm {
+
+// ---- assembly.hip
+hipError_t launch_phase_matrix(hipStream_t st, const double *pos, int64_t n, int64_t ld,
+                               const double box[3], const int32_t *kn, const double *kw,
+                               int64_t k0, int64_t kc, int64_t lda, double *A);
+hipError_t launch_syrk_lower(hipStream_t st, const double *A, int64_t lda, int64_t kdim,
+                             int64_t ld, double *E, int64_t lde, bool accumulate,
+                             hipEvent_t ev_start, hipEvent_t ev_stop);
+hipError_t launch_finalize(hipStream_t st, const double *pos, const double *width, int64_t n,
+                           int64_t ld, const double box[3], double beta, double rcut,
+                           double *E64, float *E32, uint16_t *E16);
+
+// ---- rhs.hip
+int64_t rhs_scratch_elems(int64_t n, int64_t nk, int64_t f);
+hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos,
+                      const double *ion_q, int64_t m, int64_t f, const double *chi,
+                      double *S, double *b_out, double *qsol_out);
+
+// ---- cg.hip
+cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
+                       const cpm_solve_opts &o, double *q_out_dev, cpm_solve_info *info,
+                       const double *x0_dev);
+cpm_status solve_dprime(cpm_system *s, double tol, int max_iter);
+cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_t f,
+                       double *v_dev);
+hipError_t launch_diag_inverse(hipStream_t st, const double *E, int64_t n, int64_t ld,
+                               double *dinv);
+
+// ---- mlp.hip
+cpm_status warm_start_impl(cpm_system *s, bool use_mlp, const double *b, const double *qsol,
+                           int64_t f, double *x0);
+hipError_t launch_mlp_forward(hipStream_t st, const float *params, const float *feat,
+                              int64_t rows, float *y);
+
+}  // namespace cpm
+
+#define CPM_HIP_CHECK(expr)                                                   \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      cpm::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));     \
+      return CPM_EDEVICE;                                                     \
+    }                                                                         \
+  } while (0)

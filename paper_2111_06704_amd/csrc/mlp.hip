@@ -1,0 +1,858 @@
+// Learned CG starting point: a per-atom network 26 -> 64 -> 64 -> 1 (SiLU).
+//
+// Inputs of atom i in a frame with right-hand side b (Eq. 25):
+//   [ (b_i - mean b) / b_scale, layer_i / (n_layers - 1),
+//     (b_j - mean b) / b_scale for its 12 nearest electrode neighbours j,
+//     r_ij / r_scale for the same neighbours ].
+// Output y_i; predicted charge q0_i = q_scale * y_i.
+//
+// Warm start of the two-step solve (Eq. 29-35): q0 is shifted to
+// sum(q0) = -Q_sol; then mu0 = mean(b - E q0) estimates the Lagrange shift
+// of Eq. 29, and q_b0 = q0 + mu0 d' (d' = E^-1 1, S9) starts E q_b = b.
+// The same construction with q0 = q_chi (the solution without electrolyte)
+// is the non-learned warm start.
+//
+// Training: mean squared error on q / q_scale, gradient by a hand-written
+// backward pass (per 64-row tile in LDS), fixed-order reduction over tiles,
+// and the Adam update (Kingma & Ba 2015).
+#include "cpm_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace cpm {
+namespace {
+
+constexpr int NIN = CPM_MLP_IN;
+constexpr int NH = CPM_MLP_HIDDEN;
+constexpr int NP = CPM_MLP_NPARAM;
+constexpr int NNB = 12;
+constexpr int TR = 32;          // rows per tile (LDS footprint < 64 KB)
+constexpr int RPG = TR / 16;    // rows per thread group in the layer products
+constexpr int TT = 256;         // threads per tile block
+// parameter offsets
+constexpr int OW1 = 0, OB1 = OW1 + NIN * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
+              OB3 = OW3 + NH;
+
+__device__ inline float sigm(float a) { return 1.0f / (1.0f + __expf(-a)); }
+
+// per-frame mean of b (fixed-order block reduction)
+__global__ __launch_bounds__(256) void frame_mean_kernel(const double *__restrict__ b, int64_t n,
+                                                         double *__restrict__ mean) {
+  __shared__ double red[256];
+  const int64_t f = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += b[f * n + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mean[f] = red[0] / (double)n;
+}
+
+// features of rows; row r is (frame, atom) = (id / n, id % n) with id =
+// rows_idx ? rows_idx[r] : r0 + r.
+__global__ void features_kernel(const double *__restrict__ b, const double *__restrict__ mean,
+                                int64_t n, const int32_t *__restrict__ nbr,
+                                const float *__restrict__ nbr_r, const int32_t *__restrict__ layer,
+                                float inv_layers, float inv_bs, float inv_rs,
+                                const int64_t *__restrict__ rows_idx, int64_t r0, int64_t rows,
+                                float *__restrict__ feat) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t id = rows_idx ? rows_idx[r] : r0 + r;
+  const int64_t f = id / n, i = id % n;
+  const double mb = mean[f];
+  const double *bf = b + f * n;
+  float *o = feat + r * NIN;
+  o[0] = (float)((bf[i] - mb) * (double)inv_bs);
+  o[1] = (float)layer[i] * inv_layers;
+#pragma unroll
+  for (int k = 0; k < NNB; ++k) {
+    o[2 + k] = (float)((bf[nbr[i * NNB + k]] - mb) * (double)inv_bs);
+    o[2 + NNB + k] = nbr_r[i * NNB + k] * inv_rs;
+  }
+}
+
+struct TileLds {
+  float x[TR][NIN + 1];
+  float a1[TR][NH + 1];
+  float a2[TR][NH + 1];
+  float g2[TR][NH + 1];   // dL/da2
+  float g1[TR][NH + 1];   // dL/da1
+  float w1[NIN][NH];
+  float w2[NH][NH];
+  float w3[NH];
+  float b1[NH], b2[NH];
+  float y[TR], dy[TR];
+  float b3;
+};
+
+__device__ inline void load_params(TileLds &L, const float *__restrict__ prm) {
+  for (int t = threadIdx.x; t < NIN * NH; t += TT) L.w1[t / NH][t % NH] = prm[OW1 + t];
+  for (int t = threadIdx.x; t < NH * NH; t += TT) L.w2[t / NH][t % NH] = prm[OW2 + t];
+  for (int t = threadIdx.x; t < NH; t += TT) {
+    L.w3[t] = prm[OW3 + t];
+    L.b1[t] = prm[OB1 + t];
+    L.b2[t] = prm[OB2 + t];
+  }
+  if (threadIdx.x == 0) L.b3 = prm[OB3];
+}
+
+// forward pass of one tile: a1, a2 pre-activations and y
+__device__ inline void tile_forward(TileLds &L, int nrows) {
+  const int t = threadIdx.x;
+  const int rg = t >> 4, ug = t & 15;   // rows rg*RPG.., units ug*4..+3
+  {
+    float acc[RPG][4];
+#pragma unroll
+    for (int a = 0; a < RPG; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = L.b1[ug * 4 + c];
+    for (int k = 0; k < NIN; ++k) {
+      float xv[RPG], wv[4];
+#pragma unroll
+      for (int a = 0; a < RPG; ++a) xv[a] = L.x[rg * RPG + a][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) wv[c] = L.w1[k][ug * 4 + c];
+#pragma unroll
+      for (int a = 0; a < RPG; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xv[a], wv[c], acc[a][c]);
+    }
+#pragma unroll
+    for (int a = 0; a < RPG; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) L.a1[rg * RPG + a][ug * 4 + c] = acc[a][c];
+  }
+  __syncthreads();
+  {
+    float acc[RPG][4];
+#pragma unroll
+    for (int a = 0; a < RPG; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = L.b2[ug * 4 + c];
+    for (int k = 0; k < NH; ++k) {
+      float hv[RPG], wv[4];
+#pragma unroll
+      for (int a = 0; a < RPG; ++a) {
+        const float z = L.a1[rg * RPG + a][k];
+        hv[a] = z * sigm(z);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) wv[c] = L.w2[k][ug * 4 + c];
+#pragma unroll
+      for (int a = 0; a < RPG; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(hv[a], wv[c], acc[a][c]);
+    }
+#pragma unroll
+    for (int a = 0; a < RPG; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) L.a2[rg * RPG + a][ug * 4 + c] = acc[a][c];
+  }
+  __syncthreads();
+  // y[r] = sum_j silu(a2[r][j]) w3[j] + b3: 4 threads per row, fixed order
+  if (t < 4 * TR) {
+    const int r = t >> 2, part = t & 3;
+    float s = 0.0f;
+    for (int j = part * 16; j < part * 16 + 16; ++j) {
+      const float z = L.a2[r][j];
+      s = fmaf(z * sigm(z), L.w3[j], s);
+    }
+    L.g1[r][part] = s;   // scratch
+  }
+  __syncthreads();
+  if (t < TR) {
+    L.y[t] = ((L.g1[t][0] + L.g1[t][1]) + (L.g1[t][2] + L.g1[t][3])) + L.b3;
+  }
+  __syncthreads();
+  (void)nrows;
+}
+
+__device__ inline void load_rows(TileLds &L, const float *__restrict__ feat, int64_t r0,
+                                 int nrows) {
+  for (int t = threadIdx.x; t < TR * NIN; t += TT) {
+    const int r = t / NIN, k = t % NIN;
+    L.x[r][k] = (r < nrows) ? feat[(r0 + r) * NIN + k] : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(TT) void mlp_forward_kernel(const float *__restrict__ prm,
+                                                         const float *__restrict__ feat,
+                                                         int64_t rows, float *__restrict__ y) {
+  extern __shared__ unsigned char smem[];
+  TileLds &L = *reinterpret_cast<TileLds *>(smem);
+  const int64_t r0 = (int64_t)blockIdx.x * TR;
+  const int nrows = (int)std::min<int64_t>(TR, rows - r0);
+  load_params(L, prm);
+  load_rows(L, feat, r0, nrows);
+  __syncthreads();
+  tile_forward(L, nrows);
+  if ((int)threadIdx.x < nrows) y[r0 + threadIdx.x] = L.y[threadIdx.x];
+}
+
+// Forward + backward of one tile; writes the tile's gradient (sum over its
+// rows of d/dtheta of (y - t)^2 / rows_total) and its loss sum.
+__global__ __launch_bounds__(TT) void mlp_grad_kernel(const float *__restrict__ prm,
+                                                      const float *__restrict__ feat,
+                                                      const float *__restrict__ target,
+                                                      int64_t rows, float inv_rows,
+                                                      float *__restrict__ gpart,
+                                                      double *__restrict__ lpart) {
+  extern __shared__ unsigned char smem[];
+  TileLds &L = *reinterpret_cast<TileLds *>(smem);
+  const int64_t r0 = (int64_t)blockIdx.x * TR;
+  const int nrows = (int)std::min<int64_t>(TR, rows - r0);
+  const int t = threadIdx.x;
+  load_params(L, prm);
+  load_rows(L, feat, r0, nrows);
+  __syncthreads();
+  tile_forward(L, nrows);
+  if (t < TR) {
+    const float e = (t < nrows) ? (L.y[t] - target[r0 + t]) : 0.0f;
+    L.dy[t] = 2.0f * e * inv_rows;
+    L.y[t] = e * e;   // squared error for the loss
+  }
+  __syncthreads();
+  float *g = gpart + (int64_t)blockIdx.x * NP;
+  if (t == 0) {
+    double ls = 0.0;
+    float db3 = 0.0f;
+    for (int r = 0; r < TR; ++r) {
+      ls += (double)L.y[r];
+      db3 += L.dy[r];
+    }
+    lpart[blockIdx.x] = ls;
+    g[OB3] = db3;
+  }
+  // dW3[j] = sum_r silu(a2[r][j]) dy[r]; g2[r][j] = dy[r] w3[j] silu'(a2[r][j])
+  if (t < NH) {
+    float s = 0.0f;
+    for (int r = 0; r < TR; ++r) {
+      const float z = L.a2[r][t];
+      s = fmaf(z * sigm(z), L.dy[r], s);
+    }
+    g[OW3 + t] = s;
+  }
+  for (int q = t; q < TR * NH; q += TT) {
+    const int r = q / NH, j = q % NH;
+    const float z = L.a2[r][j];
+    const float sg = sigm(z);
+    L.g2[r][j] = L.dy[r] * L.w3[j] * (sg * (1.0f + z * (1.0f - sg)));
+  }
+  __syncthreads();
+  // dW2[k][j] = sum_r silu(a1[r][k]) g2[r][j]; db2[j] = sum_r g2[r][j]
+  for (int q = t; q < NH * NH; q += TT) {
+    const int k = q / NH, j = q % NH;
+    float s = 0.0f;
+    for (int r = 0; r < TR; ++r) {
+      const float z = L.a1[r][k];
+      s = fmaf(z * sigm(z), L.g2[r][j], s);
+    }
+    g[OW2 + q] = s;
+  }
+  if (t < NH) {
+    float s = 0.0f;
+    for (int r = 0; r < TR; ++r) s += L.g2[r][t];
+    g[OB2 + t] = s;
+  }
+  // g1[r][k] = (sum_j g2[r][j] w2[k][j]) silu'(a1[r][k])
+  for (int q = t; q < TR * NH; q += TT) {
+    const int r = q / NH, k = q % NH;
+    float s = 0.0f;
+    for (int j = 0; j < NH; ++j) s = fmaf(L.g2[r][j], L.w2[k][j], s);
+    const float z = L.a1[r][k];
+    const float sg = sigm(z);
+    L.g1[r][k] = s * (sg * (1.0f + z * (1.0f - sg)));
+  }
+  __syncthreads();
+  // dW1[m][k] = sum_r x[r][m] g1[r][k]; db1[k] = sum_r g1[r][k]
+  for (int q = t; q < NIN * NH; q += TT) {
+    const int m = q / NH, k = q % NH;
+    float s = 0.0f;
+    for (int r = 0; r < TR; ++r) s = fmaf(L.x[r][m], L.g1[r][k], s);
+    g[OW1 + q] = s;
+  }
+  if (t < NH) {
+    float s = 0.0f;
+    for (int r = 0; r < TR; ++r) s += L.g1[r][t];
+    g[OB1 + t] = s;
+  }
+}
+
+// grad[p] = sum over tiles (fixed order, FP64 accumulation); loss likewise.
+__global__ void grad_reduce_kernel(const float *__restrict__ gpart, int64_t tiles,
+                                   float *__restrict__ grad, const double *__restrict__ lpart,
+                                   double *__restrict__ loss, double inv_rows) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < NP) {
+    double s = 0.0;
+    for (int64_t tl = 0; tl < tiles; ++tl) s += (double)gpart[tl * NP + p];
+    grad[p] = (float)s;
+  }
+  if (p == 0) {
+    double s = 0.0;
+    for (int64_t tl = 0; tl < tiles; ++tl) s += lpart[tl];
+    loss[0] = s * inv_rows;
+  }
+}
+
+__global__ void adam_kernel(float *__restrict__ prm, float *__restrict__ m, float *__restrict__ v,
+                            const float *__restrict__ g, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NP) return;
+  const float gi = g[p];
+  const float mi = b1 * m[p] + (1.0f - b1) * gi;
+  const float vi = b2 * v[p] + (1.0f - b2) * gi * gi;
+  m[p] = mi;
+  v[p] = vi;
+  const float mh = mi / c1, vh = vi / c2;
+  prm[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// flags[0] = 1 if any row id lies outside [0, total)
+__global__ void check_rows_kernel(const int64_t *__restrict__ ids, int64_t count, int64_t total,
+                                  int *__restrict__ flag) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < count && (ids[r] < 0 || ids[r] >= total)) flag[0] = 1;
+}
+
+// gather q / q_scale of rows as float targets
+__global__ void targets_kernel(const double *__restrict__ q, const int64_t *__restrict__ rows_idx,
+                               int64_t r0, int64_t rows, double inv_qs, float *__restrict__ t) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t id = rows_idx ? rows_idx[r] : r0 + r;
+  t[r] = (float)(q[id] * inv_qs);
+}
+
+// q0 = q_scale * y, frame-wise shift to sum(q0) = -Q_sol (one block per frame)
+__global__ __launch_bounds__(256) void neutral_shift_kernel(const float *__restrict__ y,
+                                                            const double *__restrict__ qchi,
+                                                            int64_t n, double qs,
+                                                            const double *__restrict__ qsol,
+                                                            double *__restrict__ q0) {
+  __shared__ double red[256];
+  const int64_t f = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double v = y ? qs * (double)y[f * n + i] : qchi[i];
+    q0[f * n + i] = v;
+    s += v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  const double shift = (red[0] + qsol[f]) / (double)n;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += 256) q0[f * n + i] -= shift;
+}
+
+// x0 = q0 + mu0 d' with mu0 = mean(b - E q0) (Eq = E q0 given in eq)
+__global__ __launch_bounds__(256) void lagrange_shift_kernel(const double *__restrict__ b,
+                                                             const double *__restrict__ eq,
+                                                             const double *__restrict__ dprime,
+                                                             int64_t n, double *__restrict__ x0) {
+  __shared__ double red[256];
+  const int64_t f = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += b[f * n + i] - eq[f * n + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  const double mu = red[0] / (double)n;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += 256) x0[f * n + i] += mu * dprime[i];
+}
+
+size_t tile_lds_bytes() { return sizeof(TileLds); }
+
+// Host 12-neighbour list: order by distance, then azimuth about +z from +x,
+// then index; distance and angle compared after rounding to 1e-6.
+cpm_status build_neighbours(const cpm_system *s, std::vector<int32_t> &nbr,
+                            std::vector<float> &nbr_r) {
+  const int64_t n = s->n;
+  if (n < NNB + 1) {
+    set_error("the warm-start network needs at least 13 electrode atoms");
+    return CPM_EINVAL;
+  }
+  const double *box = s->box;
+  nbr.assign(n * NNB, 0);
+  nbr_r.assign(n * NNB, 0.0f);
+  const double *pos = s->pos_host.data();
+  // cell grid
+  double reach = 3.0;
+  for (;;) {
+    int nc[3];
+    for (int d = 0; d < 3; ++d) nc[d] = std::max(1, (int)(box[d] / reach));
+    std::vector<std::vector<int64_t>> cells((size_t)nc[0] * nc[1] * nc[2]);
+    auto cell_of = [&](int64_t i, int d) {
+      int c = (int)(pos[3 * i + d] / box[d] * nc[d]);
+      return std::min(std::max(c, 0), nc[d] - 1);
+    };
+    for (int64_t i = 0; i < n; ++i)
+      cells[((size_t)cell_of(i, 0) * nc[1] + cell_of(i, 1)) * nc[2] + cell_of(i, 2)].push_back(i);
+    bool ok = true;
+    struct Cand {
+      long long kd, ka;
+      int64_t j;
+      double d;
+    };
+    std::vector<Cand> cand;
+    for (int64_t i = 0; i < n && ok; ++i) {
+      cand.clear();
+      const int ci[3] = {cell_of(i, 0), cell_of(i, 1), cell_of(i, 2)};
+      int span[3];
+      for (int d = 0; d < 3; ++d) span[d] = std::min(1, (nc[d] - 1) / 2 > 0 ? 1 : 0) + 0;
+      for (int d = 0; d < 3; ++d) span[d] = nc[d] >= 3 ? 1 : 0;
+      std::vector<size_t> seen;
+      for (int a = -span[0]; a <= span[0]; ++a)
+        for (int bb = -span[1]; bb <= span[1]; ++bb)
+          for (int c = -span[2]; c <= span[2]; ++c) {
+            const size_t cell = ((size_t)((ci[0] + a + nc[0]) % nc[0]) * nc[1] +
+                                 (ci[1] + bb + nc[1]) % nc[1]) * nc[2] + (ci[2] + c + nc[2]) % nc[2];
+            if (std::find(seen.begin(), seen.end(), cell) != seen.end()) continue;
+            seen.push_back(cell);
+            for (int64_t j : cells[cell]) {
+              if (j == i) continue;
+              double dv[3];
+              for (int d = 0; d < 3; ++d) {
+                double x = pos[3 * j + d] - pos[3 * i + d];
+                x -= box[d] * std::nearbyint(x / box[d]);
+                dv[d] = x;
+              }
+              const double dd = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+              if (dd > reach) continue;
+              double az = std::atan2(dv[1], dv[0]);
+              if (az < 0) az += 2.0 * M_PI;
+              cand.push_back({std::llround(dd * 1e6), std::llround(az * 1e6), j, dd});
+            }
+          }
+      if ((int64_t)cand.size() < NNB) {
+        ok = false;
+        break;
+      }
+      std::sort(cand.begin(), cand.end(), [](const Cand &x, const Cand &y) {
+        if (x.kd != y.kd) return x.kd < y.kd;
+        if (x.ka != y.ka) return x.ka < y.ka;
+        return x.j < y.j;
+      });
+      for (int k = 0; k < NNB; ++k) {
+        nbr[i * NNB + k] = (int32_t)cand[k].j;
+        nbr_r[i * NNB + k] = (float)cand[k].d;
+      }
+    }
+    if (ok) return CPM_OK;
+    reach *= 1.5;
+    if (reach > std::max(box[0], std::max(box[1], box[2]))) {
+      set_error("could not find 12 neighbours");
+      return CPM_EINVAL;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_mlp_forward(hipStream_t st, const float *params, const float *feat,
+                              int64_t rows, float *y) {
+  const int64_t tiles = (rows + TR - 1) / TR;
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)tiles), dim3(TT), tile_lds_bytes(), st,
+                     params, feat, rows, y);
+  return hipGetLastError();
+}
+
+static cpm_status ensure_rows(cpm_system *s, int64_t rows) {
+  Mlp &M = s->mlp;
+  if (M.feat_rows >= rows) return CPM_OK;
+  if (M.feat) (void)hipFree(M.feat);
+  if (M.yout) (void)hipFree(M.yout);
+  M.feat = nullptr;
+  M.yout = nullptr;
+  M.feat_rows = 0;
+  if (hipMalloc((void **)&M.feat, sizeof(float) * NIN * rows) != hipSuccess ||
+      hipMalloc((void **)&M.yout, sizeof(float) * rows) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("network scratch allocation failed");
+    return CPM_ENOMEM;
+  }
+  M.feat_rows = rows;
+  return CPM_OK;
+}
+
+static cpm_status ensure_gpart(cpm_system *s, int64_t tiles) {
+  Mlp &M = s->mlp;
+  if (M.gpart_tiles >= tiles) return CPM_OK;
+  if (M.gpart) (void)hipFree(M.gpart);
+  M.gpart = nullptr;
+  double *lp = nullptr;
+  if (hipMalloc((void **)&M.gpart, sizeof(float) * round_up((int64_t)NP * tiles, 64) +
+                                        sizeof(double) * (tiles + 8)) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    M.gpart_tiles = 0;
+    set_error("gradient scratch allocation failed");
+    return CPM_ENOMEM;
+  }
+  (void)lp;
+  M.gpart_tiles = tiles;
+  return CPM_OK;
+}
+
+static double *lpart_of(cpm_system *s) {
+  // the loss partials follow the gradient partials at a 256-byte boundary
+  return reinterpret_cast<double *>(s->mlp.gpart + round_up((int64_t)NP * s->mlp.gpart_tiles, 64));
+}
+
+static cpm_status loss_grad_impl(cpm_system *s, const float *feat, const float *target,
+                                 int64_t rows, float *grad_out) {
+  const int64_t tiles = (rows + TR - 1) / TR;
+  cpm_status rc = ensure_gpart(s, tiles);
+  if (rc != CPM_OK) return rc;
+  hipStream_t st = s->stream;
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)tiles), dim3(TT), tile_lds_bytes(), st,
+                     s->mlp.params, feat, target, rows, (float)(1.0 / (double)rows), s->mlp.gpart,
+                     lpart_of(s));
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, s->mlp.gpart,
+                     tiles, grad_out, lpart_of(s), s->mlp.loss, 1.0 / (double)rows);
+  CPM_HIP_CHECK(hipGetLastError());
+  return CPM_OK;
+}
+
+static cpm_status adam_impl(cpm_system *s, float lr, float b1, float b2, float eps) {
+  Mlp &M = s->mlp;
+  M.step += 1;
+  const float c1 = (float)(1.0 - std::pow((double)b1, (double)M.step));
+  const float c2 = (float)(1.0 - std::pow((double)b2, (double)M.step));
+  hipLaunchKernelGGL(adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, s->stream, M.params,
+                     M.adam_m, M.adam_v, M.grad, lr, b1, b2, eps, c1, c2);
+  CPM_HIP_CHECK(hipGetLastError());
+  return CPM_OK;
+}
+
+static cpm_status features_impl(cpm_system *s, const double *b, int64_t f,
+                                const int64_t *rows_idx, int64_t r0, int64_t rows, float *feat,
+                                double *mean_buf, bool compute_mean) {
+  const Mlp &M = s->mlp;
+  hipStream_t st = s->stream;
+  if (compute_mean)
+    hipLaunchKernelGGL(frame_mean_kernel, dim3((unsigned)f), dim3(256), 0, st, b, s->n, mean_buf);
+  const float inv_layers = M.n_layers > 1 ? 1.0f / (float)(M.n_layers - 1) : 0.0f;
+  hipLaunchKernelGGL(features_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, b,
+                     mean_buf, s->n, M.nbr, M.nbr_r, M.layer, inv_layers, 1.0f / M.b_scale,
+                     1.0f / M.r_scale, rows_idx, r0, rows, feat);
+  CPM_HIP_CHECK(hipGetLastError());
+  return CPM_OK;
+}
+
+// x0 (f, n) for the warm start; mode from the system state: network if its
+// parameters are set and requested, else q_chi.
+cpm_status warm_start_impl(cpm_system *s, bool use_mlp, const double *b, const double *qsol,
+                           int64_t f, double *x0) {
+  hipStream_t st = s->stream;
+  const int64_t n = s->n;
+  const float *y = nullptr;
+  double *mean = nullptr;
+  CPM_HIP_CHECK(hipMallocAsync((void **)&mean, sizeof(double) * f, st));
+  if (use_mlp) {
+    cpm_status rc = ensure_rows(s, f * n);
+    if (rc == CPM_OK) rc = features_impl(s, b, f, nullptr, 0, f * n, s->mlp.feat, mean, true);
+    if (rc != CPM_OK) {
+      (void)hipFreeAsync(mean, st);
+      return rc;
+    }
+    CPM_HIP_CHECK(launch_mlp_forward(st, s->mlp.params, s->mlp.feat, f * n, s->mlp.yout));
+    y = s->mlp.yout;
+  }
+  hipLaunchKernelGGL(neutral_shift_kernel, dim3((unsigned)f), dim3(256), 0, st, y, s->qchi, n,
+                     (double)s->mlp.q_scale, qsol, x0);
+  // E q0 (FP64) for the Lagrange shift
+  double *eq = nullptr;
+  CPM_HIP_CHECK(hipMallocAsync((void **)&eq, sizeof(double) * f * n, st));
+  cpm_status rc = matvec_cols(s, CPM_PREC_F64, x0, f, eq);
+  if (rc == CPM_OK)
+    hipLaunchKernelGGL(lagrange_shift_kernel, dim3((unsigned)f), dim3(256), 0, st, b, eq,
+                       s->dprime, n, x0);
+  (void)hipFreeAsync(eq, st);
+  (void)hipFreeAsync(mean, st);
+  CPM_HIP_CHECK(hipGetLastError());
+  return rc;
+}
+
+}  // namespace cpm
+
+using namespace cpm;
+
+extern "C" {
+
+cpm_status cpm_mlp_init(cpm_system *s, const int32_t *layer_host, int32_t n_layers, float b_scale,
+                        float r_scale, float q_scale) {
+  if (!s || !layer_host || n_layers < 1 || !(b_scale > 0) || !(r_scale > 0) || !(q_scale > 0)) {
+    set_error("invalid argument");
+    return CPM_EINVAL;
+  }
+  for (int64_t i = 0; i < s->n; ++i)
+    if (layer_host[i] < 0 || layer_host[i] >= n_layers) {
+      set_error("layer index out of range");
+      return CPM_EINVAL;
+    }
+  std::vector<int32_t> nbr;
+  std::vector<float> nbr_r;
+  cpm_status rc = build_neighbours(s, nbr, nbr_r);
+  if (rc != CPM_OK) return rc;
+  Mlp &M = s->mlp;
+  auto alloc = [&](void **p, size_t bytes) {
+    if (*p) return true;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return true;
+  };
+  if (!alloc((void **)&M.nbr, sizeof(int32_t) * s->n * NNB) ||
+      !alloc((void **)&M.nbr_r, sizeof(float) * s->n * NNB) ||
+      !alloc((void **)&M.layer, sizeof(int32_t) * s->n) ||
+      !alloc((void **)&M.params, sizeof(float) * NP) ||
+      !alloc((void **)&M.adam_m, sizeof(float) * NP) ||
+      !alloc((void **)&M.adam_v, sizeof(float) * NP) ||
+      !alloc((void **)&M.grad, sizeof(float) * NP) || !alloc((void **)&M.loss, sizeof(double) * 8)) {
+    set_error("network allocation failed");
+    return CPM_ENOMEM;
+  }
+  hipStream_t st = s->stream;
+  CPM_HIP_CHECK(hipMemcpyAsync(M.nbr, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice, st));
+  CPM_HIP_CHECK(hipMemcpyAsync(M.nbr_r, nbr_r.data(), sizeof(float) * nbr_r.size(), hipMemcpyHostToDevice, st));
+  CPM_HIP_CHECK(hipMemcpyAsync(M.layer, layer_host, sizeof(int32_t) * s->n, hipMemcpyHostToDevice, st));
+  CPM_HIP_CHECK(hipStreamSynchronize(st));
+  M.n_layers = n_layers;
+  M.b_scale = b_scale;
+  M.r_scale = r_scale;
+  M.q_scale = q_scale;
+  M.ready = true;
+  return CPM_OK;
+}
+
+cpm_status cpm_mlp_neighbours(const cpm_system *s, int32_t *nbr_host) {
+  if (!s || !nbr_host || !s->mlp.ready) {
+    set_error("network not initialised");
+    return CPM_ESTATE;
+  }
+  CPM_HIP_CHECK(hipMemcpyAsync(nbr_host, s->mlp.nbr, sizeof(int32_t) * s->n * NNB,
+                               hipMemcpyDeviceToHost, s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return CPM_OK;
+}
+
+cpm_status cpm_mlp_set_params(cpm_system *s, const float *params_host) {
+  if (!s || !params_host) {
+    set_error("NULL argument");
+    return CPM_EINVAL;
+  }
+  if (!s->mlp.ready) {
+    set_error("cpm_mlp_init first");
+    return CPM_ESTATE;
+  }
+  for (int p = 0; p < NP; ++p)
+    if (!std::isfinite(params_host[p])) {
+      // accepted: a broken network is caught by the residual check of the
+      // warm start and the solve falls back to a zero start
+      break;
+    }
+  Mlp &M = s->mlp;
+  CPM_HIP_CHECK(hipMemcpyAsync(M.params, params_host, sizeof(float) * NP, hipMemcpyHostToDevice, s->stream));
+  CPM_HIP_CHECK(hipMemsetAsync(M.adam_m, 0, sizeof(float) * NP, s->stream));
+  CPM_HIP_CHECK(hipMemsetAsync(M.adam_v, 0, sizeof(float) * NP, s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  M.step = 0;
+  M.params_set = true;
+  return CPM_OK;
+}
+
+cpm_status cpm_mlp_get_params(const cpm_system *s, float *params_host) {
+  if (!s || !params_host || !s->mlp.params_set) {
+    set_error("no parameters set");
+    return CPM_ESTATE;
+  }
+  CPM_HIP_CHECK(hipMemcpyAsync(params_host, s->mlp.params, sizeof(float) * NP, hipMemcpyDeviceToHost, s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return CPM_OK;
+}
+
+cpm_status cpm_mlp_features(cpm_system *s, const double *b_dev, int64_t f, float *feat_out_dev) {
+  if (!s || !b_dev || !feat_out_dev || f < 1) {
+    set_error("invalid argument");
+    return CPM_EINVAL;
+  }
+  if (!s->mlp.ready) {
+    set_error("cpm_mlp_init first");
+    return CPM_ESTATE;
+  }
+  double *mean = nullptr;
+  CPM_HIP_CHECK(hipMallocAsync((void **)&mean, sizeof(double) * f, s->stream));
+  cpm_status rc = features_impl(s, b_dev, f, nullptr, 0, f * s->n, feat_out_dev, mean, true);
+  (void)hipFreeAsync(mean, s->stream);
+  if (rc == CPM_OK) CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return rc;
+}
+
+cpm_status cpm_mlp_forward(cpm_system *s, const float *feat_dev, int64_t rows, float *y_out_dev) {
+  if (!s || !feat_dev || !y_out_dev || rows < 1) {
+    set_error("invalid argument");
+    return CPM_EINVAL;
+  }
+  if (!s->mlp.params_set) {
+    set_error("cpm_mlp_set_params first");
+    return CPM_ESTATE;
+  }
+  CPM_HIP_CHECK(launch_mlp_forward(s->stream, s->mlp.params, feat_dev, rows, y_out_dev));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return CPM_OK;
+}
+
+cpm_status cpm_mlp_loss_grad(cpm_system *s, const float *feat_dev, const float *target_dev,
+                             int64_t rows, float *grad_out_dev, double *loss) {
+  if (!s || !feat_dev || !target_dev || !grad_out_dev || rows < 1) {
+    set_error("invalid argument");
+    return CPM_EINVAL;
+  }
+  if (!s->mlp.params_set) {
+    set_error("cpm_mlp_set_params first");
+    return CPM_ESTATE;
+  }
+  cpm_status rc = loss_grad_impl(s, feat_dev, target_dev, rows, grad_out_dev);
+  if (rc != CPM_OK) return rc;
+  double l = 0;
+  CPM_HIP_CHECK(hipMemcpyAsync(&l, s->mlp.loss, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  if (loss) *loss = l;
+  return CPM_OK;
+}
+
+cpm_status cpm_mlp_train_step(cpm_system *s, const float *feat_dev, const float *target_dev,
+                              int64_t rows, float lr, float beta1, float beta2, float eps,
+                              double *loss) {
+  if (!s || !feat_dev || !target_dev || rows < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+      !(beta2 >= 0 && beta2 < 1) || !(eps > 0)) {
+    set_error("invalid argument");
+    return CPM_EINVAL;
+  }
+  if (!s->mlp.params_set) {
+    set_error("cpm_mlp_set_params first");
+    return CPM_ESTATE;
+  }
+  cpm_status rc = loss_grad_impl(s, feat_dev, target_dev, rows, s->mlp.grad);
+  if (rc == CPM_OK) rc = adam_impl(s, lr, beta1, beta2, eps);
+  if (rc != CPM_OK) return rc;
+  double l = 0;
+  CPM_HIP_CHECK(hipMemcpyAsync(&l, s->mlp.loss, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  if (loss) *loss = l;
+  return CPM_OK;
+}
+
+cpm_status cpm_mlp_train_epoch(cpm_system *s, const double *b_dev, const double *q_dev, int64_t f,
+                               const int64_t *perm_dev, int64_t batch, float lr, float beta1,
+                               float beta2, float eps, double *mean_loss) {
+  if (!s || !b_dev || !q_dev || !perm_dev || f < 1 || batch < 1 || !(lr > 0)) {
+    set_error("invalid argument");
+    return CPM_EINVAL;
+  }
+  if (!s->mlp.params_set) {
+    set_error("cpm_mlp_set_params first");
+    return CPM_ESTATE;
+  }
+  hipStream_t st = s->stream;
+  const int64_t rows_total = f * s->n;
+  cpm_status rc = ensure_rows(s, batch);
+  if (rc != CPM_OK) return rc;
+  {
+    int *flag = nullptr, hflag = 0;
+    CPM_HIP_CHECK(hipMallocAsync((void **)&flag, sizeof(int), st));
+    CPM_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
+    hipLaunchKernelGGL(check_rows_kernel, dim3((unsigned)((rows_total + 255) / 256)), dim3(256), 0,
+                       st, perm_dev, rows_total, rows_total, flag);
+    CPM_HIP_CHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    (void)hipFreeAsync(flag, st);
+    CPM_HIP_CHECK(hipStreamSynchronize(st));
+    if (hflag) {
+      set_error("perm holds a row id outside [0, f*n)");
+      return CPM_EINVAL;
+    }
+  }
+  double *mean = nullptr;
+  CPM_HIP_CHECK(hipMallocAsync((void **)&mean, sizeof(double) * f, st));
+  hipLaunchKernelGGL(frame_mean_kernel, dim3((unsigned)f), dim3(256), 0, st, b_dev, s->n, mean);
+  const double inv_qs = 1.0 / (double)s->mlp.q_scale;
+  std::vector<double> losses;
+  double *lhist = nullptr;
+  const int64_t nb = (rows_total + batch - 1) / batch;
+  CPM_HIP_CHECK(hipMallocAsync((void **)&lhist, sizeof(double) * nb, st));
+  for (int64_t bi = 0; bi < nb; ++bi) {
+    const int64_t r0 = bi * batch;
+    const int64_t rows = std::min(batch, rows_total - r0);
+    rc = features_impl(s, b_dev, f, perm_dev + r0, 0, rows, s->mlp.feat, mean, false);
+    if (rc != CPM_OK) break;
+    hipLaunchKernelGGL(targets_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, q_dev,
+                       perm_dev + r0, 0, rows, inv_qs, s->mlp.yout);
+    rc = loss_grad_impl(s, s->mlp.feat, s->mlp.yout, rows, s->mlp.grad);
+    if (rc == CPM_OK) rc = adam_impl(s, lr, beta1, beta2, eps);
+    if (rc != CPM_OK) break;
+    CPM_HIP_CHECK(hipMemcpyAsync(lhist + bi, s->mlp.loss, sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  std::vector<double> lh(nb);
+  if (rc == CPM_OK)
+    CPM_HIP_CHECK(hipMemcpyAsync(lh.data(), lhist, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  (void)hipFreeAsync(lhist, st);
+  (void)hipFreeAsync(mean, st);
+  CPM_HIP_CHECK(hipStreamSynchronize(st));
+  if (rc != CPM_OK) return rc;
+  if (mean_loss) {
+    double sum = 0;
+    for (double v : lh) sum += v;
+    *mean_loss = sum / (double)nb;
+  }
+  return CPM_OK;
+}
+
+cpm_status cpm_set_warm_chi(cpm_system *s, const double *chi_dev, const cpm_solve_opts *opts) {
+  if (!s || !chi_dev || !opts) {
+    set_error("NULL argument");
+    return CPM_EINVAL;
+  }
+  if (!s->dprime_ready) {
+    cpm_status rd = solve_dprime(s, 1e-13, 20000);
+    if (rd != CPM_OK) return rd;
+    s->dprime_ready = true;
+  }
+  // b = chi / k_e (no electrolyte), Q_sol = 0: q_chi by the two-step solve
+  double *b = nullptr, *q0 = nullptr;
+  hipStream_t st = s->stream;
+  CPM_HIP_CHECK(hipMallocAsync((void **)&b, sizeof(double) * s->n, st));
+  CPM_HIP_CHECK(hipMallocAsync((void **)&q0, sizeof(double) * 2, st));
+  CPM_HIP_CHECK(hipMemsetAsync(q0, 0, sizeof(double) * 2, st));
+  cpm_status rc = cpm_rhs(s, nullptr, nullptr, 0, 1, chi_dev, b, q0 + 1);
+  if (rc == CPM_OK) {
+    cpm_solve_opts o = *opts;
+    o.warm_start = CPM_WARM_ZERO;
+    rc = solve_block(s, b, q0, 1, o, s->qchi, nullptr, nullptr);
+  }
+  (void)hipFreeAsync(b, st);
+  (void)hipFreeAsync(q0, st);
+  CPM_HIP_CHECK(hipStreamSynchronize(st));
+  if (rc == CPM_OK) s->qchi_ready = true;
+  return rc;
+}
+
+}  // extern "C"

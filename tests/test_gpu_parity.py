@@ -1,0 +1,285 @@
+"""GPU path (C ABI through the ctypes binding) against the FP64 CPU oracle.
+
+Tolerances:
+  * E (FP64): |E_gpu - E| <= 1e-12 max|E|  (both sides FP64; phases from the
+    same integer k-vectors, erfc from two libraries: ~1e-15 observed).
+  * E (FP32 / BF16 copies): |E_low - E| <= u |E| (1 + 1e-6) with the unit
+    roundoff u = 2^-24 / 2^-8 of round-to-nearest.
+  * b: <= 1e-12 max|b|.
+  * q (FP64 CG to tol 1e-12): rel_2 <= 1e-9 per frame; mixed refinement to
+    tol 1e-11: rel_2 <= 1e-8; |sum q + Q_sol| <= 1e-12 e.
+The charge error bound follows from |dq| / |q| <= kappa(E) |r| / |b| with
+kappa(E) ~ 62 (workload 1) and ~ 310 (workload 2), measured by the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cpm as ocpm
+from oracle import ewald as ew
+from paper_2111_06704_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+A, BETA, RC, EPS = wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, wl.KSPACE_EPS
+
+
+def _cpm():
+    from paper_2111_06704_amd import cpm
+    cpm.lib()
+    return cpm
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+class Case:
+    def __init__(self, cfg, frames, store=("f32", "bf16")):
+        cpm = _cpm()
+        self.dev = _dev()
+        self.geo, self.ipos, self.iq, self.chi = wl.workload(cfg, frames=frames)
+        self.km = ew.kmax_from_eps(BETA, EPS)
+        g = self.geo
+        print(f"[case] workload {cfg}: N={g.n} frames={frames}", flush=True)
+        self.S = cpm.System(g.pos, g.box, A, BETA, RC, EPS, store=store)
+        self.E = ew.ewald_matrix(g.pos, g.box, A, BETA, RC, self.km)
+        self.bo, self.qso = ew.rhs(g.pos, A, self.ipos, self.iq, self.chi, g.box, BETA, RC, self.km)
+        self.fac = ocpm.cholesky(self.E)
+        _, self.d, _ = ocpm.neutralising_vector(self.fac, g.n)
+        self.qo = ocpm.two_step(self.fac, self.bo, self.qso, self.d)
+        self.t_ipos = torch.tensor(self.ipos, device=self.dev)
+        self.t_iq = torch.tensor(self.iq, device=self.dev)
+        self.t_chi = torch.tensor(self.chi, device=self.dev)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return Case(1, 16)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return Case(2, 16)
+
+
+def _check_E(case):
+    cpm = _cpm()
+    E = case.E
+    Eg = case.S.get_E(cpm.PREC_F64).cpu().numpy()
+    assert np.max(np.abs(Eg - E)) <= 1e-12 * np.max(np.abs(E))
+    assert np.array_equal(Eg, Eg.T)
+    E32 = case.S.get_E(cpm.PREC_F32).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(E32 - E) <= 2.0 ** -24 * np.abs(E) * (1 + 1e-6) + 1e-300)
+    E16 = case.S.get_E(cpm.PREC_BF16).float().cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(E16 - E) <= 2.0 ** -8 * np.abs(E) * (1 + 1e-6) + 1e-300)
+
+
+def test_matrix_workload1(c1):
+    _check_E(c1)
+
+
+def test_matrix_workload2(c2):
+    _check_E(c2)
+
+
+def test_kvector_count(c1, c2):
+    for c in (c1, c2):
+        _, K, _ = ew.kvectors(c.geo.box, BETA, c.km)
+        d = c.S.describe()
+        assert d["n_kvec"] == len(K) and abs(d["kmax"] - c.km) < 1e-14
+
+
+def _check_rhs(case):
+    b, qsol = case.S.rhs(case.t_ipos, case.t_iq, case.t_chi)
+    bg = b.cpu().numpy()
+    assert np.max(np.abs(bg - case.bo)) <= 1e-12 * np.max(np.abs(case.bo))
+    assert np.allclose(qsol.cpu().numpy(), case.qso, atol=0, rtol=0)
+    return b, qsol
+
+
+def test_rhs_workload1(c1):
+    _check_rhs(c1)
+
+
+def test_rhs_workload2(c2):
+    _check_rhs(c2)
+
+
+def test_rhs_without_ions(c1):
+    b, qsol = c1.S.rhs(None, None, c1.t_chi)
+    assert np.allclose(b.cpu().numpy()[0], c1.chi / ew.K_E, rtol=1e-15, atol=0)
+    assert qsol.item() == 0.0
+
+
+def test_rhs_is_deterministic(c1):
+    b1, _ = c1.S.rhs(c1.t_ipos, c1.t_iq, c1.t_chi)
+    b2, _ = c1.S.rhs(c1.t_ipos, c1.t_iq, c1.t_chi)
+    assert torch.equal(b1, b2)
+
+
+def test_dprime(c1, c2):
+    for c in (c1, c2):
+        dp, cele = c.S.dprime()
+        dpo = ocpm.neutralising_vector(c.fac, c.geo.n)[0]
+        assert np.max(np.abs(dp.cpu().numpy() - dpo)) <= 1e-11 * np.max(np.abs(dpo))
+        assert abs(cele / np.sum(dpo) - 1) < 1e-11
+
+
+@pytest.mark.parametrize("nf", [1, 5, 16, 17, 64, 70])
+def test_matvec_all_precisions(c1, nf):
+    cpm = _cpm()
+    g = torch.Generator(device="cpu").manual_seed(nf)
+    P = torch.randn(nf, c1.geo.n, dtype=torch.float64, generator=g).to(c1.dev)
+    ref = P.cpu().numpy() @ c1.E.T
+    scale = np.max(np.abs(P.cpu().numpy())) * np.max(np.sum(np.abs(c1.E), axis=1))
+    for prec, tol in ((cpm.PREC_F64, 1e-14), (cpm.PREC_F32, 1e-6), (cpm.PREC_BF16, 1e-2)):
+        V = c1.S.matvec(P, prec).cpu().numpy()
+        assert np.max(np.abs(V - ref)) <= tol * scale, prec
+
+
+def _solve_and_check(case, precision, tol, bound, **kw):
+    cpm = _cpm()
+    b, qsol = case.S.rhs(case.t_ipos, case.t_iq, case.t_chi)
+    q, st = case.S.solve(b, qsol, tol=tol, precision=precision, **kw)
+    qg = q.cpu().numpy()
+    r2, rm = ocpm.rel_errors(qg, case.qo)
+    print(f"[solve] prec={precision} rel2={r2.max():.2e} relmax={rm.max():.2e} "
+          f"iters={st['iterations']} outer={st['outer']}", flush=True)
+    assert r2.max() <= bound, r2.max()
+    assert np.max(np.abs(qg.sum(1) + case.qso)) <= 1e-12
+    assert st["max_abs_sum_q"] <= 1e-12
+    assert st["max_rel_resid"] <= tol
+    return q, st
+
+
+def test_solve_fp64_workload1(c1):
+    _solve_and_check(c1, _cpm().PREC_F64, 1e-12, 1e-9)
+
+
+def test_solve_fp64_workload2(c2):
+    _solve_and_check(c2, _cpm().PREC_F64, 1e-12, 1e-9)
+
+
+@pytest.mark.parametrize("prec_name", ["f32", "bf16"])
+@pytest.mark.parametrize("check_every", [1, 8])
+def test_solve_mixed_workload1(c1, prec_name, check_every):
+    cpm = _cpm()
+    prec = {"f32": cpm.PREC_F32, "bf16": cpm.PREC_BF16}[prec_name]
+    _solve_and_check(c1, prec, 1e-11, 1e-8, inner_tol=1e-3, check_every=check_every)
+
+
+@pytest.mark.parametrize("prec_name", ["f32", "bf16"])
+def test_solve_mixed_workload2(c2, prec_name):
+    cpm = _cpm()
+    prec = {"f32": cpm.PREC_F32, "bf16": cpm.PREC_BF16}[prec_name]
+    _solve_and_check(c2, prec, 1e-11, 1e-8, inner_tol=1e-2)
+
+
+def test_solve_ragged_frames(c1):
+    """Frame counts that are not a multiple of 16 and exceed one 64-column block."""
+    cpm = _cpm()
+    ipos, iq = wl.ion_frames(c1.geo, 200, [wl.frame_seed(1, 100 + f) for f in range(70)])
+    bo, qso = ew.rhs(c1.geo.pos, A, ipos, iq, c1.chi, c1.geo.box, BETA, RC, c1.km)
+    qo = ocpm.two_step(c1.fac, bo, qso, c1.d)
+    for nf in (1, 3, 70):
+        b, qsol = c1.S.rhs(torch.tensor(ipos[:nf], device=c1.dev), torch.tensor(iq[:nf], device=c1.dev),
+                           c1.t_chi)
+        q, st = c1.S.solve(b, qsol, tol=1e-12, precision=cpm.PREC_F64)
+        r2, _ = ocpm.rel_errors(q.cpu().numpy(), qo[:nf])
+        assert r2.max() <= 1e-9 and len(st["frame_iters"]) == nf
+
+
+def test_warm_chi_start(c1):
+    cpm = _cpm()
+    c1.S.set_warm_chi(c1.t_chi)
+    b, qsol = c1.S.rhs(c1.t_ipos, c1.t_iq, c1.t_chi)
+    q, st = c1.S.solve(b, qsol, tol=1e-12, warm_start=cpm.WARM_CHI)
+    r2, _ = ocpm.rel_errors(q.cpu().numpy(), c1.qo)
+    assert r2.max() <= 1e-9
+
+
+def test_not_converged_status(c1):
+    cpm = _cpm()
+    b, qsol = c1.S.rhs(c1.t_ipos, c1.t_iq, c1.t_chi)
+    q, st = c1.S.solve(b, qsol, tol=1e-12, max_iter=3, check_every=1, allow_notconv=True)
+    assert st["status"] == cpm.CPM_ENOTCONV
+    # the returned iterate is still projected to the neutral subspace
+    assert np.max(np.abs(q.cpu().numpy().sum(1) + c1.qso)) <= 1e-12
+
+
+def test_capacitor_through_gpu():
+    """Capacitor pin (Sec. III.C) on the GPU path: a = a0, 1 V, no electrolyte."""
+    cpm = _cpm()
+    dev = _dev()
+    geo = wl.geometry(1)
+    a0 = 2.93295072600296
+    S = cpm.System(geo.pos, geo.box, a0, 0.3, ew.rcut_from_eps(0.3, 1e-12), 1e-12)
+    chi = torch.tensor(wl.electrode_potential(geo), device=dev)
+    b, qsol = S.rhs(None, None, chi)
+    q, _ = S.solve(b, qsol, tol=1e-13)
+    q = q.cpu().numpy()[0]
+    na = int(np.sum(geo.electrode == 0))
+    eps0 = 1.0 / (4 * math.pi * ew.K_E)
+    q_cont = eps0 * (1 / 40.0 + 1 / 20.0) / geo.sheet_density
+    assert np.ptp(q[:na]) / abs(q[:na].mean()) < 1e-9
+    assert abs(q[:na].mean() / q_cont - 1) < 1e-5
+
+
+def test_point_charge_madelung_through_gpu():
+    """SC and BCC Wigner constants (Supplementary Note) with point charges."""
+    cpm = _cpm()
+    _dev()
+    beta = 5.0
+    rc, km = ew.rcut_from_eps(beta, 1e-14), ew.kmax_from_eps(beta, 1e-14)
+    S = cpm.System(np.array([[0.3, 0.2, 0.1]]), [1, 1, 1], math.inf, beta, rc, kmax_override=km)
+    assert abs(S.get_E().item() + 2.837297479) < 1e-9
+    S2 = cpm.System(np.array([[0.1, 0.1, 0.1], [0.6, 0.6, 0.6]]), [1, 1, 1], math.inf, beta, rc,
+                    kmax_override=km)
+    assert np.all(np.abs(S2.get_E().sum(1).cpu().numpy() / -3.63923345028097 - 1) < 1e-9)
+
+
+def test_mixed_widths_literal():
+    """Per-atom Gaussian widths, a point charge and an anisotropic box vs the
+    literal term-by-term Eq. 22."""
+    cpm = _cpm()
+    _dev()
+    rng = np.random.default_rng(3)
+    box = np.array([5.0, 6.0, 7.5])
+    pos = rng.random((5, 3)) * box
+    a = np.array([1.2, 2.0, np.inf, 1.7, 3.0])
+    km = ew.kmax_from_eps(0.9, 1e-10)
+    rc = ew.rcut_from_eps(0.9, 1e-10)
+    El = ew.ewald_matrix_literal(pos, box, a, 0.9, rc, km)
+    S = cpm.System(pos, box, 1.0, 0.9, rc, kmax_override=km, per_atom_width=a)
+    assert np.max(np.abs(S.get_E().cpu().numpy() - El)) <= 1e-12 * np.max(np.abs(El))
+
+
+def test_invalid_inputs():
+    cpm = _cpm()
+    _dev()
+    geo = wl.geometry(1)
+    bad = geo.pos.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(cpm.CpmError) as e:
+        cpm.System(bad, geo.box)
+    assert e.value.status == cpm.CPM_EINVAL
+    dup = geo.pos.copy()
+    dup[5] = dup[4] + 1e-8
+    with pytest.raises(cpm.CpmError) as e:
+        cpm.System(dup, geo.box)
+    assert e.value.status == cpm.CPM_EINVAL
+    with pytest.raises(cpm.CpmError):
+        cpm.System(geo.pos, geo.box, gauss_inv_width=-1.0)
+    S = cpm.System(geo.pos, geo.box)           # no FP32 copy stored
+    b = torch.zeros((1, geo.n), dtype=torch.float64, device="cuda")
+    with pytest.raises(cpm.CpmError) as e:
+        S.solve(b, torch.zeros(1, dtype=torch.float64, device="cuda"), precision=cpm.PREC_F32)
+    assert e.value.status == cpm.CPM_EINVAL
+    with pytest.raises(cpm.CpmError) as e:
+        S.solve(b, torch.zeros(1, dtype=torch.float64, device="cuda"), warm_start=cpm.WARM_MLP)
+    assert e.value.status == cpm.CPM_ESTATE
