@@ -8,15 +8,17 @@
 // are zero, and 0 * NaN would not be).
 //
 // One iteration is three kernels:
-//   block_matvec_kernel  v = E p. A workgroup owns 16*RT rows; its 16/NG waves
-//     split the k range, each accumulating 16x16 MFMA blocks
+//   block_matvec_kernel  v = E p as k-slice partials: workgroup (tile, slice)
+//     owns 16*RT rows and one k slice split over its 4 waves, each
+//     accumulating 16x16 MFMA blocks
 //     (v_mfma_f64_16x16x4f64 for FP64 E, v_mfma_f32_16x16x4f32 for FP32 and
 //     BF16 E, products accumulated in FP32). Lane l supplies A[l % 16][l / 16]
 //     and B[l / 16][l % 16]; the k slots of the MFMA are mapped to 32
 //     contiguous bytes of an E row per lane, so E and P are read with wide,
 //     coalesced loads. The waves' partial tiles are summed in LDS in a fixed
-//     order, v is written, and the block's share of p.v is reduced.
-//   cg_update_kernel     alpha = r.z / p.v; x += alpha p; r -= alpha v;
+//     order and the workgroup's share of p.v is reduced.
+//   cg_update_kernel     v = sum of the slices; alpha = r.z / p.v;
+//                        x += alpha p; r -= alpha v;
 //                        z = M^-1 r (Jacobi, M = diag E); partial r.r, r.z.
 //   cg_direction_kernel  beta = r'.z' / r.z; p = z + beta p.
 // All dots are FP64 and reduced in a fixed order (bitwise reproducible).
@@ -45,7 +47,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int RED_THREADS = 256;
 constexpr int MAX_COLS = 64;
-constexpr int64_t CHUNK = 1024;   // rows per block of the vector kernels
+constexpr int64_t CHUNK = 256;    // rows per block of the vector kernels
 
 // scalar fields (struct of arrays, cols entries each)
 enum { S_RZ0 = 0, S_RZ1 = 1, S_RR = 2, S_BN2 = 3, S_ACT = 4, S_NFIELDS = 5 };
@@ -123,30 +125,30 @@ template <typename VT, int VEC> __device__ inline void load_vec(const VT *p, VT 
   }
 }
 
-// Waves per workgroup of the block product: 16 / NG, so that the LDS
-// reduction buffer stays at 32 KB and the grid keeps ~16 waves per 16*RT rows.
-template <int NG> constexpr int mv_waves() { return 16 / NG; }
-
-// Load stages kept in flight per wave (register budget: <= 128 VGPRs at
-// 1024 threads per workgroup).
+// Load stages kept in flight per wave (register budget <= 128 VGPRs).
 template <typename T, int NG> constexpr int mv_stages() {
-  return sizeof(T) == 8 ? (NG == 1 ? 4 : (NG == 2 ? 2 : 1)) : (NG == 1 ? 2 : 1);
+  return sizeof(T) == 8 ? (NG == 1 ? 4 : (NG == 2 ? 2 : 1))
+                        : (NG == 1 ? (sizeof(T) == 4 ? 4 : 3) : (NG == 2 ? 2 : 1));
 }
 
-// V[c][row] = sum_k E[row][k] P[c][k] for the block's 16*RT rows; optionally
-// pv_part[block][c] = sum over those rows of P[c][row] V[c][row]. The
-// workgroup's waves split the k range; each wave keeps two independent
-// accumulator chains per output tile (even / odd k slot) so that consecutive
-// MFMAs do not wait on each other.
+// Partial block product over one k slice: grid (row tiles, k slices), one
+// workgroup of 4 waves per (tile, slice); the waves split the slice and
+// their 16*RT x 16*NG tiles are summed in LDS in a fixed order.
+//   part[s][c][row] = sum_{k in slice s} E[row][k] P[c][k]
+//   pv_part[s][tile][c] = sum over the tile's rows of P[c][row] part[s][c][row]
+// (p^T E p is linear in the partial products, so the slices' contributions
+// sum to p.v without any communication between workgroups). Each wave keeps
+// two independent accumulator chains per output tile and U load stages in
+// flight.
 template <typename T, int NG>
-__global__ __launch_bounds__(64 * mv_waves<NG>()) void block_matvec_kernel(
+__global__ __launch_bounds__(256) void block_matvec_kernel(
     const T *__restrict__ E, int64_t ld, const typename Mv<T>::VT *__restrict__ P,
-    typename Mv<T>::VT *__restrict__ V, int64_t kq, double *__restrict__ pv_part) {
+    typename Mv<T>::VT *__restrict__ part, int64_t kslice, int64_t split_stride,
+    double *__restrict__ pv_part) {
   using M = Mv<T>;
   using VT = typename M::VT;
   using Acc = typename M::Acc;
-  constexpr int W = mv_waves<NG>();
-  constexpr int NT = 64 * W;
+  constexpr int W = 4;
   constexpr int VEC = M::VEC;
   constexpr int KB = 4 * VEC;
   constexpr int RT = M::RT;
@@ -156,8 +158,10 @@ __global__ __launch_bounds__(64 * mv_waves<NG>()) void block_matvec_kernel(
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lr = lane & 15, lg = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * ROWS;
-  const int64_t kbeg = (int64_t)wave * kq;
+  const int64_t tile = blockIdx.x, sl = blockIdx.y;
+  const int64_t r0 = tile * ROWS;
+  const int64_t kq = kslice / W;   // multiple of KB by construction
+  const int64_t kbeg = sl * kslice + wave * kq;
   const int64_t kend = min(ld, kbeg + kq);
 
   Acc acc[2][RT][NG];
@@ -223,19 +227,19 @@ __global__ __launch_bounds__(64 * mv_waves<NG>()) void block_matvec_kernel(
   __syncthreads();
 
   // thread -> (row, column group); the ROWS threads of a group are adjacent lanes
-  constexpr int TPR = NT / ROWS;
+  constexpr int TPR = 64 * W / ROWS;
   const int row = threadIdx.x % ROWS, cg0 = threadIdx.x / ROWS;
-  for (int c = cg0; c < COLS; c += TPR) {
-    VT s = red[0][row][c];
+  VT *out = part + sl * split_stride;
 #pragma unroll
-    for (int w = 1; w < W; ++w) s += red[w][row][c];
+  for (int c = cg0; c < COLS; c += TPR) {
+    const VT sv = ((red[0][row][c] + red[1][row][c]) + red[2][row][c]) + red[3][row][c];
     const int64_t idx = (int64_t)c * ld + r0 + row;
-    V[idx] = s;
+    out[idx] = sv;
     if (pv_part) {
-      double pv = (double)P[idx] * (double)s;
+      double pv = (double)P[idx] * (double)sv;
 #pragma unroll
       for (int off = ROWS / 2; off > 0; off >>= 1) pv += __shfl_xor(pv, off, ROWS);
-      if (row == 0) pv_part[(int64_t)blockIdx.x * COLS + c] = pv;
+      if (row == 0) pv_part[(sl * gridDim.x + tile) * COLS + c] = pv;
     }
   }
 }
@@ -252,10 +256,19 @@ __device__ inline double block_sum(double v, double *red) {
   return r;
 }
 
-// r = b - v (v = E x from the FP64 product); partial[blk][c][0] = |r|^2.
+// sum of the k-slice partial products of element idx (fixed order)
+template <typename VT>
+__device__ inline double sum_slices(const VT *__restrict__ part, int slices, int64_t stride,
+                                    int64_t idx) {
+  double v = (double)part[idx];
+  for (int sl = 1; sl < slices; ++sl) v += (double)part[sl * stride + idx];
+  return v;
+}
+
+// r = b - E x (k-slice partials of the FP64 product); partial[blk][c][0] = |r|^2.
 __global__ __launch_bounds__(RED_THREADS) void residual_kernel(
-    const double *__restrict__ v, const double *__restrict__ b, double *__restrict__ r,
-    int64_t ld, int64_t n, int cols, double *__restrict__ partial) {
+    const double *__restrict__ vpart, int slices, int64_t stride, const double *__restrict__ b,
+    double *__restrict__ r, int64_t ld, int64_t n, int cols, double *__restrict__ partial) {
   __shared__ double red[RED_THREADS];
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
@@ -264,7 +277,7 @@ __global__ __launch_bounds__(RED_THREADS) void residual_kernel(
   double acc = 0.0;
   for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) {
     const int64_t idx = (int64_t)c * ld + i;
-    const double ri = b[idx] - v[idx];
+    const double ri = b[idx] - sum_slices(vpart, slices, stride, idx);
     r[idx] = ri;
     acc += ri * ri;
   }
@@ -351,8 +364,9 @@ __global__ void set_scalars_kernel(const double *__restrict__ partial, int nblk,
 template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
     double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
-    const VT *__restrict__ p, const VT *__restrict__ v, const double *__restrict__ dinv,
-    int64_t ld, int64_t n, int cols, int npv, const double *__restrict__ pv_part,
+    const VT *__restrict__ p, const VT *__restrict__ vpart, int slices, int64_t stride,
+    const double *__restrict__ dinv, int64_t ld, int64_t n, int cols, int npv,
+    const double *__restrict__ pv_part,
     const double *__restrict__ scal, int slot, double *__restrict__ partial,
     int *__restrict__ flags) {
   __shared__ double red[RED_THREADS];
@@ -380,7 +394,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
     for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) {
       const int64_t idx = (int64_t)c * ld + i;
       x[idx] += alpha * (double)p[idx];
-      const double ri = r[idx] - alpha * (double)v[idx];
+      const double ri = r[idx] - alpha * sum_slices(vpart, slices, stride, idx);
       r[idx] = ri;
       const double zi = ri * dinv[i];
       z[idx] = zi;
@@ -421,6 +435,13 @@ __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
     scal[(S_RZ0 + (slot ^ 1)) * cols + c] = rzn;
     scal[S_RR * cols + c] = rr;
   }
+}
+
+template <typename VT>
+__global__ void sum_slices_kernel(const VT *__restrict__ part, int slices, int64_t stride,
+                                  double *__restrict__ out, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = sum_slices(part, slices, stride, i);
 }
 
 __global__ void f64_to_f32_kernel(const double *__restrict__ a, float *__restrict__ b,
@@ -489,16 +510,40 @@ template <typename T> constexpr int prec_of() {
   return sizeof(T) == 8 ? CPM_PREC_F64 : (sizeof(T) == 4 ? CPM_PREC_F32 : CPM_PREC_BF16);
 }
 
-// number of row blocks of the block product for storage type T
-template <typename T> int64_t matvec_blocks(int64_t ld) { return ld / (16 * Mv<T>::RT); }
+template <typename T> int64_t matvec_tiles(int64_t ld) { return ld / (16 * Mv<T>::RT); }
+
+// k slices of the block product: enough workgroups (~1024) to fill the chip;
+// each slice is a multiple of 4 waves x KB columns.
+template <typename T> int64_t matvec_slices(int64_t ld, int64_t &kslice) {
+  constexpr int64_t unit = 4 * 4 * Mv<T>::VEC;
+  const int64_t tiles = matvec_tiles<T>(ld);
+  const int64_t units = ld / unit;   // ld is a multiple of 128 >= unit
+  int64_t want = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
+  want = std::min<int64_t>(want, std::max<int64_t>(1, units));
+  // prefer a slice count near want that splits the k range evenly
+  int64_t best = want;
+  for (int64_t c = want; c <= std::min<int64_t>(2 * want, units); ++c)
+    if (units % c == 0) {
+      best = c;
+      break;
+    }
+  kslice = (units + best - 1) / best * unit;
+  return (ld + kslice - 1) / kslice;
+}
+
+// largest slice count of any storage type (buffer sizing)
+int64_t max_slices(int64_t ld) {
+  int64_t k = 0;
+  return std::max(matvec_slices<double>(ld, k),
+                  std::max(matvec_slices<float>(ld, k), matvec_slices<uint16_t>(ld, k)));
+}
 
 template <typename T, int NG>
 hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typename Mv<T>::VT *P,
-                           typename Mv<T>::VT *V, double *pv_part) {
-  constexpr int KB = 4 * Mv<T>::VEC;
-  constexpr int W = mv_waves<NG>();
-  const int64_t kq = ((ld + W - 1) / W + KB - 1) / KB * KB;
-  const int64_t blocks = matvec_blocks<T>(ld);
+                           typename Mv<T>::VT *part, double *pv_part, int &slices) {
+  int64_t kslice = 0;
+  slices = (int)matvec_slices<T>(ld, kslice);
+  const int64_t tiles = matvec_tiles<T>(ld);
   hipEvent_t ea = nullptr, eb = nullptr;
   if (t_prof && t_prof->enabled) {
     // algorithmic traffic: E (n x n) once, the n x cols block P read and V written
@@ -508,19 +553,21 @@ hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typenam
     ea = r.a;
     eb = r.b;
   }
-  hipExtLaunchKernelGGL((block_matvec_kernel<T, NG>), dim3((unsigned)blocks), dim3(64 * W), 0,
-                        st, ea, eb, 0, E, ld, P, V, kq, pv_part);
+  hipExtLaunchKernelGGL((block_matvec_kernel<T, NG>), dim3((unsigned)tiles, (unsigned)slices),
+                        dim3(256), 0, st, ea, eb, 0, E, ld, P, part, kslice,
+                        (int64_t)(NG * 16) * ld, pv_part);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_matvec(hipStream_t st, const T *E, int64_t ld, int64_t cols,
-                         const typename Mv<T>::VT *P, typename Mv<T>::VT *V, double *pv_part) {
+                         const typename Mv<T>::VT *P, typename Mv<T>::VT *part, double *pv_part,
+                         int &slices) {
   switch (cols / 16) {
-    case 1: return launch_matvec_t<T, 1>(st, E, ld, P, V, pv_part);
-    case 2: return launch_matvec_t<T, 2>(st, E, ld, P, V, pv_part);
-    case 3: return launch_matvec_t<T, 3>(st, E, ld, P, V, pv_part);
-    case 4: return launch_matvec_t<T, 4>(st, E, ld, P, V, pv_part);
+    case 1: return launch_matvec_t<T, 1>(st, E, ld, P, part, pv_part, slices);
+    case 2: return launch_matvec_t<T, 2>(st, E, ld, P, part, pv_part, slices);
+    case 3: return launch_matvec_t<T, 3>(st, E, ld, P, part, pv_part, slices);
+    case 4: return launch_matvec_t<T, 4>(st, E, ld, P, part, pv_part, slices);
     default: return hipErrorInvalidValue;
   }
 }
@@ -541,7 +588,8 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
   const int64_t ld = s->ld;
   const size_t vec = sizeof(double) * (size_t)ld * (size_t)cols;
   const int64_t nblk = (s->n + CHUNK - 1) / CHUNK;
-  const int64_t npv = ld / 16;   // most row blocks of the block product (FP64)
+  const int64_t nsl = max_slices(ld);
+  const int64_t npv = nsl * (ld / 16);   // most (slice, tile) pairs of the block product
   size_t total = 0;
   auto alloc = [&](void **p, size_t bytes) -> bool {
     if (hipMalloc(p, bytes) != hipSuccess) {
@@ -553,8 +601,9 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
   };
   // x, r, z, b, v (FP64); p (FP64) and pf, vf (FP32) for the mixed modes
   bool ok = alloc(&w.x, vec) && alloc(&w.r, vec) && alloc(&w.p, vec) && alloc(&w.z, vec) &&
-            alloc(&w.v, vec) && alloc((void **)&w.bx, vec) && alloc((void **)&w.bres, vec) &&
-            alloc(&w.pf, vec / 2) && alloc(&w.vf, vec / 2) &&
+            alloc(&w.v, vec * (size_t)nsl) && alloc((void **)&w.bx, vec) &&
+            alloc((void **)&w.bres, vec) &&
+            alloc(&w.pf, vec / 2) && alloc(&w.vf, vec / 2 * (size_t)nsl) &&
             alloc((void **)&w.partial, sizeof(double) * 2 * (size_t)(nblk + npv) * cols) &&
             alloc((void **)&w.scal, sizeof(double) * S_NFIELDS * cols) &&
             alloc((void **)&w.flags, sizeof(int) * 8);
@@ -563,13 +612,18 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
     set_error("workspace allocation failed");
     return CPM_ENOMEM;
   }
-  void *zs[] = {w.x, w.r, w.p, w.z, w.v, w.bx, w.bres};
+  void *zs[] = {w.x, w.r, w.p, w.z, w.bx, w.bres};
   for (void *q : zs)
     if (hipMemset(q, 0, vec) != hipSuccess) {
       set_error("workspace memset failed");
       return CPM_EDEVICE;
     }
-  void *zf[] = {w.pf, w.vf};
+  if (hipMemset(w.v, 0, vec * (size_t)nsl) != hipSuccess ||
+      hipMemset(w.vf, 0, vec / 2 * (size_t)nsl) != hipSuccess) {
+    set_error("workspace memset failed");
+    return CPM_EDEVICE;
+  }
+  void *zf[] = {w.pf};
   for (void *q : zf)
     if (hipMemset(q, 0, vec / 2) != hipSuccess) {
       set_error("workspace memset failed");
@@ -624,7 +678,8 @@ template <typename T> struct Solver {
     ld = s->ld;
     cols = cols_;
     nblk = (int)((n + CHUNK - 1) / CHUNK);
-    npv = (int)matvec_blocks<T>(ld);
+    int64_t ks = 0;
+    npv = (int)(matvec_slices<T>(ld, ks) * matvec_tiles<T>(ld));
     Workspace &w = s->ws;
     x = (double *)w.x; r = (double *)w.r; z = (double *)w.z; b = w.bx; v64 = (double *)w.v;
     partial = w.partial;
@@ -643,10 +698,11 @@ template <typename T> struct Solver {
 
   // r = b - E64 x for all columns; scal RR = |r|^2
   hipError_t true_residual() {
-    hipError_t e = launch_matvec<double>(st, s->E64, ld, cols, x, v64, nullptr);
+    int sl = 0;
+    hipError_t e = launch_matvec<double>(st, s->E64, ld, cols, x, v64, nullptr, sl);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(residual_kernel, grid(), dim3(RED_THREADS), 0, st, v64, b, r, ld, n,
-                       (int)cols, partial);
+    hipLaunchKernelGGL(residual_kernel, grid(), dim3(RED_THREADS), 0, st, v64, sl, ld * cols, b,
+                       r, ld, n, (int)cols, partial);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, partial, nblk,
                        (int)cols, scal, (int)S_RR);
     return hipGetLastError();
@@ -662,10 +718,11 @@ template <typename T> struct Solver {
   }
 
   hipError_t iterate() {
-    hipError_t e = launch_matvec<T>(st, E, ld, cols, p, v, pvp);
+    int sl = 0;
+    hipError_t e = launch_matvec<T>(st, E, ld, cols, p, v, pvp, sl);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cg_update_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, x, r, z, p, v,
-                       s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial, flags);
+    hipLaunchKernelGGL(cg_update_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, x, r, z, p, v, sl,
+                       ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial, flags);
     hipLaunchKernelGGL(cg_direction_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, p, z, ld, n,
                        (int)cols, nblk, partial, scal, slot);
     slot ^= 1;
@@ -943,19 +1000,24 @@ cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_
     double *out = (double *)s->ws.v;
     hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)cols), dim3(256),
                        0, st, p_dev + f0 * n, n, (int64_t)fc, in, ld, cols);
+    int sl = 0;
+    double *res = s->ws.bx;   // summed product (double)
     if (precision == CPM_PREC_F64) {
-      CPM_HIP_CHECK(launch_matvec<double>(st, s->E64, ld, cols, in, out, nullptr));
+      CPM_HIP_CHECK(launch_matvec<double>(st, s->E64, ld, cols, in, out, nullptr, sl));
+      hipLaunchKernelGGL(sum_slices_kernel<double>, elem_grid(ld * cols), dim3(256), 0, st,
+                         (const double *)out, sl, ld * cols, res, ld * cols);
     } else {
       float *pf = (float *)s->ws.pf, *vf = (float *)s->ws.vf;
       hipLaunchKernelGGL(f64_to_f32_kernel, elem_grid(ld * cols), dim3(256), 0, st, in, pf,
                          ld * cols);
       if (precision == CPM_PREC_F32)
-        CPM_HIP_CHECK(launch_matvec<float>(st, s->E32, ld, cols, pf, vf, nullptr));
+        CPM_HIP_CHECK(launch_matvec<float>(st, s->E32, ld, cols, pf, vf, nullptr, sl));
       else
-        CPM_HIP_CHECK(launch_matvec<uint16_t>(st, s->E16, ld, cols, pf, vf, nullptr));
-      hipLaunchKernelGGL(f32_to_f64_kernel, elem_grid(ld * cols), dim3(256), 0, st, vf, out,
-                         ld * cols);
+        CPM_HIP_CHECK(launch_matvec<uint16_t>(st, s->E16, ld, cols, pf, vf, nullptr, sl));
+      hipLaunchKernelGGL(sum_slices_kernel<float>, elem_grid(ld * cols), dim3(256), 0, st,
+                         (const float *)vf, sl, ld * cols, res, ld * cols);
     }
+    out = res;
     CPM_HIP_CHECK(hipMemcpy2DAsync(v_dev + f0 * n, sizeof(double) * n, out, sizeof(double) * ld,
                                    sizeof(double) * n, fc, hipMemcpyDeviceToDevice, st));
   }

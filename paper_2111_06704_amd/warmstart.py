@@ -1,0 +1,150 @@
+"""Learned warm start: training data from the library's own solver, training
+with the library's own network kernels, and loading trained weights.
+
+The network (cpm_mlp_* in include/cpm.h) maps each electrode atom's local
+right-hand side pattern to a predicted charge; cpm_solve(warm_start=
+CPM_WARM_MLP) turns the prediction into a CG starting point. Training pairs
+(b, q) come from cpm_rhs + cpm_solve on seeded electrolyte frames that are
+disjoint from the evaluation frames. Random numbers (initial weights, row
+order of each epoch) are drawn here from seeded generators and passed to the
+library.
+
+    python -m paper_2111_06704_amd.warmstart --frames 10000 --epochs 8
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import cpm, workloads as wl
+
+NIN, NH = cpm.MLP_IN, cpm.MLP_HIDDEN
+DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                            "warmstart_cfg2.npz")
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-style initial weights, biases zero (float32 parameter vector)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = [rng.standard_normal((NIN, NH)) * np.sqrt(2.0 / NIN), np.zeros(NH),
+             rng.standard_normal((NH, NH)) * np.sqrt(2.0 / NH), np.zeros(NH),
+             rng.standard_normal(NH) * np.sqrt(1.0 / NH), np.zeros(1)]
+    theta = np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+    assert theta.size == cpm.MLP_NPARAM
+    return theta
+
+
+def init_network(S: cpm.System, geo: wl.Geometry, b_scale: float, q_scale: float,
+                 r_scale: float = wl.BOND):
+    S.mlp_init(geo.layer, geo.n_layers, b_scale, r_scale, q_scale)
+
+
+def generate(S: cpm.System, geo: wl.Geometry, seeds, m: int, chi, block: int = 64,
+             tol: float = 1e-10, precision: int = cpm.PREC_F32, log=None):
+    """(b, q) device tensors (T, N) for the electrolyte frames of ``seeds``."""
+    import torch
+    dev = chi.device
+    T = len(seeds)
+    b_all = torch.empty((T, geo.n), dtype=torch.float64, device=dev)
+    q_all = torch.empty_like(b_all)
+    t0 = time.perf_counter()
+    for s0 in range(0, T, block):
+        ss = seeds[s0:s0 + block]
+        ipos, iq = wl.ion_frames(geo, m, ss)
+        b, qsol = S.rhs(torch.tensor(ipos, device=dev), torch.tensor(iq, device=dev), chi,
+                        b_out=b_all[s0:s0 + len(ss)])
+        S.solve(b, qsol, tol=tol, precision=precision, inner_tol=1e-2, q_out=q_all[s0:s0 + len(ss)])
+        if log and (s0 // block) % 20 == 0:
+            log(f"  generated {s0 + len(ss)}/{T} frames ({time.perf_counter() - t0:.1f} s)")
+    return b_all, q_all
+
+
+def scales(b_all, q_all, frames: int = 64):
+    """Input / output scales from a few frames: std of b - mean(b) and of q."""
+    b = b_all[:frames].cpu().numpy()
+    q = q_all[:frames].cpu().numpy()
+    bs = float(np.std(b - b.mean(axis=1, keepdims=True)))
+    qs = float(np.std(q))
+    return bs, qs
+
+
+def train(S: cpm.System, b_all, q_all, epochs: int, batch: int = 8192, lr: float = 2e-3,
+          lr_final: float = 1e-4, seed: int = 11, log=None):
+    """Adam over shuffled (frame, atom) rows; the learning rate decays
+    geometrically from lr to lr_final. Returns the mean loss per epoch."""
+    import torch
+    rows = b_all.shape[0] * b_all.shape[1]
+    g = torch.Generator(device=b_all.device)
+    g.manual_seed(seed)
+    losses = []
+    for e in range(epochs):
+        lr_e = lr * (lr_final / lr) ** (e / max(1, epochs - 1))
+        perm = torch.randperm(rows, generator=g, device=b_all.device, dtype=torch.int64)
+        t0 = time.perf_counter()
+        loss = S.mlp_train_epoch(b_all, q_all, perm, batch=batch, lr=lr_e)
+        losses.append(loss)
+        if log:
+            log(f"  epoch {e + 1}/{epochs}: lr={lr_e:.2e} loss={loss:.4e} ({time.perf_counter() - t0:.2f} s)")
+    return losses
+
+
+def save(path: str, params: np.ndarray, b_scale: float, q_scale: float, r_scale: float, meta: dict):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, params=params.astype(np.float32), b_scale=b_scale, q_scale=q_scale,
+             r_scale=r_scale, meta=json.dumps(meta))
+
+
+def load_into(S: cpm.System, geo: wl.Geometry, path: str = DEFAULT_PATH):
+    z = np.load(path, allow_pickle=False)
+    S.mlp_init(geo.layer, geo.n_layers, float(z["b_scale"]), float(z["r_scale"]), float(z["q_scale"]))
+    S.mlp_set_params(z["params"])
+    return json.loads(str(z["meta"]))
+
+
+def main(argv=None):
+    import torch
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--frames", type=int, default=10000)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    args = ap.parse_args(argv)
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    geo = wl.geometry(args.workload)
+    m = wl.CONFIGS[args.workload]["m"]
+    S = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, wl.KSPACE_EPS,
+                   store=("f32",))
+    chi = torch.tensor(wl.electrode_potential(geo), device=dev)
+    seeds = [wl.train_seed(t) for t in range(args.frames)]
+    log(f"generating {args.frames} training frames (workload {args.workload}, N={geo.n})")
+    t0 = time.perf_counter()
+    b_all, q_all = generate(S, geo, seeds, m, chi, log=log)
+    t_gen = time.perf_counter() - t0
+    bs, qs = scales(b_all, q_all)
+    init_network(S, geo, bs, qs)
+    S.mlp_set_params(init_params(args.seed))
+    t0 = time.perf_counter()
+    losses = train(S, b_all, q_all, args.epochs, args.batch, args.lr, seed=args.seed + 1, log=log)
+    t_train = time.perf_counter() - t0
+    params = S.mlp_get_params()
+    meta = dict(workload=args.workload, frames=args.frames, epochs=args.epochs, batch=args.batch,
+                lr=args.lr, seed=args.seed, losses=losses, gen_s=t_gen, train_s=t_train,
+                train_seeds=f"{wl.train_seed(0)}..{wl.train_seed(args.frames - 1)}")
+    save(args.out, params, bs, qs, wl.BOND, meta)
+    print(json.dumps(meta))
+
+
+if __name__ == "__main__":
+    main()
