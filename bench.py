@@ -13,8 +13,12 @@ beta = 0.3 /A, rcut = 12 A, k-space accuracy 1e-6, 1 V.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,6 +29,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# plain copy run after the timed region: its counter readings calibrate the
+# FETCH_SIZE / WRITE_SIZE counters (bytes moved are known exactly)
+CALIB_BYTES = 1 << 30
+KERNEL_OF_KIND = {"matvec_f64": "block_matvec_kernel<double, {ng}>",
+                  "matvec_f32": "block_matvec_kernel<float, {ng}>",
+                  "matvec_bf16": "block_matvec_kernel<unsigned short, {ng}>"}
+CG_SOURCE = os.path.join(ROOT, "paper_2111_06704_amd", "csrc", "cg.hip")
 
 
 def log(*a):
@@ -44,7 +55,87 @@ def parse():
                                                       "warmstart_cfg2.npz"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--traffic-record", default=None,
+                    help="JSON written by --summarize-pmc (default: profiles/traffic_workload<W>.json)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, then "
+                         "WRITE_SIZE) into a traffic record and exit")
+    ap.add_argument("--out", default=None, help="output path of --summarize-pmc")
     return ap.parse_args()
+
+
+def _sha256(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def _read_counters(d, counter):
+    """Per kernel name: list of counter values (one per dispatch) from every
+    counter_collection.csv under directory d."""
+    out = {}
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    for fn in files:
+        with open(fn, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(fetch_dir, write_dir, out_path):
+    """Traffic record: mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of
+    every block-product kernel, and the factors that turn each counter into
+    bytes, from the calibration copy (CALIB_BYTES read, CALIB_BYTES written)."""
+    fetch = _read_counters(fetch_dir, "FETCH_SIZE")
+    write = _read_counters(write_dir, "WRITE_SIZE")
+
+    def calib(d):
+        # the copy kernel: the elementwise kernel whose mean reading is largest
+        cands = {k: v for k, v in d.items() if "elementwise" in k or "copy" in k.lower()}
+        if not cands:
+            raise SystemExit("calibration copy kernel not found in the counter run")
+        k = max(cands, key=lambda x: np.mean(cands[x]))
+        return k, float(np.median(cands[k]))
+
+    kf, cf = calib(fetch)
+    kw, cw = calib(write)
+    rec = {"counter_unit": "KiB per dispatch",
+           "calibration": {"kernel_fetch": kf, "kernel_write": kw, "bytes": CALIB_BYTES,
+                           "fetch_kib": cf, "write_kib": cw,
+                           "fetch_factor": CALIB_BYTES / (cf * 1024.0),
+                           "write_factor": CALIB_BYTES / (cw * 1024.0)},
+           "cg_source_sha256": _sha256(CG_SOURCE), "kernels": {}}
+    for name in sorted(set(fetch) | set(write)):
+        m = re.search(r"block_matvec_kernel<([^>]*)>", name)
+        if not m:
+            continue
+        key = "block_matvec_kernel<" + m.group(1) + ">"
+        rec["kernels"][key] = {"dispatches": len(fetch.get(name, [])),
+                               "fetch_kib": float(np.mean(fetch[name])) if name in fetch else None,
+                               "write_kib": float(np.mean(write[name])) if name in write else None}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec))
+
+
+def traffic_bytes(record_path, kind, ng):
+    """HBM bytes per launch of the dominant kernel from a committed traffic
+    record; None if there is none or the block-product source has changed."""
+    if not record_path or not os.path.exists(record_path):
+        return None
+    with open(record_path) as fh:
+        rec = json.load(fh)
+    if rec.get("cg_source_sha256") != _sha256(CG_SOURCE):
+        return None
+    k = rec["kernels"].get(KERNEL_OF_KIND[kind].format(ng=ng))
+    if not k or k.get("fetch_kib") is None or k.get("write_kib") is None:
+        return None
+    c = rec["calibration"]
+    return 1024.0 * (k["fetch_kib"] * c["fetch_factor"] + k["write_kib"] * c["write_factor"])
 
 
 def cpu_baseline(geo, ipos, iq, chi, nframes, q_gpu):
@@ -80,6 +171,10 @@ def cpu_baseline(geo, ipos, iq, chi, nframes, q_gpu):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
+                      args.out or os.path.join(ROOT, "profiles", f"traffic_workload{args.workload}.json"))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (single-GPU build)")
@@ -182,11 +277,23 @@ def main():
     avg_ms = prof[k]["ms"] / max(1, prof[k]["launches"])
     bytes_per_launch = prof[k]["work"] / max(1, prof[k]["launches"])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    ng = min(4, (nf + 15) // 16)
+    rec_path = args.traffic_record or os.path.join(ROOT, "profiles", f"traffic_workload{cfg}.json")
+    traffic = traffic_bytes(rec_path, kinds[k], ng)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kinds[k],
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
+                "kernel": KERNEL_OF_KIND[kinds[k]].format(ng=ng),
                 "avg_launch_us": avg_ms * 1e3, "launches": prof[k]["launches"],
                 "bytes_per_launch": bytes_per_launch,
                 "kernel_share_of_step": prof[k]["ms"] / (elapsed * 1e3)}
+
+    # counter calibration: a plain copy of CALIB_BYTES (outside the timed region)
+    src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)   # an elementwise kernel, never a DMA copy
+    torch.cuda.synchronize()
+    del src, dst
 
     qg = q.cpu().numpy()
     q64g = q64.cpu().numpy()
