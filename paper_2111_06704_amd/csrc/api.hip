@@ -36,7 +36,47 @@ Kset make_kset(const double box[3], double beta, double kmax) {
         ks.w.push_back(2.0 * (4.0 * M_PI / vol) * std::exp(-k2 / (4.0 * beta * beta)) / k2);
       }
   ks.nk = (int64_t)ks.w.size();
+  // runs: each (n_x, n_y) column (consecutive n_z) split into nearly equal
+  // pieces of at most kRun vectors
+  ks.info.assign(4 * ks.nk, 0);
+  for (int64_t k = 0; k < ks.nk; ++k) {
+    ks.info[4 * k] = ks.n[3 * k];
+    ks.info[4 * k + 1] = ks.n[3 * k + 1];
+    ks.info[4 * k + 2] = ks.n[3 * k + 2];
+  }
+  for (int64_t c0 = 0; c0 < ks.nk;) {
+    int64_t c1 = c0 + 1;
+    while (c1 < ks.nk && ks.n[3 * c1] == ks.n[3 * c0] && ks.n[3 * c1 + 1] == ks.n[3 * c0 + 1]) ++c1;
+    const int64_t len = c1 - c0, pieces = (len + kRun - 1) / kRun;
+    int64_t k = c0;
+    for (int64_t p = 0; p < pieces; ++p) {
+      const int64_t l = len / pieces + (p < len % pieces ? 1 : 0);
+      ks.runs.push_back((int32_t)k);
+      ks.runs.push_back((int32_t)l);
+      ks.info[4 * k + 3] = 1;
+      k += l;
+    }
+    c0 = c1;
+  }
+  ks.nruns = (int64_t)ks.runs.size() / 2;
   return ks;
+}
+
+// Atoms ordered by cubic tiles of edge 8 A (z, then y, then x tile, then
+// index): the 64 atoms of a wavefront sit close together, so a distant
+// ion leaves every lane outside the real-space cutoff.
+std::vector<int32_t> spatial_order(const std::vector<double> &pos, int64_t n) {
+  const double T = 8.0;
+  std::vector<int64_t> key(n);
+  std::vector<int32_t> idx(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t tx = (int64_t)std::floor(pos[3 * i] / T), ty = (int64_t)std::floor(pos[3 * i + 1] / T),
+                  tz = (int64_t)std::floor(pos[3 * i + 2] / T);
+    key[i] = (tz * 65536 + ty) * 65536 + tx;
+    idx[i] = (int32_t)i;
+  }
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  return idx;
 }
 
 hipEvent_t Profile::get() {
@@ -66,6 +106,7 @@ void Profile::reset() {
     pool.push_back(r.b);
   }
   recs.clear();
+  next_mark = 0;
 }
 
 }  // namespace cpm
@@ -89,16 +130,16 @@ template <typename T> cpm_status dev_alloc(cpm_system *s, T **p, size_t count) {
 
 void free_system(cpm_system *s) {
   if (!s) return;
-  void *ptrs[] = {s->pos, s->width, s->kn, s->kw, s->E64, s->E32, s->E16, s->dinv, s->dprime,
-                  s->dvec, s->qchi, s->rhs_S, s->ws.x, s->ws.r, s->ws.p, s->ws.z, s->ws.v,
-                  s->ws.vpart, s->ws.xf, s->ws.rf, s->ws.pf, s->ws.zf, s->ws.vf, s->ws.partial, s->ws.scal, s->ws.bx, s->ws.bres,
-                  s->ws.flags, s->mlp.nbr, s->mlp.nbr_r, s->mlp.layer, s->mlp.params,
+  void *ptrs[] = {s->pos, s->width, s->kn, s->kw, s->kinfo, s->krun, s->atom_order, s->E64, s->E32, s->E16, s->dinv, s->dprime,
+                  s->dvec, s->qchi, s->rhs_S, s->mlp.nbr, s->mlp.nbr_r, s->mlp.layer, s->mlp.params,
                   s->mlp.adam_m, s->mlp.adam_v, s->mlp.grad, s->mlp.gpart, s->mlp.loss,
                   s->mlp.feat, s->mlp.yout};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  release_workspace(s);
   s->prof.reset();
   for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);
+  if (s->prof.marks) (void)hipFree(s->prof.marks);
   delete s;
 }
 
@@ -257,6 +298,9 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
   if ((rc = dev_alloc(s, &s->pos, 3 * n)) || (rc = dev_alloc(s, &s->width, n)) ||
       (rc = dev_alloc(s, &s->kn, 3 * std::max<int64_t>(nk, 1))) ||
       (rc = dev_alloc(s, &s->kw, std::max<int64_t>(nk, 1))) ||
+      (rc = dev_alloc(s, &s->kinfo, 4 * std::max<int64_t>(nk, 1))) ||
+      (rc = dev_alloc(s, &s->krun, 2 * std::max<int64_t>(s->kset.nruns, 1))) ||
+      (rc = dev_alloc(s, &s->atom_order, n)) ||
       (rc = dev_alloc(s, &s->E64, (size_t)ld * ld)) || (rc = dev_alloc(s, &s->dinv, ld)) ||
       (rc = dev_alloc(s, &s->dprime, ld)) || (rc = dev_alloc(s, &s->dvec, ld)) ||
       (rc = dev_alloc(s, &s->qchi, ld)))
@@ -282,7 +326,14 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
                                hipMemcpyHostToDevice, st));
     BUILD_CHECK(hipMemcpyAsync(s->kw, s->kset.w.data(), sizeof(double) * nk, hipMemcpyHostToDevice,
                                st));
+    BUILD_CHECK(hipMemcpyAsync(s->kinfo, s->kset.info.data(), sizeof(int32_t) * 4 * nk,
+                               hipMemcpyHostToDevice, st));
+    BUILD_CHECK(hipMemcpyAsync(s->krun, s->kset.runs.data(), sizeof(int32_t) * 2 * s->kset.nruns,
+                               hipMemcpyHostToDevice, st));
   }
+  const std::vector<int32_t> order = spatial_order(pos, n);
+  BUILD_CHECK(hipMemcpyAsync(s->atom_order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
+                             st));
   BUILD_CHECK(hipMemsetAsync(s->E64, 0, sizeof(double) * ld * ld, st));
   if (s->E32) BUILD_CHECK(hipMemsetAsync(s->E32, 0, sizeof(float) * ld * ld, st));
   if (s->E16) BUILD_CHECK(hipMemsetAsync(s->E16, 0, sizeof(uint16_t) * ld * ld, st));
@@ -376,9 +427,10 @@ cpm_status cpm_rhs(cpm_system *s, const double *ion_pos_dev, const double *ion_q
     set_error("need f >= 1 and m >= 0");
     return CPM_EINVAL;
   }
-  const int64_t nk = s->kset.nk;
   const int64_t fchunk = 1024;
-  const int64_t need = rhs_scratch_elems(s->n, nk, std::min(f, fchunk));
+  // scratch for the largest of the chunk sizes used (full chunks and the tail)
+  int64_t need = rhs_scratch_elems(s, m, std::min(f, fchunk));
+  if (f > fchunk && f % fchunk) need = std::max(need, rhs_scratch_elems(s, m, f % fchunk));
   if (s->rhs_S_elems < need) {
     if (s->rhs_S) {
       (void)hipFree(s->rhs_S);
@@ -533,6 +585,12 @@ cpm_status cpm_profile_enable(cpm_system *s, int on) {
   }
   CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   s->prof.reset();
+  if (on && !s->prof.marks) {
+    if (hipMalloc((void **)&s->prof.marks, sizeof(int) * Profile::kMarks) != hipSuccess) {
+      (void)hipGetLastError();
+      s->prof.marks = nullptr;   // gated launches are then all counted
+    }
+  }
   s->prof.enabled = on != 0;
   return CPM_OK;
 }
@@ -544,7 +602,12 @@ cpm_status cpm_profile_read(cpm_system *s, cpm_profile_info *out) {
   }
   CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   std::memset(out, 0, sizeof(*out));
+  std::vector<int> marks(s->prof.next_mark, 1);
+  if (s->prof.next_mark > 0)
+    CPM_HIP_CHECK(hipMemcpy(marks.data(), s->prof.marks, sizeof(int) * s->prof.next_mark,
+                            hipMemcpyDeviceToHost));
   for (const Profile::Rec &r : s->prof.recs) {
+    if (r.mark >= 0 && marks[r.mark] == 0) continue;   // gated off: no product computed
     float ms = 0.f;
     CPM_HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
     out->launches[r.kind] += 1;

@@ -23,6 +23,16 @@
 //   cg_direction_kernel  beta = r'.z' / r.z; p = z + beta p.
 // All dots are FP64 and reduced in a fixed order (bitwise reproducible).
 //
+// Control runs on the device: every check_every iterations a one-wave
+// kernel decides per column whether the true residual is due (converged
+// recursively, reliable-update point, or iteration limit); the FP64
+// residual kernels that follow are gated by that decision and exit at once
+// when it is negative, and a second control kernel retires converged
+// columns. The host only enqueues batches ahead of the GPU and reads a
+// status word one batch behind, so the queue never drains while the solve
+// runs; kernels of a batch enqueued after the last column converged exit
+// at once.
+//
 // Precision: x, r, z are FP64 in every mode. FP64 mode streams the FP64 E.
 // FP32 / BF16 modes stream the rounded E (p and v in FP32) and use true-
 // residual updates: whenever the recursive residual has fallen by the factor
@@ -49,8 +59,20 @@ constexpr int RED_THREADS = 256;
 constexpr int MAX_COLS = 64;
 constexpr int64_t CHUNK = 256;    // rows per block of the vector kernels
 
-// scalar fields (struct of arrays, cols entries each)
-enum { S_RZ0 = 0, S_RZ1 = 1, S_RR = 2, S_BN2 = 3, S_ACT = 4, S_NFIELDS = 5 };
+// scalar fields (struct of arrays, cols entries each): r.z (two slots), r.r,
+// |b|^2, active flag, last true residual norm, relative true residual,
+// iterations, initial relative residual, start-discarded flag
+enum {
+  S_RZ0 = 0, S_RZ1 = 1, S_RR = 2, S_BN2 = 3, S_ACT = 4, S_RT = 5, S_RES = 6, S_IT = 7,
+  S_INIT = 8, S_FB = 9, S_NFIELDS = 10
+};
+// status words (ints): breakdown flag and column, debug doubles (ints 2..5),
+// true residual due, any column active, non-finite residual seen, number of
+// true-residual updates, a start was discarded
+enum {
+  F_BREAK = 0, F_COL = 1, F_NEED = 6, F_ANY = 7, F_NONFINITE = 8, F_UPDATES = 9, F_FELLBACK = 10,
+  F_NWORDS = 16
+};
 
 template <typename T> struct Mv;
 template <> struct Mv<double> {
@@ -144,8 +166,16 @@ template <typename T, int NG>
 __global__ __launch_bounds__(256) void block_matvec_kernel(
     const T *__restrict__ E, int64_t ld, const typename Mv<T>::VT *__restrict__ P,
     typename Mv<T>::VT *__restrict__ part, int64_t kslice, int64_t split_stride,
-    double *__restrict__ pv_part) {
+    double *__restrict__ pv_part, const int *__restrict__ gate, int *__restrict__ mark) {
   using M = Mv<T>;
+  // gate == 0: nothing to do (device-side control); mark records whether
+  // this launch did the product (for the live kernel timing)
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  if (gate != nullptr && *gate == 0) {
+    if (mark != nullptr && first) *mark = 0;
+    return;
+  }
+  if (mark != nullptr && first) *mark = 1;
   using VT = typename M::VT;
   using Acc = typename M::Acc;
   constexpr int W = 4;
@@ -244,16 +274,21 @@ __global__ __launch_bounds__(256) void block_matvec_kernel(
   }
 }
 
+// Sum over the block (RED_THREADS = 4 waves): butterfly within each wave,
+// then the four wave sums in a fixed order; every thread gets the result.
+// red must hold 4 doubles and not be reused by the caller before the next
+// __syncthreads.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __device__ inline double block_sum(double v, double *red) {
-  red[threadIdx.x] = v;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
+  return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // sum of the k-slice partial products of element idx (fixed order)
@@ -268,8 +303,10 @@ __device__ inline double sum_slices(const VT *__restrict__ part, int slices, int
 // r = b - E x (k-slice partials of the FP64 product); partial[blk][c][0] = |r|^2.
 __global__ __launch_bounds__(RED_THREADS) void residual_kernel(
     const double *__restrict__ vpart, int slices, int64_t stride, const double *__restrict__ b,
-    double *__restrict__ r, int64_t ld, int64_t n, int cols, double *__restrict__ partial) {
-  __shared__ double red[RED_THREADS];
+    double *__restrict__ r, int64_t ld, int64_t n, int cols, double *__restrict__ partial,
+    const int *__restrict__ gate) {
+  __shared__ double red[3][4];
+  if (gate != nullptr && *gate == 0) return;
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
   const int64_t i0 = (int64_t)blk * CHUNK;
@@ -281,7 +318,7 @@ __global__ __launch_bounds__(RED_THREADS) void residual_kernel(
     r[idx] = ri;
     acc += ri * ri;
   }
-  acc = block_sum(acc, red);
+  acc = block_sum(acc, red[0]);
   if (threadIdx.x == 0) partial[((int64_t)blk * cols + c) * 2] = acc;
 }
 
@@ -289,7 +326,7 @@ __global__ __launch_bounds__(RED_THREADS) void residual_kernel(
 __global__ __launch_bounds__(RED_THREADS) void sumsq_kernel(const double *__restrict__ a,
                                                             int64_t ld, int64_t n, int cols,
                                                             double *__restrict__ partial) {
-  __shared__ double red[RED_THREADS];
+  __shared__ double red[3][4];
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
   const int64_t i0 = (int64_t)blk * CHUNK;
@@ -299,13 +336,15 @@ __global__ __launch_bounds__(RED_THREADS) void sumsq_kernel(const double *__rest
     const double ai = a[(int64_t)c * ld + i];
     acc += ai * ai;
   }
-  acc = block_sum(acc, red);
+  acc = block_sum(acc, red[0]);
   if (threadIdx.x == 0) partial[((int64_t)blk * cols + c) * 2] = acc;
 }
 
 // scal[field][c] = sum over blocks of partial[blk][c][0]
 __global__ void sum_partials_kernel(const double *__restrict__ partial, int nblk, int cols,
-                                    double *__restrict__ scal, int field) {
+                                    double *__restrict__ scal, int field,
+                                    const int *__restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int c = threadIdx.x;
   if (c >= cols) return;
   double s = 0.0;
@@ -318,8 +357,10 @@ template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void cg_refresh_kernel(
     const double *__restrict__ r, double *__restrict__ z, VT *__restrict__ p,
     const double *__restrict__ dinv, int64_t ld, int64_t n, int cols,
-    const double *__restrict__ scal, double *__restrict__ partial, int set_p) {
-  __shared__ double red[RED_THREADS];
+    const double *__restrict__ scal, double *__restrict__ partial, int set_p,
+    const int *__restrict__ gate) {
+  __shared__ double red[3][4];
+  if (gate != nullptr && *gate == 0) return;
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
   const bool act = scal[S_ACT * cols + c] != 0.0;
@@ -337,8 +378,8 @@ __global__ __launch_bounds__(RED_THREADS) void cg_refresh_kernel(
       arz += ri * zi;
     }
   }
-  arr = block_sum(arr, red);
-  arz = block_sum(arz, red);
+  arr = block_sum(arr, red[1]);
+  arz = block_sum(arz, red[2]);
   if (threadIdx.x == 0) {
     partial[((int64_t)blk * cols + c) * 2] = arr;
     partial[((int64_t)blk * cols + c) * 2 + 1] = arz;
@@ -347,7 +388,9 @@ __global__ __launch_bounds__(RED_THREADS) void cg_refresh_kernel(
 
 // Reduce (rr, rz) partials into the scalars of active columns.
 __global__ void set_scalars_kernel(const double *__restrict__ partial, int nblk, int cols,
-                                   double *__restrict__ scal, int slot) {
+                                   double *__restrict__ scal, int slot,
+                                   const int *__restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int c = threadIdx.x;
   if (c >= cols) return;
   if (scal[S_ACT * cols + c] == 0.0) return;
@@ -369,7 +412,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
     const double *__restrict__ pv_part,
     const double *__restrict__ scal, int slot, double *__restrict__ partial,
     int *__restrict__ flags) {
-  __shared__ double red[RED_THREADS];
+  __shared__ double red[3][4];
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
   const bool act = scal[S_ACT * cols + c] != 0.0;
@@ -377,7 +420,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
   if (act) {
     double pv = 0.0;
     for (int b = threadIdx.x; b < npv; b += RED_THREADS) pv += pv_part[(int64_t)b * cols + c];
-    pv = block_sum(pv, red);
+    pv = block_sum(pv, red[0]);
     const double rz = scal[(S_RZ0 + slot) * cols + c];
     double alpha = 0.0;
     if (pv > 0.0 && isfinite(pv)) {
@@ -402,8 +445,8 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
       arz += ri * zi;
     }
   }
-  arr = block_sum(arr, red);
-  arz = block_sum(arz, red);
+  arr = block_sum(arr, red[1]);
+  arz = block_sum(arz, red[2]);
   if (threadIdx.x == 0) {
     partial[((int64_t)blk * cols + c) * 2] = arr;
     partial[((int64_t)blk * cols + c) * 2 + 1] = arz;
@@ -419,6 +462,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
   const int blk = blockIdx.x;
   if (scal[S_ACT * cols + c] == 0.0) return;
   double rr = 0.0, rzn = 0.0;
+#pragma unroll 8
   for (int b = 0; b < nblk; ++b) {
     rr += partial[((int64_t)b * cols + c) * 2];
     rzn += partial[((int64_t)b * cols + c) * 2 + 1];
@@ -434,6 +478,120 @@ __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
   if (blk == 0 && threadIdx.x == 0) {
     scal[(S_RZ0 + (slot ^ 1)) * cols + c] = rzn;
     scal[S_RR * cols + c] = rr;
+  }
+}
+
+// ---- device-side control (one wave, thread c = column)
+
+// After the start residual: |b| and |r| per column; a warm start that is not
+// better than zero (or not finite) is discarded (x = 0, r = b: applied by
+// fallback_kernel); b = 0 gives q_b = 0. Sets the active flags and clears
+// the status words.
+__global__ void ctl_init_kernel(double *__restrict__ scal, int cols, int fc, int x_zero, double tol,
+                                int *__restrict__ flags) {
+  const int c = threadIdx.x;
+  bool act = false, fb_any = false;
+  if (c < cols) {
+    const double bn = sqrt(scal[S_BN2 * cols + c]);
+    double rn = sqrt(scal[S_RR * cols + c]);
+    bool fb = false;
+    double res = 0.0, init = 0.0;
+    if (c < fc) {
+      if (bn == 0.0) {
+        fb = !x_zero;
+        rn = 0.0;
+      } else {
+        if (!x_zero && !(rn < bn)) {
+          fb = true;
+          fb_any = true;
+          rn = bn;
+        }
+        res = rn / bn;
+        init = res;
+        act = rn > tol * bn;
+      }
+    }
+    if (fb) scal[S_RR * cols + c] = rn * rn;
+    scal[S_ACT * cols + c] = act ? 1.0 : 0.0;
+    scal[S_FB * cols + c] = fb ? 1.0 : 0.0;
+    scal[S_RT * cols + c] = rn;
+    scal[S_RES * cols + c] = res;
+    scal[S_INIT * cols + c] = init;
+    scal[S_IT * cols + c] = 0.0;
+  }
+  const bool any = __any(act), anyfb = __any(fb_any);
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < F_NWORDS; ++w) flags[w] = 0;
+    flags[F_ANY] = any ? 1 : 0;
+    flags[F_FELLBACK] = anyfb ? 1 : 0;
+  }
+}
+
+// x = 0, r = b for the columns whose start was discarded
+__global__ __launch_bounds__(RED_THREADS) void fallback_kernel(
+    double *__restrict__ x, double *__restrict__ r, const double *__restrict__ b,
+    const double *__restrict__ scal, int64_t ld, int64_t n, int cols) {
+  const int c = blockIdx.y;
+  if (scal[S_FB * cols + c] == 0.0) return;
+  const int64_t i0 = (int64_t)blockIdx.x * CHUNK;
+  const int64_t i1 = min(n, i0 + CHUNK);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) {
+    const int64_t idx = (int64_t)c * ld + i;
+    x[idx] = 0.0;
+    r[idx] = b[idx];
+  }
+}
+
+// After a batch of `todo` iterations (it_after in total): count iterations
+// of the active columns and decide whether the true residual is due — the
+// recursive residual met half the tolerance, fell by the reliable-update
+// factor ru below the last true residual (ru = 0: never), or the iteration
+// limit is reached.
+__global__ void ctl_check_kernel(double *__restrict__ scal, int cols, int it_after, int todo,
+                                 int max_iter, double tol, double ru, int *__restrict__ flags) {
+  const int c = threadIdx.x;
+  bool need = false, bad = false;
+  if (c < cols && scal[S_ACT * cols + c] != 0.0) {
+    scal[S_IT * cols + c] += (double)todo;
+    const double bn = sqrt(scal[S_BN2 * cols + c]);
+    const double rn = sqrt(scal[S_RR * cols + c]);
+    if (!isfinite(rn)) bad = true;
+    need = rn <= 0.5 * tol * bn || (ru > 0.0 && rn <= ru * scal[S_RT * cols + c]) ||
+           it_after >= max_iter;
+  }
+  const bool any_need = __any(need), any_bad = __any(bad);
+  if (threadIdx.x == 0) {
+    flags[F_NEED] = any_need ? 1 : 0;
+    if (any_bad) flags[F_NONFINITE] = 1;
+  }
+}
+
+// After a true residual (only when one was due): record it, retire the
+// columns that meet the tolerance, count the update.
+__global__ void ctl_update_kernel(double *__restrict__ scal, int cols, int fc, double tol,
+                                  int *__restrict__ flags) {
+  if (flags[F_NEED] == 0) return;
+  const int c = threadIdx.x;
+  bool act = false;
+  if (c < cols) {
+    act = scal[S_ACT * cols + c] != 0.0;
+    const double bn = sqrt(scal[S_BN2 * cols + c]);
+    if (c < fc && bn != 0.0) {
+      const double rn = sqrt(scal[S_RR * cols + c]);
+      scal[S_RES * cols + c] = rn / bn;
+      if (act) {
+        scal[S_RT * cols + c] = rn;
+        if (rn <= tol * bn) {
+          act = false;
+          scal[S_ACT * cols + c] = 0.0;
+        }
+      }
+    }
+  }
+  const bool any = __any(act);
+  if (threadIdx.x == 0) {
+    flags[F_ANY] = any ? 1 : 0;
+    flags[F_UPDATES] += 1;
   }
 }
 
@@ -475,12 +633,12 @@ __global__ void pack_kernel(const double *__restrict__ src, int64_t n, int64_t f
 __global__ __launch_bounds__(RED_THREADS) void project_kernel(
     const double *__restrict__ x, int64_t ld, int64_t n, const double *__restrict__ d,
     const double *__restrict__ qsol, double *__restrict__ q, double *__restrict__ sum_err) {
-  __shared__ double red[RED_THREADS];
+  __shared__ double red[3][4];
   const int64_t f = blockIdx.x;
   const double *xf = x + f * ld;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) s += xf[i];
-  s = block_sum(s, red);
+  s = block_sum(s, red[0]);
   const double shift = s + qsol[f];
   double t = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) {
@@ -488,7 +646,7 @@ __global__ __launch_bounds__(RED_THREADS) void project_kernel(
     q[f * n + i] = qi;
     t += qi;
   }
-  t = block_sum(t, red);
+  t = block_sum(t, red[1]);
   if (threadIdx.x == 0) sum_err[f] = fabs(t + qsol[f]);
 }
 
@@ -540,11 +698,13 @@ int64_t max_slices(int64_t ld) {
 
 template <typename T, int NG>
 hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typename Mv<T>::VT *P,
-                           typename Mv<T>::VT *part, double *pv_part, int &slices) {
+                           typename Mv<T>::VT *part, double *pv_part, int &slices,
+                           const int *gate) {
   int64_t kslice = 0;
   slices = (int)matvec_slices<T>(ld, kslice);
   const int64_t tiles = matvec_tiles<T>(ld);
   hipEvent_t ea = nullptr, eb = nullptr;
+  int *mark = nullptr;
   if (t_prof && t_prof->enabled) {
     // algorithmic traffic: E (n x n) once, the n x cols block P read and V written
     const double n = (double)t_n;
@@ -552,22 +712,25 @@ hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typenam
     Profile::Rec &r = t_prof->add(prec_of<T>(), work);
     ea = r.a;
     eb = r.b;
+    if (gate) mark = t_prof->take_mark(r);
   }
   hipExtLaunchKernelGGL((block_matvec_kernel<T, NG>), dim3((unsigned)tiles, (unsigned)slices),
                         dim3(256), 0, st, ea, eb, 0, E, ld, P, part, kslice,
-                        (int64_t)(NG * 16) * ld, pv_part);
+                        (int64_t)(NG * 16) * ld, pv_part, gate, mark);
   return hipGetLastError();
 }
 
+// V = E P for cols = 16..64 columns; gate (device int, may be null): the
+// launch does nothing when it reads 0
 template <typename T>
 hipError_t launch_matvec(hipStream_t st, const T *E, int64_t ld, int64_t cols,
                          const typename Mv<T>::VT *P, typename Mv<T>::VT *part, double *pv_part,
-                         int &slices) {
+                         int &slices, const int *gate = nullptr) {
   switch (cols / 16) {
-    case 1: return launch_matvec_t<T, 1>(st, E, ld, P, part, pv_part, slices);
-    case 2: return launch_matvec_t<T, 2>(st, E, ld, P, part, pv_part, slices);
-    case 3: return launch_matvec_t<T, 3>(st, E, ld, P, part, pv_part, slices);
-    case 4: return launch_matvec_t<T, 4>(st, E, ld, P, part, pv_part, slices);
+    case 1: return launch_matvec_t<T, 1>(st, E, ld, P, part, pv_part, slices, gate);
+    case 2: return launch_matvec_t<T, 2>(st, E, ld, P, part, pv_part, slices, gate);
+    case 3: return launch_matvec_t<T, 3>(st, E, ld, P, part, pv_part, slices, gate);
+    case 4: return launch_matvec_t<T, 4>(st, E, ld, P, part, pv_part, slices, gate);
     default: return hipErrorInvalidValue;
   }
 }
@@ -577,6 +740,9 @@ void free_workspace(Workspace &w) {
                   w.xf, w.rf, w.pf, w.zf, w.vf};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
+  if (w.hstat) (void)hipHostFree(w.hstat);
+  for (hipEvent_t e : w.ev)
+    if (e) (void)hipEventDestroy(e);
   w = Workspace();
 }
 
@@ -606,11 +772,28 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
             alloc(&w.pf, vec / 2) && alloc(&w.vf, vec / 2 * (size_t)nsl) &&
             alloc((void **)&w.partial, sizeof(double) * 2 * (size_t)(nblk + npv) * cols) &&
             alloc((void **)&w.scal, sizeof(double) * S_NFIELDS * cols) &&
-            alloc((void **)&w.flags, sizeof(int) * 8);
+            alloc((void **)&w.flags, sizeof(int) * F_NWORDS);
+  if (ok && hipHostMalloc((void **)&w.hstat, sizeof(int) * F_NWORDS * kStatusSlots,
+                          hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    w.hstat = nullptr;
+    ok = false;
+  }
+  for (hipEvent_t &e : w.ev)
+    if (ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      e = nullptr;
+      ok = false;
+    }
   if (!ok) {
     free_workspace(w);
     set_error("workspace allocation failed");
     return CPM_ENOMEM;
+  }
+  if (hipMemset(w.flags, 0, sizeof(int) * F_NWORDS) != hipSuccess ||
+      hipMemset(w.scal, 0, sizeof(double) * S_NFIELDS * cols) != hipSuccess) {
+    set_error("workspace memset failed");
+    return CPM_EDEVICE;
   }
   void *zs[] = {w.x, w.r, w.p, w.z, w.bx, w.bres};
   for (void *q : zs)
@@ -632,30 +815,6 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
   w.cols = cols;
   w.bytes = total;
   s->device_bytes += (int64_t)total;
-  return CPM_OK;
-}
-
-struct HostScal {
-  std::vector<double> v;
-  int cols = 0;
-  double rr(int c) const { return v[S_RR * cols + c]; }
-  double bn2(int c) const { return v[S_BN2 * cols + c]; }
-};
-
-cpm_status read_scal(cpm_system *s, int cols, HostScal &h, int *flag) {
-  h.cols = cols;
-  h.v.resize(S_NFIELDS * cols);
-  CPM_HIP_CHECK(hipMemcpyAsync(h.v.data(), s->ws.scal, sizeof(double) * S_NFIELDS * cols,
-                               hipMemcpyDeviceToHost, s->stream));
-  if (flag)
-    CPM_HIP_CHECK(hipMemcpyAsync(flag, s->ws.flags, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
-  return CPM_OK;
-}
-
-cpm_status write_active(cpm_system *s, int cols, const std::vector<double> &act) {
-  CPM_HIP_CHECK(hipMemcpyAsync(s->ws.scal + S_ACT * cols, act.data(), sizeof(double) * cols,
-                               hipMemcpyHostToDevice, s->stream));
   return CPM_OK;
 }
 
@@ -695,31 +854,33 @@ template <typename T> struct Solver {
     }
   }
   dim3 grid() const { return dim3((unsigned)nblk, (unsigned)cols); }
+  const int *need() const { return flags + F_NEED; }
 
-  // r = b - E64 x for all columns; scal RR = |r|^2
-  hipError_t true_residual() {
+  // r = b - E64 x for all columns; scal RR = |r|^2 (gate: skipped when *gate == 0)
+  hipError_t true_residual(const int *gate) {
     int sl = 0;
-    hipError_t e = launch_matvec<double>(st, s->E64, ld, cols, x, v64, nullptr, sl);
+    hipError_t e = launch_matvec<double>(st, s->E64, ld, cols, x, v64, nullptr, sl, gate);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(residual_kernel, grid(), dim3(RED_THREADS), 0, st, v64, sl, ld * cols, b,
-                       r, ld, n, (int)cols, partial);
+                       r, ld, n, (int)cols, partial, gate);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, partial, nblk,
-                       (int)cols, scal, (int)S_RR);
+                       (int)cols, scal, (int)S_RR, gate);
     return hipGetLastError();
   }
 
   // z = M^-1 r (and p = z when restarting); rz into the current slot
-  hipError_t refresh(bool set_p) {
+  hipError_t refresh(bool set_p, const int *gate) {
     hipLaunchKernelGGL(cg_refresh_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, r, z, p, s->dinv,
-                       ld, n, (int)cols, scal, partial, set_p ? 1 : 0);
+                       ld, n, (int)cols, scal, partial, set_p ? 1 : 0, gate);
     hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(MAX_COLS), 0, st, partial, nblk,
-                       (int)cols, scal, slot);
+                       (int)cols, scal, slot, gate);
     return hipGetLastError();
   }
 
+  // one CG iteration of the active columns (nothing once none is active)
   hipError_t iterate() {
     int sl = 0;
-    hipError_t e = launch_matvec<T>(st, E, ld, cols, p, v, pvp, sl);
+    hipError_t e = launch_matvec<T>(st, E, ld, cols, p, v, pvp, sl, flags + F_ANY);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(cg_update_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, x, r, z, p, v, sl,
                        ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial, flags);
@@ -730,21 +891,20 @@ template <typename T> struct Solver {
   }
 };
 
-cpm_status breakdown_error(cpm_system *s, int it_done, int cols, const HostScal &h) {
-  int fl[8] = {0};
-  CPM_HIP_CHECK(hipMemcpy(fl, s->ws.flags, sizeof(fl), hipMemcpyDeviceToHost));
+cpm_status breakdown_error(int it_done, const int *fl) {
   double dbg[2];
   std::memcpy(dbg, fl + 2, sizeof(dbg));
-  const int c = fl[1];
   set_error("CG breakdown: p^T E p <= 0 (E is not positive definite); column " +
-            std::to_string(c) + " after " + std::to_string(it_done) + " iterations, p.Ep=" +
-            std::to_string(dbg[0]) + " r.z=" + std::to_string(dbg[1]) +
-            " |r|^2=" + std::to_string(c >= 0 && c < cols ? h.rr(c) : -1.0));
+            std::to_string(fl[F_COL]) + " within the first " + std::to_string(it_done) +
+            " iterations, p.Ep=" + std::to_string(dbg[0]) + " r.z=" + std::to_string(dbg[1]));
   return CPM_ENOTSPD;
 }
 
 // CG with reliable updates on columns [0, fc) of the workspace block: b in
 // ws.bx, start in ws.x (x_zero: it is zero). On return ws.x holds q_b.
+// Every decision is taken on the device (ctl_* kernels); the host enqueues
+// batches of check_every iterations and looks at the status words of the
+// batch before the one it has just enqueued.
 template <typename T>
 cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o,
                       cpm_solve_info *info, std::vector<int> &frame_iters,
@@ -752,111 +912,92 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
   const int64_t cols = round_up(fc, kColGroup);
   Solver<T> sv(s, E, cols);
   hipStream_t st = s->stream;
+  Workspace &w = s->ws;
   const bool f64 = sizeof(T) == 8;
   // reliable-update factor: the recursive residual may fall this far below
   // the last true residual before it is replaced (FP64: only at the end)
   const double ru = f64 ? 0.0 : std::min(0.5, std::max(1e-8, o.inner_tol));
+  // FP32 keeps the search direction at a true-residual update (reliable
+  // update). BF16: its matrix error (~2^-9 per entry) is too large for the
+  // old direction to stay conjugate, so the iteration restarts from the true
+  // residual (iterative refinement).
   const bool restart = sizeof(T) == 2;
   const double tol = o.tol;
-  std::vector<double> act(cols, 0.0);
-  for (int c = 0; c < fc; ++c) act[c] = 1.0;
-  cpm_status stt = write_active(s, (int)cols, act);
-  if (stt != CPM_OK) return stt;
-  CPM_HIP_CHECK(hipMemsetAsync(sv.flags, 0, sizeof(int) * 8, st));
 
-  // |b|^2
+  // |b|^2 and the start residual
   hipLaunchKernelGGL(sumsq_kernel, sv.grid(), dim3(RED_THREADS), 0, st, sv.b, sv.ld, sv.n,
                      (int)cols, sv.partial);
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.partial, sv.nblk,
-                     (int)cols, sv.scal, (int)S_BN2);
-  // start residual
+                     (int)cols, sv.scal, (int)S_BN2, nullptr);
   if (x_zero) {
     CPM_HIP_CHECK(hipMemcpyAsync(sv.r, sv.b, sizeof(double) * sv.ld * cols,
                                  hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(sumsq_kernel, sv.grid(), dim3(RED_THREADS), 0, st, sv.r, sv.ld, sv.n,
                        (int)cols, sv.partial);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.partial, sv.nblk,
-                       (int)cols, sv.scal, (int)S_RR);
+                       (int)cols, sv.scal, (int)S_RR, nullptr);
   } else {
-    CPM_HIP_CHECK(sv.true_residual());
+    CPM_HIP_CHECK(sv.true_residual(nullptr));
   }
-  HostScal h;
-  if ((stt = read_scal(s, (int)cols, h, nullptr)) != CPM_OK) return stt;
-  std::vector<double> bn(cols, 0.0), rtrue(cols, 0.0);
-  double init_res = 0.0;
-  for (int c = 0; c < fc; ++c) {
-    bn[c] = std::sqrt(h.bn2(c));
-    double rn = std::sqrt(h.rr(c));
-    if (bn[c] == 0.0) {   // b = 0: q_b = 0
-      act[c] = 0.0;
-      continue;
-    }
-    if (!x_zero && !(rn < bn[c])) {
-      // a start no better than zero (or non-finite): discard it
-      CPM_HIP_CHECK(hipMemsetAsync(sv.x + c * sv.ld, 0, sizeof(double) * sv.ld, st));
-      CPM_HIP_CHECK(hipMemcpyAsync(sv.r + c * sv.ld, sv.b + c * sv.ld, sizeof(double) * sv.ld,
-                                   hipMemcpyDeviceToDevice, st));
-      rn = bn[c];
-      if (info) info->fell_back = 1;
-    }
-    rtrue[c] = rn;
-    init_res = std::max(init_res, rn / bn[c]);
-    if (rn <= tol * bn[c]) act[c] = 0.0;
-    frame_res[c] = rn / bn[c];
-  }
-  if (info) info->initial_rel_resid = std::max(info->initial_rel_resid, init_res);
-  if ((stt = write_active(s, (int)cols, act)) != CPM_OK) return stt;
+  hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.scal, (int)cols, fc,
+                     x_zero ? 1 : 0, tol, sv.flags);
+  if (!x_zero)
+    hipLaunchKernelGGL(fallback_kernel, sv.grid(), dim3(RED_THREADS), 0, st, sv.x, sv.r, sv.b,
+                       sv.scal, sv.ld, sv.n, (int)cols);
   sv.slot = 0;
-  CPM_HIP_CHECK(sv.refresh(true));
+  CPM_HIP_CHECK(sv.refresh(true, nullptr));
 
-  auto any_active = [&]() {
-    for (int c = 0; c < fc; ++c)
-      if (act[c] != 0.0) return true;
-    return false;
-  };
   const int check = std::max(1, o.check_every);
-  int it = 0, updates = 0;
-  int flag = 0;
-  while (any_active() && it < o.max_iter) {
+  int it = 0, pending = -1, batch = 0;
+  auto status_of = [&](int slot) { return w.hstat + slot * F_NWORDS; };
+  while (it < o.max_iter) {
     const int todo = std::min(check, o.max_iter - it);
     for (int k = 0; k < todo; ++k) CPM_HIP_CHECK(sv.iterate());
-    for (int c = 0; c < fc; ++c)
-      if (act[c] != 0.0) frame_iters[c] += todo;
     it += todo;
-    if ((stt = read_scal(s, (int)cols, h, &flag)) != CPM_OK) return stt;
-    if (flag) return breakdown_error(s, it, (int)cols, h);
-    bool need = it >= o.max_iter;
-    for (int c = 0; c < fc && !need; ++c) {
-      if (act[c] == 0.0) continue;
-      const double rn = std::sqrt(h.rr(c));
-      if (!std::isfinite(rn)) {
-        set_error("CG produced a non-finite residual");
-        return CPM_ENOTSPD;
-      }
-      if (rn <= 0.5 * tol * bn[c] || (ru > 0.0 && rn <= ru * rtrue[c])) need = true;
+    hipLaunchKernelGGL(ctl_check_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.scal, (int)cols, it,
+                       todo, o.max_iter, tol, ru, sv.flags);
+    CPM_HIP_CHECK(sv.true_residual(sv.need()));
+    hipLaunchKernelGGL(ctl_update_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.scal, (int)cols, fc,
+                       tol, sv.flags);
+    CPM_HIP_CHECK(sv.refresh(restart, sv.need()));
+    const int slot = batch % kStatusSlots;
+    CPM_HIP_CHECK(hipMemcpyAsync(status_of(slot), sv.flags, sizeof(int) * F_NWORDS,
+                                 hipMemcpyDeviceToHost, st));
+    CPM_HIP_CHECK(hipEventRecord(w.ev[slot], st));
+    ++batch;
+    // the previous batch's status: stop enqueuing once nothing is active
+    if (pending >= 0) {
+      CPM_HIP_CHECK(hipEventSynchronize(w.ev[pending]));
+      const int *fl = status_of(pending);
+      if (fl[F_BREAK] || fl[F_NONFINITE] || fl[F_ANY] == 0) break;
     }
-    if (!need) continue;
-    // reliable update: true FP64 residual of every column
-    CPM_HIP_CHECK(sv.true_residual());
-    if ((stt = read_scal(s, (int)cols, h, nullptr)) != CPM_OK) return stt;
-    ++updates;
-    for (int c = 0; c < fc; ++c) {
-      if (bn[c] == 0.0) continue;
-      const double rn = std::sqrt(h.rr(c));
-      frame_res[c] = rn / bn[c];
-      if (act[c] == 0.0) continue;
-      rtrue[c] = rn;
-      if (rn <= tol * bn[c]) act[c] = 0.0;
-    }
-    if ((stt = write_active(s, (int)cols, act)) != CPM_OK) return stt;
-    // FP32: keep the search direction (reliable update). BF16: its matrix
-    // error (~2^-9 per entry) is too large for the old direction to stay
-    // conjugate, so the iteration restarts from the true residual.
-    if (any_active()) CPM_HIP_CHECK(sv.refresh(restart));
+    pending = slot;
+  }
+  // final state
+  std::vector<double> hs(S_NFIELDS * cols);
+  int fl[F_NWORDS];
+  CPM_HIP_CHECK(hipMemcpyAsync(hs.data(), sv.scal, sizeof(double) * hs.size(),
+                               hipMemcpyDeviceToHost, st));
+  CPM_HIP_CHECK(hipMemcpyAsync(fl, sv.flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+  CPM_HIP_CHECK(hipStreamSynchronize(st));
+  if (fl[F_BREAK]) return breakdown_error(it, fl);
+  if (fl[F_NONFINITE]) {
+    set_error("CG produced a non-finite residual");
+    return CPM_ENOTSPD;
+  }
+  int iters = 0;
+  double init_res = 0.0;
+  for (int c = 0; c < fc; ++c) {
+    frame_iters[c] = (int)hs[S_IT * cols + c];
+    frame_res[c] = hs[S_RES * cols + c];
+    iters = std::max(iters, frame_iters[c]);
+    init_res = std::max(init_res, hs[S_INIT * cols + c]);
   }
   if (info) {
-    info->iterations = std::max(info->iterations, it);
-    info->outer = std::max(info->outer, updates);
+    info->initial_rel_resid = std::max(info->initial_rel_resid, init_res);
+    if (fl[F_FELLBACK]) info->fell_back = 1;
+    info->iterations = std::max(info->iterations, iters);
+    info->outer = std::max(info->outer, fl[F_UPDATES]);
     for (int c = 0; c < fc; ++c) info->max_rel_resid = std::max(info->max_rel_resid, frame_res[c]);
   }
   for (int c = 0; c < fc; ++c)
@@ -881,6 +1022,11 @@ cpm_status solve_columns(cpm_system *s, int fc, const cpm_solve_opts &o, cpm_sol
 }
 
 }  // namespace
+
+void release_workspace(cpm_system *s) {
+  s->device_bytes -= (int64_t)s->ws.bytes;
+  free_workspace(s->ws);
+}
 
 hipError_t launch_diag_inverse(hipStream_t st, const double *E, int64_t n, int64_t ld,
                                double *dinv) {

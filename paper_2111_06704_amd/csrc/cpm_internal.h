@@ -27,7 +27,16 @@ struct Kset {
   int nmax[3] = {0, 0, 0};
   std::vector<int32_t> n;      // nk*3 integer triplets
   std::vector<double> w;       // nk weights 2 (4 pi / V) exp(-K^2/4 beta^2) / K^2
+  // The vectors are ordered by (n_x, n_y, n_z), so each (n_x, n_y) column is
+  // a contiguous range of consecutive n_z. Runs split every column into
+  // pieces of at most kRun vectors: runs[2r] = first index, runs[2r+1] = length.
+  std::vector<int32_t> runs;
+  int64_t nruns = 0;
+  // info[4k..4k+3] = n_x, n_y, n_z, 1 if k starts a run (else 0)
+  std::vector<int32_t> info;
 };
+
+constexpr int kRun = 16;       // longest run of consecutive n_z (phase recurrence length)
 
 // Half-space reciprocal vectors with |K| <= kmax, K != 0 (host).
 Kset make_kset(const double box[3], double beta, double kmax);
@@ -44,9 +53,12 @@ struct Workspace {            // CG scratch, grown on demand
   double *scal = nullptr;     // per-column scalars, see cg.hip
   double *bx = nullptr;       // n_pad*cols double: right-hand sides / outer iterate
   double *bres = nullptr;     // n_pad*cols double: outer residual
-  int *flags = nullptr;       // device flags
+  int *flags = nullptr;       // device status words
+  int *hstat = nullptr;       // pinned host copies of the status words (ring of kStatusSlots)
+  hipEvent_t ev[2] = {nullptr, nullptr};
   size_t bytes = 0;
 };
+constexpr int kStatusSlots = 2;
 
 struct Mlp {
   bool ready = false;
@@ -77,9 +89,19 @@ struct Profile {
     int kind;              // 0..2: matvec FP64/FP32/BF16, 3: assembly contraction
     double work;           // algorithmic bytes (matvec) or flops (assembly) of the launch
     hipEvent_t a, b;
+    int mark = -1;         // slot in marks: 1 if the launch did its work, 0 if it was gated off
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
+  static constexpr int kMarks = 1 << 16;
+  int *marks = nullptr;    // device, kMarks ints (allocated when profiling is enabled)
+  int next_mark = 0;
+  // a mark slot for a gated launch (nullptr when none is left)
+  int *take_mark(Rec &r) {
+    if (!marks || next_mark >= kMarks) return nullptr;
+    r.mark = next_mark++;
+    return marks + r.mark;
+  }
   hipEvent_t get();
   // new record; its events are passed to hipExtLaunchKernelGGL, which
   // stamps them as part of the kernel dispatch (no extra queue packets)
@@ -100,6 +122,9 @@ struct cpm_system {
   double *width = nullptr;    // n device (Gaussian inverse widths)
   int32_t *kn = nullptr;      // nk*3 device
   double *kw = nullptr;       // nk device
+  int32_t *kinfo = nullptr;   // nk*4 device (Kset::info)
+  int32_t *krun = nullptr;    // nruns*2 device (Kset::runs)
+  int32_t *atom_order = nullptr;  // n device: atoms in compact spatial tiles (real-space sums)
   double *E64 = nullptr;      // ld*ld device (rows >= n and cols >= n are zero)
   float *E32 = nullptr;
   uint16_t *E16 = nullptr;
@@ -133,12 +158,13 @@ hipError_t launch_finalize(hipStream_t st, const double *pos, const double *widt
                            double *E64, float *E32, uint16_t *E16);
 
 // ---- rhs.hip
-int64_t rhs_scratch_elems(int64_t n, int64_t nk, int64_t f);
+int64_t rhs_scratch_elems(const cpm_system *s, int64_t m, int64_t f);
 hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos,
                       const double *ion_q, int64_t m, int64_t f, const double *chi,
                       double *S, double *b_out, double *qsol_out);
 
 // ---- cg.hip
+void release_workspace(cpm_system *s);
 cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
                        const cpm_solve_opts &o, double *q_out_dev, cpm_solve_info *info,
                        const double *x0_dev);

@@ -19,8 +19,9 @@ namespace cpm {
 namespace {
 
 constexpr int RB = 256;       // threads per block
-constexpr int KCH = 64;       // k-vectors per LDS chunk in the back-projection
 constexpr int FG = 16;        // frames per thread in the back-projection
+constexpr int BP_AT = 4;      // atoms per thread in the back-projection
+constexpr int BP_KCH = 32;    // k-vectors per LDS chunk in the back-projection
 
 __global__ __launch_bounds__(RB) void qsum_kernel(const double *__restrict__ q, int64_t m,
                                                   double *__restrict__ qsol) {
@@ -37,122 +38,202 @@ __global__ __launch_bounds__(RB) void qsum_kernel(const double *__restrict__ q, 
   if (threadIdx.x == 0) qsol[f] = red[0];
 }
 
-// One thread per k-vector, one grid row per frame; ions stream through LDS.
+// Ion structure factors of one group of ions, S_fK = sum_I q_I exp(i K.r_I).
+// One thread per (run, frame): a run is up to kRun vectors of one (n_x, n_y)
+// column with consecutive n_z. The phase of the run's first vector is
+// evaluated directly (sincospi of the fractional phase); each following one
+// is the previous times exp(2 pi i z_I / L_z), so kRun vectors cost one
+// sincospi and kRun complex products per ion. Ions stream through LDS.
+// Output layout: Sg[((g * nk + k) * f_total + f) * 2 + {0: Re, 1: Im}].
 __global__ __launch_bounds__(RB) void structure_factor_kernel(
-    const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m,
-    const int32_t *__restrict__ kn, int64_t nk, double inv_lx, double inv_ly, double inv_lz,
-    double *__restrict__ S) {
-  __shared__ double su[RB][4];
-  const int64_t f = blockIdx.y;
-  const int64_t k = (int64_t)blockIdx.x * RB + threadIdx.x;
+    const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m, int64_t ipg,
+    const int32_t *__restrict__ kinfo, const int32_t *__restrict__ runs, int64_t nruns,
+    int64_t nk, double inv_lx, double inv_ly, double inv_lz, int64_t f_total,
+    double *__restrict__ Sg) {
+  __shared__ double su[RB][6];   // x/L, y/L, z/L, q, cos and sin of 2 pi z/L
+  const int64_t f = blockIdx.y, g = blockIdx.z;
+  const int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x;
+  int64_t k0 = 0;
+  int len = 0;
   double nx = 0, ny = 0, nz = 0;
-  if (k < nk) {
-    nx = kn[3 * k];
-    ny = kn[3 * k + 1];
-    nz = kn[3 * k + 2];
+  if (r < nruns) {
+    k0 = runs[2 * r];
+    len = runs[2 * r + 1];
+    nx = kinfo[4 * k0];
+    ny = kinfo[4 * k0 + 1];
+    nz = kinfo[4 * k0 + 2];
   }
-  double sr = 0.0, si = 0.0;
+  double ar[kRun], ai[kRun];
+#pragma unroll
+  for (int st = 0; st < kRun; ++st) ar[st] = ai[st] = 0.0;
   const double *pf = ion_pos + f * m * 3;
   const double *qf = ion_q + f * m;
-  for (int64_t base = 0; base < m; base += RB) {
+  const int64_t i0 = g * ipg, i1 = min(m, i0 + ipg);
+  for (int64_t base = i0; base < i1; base += RB) {
     const int64_t I = base + threadIdx.x;
-    if (I < m) {
+    if (I < i1) {
+      const double uz = pf[3 * I + 2] * inv_lz;
       su[threadIdx.x][0] = pf[3 * I] * inv_lx;
       su[threadIdx.x][1] = pf[3 * I + 1] * inv_ly;
-      su[threadIdx.x][2] = pf[3 * I + 2] * inv_lz;
+      su[threadIdx.x][2] = uz;
       su[threadIdx.x][3] = qf[I];
+      double zs, zc;
+      sincospi(2.0 * (uz - rint(uz)), &zs, &zc);
+      su[threadIdx.x][4] = zc;
+      su[threadIdx.x][5] = zs;
     }
     __syncthreads();
-    const int cnt = (int)((m - base) < RB ? (m - base) : RB);
+    const int cnt = (int)((i1 - base) < RB ? (i1 - base) : RB);
     for (int j = 0; j < cnt; ++j) {
       double t = nx * su[j][0] + ny * su[j][1] + nz * su[j][2];
       t -= rint(t);
-      double s, c;
-      sincospi(2.0 * t, &s, &c);
-      sr += su[j][3] * c;
-      si += su[j][3] * s;
+      double sn, cs;
+      sincospi(2.0 * t, &sn, &cs);
+      const double q = su[j][3], zc = su[j][4], zs = su[j][5];
+#pragma unroll
+      for (int st = 0; st < kRun; ++st) {
+        ar[st] += q * cs;
+        ai[st] += q * sn;
+        const double c2 = cs * zc - sn * zs;
+        sn = cs * zs + sn * zc;
+        cs = c2;
+      }
     }
     __syncthreads();
   }
-  if (k < nk) {
-    S[(f * nk + k) * 2] = sr;
-    S[(f * nk + k) * 2 + 1] = si;
+  if (r < nruns) {
+    double *out = Sg + ((g * nk + k0) * f_total + f) * 2;
+#pragma unroll
+    for (int st = 0; st < kRun; ++st)
+      if (st < len) {
+        out[st * f_total * 2] = ar[st];
+        out[st * f_total * 2 + 1] = ai[st];
+      }
   }
+}
+
+// S[e] = sum_g Sg[g][e] over the ion groups (fixed order)
+__global__ void sum_groups_kernel(const double *__restrict__ Sg, int groups, int64_t len,
+                                  double *__restrict__ S) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  double s = 0.0;
+  for (int g = 0; g < groups; ++g) s += Sg[(int64_t)g * len + e];
+  S[e] = s;
 }
 
 // Back-projection of the ion structure factors onto the electrode atoms,
 // split over k ranges: part[ks][f][i] = sum_{K in range ks} w_K (c_iK Re S_fK
-// + s_iK Im S_fK). One thread per atom, FG frames per thread (the phase of
-// (i, K) is evaluated once for all FG frames); grid (atom blocks, k splits,
+// + s_iK Im S_fK). Each thread takes AT atoms (i = block base + thread +
+// RB a) and FG frames; K data and S_f.K of BP_KCH vectors at a time are
+// staged in LDS and read by all lanes at the same address. The phase of
+// (i, K) is evaluated directly at the start of every run (and of the range)
+// and by the n_z recurrence inside a run. Grid (atom blocks, k splits,
 // frame groups).
+template <int AT>
 __global__ __launch_bounds__(RB) void backproject_kernel(
-    const double *__restrict__ pos, int64_t n, const int32_t *__restrict__ kn,
+    const double *__restrict__ pos, int64_t n, const int32_t *__restrict__ kinfo,
     const double *__restrict__ kw, int64_t nk, int64_t kper, double inv_lx, double inv_ly,
     double inv_lz, const double *__restrict__ S, int64_t f_total, double *__restrict__ part) {
-  __shared__ double sk[KCH][4];            // nx, ny, nz, w
-  __shared__ double ss[FG][KCH][2];        // S for this block's frames
-  const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+  __shared__ int4 sk[BP_KCH];
+  __shared__ double sw[BP_KCH];
+  __shared__ double2 ss[BP_KCH][FG];
+  const int64_t ibase = (int64_t)blockIdx.x * RB * AT + threadIdx.x;
   const int64_t kbeg = (int64_t)blockIdx.y * kper;
   const int64_t kend = min(nk, kbeg + kper);
   const int64_t f0 = (int64_t)blockIdx.z * FG;
   const int nf = (int)((f_total - f0) < FG ? (f_total - f0) : FG);
-  double ux = 0, uy = 0, uz = 0;
-  if (i < n) {
-    ux = pos[3 * i] * inv_lx;
-    uy = pos[3 * i + 1] * inv_ly;
-    uz = pos[3 * i + 2] * inv_lz;
-  }
-  double acc[FG];
+  double ux[AT], uy[AT], uz[AT], zs[AT], zc[AT], cs[AT], sn[AT];
 #pragma unroll
-  for (int g = 0; g < FG; ++g) acc[g] = 0.0;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += KCH) {
-    const int cnt = (int)((kend - k0) < KCH ? (kend - k0) : KCH);
-    for (int t = threadIdx.x; t < KCH; t += RB) {
-      if (t < cnt) {
-        sk[t][0] = kn[3 * (k0 + t)];
-        sk[t][1] = kn[3 * (k0 + t) + 1];
-        sk[t][2] = kn[3 * (k0 + t) + 2];
-        sk[t][3] = kw[k0 + t];
-      }
+  for (int a = 0; a < AT; ++a) {
+    const int64_t i = ibase + RB * a;
+    ux[a] = uy[a] = uz[a] = 0.0;
+    if (i < n) {
+      ux[a] = pos[3 * i] * inv_lx;
+      uy[a] = pos[3 * i + 1] * inv_ly;
+      uz[a] = pos[3 * i + 2] * inv_lz;
     }
-    for (int t = threadIdx.x; t < FG * KCH; t += RB) {
-      const int g = t / KCH, kk = t % KCH;
-      double re = 0.0, im = 0.0;
-      if (g < nf && kk < cnt) {
-        re = S[((f0 + g) * nk + k0 + kk) * 2];
-        im = S[((f0 + g) * nk + k0 + kk) * 2 + 1];
-      }
-      ss[g][kk][0] = re;
-      ss[g][kk][1] = im;
+    sincospi(2.0 * (uz[a] - rint(uz[a])), &zs[a], &zc[a]);
+    cs[a] = 1.0;
+    sn[a] = 0.0;
+  }
+  double acc[AT][FG];
+#pragma unroll
+  for (int a = 0; a < AT; ++a)
+#pragma unroll
+    for (int g = 0; g < FG; ++g) acc[a][g] = 0.0;
+  const int4 *ki4 = reinterpret_cast<const int4 *>(kinfo);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BP_KCH) {
+    const int cnt = (int)((kend - k0) < BP_KCH ? (kend - k0) : BP_KCH);
+    for (int t = threadIdx.x; t < BP_KCH * FG; t += RB) {
+      const int kk = t / FG, g = t % FG;
+      double2 v = make_double2(0.0, 0.0);
+      if (kk < cnt && g < nf) v = *reinterpret_cast<const double2 *>(S + ((k0 + kk) * f_total + f0 + g) * 2);
+      ss[kk][g] = v;
+    }
+    if (threadIdx.x < cnt) {
+      sk[threadIdx.x] = ki4[k0 + threadIdx.x];
+      sw[threadIdx.x] = kw[k0 + threadIdx.x];
     }
     __syncthreads();
     for (int kk = 0; kk < cnt; ++kk) {
-      double t = sk[kk][0] * ux + sk[kk][1] * uy + sk[kk][2] * uz;
-      t -= rint(t);
-      double sn, cs;
-      sincospi(2.0 * t, &sn, &cs);
-      cs *= sk[kk][3];
-      sn *= sk[kk][3];
+      const int4 ki = sk[kk];
+      const double w = sw[kk];
+      if (ki.w != 0 || k0 + kk == kbeg) {
 #pragma unroll
-      for (int g = 0; g < FG; ++g) acc[g] += cs * ss[g][kk][0] + sn * ss[g][kk][1];
+        for (int a = 0; a < AT; ++a) {
+          double t = (double)ki.x * ux[a] + (double)ki.y * uy[a] + (double)ki.z * uz[a];
+          t -= rint(t);
+          sincospi(2.0 * t, &sn[a], &cs[a]);
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < AT; ++a) {
+          const double c2 = cs[a] * zc[a] - sn[a] * zs[a];
+          sn[a] = cs[a] * zs[a] + sn[a] * zc[a];
+          cs[a] = c2;
+        }
+      }
+      double wc[AT], ws[AT];
+#pragma unroll
+      for (int a = 0; a < AT; ++a) {
+        wc[a] = w * cs[a];
+        ws[a] = w * sn[a];
+      }
+#pragma unroll
+      for (int g = 0; g < FG; ++g) {
+        const double2 sv = ss[kk][g];
+#pragma unroll
+        for (int a = 0; a < AT; ++a) acc[a][g] += wc[a] * sv.x + ws[a] * sv.y;
+      }
     }
     __syncthreads();
   }
-  if (i < n) {
-    for (int g = 0; g < nf; ++g) part[((int64_t)blockIdx.y * f_total + f0 + g) * n + i] = acc[g];
+#pragma unroll
+  for (int a = 0; a < AT; ++a) {
+    const int64_t i = ibase + RB * a;
+    if (i < n) {
+#pragma unroll
+      for (int g = 0; g < FG; ++g)
+        if (g < nf) part[((int64_t)blockIdx.y * f_total + f0 + g) * n + i] = acc[a][g];
+    }
   }
 }
 
-// b[f, i] = chi_i / k_e - sum_ks part[ks][f][i] - c0 Q_f (fixed order over ks)
-__global__ void assemble_b_kernel(const double *__restrict__ part, int ksplits, int64_t n,
+// b[f, i] = chi_i / k_e - sum_ks bp[ks][f][i] - sum_g rs[g][f][i] - c0 Q_f
+// (fixed order over the k splits and ion groups)
+__global__ void assemble_b_kernel(const double *__restrict__ bp, int ksplits,
+                                  const double *__restrict__ rs, int rgroups, int64_t n,
                                   int64_t f_total, const double *__restrict__ chi,
                                   const double *__restrict__ qsol, double c0,
                                   double *__restrict__ b) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * f_total) return;
   const int64_t f = idx / n, i = idx % n;
+  const int64_t fn = n * f_total;
   double s = 0.0;
-  for (int ks = 0; ks < ksplits; ++ks) s += part[((int64_t)ks * f_total + f) * n + i];
+  for (int ks = 0; ks < ksplits; ++ks) s += bp[ks * fn + idx];
+  for (int g = 0; g < rgroups; ++g) s += rs[g * fn + idx];
   b[idx] = chi[i] * (1.0 / kCoulombVA) - s - c0 * qsol[f];
 }
 
@@ -170,17 +251,22 @@ __device__ inline void image_range(double d, double L, double invL, double rcut,
   }
 }
 
-// One thread per (electrode atom, frame); ions stream through LDS.
-// b[f, i] -= sum_I q_I sum_images [erfc(beta d) - erfc(a_i d)] / d.
+// One thread per (electrode atom, frame, ion group); ions stream through LDS.
+// rs[g][f][i] = sum_{I in group g} q_I sum_images [erfc(beta d) - erfc(a_i d)] / d.
+// Thread t takes atom order[t] (compact spatial tiles), so a wavefront's
+// atoms are close together and the branch into the erfc terms is taken by
+// all lanes or none for most ions.
 __global__ __launch_bounds__(RB) void real_space_ions_kernel(
-    const double *__restrict__ pos, const double *__restrict__ width, int64_t n,
-    const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m, double lx,
-    double ly, double lz, double beta, double rcut, double *__restrict__ b) {
+    const double *__restrict__ pos, const double *__restrict__ width,
+    const int32_t *__restrict__ order, int64_t n, const double *__restrict__ ion_pos,
+    const double *__restrict__ ion_q, int64_t m, int64_t ipg, double lx, double ly, double lz,
+    double beta, double rcut, int64_t f_total, double *__restrict__ rs) {
   __shared__ double si[RB][4];
-  const int64_t f = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+  const int64_t f = blockIdx.y, g = blockIdx.z;
+  const int64_t t = (int64_t)blockIdx.x * RB + threadIdx.x;
+  const int64_t i = t < n ? (int64_t)order[t] : -1;
   double xi = 0, yi = 0, zi = 0, ai = 1.0;
-  if (i < n) {
+  if (i >= 0) {
     xi = pos[3 * i];
     yi = pos[3 * i + 1];
     zi = pos[3 * i + 2];
@@ -194,17 +280,18 @@ __global__ __launch_bounds__(RB) void real_space_ions_kernel(
   double acc = 0.0;
   const double *pf = ion_pos + f * m * 3;
   const double *qf = ion_q + f * m;
-  for (int64_t base = 0; base < m; base += RB) {
+  const int64_t i0 = g * ipg, i1 = min(m, i0 + ipg);
+  for (int64_t base = i0; base < i1; base += RB) {
     const int64_t I = base + threadIdx.x;
-    if (I < m) {
+    if (I < i1) {
       si[threadIdx.x][0] = pf[3 * I];
       si[threadIdx.x][1] = pf[3 * I + 1];
       si[threadIdx.x][2] = pf[3 * I + 2];
       si[threadIdx.x][3] = qf[I];
     }
     __syncthreads();
-    const int cnt = (int)((m - base) < RB ? (m - base) : RB);
-    if (i < n) {
+    const int cnt = (int)((i1 - base) < RB ? (i1 - base) : RB);
+    if (i >= 0) {
       for (int j = 0; j < cnt; ++j) {
         double dz = zi - si[j][2];
         dz -= lz * rint(dz * ilz);
@@ -243,58 +330,101 @@ __global__ __launch_bounds__(RB) void real_space_ions_kernel(
     }
     __syncthreads();
   }
-  if (i < n) b[f * n + i] -= acc;
+  if (i >= 0) rs[(g * f_total + f) * n + i] = acc;
 }
 
 }  // namespace
 
-// k splits of the back-projection: enough blocks to fill the chip (~2048),
-// at most 64, and a partial buffer of at most ~2^27 doubles.
-static int64_t backproject_ksplit(int64_t n, int64_t nk, int64_t f, int64_t &kper) {
-  const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
-  const int64_t nkk = std::max<int64_t>(nk, 1);
-  int64_t ksplit = (2048 + iblocks * fgroups - 1) / (iblocks * fgroups);
-  const int64_t cap = std::max<int64_t>(1, ((int64_t)1 << 27) / std::max<int64_t>(1, f * n));
-  ksplit = std::max<int64_t>(1, std::min<int64_t>({ksplit, 64, nkk, cap}));
-  kper = (nkk + ksplit - 1) / ksplit;
-  return (nkk + kper - 1) / kper;
+namespace {
+
+// Work split of one cpm_rhs call over f frames of m ions, and the layout of
+// its scratch buffer:
+//   S   [nk][f][2]             structure factors
+//   Sg  [sf_groups][nk][f][2]  per ion group (only when sf_groups > 1)
+//   bp  [ksplit][f][n]         back-projection partials
+//   rs  [rs_groups][f][n]      real-space partials
+struct RhsPlan {
+  int64_t sf_groups = 1, sf_ipg = 0, ksplit = 0, kper = 0, rs_groups = 0, rs_ipg = 0;
+  int64_t off_sg = 0, off_bp = 0, off_rs = 0, total = 0;
+};
+
+constexpr int64_t kTargetBlocks = 2048;          // workgroups that fill the chip several times
+constexpr int64_t kPartialCap = (int64_t)1 << 27;  // doubles per partial buffer
+
+// groups of at least RB items each, enough for ~kTargetBlocks workgroups,
+// at most 64 and at most cap
+int64_t groups_for(int64_t blocks, int64_t items, int64_t cap, int64_t &per) {
+  int64_t g = (kTargetBlocks + blocks - 1) / std::max<int64_t>(1, blocks);
+  g = std::min<int64_t>({g, std::max<int64_t>(1, items / RB), 64, std::max<int64_t>(1, cap)});
+  g = std::max<int64_t>(1, g);
+  per = (items + g - 1) / g;
+  return per > 0 ? (items + per - 1) / per : 1;
 }
 
-int64_t rhs_scratch_elems(int64_t n, int64_t nk, int64_t f) {
-  // structure factors (2 f nk) + back-projection partials (ksplit f n)
-  int64_t kper = 0;
-  return 2 * f * std::max<int64_t>(nk, 1) + backproject_ksplit(n, nk, f, kper) * f * n;
+RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f) {
+  RhsPlan p;
+  const int64_t n = s->n, nk = std::max<int64_t>(s->kset.nk, 1);
+  const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
+  const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
+  const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
+  if (m > 0 && s->kset.nk > 0) {
+    p.sf_groups = groups_for(std::max<int64_t>(1, rblocks) * f, m, kPartialCap / (2 * nk * f), p.sf_ipg);
+    int64_t kper = 0;
+    p.ksplit = groups_for(bblocks * fgroups, s->kset.nk, kPartialCap / (f * n), kper);
+    p.kper = kper;
+  }
+  if (m > 0) p.rs_groups = groups_for(iblocks * f, m, kPartialCap / (f * n), p.rs_ipg);
+  p.off_sg = 2 * nk * f;
+  p.off_bp = p.off_sg + (p.sf_groups > 1 ? p.sf_groups * 2 * nk * f : 0);
+  p.off_rs = p.off_bp + p.ksplit * f * n;
+  p.total = p.off_rs + p.rs_groups * f * n;
+  return p;
+}
+
+}  // namespace
+
+int64_t rhs_scratch_elems(const cpm_system *s, int64_t m, int64_t f) {
+  return rhs_plan(s, m, f).total;
 }
 
 hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos,
-                      const double *ion_q, int64_t m, int64_t f, const double *chi, double *S,
+                      const double *ion_q, int64_t m, int64_t f, const double *chi, double *scratch,
                       double *b_out, double *qsol_out) {
   const double ilx = 1.0 / s->box[0], ily = 1.0 / s->box[1], ilz = 1.0 / s->box[2];
   const int64_t nk = s->kset.nk, n = s->n;
   const double c0 = -M_PI / (s->vol * s->beta * s->beta);
+  const RhsPlan p = rhs_plan(s, m, f);
+  double *S = scratch, *bp = scratch + p.off_bp, *rs = scratch + p.off_rs;
+  const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
   if (m > 0) {
     hipLaunchKernelGGL(qsum_kernel, dim3((unsigned)f), dim3(RB), 0, st, ion_q, m, qsol_out);
-    hipLaunchKernelGGL(structure_factor_kernel, dim3((unsigned)((nk + RB - 1) / RB), (unsigned)f),
-                       dim3(RB), 0, st, ion_pos, ion_q, m, s->kn, nk, ilx, ily, ilz, S);
   } else {
     hipError_t e = hipMemsetAsync(qsol_out, 0, sizeof(double) * f, st);
     if (e != hipSuccess) return e;
-    e = hipMemsetAsync(S, 0, sizeof(double) * 2 * f * std::max<int64_t>(nk, 1), st);
-    if (e != hipSuccess) return e;
   }
-  const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
-  int64_t kper = 0;
-  const int64_t ksplit = backproject_ksplit(n, nk, f, kper);
-  double *part = S + 2 * f * std::max<int64_t>(nk, 1);
-  hipLaunchKernelGGL(backproject_kernel, dim3((unsigned)iblocks, (unsigned)ksplit, (unsigned)fgroups),
-                     dim3(RB), 0, st, s->pos, n, s->kn, s->kw, nk, kper, ilx, ily, ilz, S, f, part);
+  if (p.ksplit > 0) {
+    double *Sg = p.sf_groups > 1 ? scratch + p.off_sg : S;
+    const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
+    hipLaunchKernelGGL(structure_factor_kernel, dim3((unsigned)rblocks, (unsigned)f, (unsigned)p.sf_groups),
+                       dim3(RB), 0, st, ion_pos, ion_q, m, p.sf_ipg, s->kinfo, s->krun,
+                       s->kset.nruns, nk, ilx, ily, ilz, f, Sg);
+    if (p.sf_groups > 1) {
+      const int64_t len = 2 * nk * f;
+      hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
+                         Sg, (int)p.sf_groups, len, S);
+    }
+    const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
+    hipLaunchKernelGGL(backproject_kernel<BP_AT>, dim3((unsigned)bblocks, (unsigned)p.ksplit, (unsigned)fgroups),
+                       dim3(RB), 0, st, s->pos, n, s->kinfo, s->kw, nk, p.kper, ilx, ily, ilz, S, f,
+                       bp);
+  }
+  if (p.rs_groups > 0) {
+    hipLaunchKernelGGL(real_space_ions_kernel, dim3((unsigned)iblocks, (unsigned)f, (unsigned)p.rs_groups),
+                       dim3(RB), 0, st, s->pos, s->width, s->atom_order, n, ion_pos, ion_q, m,
+                       p.rs_ipg, s->box[0], s->box[1], s->box[2], s->beta, s->rcut, f, rs);
+  }
   hipLaunchKernelGGL(assemble_b_kernel, dim3((unsigned)((n * f + 255) / 256)), dim3(256), 0, st,
-                     part, (int)ksplit, n, f, chi, qsol_out, c0, b_out);
-  if (m > 0) {
-    hipLaunchKernelGGL(real_space_ions_kernel, dim3((unsigned)iblocks, (unsigned)f), dim3(RB), 0,
-                       st, s->pos, s->width, n, ion_pos, ion_q, m, s->box[0], s->box[1], s->box[2],
-                       s->beta, s->rcut, b_out);
-  }
+                     bp, (int)p.ksplit, rs, (int)p.rs_groups, n, f, chi, qsol_out, c0, b_out);
   return hipGetLastError();
 }
 
