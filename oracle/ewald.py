@@ -26,6 +26,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import torch
 from scipy.spatial import cKDTree
 from scipy.special import erfc, erfcinv
 
@@ -80,6 +81,26 @@ def kvectors(box, beta: float, kmax: float, half: bool = True):
     mult = 2.0 if half else 1.0
     w = mult * (4.0 * math.pi / vol) * np.exp(-k2 / (4.0 * beta * beta)) / k2
     return n, K, w
+
+
+class _Phases:
+    """cos and sin of the phases K.r of a set of points for chunks of K, in
+    float64 on PyTorch's multi-threaded CPU kernels, with the work arrays
+    allocated once (large structure-factor sums)."""
+
+    def __init__(self, rows, chunk):
+        self.ph = np.empty((rows, chunk))
+        self.c = np.empty((rows, chunk))
+        self.s = np.empty((rows, chunk))
+
+    def __call__(self, r, Kc):
+        m = Kc.shape[0]
+        ph, c, s = self.ph[:, :m], self.c[:, :m], self.s[:, :m]
+        np.matmul(r, Kc.T, out=ph)
+        t = torch.from_numpy(ph)
+        torch.cos(t, out=torch.from_numpy(c))
+        torch.sin(t, out=torch.from_numpy(s))
+        return c, s
 
 
 def _image_range(box, rcut):
@@ -222,14 +243,15 @@ def electrolyte_potential(pos, a, ion_pos, ion_q, box, beta, rcut, kmax):
     vol = float(np.prod(box))
     _, K, w = kvectors(box, beta, kmax, half=True)
     out = np.zeros((nf, n))
-    for k0 in range(0, len(K), 4096):
-        Kc, wc = K[k0:k0 + 4096], w[k0:k0 + 4096]
-        pe = pos @ Kc.T
-        ce, se = np.cos(pe), np.sin(pe)
+    chunk = 2048
+    pe, pi = _Phases(n, chunk), _Phases(ion_pos.shape[1], chunk)
+    for k0 in range(0, len(K), chunk):
+        Kc, wc = K[k0:k0 + chunk], w[k0:k0 + chunk]
+        ce, se = pe(pos, Kc)
         for f in range(nf):
-            pi_ = ion_pos[f] @ Kc.T
-            sc = ion_q[f] @ np.cos(pi_)
-            ss = ion_q[f] @ np.sin(pi_)
+            ci, si = pi(ion_pos[f], Kc)
+            sc = ion_q[f] @ ci                    # Re S(K) = sum_I q_I cos(K.r_I)
+            ss = ion_q[f] @ si                    # Im S(K)
             out[f] += ce @ (wc * sc) + se @ (wc * ss)
     for f in range(nf):
         i, I, d = real_space_pairs(pos, ion_pos[f], box, rcut)
@@ -246,28 +268,37 @@ def rhs(pos, a, ion_pos, ion_q, chi_volts, box, beta, rcut, kmax):
     return chi - bsol, np.sum(np.asarray(ion_q, dtype=np.float64), axis=-1)
 
 
-def potentials(pos, a, q, box, beta, rcut, kmax):
+def potentials(pos, a, q, box, beta, rcut, kmax, at=None):
     """Matrix-free potentials u_i = sum_j e_ij q_j of a charge configuration q
-    on the electrode atoms (the per-atom derivative of Eq. 21).
+    on the electrode atoms (the per-atom derivative of Eq. 21), at the atoms
+    ``at`` (default: all).
 
-    Reciprocal part through the structure factor S(K) = sum_j q_j exp(iK.r_j),
-    real part through the pair list, then background and self terms."""
+    Reciprocal part through the structure factor S(K) = sum_j q_j exp(iK.r_j)
+    (accumulated over chunks of K), real part through the pair list, then
+    background and self terms."""
     pos = np.asarray(pos, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     box = np.asarray(box, dtype=np.float64)
     n = len(pos)
+    idx = np.arange(n) if at is None else np.asarray(at, dtype=np.int64)
     a = np.broadcast_to(np.asarray(a, dtype=np.float64), (n,))
     vol = float(np.prod(box))
     _, K, w = kvectors(box, beta, kmax, half=True)
-    ph = pos @ K.T
-    S = q @ np.exp(1j * ph)                       # S(K)
-    u = np.real(np.exp(-1j * ph) @ (w * S))       # sum_K w Re(exp(-iK.ri) S(K))
-    i, j, d = real_space_pairs(pos, pos, box, rcut)
-    np.add.at(u, i, q[j] * _pair_potential_real(d, beta, mix_width(a[i], a[j])))
+    u = np.zeros(len(idx))
+    chunk = 2048
+    phases = _Phases(n, chunk)
+    for k0 in range(0, len(K), chunk):
+        Kc, wc = K[k0:k0 + chunk], w[k0:k0 + chunk]
+        c, s = phases(pos, Kc)
+        sr, si = q @ c, q @ s                     # S(K)
+        u += c[idx] @ (wc * sr) + s[idx] @ (wc * si)   # sum_K w Re(exp(-iK.r_i) S(K))
+    i, j, d = real_space_pairs(pos[idx], pos, box, rcut)
+    u += np.bincount(i, weights=q[j] * _pair_potential_real(d, beta, mix_width(a[idx][i], a[j])),
+                     minlength=len(idx))
     u -= math.pi / (vol * beta * beta) * float(np.sum(q))
-    aii = mix_width(a, a)
+    aii = mix_width(a[idx], a[idx])
     selfc = -2.0 * beta / math.sqrt(math.pi) + np.where(np.isinf(aii), 0.0,
                                                          2.0 * np.where(np.isinf(aii), 0.0, aii)
                                                          / math.sqrt(math.pi))
-    u += selfc * q
+    u += selfc * q[idx]
     return u

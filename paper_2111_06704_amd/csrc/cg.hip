@@ -629,13 +629,16 @@ __global__ void pack_kernel(const double *__restrict__ src, int64_t n, int64_t f
 }
 
 // Two-step neutralisation (Eq. 35): q = x - (sum(x) + Q_sol) d, one block per
-// frame; also reports |sum(q) + Q_sol|.
+// frame. The shift is applied a second time to what rounding left of
+// sum(q) + Q_sol (sum(d) = 1 holds only to ~n ulps, and sum(x) + Q_sol can be
+// large), which is the same correction along d; reports |sum(q) + Q_sol|.
 __global__ __launch_bounds__(RED_THREADS) void project_kernel(
     const double *__restrict__ x, int64_t ld, int64_t n, const double *__restrict__ d,
     const double *__restrict__ qsol, double *__restrict__ q, double *__restrict__ sum_err) {
   __shared__ double red[3][4];
   const int64_t f = blockIdx.x;
   const double *xf = x + f * ld;
+  double *qf = q + f * n;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) s += xf[i];
   s = block_sum(s, red[0]);
@@ -643,11 +646,19 @@ __global__ __launch_bounds__(RED_THREADS) void project_kernel(
   double t = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) {
     const double qi = xf[i] - shift * d[i];
-    q[f * n + i] = qi;
+    qf[i] = qi;
     t += qi;
   }
   t = block_sum(t, red[1]);
-  if (threadIdx.x == 0) sum_err[f] = fabs(t + qsol[f]);
+  const double shift2 = t + qsol[f];
+  double t2 = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) {   // each thread rereads its own q
+    const double qi = qf[i] - shift2 * d[i];
+    qf[i] = qi;
+    t2 += qi;
+  }
+  t2 = block_sum(t2, red[2]);
+  if (threadIdx.x == 0) sum_err[f] = fabs(t2 + qsol[f]);
 }
 
 __global__ void diag_inverse_kernel(const double *__restrict__ E, int64_t n, int64_t ld,

@@ -180,6 +180,23 @@ def test_solve_mixed_workload2(c2, prec_name):
     _solve_and_check(c2, prec, 1e-11, 1e-8, inner_tol=1e-2)
 
 
+def test_bench_step_workload2(c2):
+    """The step bench.py times at workload 2: FP32 E, learned warm start from
+    the committed weights, tol 1e-11, reliable-update factor 1e-2, checks
+    every 8 iterations; charges against the oracle's Cholesky solution."""
+    cpm = _cpm()
+    from paper_2111_06704_amd import warmstart
+    warmstart.load_into(c2.S, c2.geo)
+    b, qsol = c2.S.rhs(c2.t_ipos, c2.t_iq, c2.t_chi)
+    q, st = c2.S.solve(b, qsol, tol=1e-11, precision=cpm.PREC_F32, warm_start=cpm.WARM_MLP,
+                       inner_tol=1e-2, check_every=8)
+    r2, _ = ocpm.rel_errors(q.cpu().numpy(), c2.qo)
+    print(f"[bench-step] iterations {st['iterations']}, initial residual {st['initial_rel_resid']:.3f}")
+    assert r2.max() <= 1e-8
+    assert st["max_abs_sum_q"] <= 1e-12
+    assert st["fell_back"] == 0 and st["initial_rel_resid"] < 0.5
+
+
 def test_solve_ragged_frames(c1):
     """Frame counts that are not a multiple of 16 and exceed one 64-column block."""
     cpm = _cpm()
