@@ -35,6 +35,14 @@ CALIB_BYTES = 1 << 30
 KERNEL_OF_KIND = {"matvec_f64": "block_matvec_kernel<double, {ng}>",
                   "matvec_f32": "block_matvec_kernel<float, {ng}>",
                   "matvec_bf16": "block_matvec_kernel<unsigned short, {ng}>"}
+# 32..64 columns of an FP32 / BF16 E run on the split-bf16 kernel
+KERNEL_OF_KIND_WIDE = {"matvec_f64": "block_matvec_kernel<double, {ng}>",
+                       "matvec_f32": "block_matvec_split_kernel<float, {ng}>",
+                       "matvec_bf16": "block_matvec_split_kernel<unsigned short, {ng}>"}
+
+
+def kernel_name(kind, ng):
+    return (KERNEL_OF_KIND_WIDE if ng >= 2 else KERNEL_OF_KIND)[kind].format(ng=ng)
 CG_SOURCE = os.path.join(ROOT, "paper_2111_06704_amd", "csrc", "cg.hip")
 
 
@@ -109,10 +117,10 @@ def summarize_pmc(fetch_dir, write_dir, out_path):
                            "write_factor": CALIB_BYTES / (cw * 1024.0)},
            "cg_source_sha256": _sha256(CG_SOURCE), "kernels": {}}
     for name in sorted(set(fetch) | set(write)):
-        m = re.search(r"block_matvec_kernel<([^>]*)>", name)
+        m = re.search(r"(block_matvec(?:_split)?_kernel)<([^>]*)>", name)
         if not m:
             continue
-        key = "block_matvec_kernel<" + m.group(1) + ">"
+        key = m.group(1) + "<" + m.group(2) + ">"
         rec["kernels"][key] = {"dispatches": len(fetch.get(name, [])),
                                "fetch_kib": float(np.mean(fetch[name])) if name in fetch else None,
                                "write_kib": float(np.mean(write[name])) if name in write else None}
@@ -131,7 +139,7 @@ def traffic_bytes(record_path, kind, ng):
         rec = json.load(fh)
     if rec.get("cg_source_sha256") != _sha256(CG_SOURCE):
         return None
-    k = rec["kernels"].get(KERNEL_OF_KIND[kind].format(ng=ng))
+    k = rec["kernels"].get(kernel_name(kind, ng))
     if not k or k.get("fetch_kib") is None or k.get("write_kib") is None:
         return None
     c = rec["calibration"]
@@ -282,7 +290,7 @@ def main():
     traffic = traffic_bytes(rec_path, kinds[k], ng)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
-                "kernel": KERNEL_OF_KIND[kinds[k]].format(ng=ng),
+                "kernel": kernel_name(kinds[k], ng),
                 "avg_launch_us": avg_ms * 1e3, "launches": prof[k]["launches"],
                 "bytes_per_launch": bytes_per_launch,
                 "kernel_share_of_step": prof[k]["ms"] / (elapsed * 1e3)}

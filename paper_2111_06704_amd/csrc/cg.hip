@@ -274,6 +274,225 @@ __global__ __launch_bounds__(256) void block_matvec_kernel(
   }
 }
 
+// ---- block product on bf16 matrix cores (32..64 columns, FP32 or BF16 E)
+//
+// v_mfma_f32_16x16x32_bf16: lane l supplies A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16] for j = 0..7 and receives D[4 (l / 16) + v][l % 16]
+// in register v. An FP32 value x is split exactly into three bf16 parts
+// x = x0 + x1 + x2 (round to nearest, then the remainders, each exact in
+// FP32); the product of an FP32 E and an FP32 P keeps the six part products
+// whose orders add up to at most 2, which leaves an error of the order of
+// FP32 rounding. A BF16 E is one part (three products with the parts of P).
+// Workgroup: 4 waves x SP_RW row tiles of 16 rows (SP_ROWS rows) and one k
+// slice; per chunk of SP_KC columns of E the workgroup splits the matching
+// P chunk into LDS once (double buffered), each wave streams its own E rows.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+constexpr int SP_RW = 2;                     // row tiles per wave
+constexpr int SP_ROWS = 4 * 16 * SP_RW;      // rows per workgroup
+constexpr int SP_KC = 32;                    // k per chunk (one MFMA depth)
+constexpr int SP_PR = SP_KC + 8;             // LDS row length of a P part (bf16, padded)
+constexpr int SP_U = 4;                      // E chunks in flight per wave
+
+__device__ inline uint32_t cvt_bf16x2(float a, float b) {
+  const f2v v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// 8 FP32 values -> three bf16 parts (4 packed words each), x = x0 + x1 + x2
+__device__ inline void split3(const float (&x)[8], uint32_t (&w0)[4], uint32_t (&w1)[4],
+                              uint32_t (&w2)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float a = x[2 * j], b = x[2 * j + 1];
+    w0[j] = cvt_bf16x2(a, b);
+    const float ra = a - bf16_lo(w0[j]), rb = b - bf16_hi(w0[j]);
+    w1[j] = cvt_bf16x2(ra, rb);
+    const float sa = ra - bf16_lo(w1[j]), sb = rb - bf16_hi(w1[j]);
+    w2[j] = cvt_bf16x2(sa, sb);
+  }
+}
+
+__device__ inline bf16x8 as_bf16x8(const uint32_t (&w)[4]) {
+  const uint4 u = make_uint4(w[0], w[1], w[2], w[3]);
+  return __builtin_bit_cast(bf16x8, u);
+}
+__device__ inline bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
+
+__device__ inline f4 mfma_bf16(bf16x8 a, bf16x8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <typename T> struct Sp;
+template <> struct Sp<float> {
+  static constexpr int EP = 3;
+  struct Raw { float v[8]; };
+  __device__ static inline void load(const float *p, Raw &o) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+    o.v[0] = a.x; o.v[1] = a.y; o.v[2] = a.z; o.v[3] = a.w;
+    o.v[4] = b.x; o.v[5] = b.y; o.v[6] = b.z; o.v[7] = b.w;
+  }
+  // acc += E P over one chunk for one 16 x 16 block, small products first
+  __device__ static inline f4 madd(const Raw &e, const bf16x8 (&pp)[3], f4 acc) {
+    uint32_t w0[4], w1[4], w2[4];
+    split3(e.v, w0, w1, w2);
+    const bf16x8 e0 = as_bf16x8(w0), e1 = as_bf16x8(w1), e2 = as_bf16x8(w2);
+    acc = mfma_bf16(e2, pp[0], acc);
+    acc = mfma_bf16(e1, pp[1], acc);
+    acc = mfma_bf16(e0, pp[2], acc);
+    acc = mfma_bf16(e1, pp[0], acc);
+    acc = mfma_bf16(e0, pp[1], acc);
+    return mfma_bf16(e0, pp[0], acc);
+  }
+};
+template <> struct Sp<uint16_t> {
+  static constexpr int EP = 1;
+  struct Raw { uint4 w; };
+  __device__ static inline void load(const uint16_t *p, Raw &o) {
+    o.w = *reinterpret_cast<const uint4 *>(p);
+  }
+  __device__ static inline f4 madd(const Raw &e, const bf16x8 (&pp)[3], f4 acc) {
+    const bf16x8 a = as_bf16x8(e.w);
+    acc = mfma_bf16(a, pp[2], acc);
+    acc = mfma_bf16(a, pp[1], acc);
+    return mfma_bf16(a, pp[0], acc);
+  }
+};
+
+template <typename T, int NG>
+__global__ __launch_bounds__(256) void block_matvec_split_kernel(
+    const T *__restrict__ E, int64_t ld, const float *__restrict__ P, float *__restrict__ part,
+    int64_t kslice, int64_t split_stride, double *__restrict__ pv_part,
+    const int *__restrict__ gate, int *__restrict__ mark) {
+  using SP = Sp<T>;
+  constexpr int COLS = 16 * NG;
+  // one LDS buffer: the P parts during the k loop, the output tile after it
+  constexpr int PS_BYTES = 2 * 3 * COLS * SP_PR * 2;
+  constexpr int OUT_BYTES = COLS * (SP_ROWS + 1) * 4;
+  __shared__ __align__(16) unsigned char smem[PS_BYTES > OUT_BYTES ? PS_BYTES : OUT_BYTES];
+  auto ps = reinterpret_cast<uint16_t(*)[3][COLS][SP_PR]>(smem);
+  auto outs = reinterpret_cast<float(*)[SP_ROWS + 1]>(smem);
+
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  if (gate != nullptr && *gate == 0) {
+    if (mark != nullptr && first) *mark = 0;
+    return;
+  }
+  if (mark != nullptr && first) *mark = 1;
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t tile = blockIdx.x, sl = blockIdx.y;
+  const int64_t row0 = tile * SP_ROWS;
+  const int64_t kbeg = sl * kslice;
+  const int64_t kend = min(ld, kbeg + kslice);
+  const int nch = (int)((kend - kbeg) / SP_KC);
+
+  // P loader: thread -> (column, 8 consecutive k)
+  const int pcol = tid >> 2, pk = (tid & 3) * 8;
+  const bool ploader = pcol < COLS;
+  const float *pbase = P + (int64_t)(ploader ? pcol : 0) * ld + pk;
+  auto load_p = [&](int64_t k0, float (&x)[8]) {
+    const float4 a = *reinterpret_cast<const float4 *>(pbase + k0);
+    const float4 b = *reinterpret_cast<const float4 *>(pbase + k0 + 4);
+    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+    x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+  };
+  auto store_p = [&](int buf, const float (&x)[8]) {
+    uint32_t w0[4], w1[4], w2[4];
+    split3(x, w0, w1, w2);
+    *reinterpret_cast<uint4 *>(&ps[buf][0][pcol][pk]) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+    *reinterpret_cast<uint4 *>(&ps[buf][1][pcol][pk]) = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+    *reinterpret_cast<uint4 *>(&ps[buf][2][pcol][pk]) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
+  };
+
+  const T *erow[SP_RW];
+#pragma unroll
+  for (int a = 0; a < SP_RW; ++a) erow[a] = E + (row0 + wave * 16 * SP_RW + a * 16 + lr) * ld + kbeg + lg * 8;
+
+  f4 acc[SP_RW][NG];
+#pragma unroll
+  for (int a = 0; a < SP_RW; ++a)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[a][g] = f4{0, 0, 0, 0};
+
+  typename SP::Raw ring[SP_U][SP_RW];
+#pragma unroll
+  for (int u = 0; u < SP_U; ++u)
+    if (u < nch) {
+#pragma unroll
+      for (int a = 0; a < SP_RW; ++a) SP::load(erow[a] + u * SP_KC, ring[u][a]);
+    }
+  if (nch > 0 && ploader) {
+    float x[8];
+    load_p(kbeg, x);
+    store_p(0, x);
+  }
+  __syncthreads();
+
+  for (int ch0 = 0; ch0 < nch; ch0 += SP_U) {
+#pragma unroll
+    for (int u = 0; u < SP_U; ++u) {
+      const int ch = ch0 + u;
+      if (ch < nch) {
+        const int buf = u & 1;   // SP_U is even, so buf == ch & 1
+        float xn[8];
+        const bool more = ch + 1 < nch;
+        if (more && ploader) load_p(kbeg + (int64_t)(ch + 1) * SP_KC, xn);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          bf16x8 pp[3];
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            pp[q] = as_bf16x8(*reinterpret_cast<const uint4 *>(&ps[buf][q][g * 16 + lr][lg * 8]));
+#pragma unroll
+          for (int a = 0; a < SP_RW; ++a) acc[a][g] = SP::madd(ring[u][a], pp, acc[a][g]);
+        }
+        if (ch + SP_U < nch) {
+#pragma unroll
+          for (int a = 0; a < SP_RW; ++a) SP::load(erow[a] + (int64_t)(ch + SP_U) * SP_KC, ring[u][a]);
+        }
+        if (more && ploader) store_p(buf ^ 1, xn);
+        __syncthreads();
+      }
+    }
+  }
+
+  // this workgroup's partial product through LDS: coalesced rows per column
+#pragma unroll
+  for (int a = 0; a < SP_RW; ++a)
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        outs[g * 16 + lr][wave * 16 * SP_RW + a * 16 + 4 * lg + v] = acc[a][g][v];
+  __syncthreads();
+  float *out = part + sl * split_stride;
+  for (int c = tid / SP_ROWS; c < COLS; c += 256 / SP_ROWS) {
+    const int r = tid % SP_ROWS;
+    out[(int64_t)c * ld + row0 + r] = outs[c][r];
+  }
+  if (pv_part) {
+    // p.v share of the workgroup's rows: 4 threads per column, fixed order
+    constexpr int RPT = SP_ROWS / 4;
+    if (tid < COLS * 4) {
+      const int c = tid >> 2, r0 = (tid & 3) * RPT;
+      const float *pc = P + (int64_t)c * ld + row0 + r0;
+      double s = 0.0;
+      for (int r = 0; r < RPT; ++r) s += (double)pc[r] * (double)outs[c][r0 + r];
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      if ((tid & 3) == 0) pv_part[(sl * gridDim.x + tile) * COLS + c] = s;
+    }
+  }
+}
+
 // Sum over the block (RED_THREADS = 4 waves): butterfly within each wave,
 // then the four wave sums in a fixed order; every thread gets the result.
 // red must hold 4 doubles and not be reused by the caller before the next
@@ -700,20 +919,45 @@ template <typename T> int64_t matvec_slices(int64_t ld, int64_t &kslice) {
   return (ld + kslice - 1) / kslice;
 }
 
-// largest slice count of any storage type (buffer sizing)
+// k slices of the split-bf16 kernel: row tiles of SP_ROWS rows, ~1024
+// workgroups, slices a multiple of SP_KC
+int64_t split_slices(int64_t ld, int64_t &kslice) {
+  const int64_t tiles = ld / SP_ROWS;
+  const int64_t units = ld / SP_KC;
+  int64_t want = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
+  want = std::min<int64_t>(want, units);
+  kslice = (units + want - 1) / want * SP_KC;
+  return (ld + kslice - 1) / kslice;
+}
+
+// the split-bf16 kernel serves FP32 and BF16 E with 32..64 columns
+template <typename T> constexpr bool uses_split(int64_t cols) {
+  return sizeof(T) <= 4 && cols >= 32;
+}
+
+// (slice, tile) pairs of the block product for cols columns: entries of p.v
+// partials per column
+template <typename T> int64_t matvec_npv(int64_t ld, int64_t cols) {
+  int64_t k = 0;
+  if (uses_split<T>(cols)) return split_slices(ld, k) * (ld / SP_ROWS);
+  return matvec_slices<T>(ld, k) * matvec_tiles<T>(ld);
+}
+
+// largest slice count of any kernel (buffer sizing)
 int64_t max_slices(int64_t ld) {
   int64_t k = 0;
-  return std::max(matvec_slices<double>(ld, k),
-                  std::max(matvec_slices<float>(ld, k), matvec_slices<uint16_t>(ld, k)));
+  return std::max({matvec_slices<double>(ld, k), matvec_slices<float>(ld, k),
+                   matvec_slices<uint16_t>(ld, k), split_slices(ld, k)});
 }
 
 template <typename T, int NG>
 hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typename Mv<T>::VT *P,
                            typename Mv<T>::VT *part, double *pv_part, int &slices,
                            const int *gate) {
+  constexpr bool split = uses_split<T>(NG * 16);
   int64_t kslice = 0;
-  slices = (int)matvec_slices<T>(ld, kslice);
-  const int64_t tiles = matvec_tiles<T>(ld);
+  slices = split ? (int)split_slices(ld, kslice) : (int)matvec_slices<T>(ld, kslice);
+  const int64_t tiles = split ? ld / SP_ROWS : matvec_tiles<T>(ld);
   hipEvent_t ea = nullptr, eb = nullptr;
   int *mark = nullptr;
   if (t_prof && t_prof->enabled) {
@@ -725,9 +969,15 @@ hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typenam
     eb = r.b;
     if (gate) mark = t_prof->take_mark(r);
   }
-  hipExtLaunchKernelGGL((block_matvec_kernel<T, NG>), dim3((unsigned)tiles, (unsigned)slices),
-                        dim3(256), 0, st, ea, eb, 0, E, ld, P, part, kslice,
-                        (int64_t)(NG * 16) * ld, pv_part, gate, mark);
+  if constexpr (split) {
+    hipExtLaunchKernelGGL((block_matvec_split_kernel<T, NG>),
+                          dim3((unsigned)tiles, (unsigned)slices), dim3(256), 0, st, ea, eb, 0, E,
+                          ld, P, part, kslice, (int64_t)(NG * 16) * ld, pv_part, gate, mark);
+  } else {
+    hipExtLaunchKernelGGL((block_matvec_kernel<T, NG>), dim3((unsigned)tiles, (unsigned)slices),
+                          dim3(256), 0, st, ea, eb, 0, E, ld, P, part, kslice,
+                          (int64_t)(NG * 16) * ld, pv_part, gate, mark);
+  }
   return hipGetLastError();
 }
 
@@ -848,8 +1098,7 @@ template <typename T> struct Solver {
     ld = s->ld;
     cols = cols_;
     nblk = (int)((n + CHUNK - 1) / CHUNK);
-    int64_t ks = 0;
-    npv = (int)(matvec_slices<T>(ld, ks) * matvec_tiles<T>(ld));
+    npv = (int)matvec_npv<T>(ld, cols);
     Workspace &w = s->ws;
     x = (double *)w.x; r = (double *)w.r; z = (double *)w.z; b = w.bx; v64 = (double *)w.v;
     partial = w.partial;
