@@ -1,0 +1,130 @@
+"""Divide-and-conquer preconditioner of Sec. III.B.2 (PCG-DC, Eq. 36-37) in
+plain FP64 (oracle; test infrastructure only).
+
+Construction (Sec. III.B.2, steps 1-3): for each electrode atom tau
+  1. take tau and its neighbourhood, every atom (periodic image) within r_cut
+     of tau, and form the local matrix M_tau of Eq. 36 over them:
+     diagonal sqrt(2/pi) a_i, off-diagonal erfc(g r)/r - erfc(g r_cut)/r for
+     r < r_cut and 0 beyond, with r the distance between the two images;
+  2. invert M_tau; the column of M_tau^-1 that belongs to tau is written into
+     column tau of P (entries of two images of one atom add up), every other
+     entry of the column is zero;
+  3. repeat for every atom.
+Optionally the zeros of P are replaced by p_gap (Eq. 37), the mean of the
+removed entries of E^-1: p_gap = (1^T E^-1 1 - sum_ij P_ij) / n_zero.
+
+Readings (the paper is silent or ambiguous):
+  * the neighbourhood includes atoms at exactly r_cut (Fig. 2: N_cut = 21 for
+    a chain of spacing 1.5 A at r_cut = 15 A counts the atoms at 15 A); their
+    Eq. 36 coupling to tau is zero;
+  * P filled column by column is not symmetric; CG uses (P + P^T) / 2.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.spatial import cKDTree
+from scipy.special import erfc
+
+
+def neighbourhood(pos, box, rcut):
+    """For every atom: (indices, image positions) of all atoms, periodic
+    images included, with distance <= rcut (the atom itself at n = 0
+    excluded), ordered by index and then by image."""
+    pos = np.asarray(pos, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    nr = [int(math.ceil(rcut / box[d])) + 1 for d in range(3)]
+    shifts = np.array([[a, b, c] for a in range(-nr[0], nr[0] + 1)
+                       for b in range(-nr[1], nr[1] + 1)
+                       for c in range(-nr[2], nr[2] + 1)], dtype=np.float64) * box
+    imgs = (pos[None, :, :] + shifts[:, None, :]).reshape(-1, 3)
+    idx = np.tile(np.arange(len(pos)), len(shifts))
+    tree = cKDTree(imgs)
+    out = []
+    for i in range(len(pos)):
+        js = np.array(sorted(tree.query_ball_point(pos[i], rcut * (1 + 1e-12))), dtype=np.int64)
+        d = np.linalg.norm(imgs[js] - pos[i], axis=1)
+        js = js[(d > 1e-9) & (d <= rcut)]
+        order = np.lexsort((js, idx[js]))          # by atom index, then image
+        js = js[order]
+        out.append((idx[js], imgs[js]))
+    return out
+
+
+def local_matrix(X, a, g, rcut):
+    """Eq. 36 over the points X (first row tau), inverse widths a."""
+    X = np.asarray(X, dtype=np.float64)
+    d = np.linalg.norm(X[:, None, :] - X[None, :, :], axis=2)
+    M = np.zeros_like(d)
+    off = (d > 0) & (d < rcut)
+    M[off] = (erfc(g * d[off]) - erfc(g * rcut)) / d[off]
+    M[np.diag_indices(len(X))] = math.sqrt(2.0 / math.pi) * np.asarray(a, dtype=np.float64)
+    return M
+
+
+def dc_columns(n, nbhd, local):
+    """P filled column by column (step 2): nbhd[tau] = (indices, positions),
+    local(tau, indices, positions) -> M_tau with tau first."""
+    P = np.zeros((n, n))
+    for tau in range(n):
+        jj, pp = nbhd[tau]
+        M = local(tau, jj, pp)
+        e = np.zeros(len(M))
+        e[0] = 1.0
+        col = np.linalg.solve(M, e)               # column of M_tau^-1 belonging to tau
+        P[tau, tau] += col[0]
+        np.add.at(P[:, tau], jj, col[1:])
+    return P
+
+
+def dc_preconditioner(pos, box, a, g, rcut, symmetric=True):
+    """P of PCG-DC for atoms pos (inverse widths a), screening g, cutoff rcut."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = len(pos)
+    a = np.broadcast_to(np.asarray(a, dtype=np.float64), (n,))
+    nbhd = neighbourhood(pos, box, rcut)
+
+    def local(tau, jj, pp):
+        X = np.vstack([pos[tau][None, :], pp])
+        return local_matrix(X, np.concatenate([[a[tau]], a[jj]]), g, rcut)
+
+    P = dc_columns(n, nbhd, local)
+    return 0.5 * (P + P.T) if symmetric else P
+
+
+def p_gap(P, sum_einv):
+    """Eq. 37: mean of the entries of E^-1 removed by the sparsification;
+    sum_einv = 1^T E^-1 1."""
+    n_zero = int(np.count_nonzero(P == 0.0))
+    return (sum_einv - float(P.sum())) / n_zero if n_zero else 0.0
+
+
+def with_gap(P, gap):
+    """P with its zeros replaced by gap (Eq. 37)."""
+    Q = P.copy()
+    Q[P == 0.0] = gap
+    return Q
+
+
+def pcg(E, b, P, tol, max_iter=10000):
+    """Textbook preconditioned CG on E x = b with preconditioner P (dense),
+    stopped on the true residual |b - E x| <= tol |b|. Returns (x, iterations)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = P @ r
+    p = z.copy()
+    rz = r @ z
+    bn = np.linalg.norm(b)
+    for k in range(1, max_iter + 1):
+        v = E @ p
+        alpha = rz / (p @ v)
+        x += alpha * p
+        r -= alpha * v
+        if np.linalg.norm(b - E @ x) <= tol * bn:
+            return x, k
+        z = P @ r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, max_iter

@@ -1,0 +1,130 @@
+"""Pins of the PCG-DC preconditioner oracle (Sec. III.B.2, Eq. 36-37).
+
+What fixes the construction: the neighbourhood count the paper prints for
+its Fig. 2 chain; the limit where every local matrix is the whole E (then
+the column fill of step 2 must give E^-1 exactly); the closed form for
+g -> 0 (Eq. 36 has no off-diagonal then); Eq. 37's p_gap restores the sum
+of E^-1; and preconditioned CG with P reaching the Cholesky solution in
+fewer iterations than plain CG. Which P is best is a heuristic: parity
+unpinned beyond these properties.
+"""
+import json
+import math
+import os
+
+import numpy as np
+
+from oracle import cpm as ocpm
+from oracle import ewald as ew
+from oracle import precond as pc
+from paper_2111_06704_amd import workloads as wl
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
+def _small_system(n=12, seed=3):
+    rng = np.random.default_rng(seed)
+    box = np.array([9.0, 10.0, 11.0])
+    while True:
+        pos = rng.random((n, 3)) * box
+        d = np.linalg.norm(pos[:, None] - pos[None], axis=2) + np.eye(n) * 10
+        if d.min() > 1.0:
+            return pos, box
+
+
+def test_fig2_chain_neighbourhood():
+    g = GOLD["fig2_chain"]
+    L = g["box"]
+    x = np.arange(g["n_atoms"]) * (L / g["n_atoms"])
+    pos = np.stack([x, np.full_like(x, L / 2), np.full_like(x, L / 2)], axis=1)
+    nb = pc.neighbourhood(pos, np.array([L, L, L]), g["rcut"])
+    assert all(len(jj) + 1 == g["n_cut"] for jj, _ in nb)
+
+
+def test_whole_matrix_limit_gives_inverse():
+    """Local matrices equal to all of E (every atom once): P = E^-1."""
+    pos, box = _small_system()
+    km = ew.kmax_from_eps(0.5, 1e-8)
+    E = ew.ewald_matrix(pos, box, 1.2, 0.5, 6.0, km)
+    n = len(pos)
+    nbhd = [(np.array([j for j in range(n) if j != t]), None) for t in range(n)]
+
+    def local(tau, jj, pp):
+        ix = np.concatenate([[tau], jj])
+        return E[np.ix_(ix, ix)]
+
+    P = pc.dc_columns(n, nbhd, local)
+    Einv = np.linalg.inv(E)
+    assert np.max(np.abs(P - Einv)) <= 1e-12 * np.max(np.abs(Einv))
+
+
+def test_eq36_limits():
+    X = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.0, 2.0, 0], [3.0, 3.0, 0]])
+    a = np.full(4, 1.979)
+    rc = 5.0
+    M = pc.local_matrix(X, a, 0.083, rc)
+    assert np.array_equal(M, M.T)
+    assert np.allclose(np.diag(M), math.sqrt(2 / math.pi) * 1.979, rtol=0, atol=1e-15)
+    # continuity at the cutoff: the coupling vanishes as r -> r_cut
+    Y = np.array([[0.0, 0, 0], [rc * (1 - 1e-9), 0, 0]])
+    assert abs(pc.local_matrix(Y, a[:2], 0.083, rc)[0, 1]) <= 1e-9
+    # g -> 0: no off-diagonal coupling, P = diag(1 / (sqrt(2/pi) a))
+    geo = wl.geometry(1)
+    P = pc.dc_preconditioner(geo.pos, geo.box, 1.979, 1e-14, 8.0)
+    assert np.max(np.abs(P - np.eye(geo.n) / (math.sqrt(2 / math.pi) * 1.979))) <= 1e-12
+
+
+def test_images_symmetry_and_definiteness():
+    """Workload 1 (L_y = 14.76 A < 2 r_cut): some neighbourhoods hold two images
+    of one atom; the symmetrised P is symmetric positive definite."""
+    geo = wl.geometry(1)
+    prm = GOLD["pcg_dc_parameters"]
+    nb = pc.neighbourhood(geo.pos, geo.box, prm["rcut"])
+    assert any(len(np.unique(jj)) < len(jj) for jj, _ in nb)
+    P = pc.dc_preconditioner(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, prm["g"], prm["rcut"])
+    assert np.array_equal(P, P.T)
+    assert np.linalg.eigvalsh(P)[0] > 0
+
+
+def test_p_gap_restores_sum_of_inverse():
+    pos, box = _small_system(16, 5)
+    km = ew.kmax_from_eps(0.5, 1e-8)
+    E = ew.ewald_matrix(pos, box, 1.2, 0.5, 6.0, km)
+    P = pc.dc_preconditioner(pos, box, 1.2, 0.083, 3.0)
+    assert np.count_nonzero(P == 0) > 0
+    s = float(np.linalg.inv(E).sum())
+    gap = pc.p_gap(P, s)
+    assert abs(pc.with_gap(P, gap).sum() - s) <= 1e-12 * abs(s)
+
+
+def test_pcg_reaches_cholesky_solution_faster():
+    geo, ipos, iq, chi = wl.workload(1, frames=1)
+    km = ew.kmax_from_eps(wl.EWALD_SPLIT, wl.KSPACE_EPS)
+    E = ew.ewald_matrix(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, km)
+    b, _ = ew.rhs(geo.pos, wl.GAUSS_INV_WIDTH, ipos, iq, chi, geo.box, wl.EWALD_SPLIT, wl.RCUT, km)
+    b = b[0]
+    import scipy.linalg as sla
+    xo = sla.cho_solve(ocpm.cholesky(E), b)
+    prm = GOLD["pcg_dc_parameters"]
+    P = pc.dc_preconditioner(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, prm["g"], prm["rcut"])
+    x1, k1 = pc.pcg(E, b, P, 1e-12)
+    x0, k0 = pc.pcg(E, b, np.eye(geo.n) / E[0, 0], 1e-12)
+    assert np.linalg.norm(x1 - xo) <= 1e-9 * np.linalg.norm(xo)
+    assert k1 < 0.7 * k0
+
+
+def test_images_of_one_atom_add_up():
+    """Two images of atom 1 in the neighbourhood of atom 0: their entries of
+    the column of M^-1 add up in P (step 2). With M = I + c 1 1^T (m x m),
+    M^-1 e_0 = e_0 - c / (1 + c m) 1."""
+    c = 0.1
+    nbhd = [(np.array([1, 1]), None), (np.array([0]), None)]
+
+    def local(tau, jj, pp):
+        m = len(jj) + 1
+        return np.eye(m) + c * np.ones((m, m))
+
+    P = pc.dc_columns(2, nbhd, local)
+    assert math.isclose(P[1, 0], -2 * c / (1 + 3 * c), rel_tol=1e-14)
+    assert math.isclose(P[0, 0], 1 - c / (1 + 3 * c), rel_tol=1e-14)
+    assert math.isclose(P[0, 1], -c / (1 + 2 * c), rel_tol=1e-14)
