@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-11)
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--warm", default="auto", choices=["auto", "zero", "chi", "mlp"])
+    ap.add_argument("--precond", default="dc", choices=["jacobi", "dc"],
+                    help="preconditioner of the timed solves (the FP64 reference is plain CG)")
+    ap.add_argument("--dc-g", type=float, default=0.083, help="PCG-DC screening g (1/A)")
+    ap.add_argument("--dc-rcut", type=float, default=8.0, help="PCG-DC cutoff (A)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2111_06704_amd", "weights",
                                                       "warmstart_cfg2.npz"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -231,34 +235,50 @@ def main():
     else:
         wmode = cpm.WARM_ZERO
 
-    def step(precision, wm, qout):
+    pcmode = cpm.PRECOND_DC if args.precond == "dc" else cpm.PRECOND_JACOBI
+    precond_build_s = None
+    if pcmode == cpm.PRECOND_DC:
+        t0 = time.perf_counter()
+        S.precond_dc(args.dc_g, args.dc_rcut)
+        precond_build_s = time.perf_counter() - t0
+        log(f"PCG-DC preconditioner built in {precond_build_s:.2f} s")
+
+    def step(precision, wm, qout, pcm=pcmode):
         S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
         return S.solve(b, qsol, tol=args.tol, precision=precision, warm_start=wm, inner_tol=1e-2,
-                       check_every=8, q_out=qout)
+                       check_every=8, q_out=qout, preconditioner=pcm)
 
     # reference: plain FP64 CG from zero at the same tolerance
     q64 = torch.empty_like(b)
     for _ in range(max(1, args.warmup)):
-        step(cpm.PREC_F64, cpm.WARM_ZERO, q64)
+        step(cpm.PREC_F64, cpm.WARM_ZERO, q64, cpm.PRECOND_JACOBI)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     n64 = max(3, args.steps // 2)
     for _ in range(n64):
-        _, st64 = step(cpm.PREC_F64, cpm.WARM_ZERO, q64)
+        _, st64 = step(cpm.PREC_F64, cpm.WARM_ZERO, q64, cpm.PRECOND_JACOBI)
     torch.cuda.synchronize()
     fp64_ms = (time.perf_counter() - t0) / n64 * 1e3
 
     # every precision mode once (same tolerance), for the record
     modes = {}
-    for name, pm, wm in (("f64_zero", cpm.PREC_F64, cpm.WARM_ZERO), ("f32_zero", cpm.PREC_F32, cpm.WARM_ZERO),
-                         ("bf16_zero", cpm.PREC_BF16, cpm.WARM_ZERO), (f"f32_{warm}", cpm.PREC_F32, wmode),
-                         (f"bf16_{warm}", cpm.PREC_BF16, wmode)):
+    mode_list = [("f64_zero", cpm.PREC_F64, cpm.WARM_ZERO, cpm.PRECOND_JACOBI),
+                 ("f32_zero", cpm.PREC_F32, cpm.WARM_ZERO, cpm.PRECOND_JACOBI),
+                 ("bf16_zero", cpm.PREC_BF16, cpm.WARM_ZERO, cpm.PRECOND_JACOBI),
+                 (f"f32_{warm}", cpm.PREC_F32, wmode, cpm.PRECOND_JACOBI),
+                 (f"bf16_{warm}", cpm.PREC_BF16, wmode, cpm.PRECOND_JACOBI)]
+    if pcmode == cpm.PRECOND_DC:
+        mode_list += [("f64_zero_dc", cpm.PREC_F64, cpm.WARM_ZERO, pcmode),
+                      ("f32_zero_dc", cpm.PREC_F32, cpm.WARM_ZERO, pcmode),
+                      (f"f32_{warm}_dc", cpm.PREC_F32, wmode, pcmode),
+                      (f"bf16_{warm}_dc", cpm.PREC_BF16, wmode, pcmode)]
+    for name, pm, wm, pcm in mode_list:
         if (pm == cpm.PREC_F32 and "f32" not in store) or (pm == cpm.PREC_BF16 and "bf16" not in store):
             continue
-        step(pm, wm, q)
+        step(pm, wm, q, pcm)
         torch.cuda.synchronize()
         tm = time.perf_counter()
-        _, sm = step(pm, wm, q)
+        _, sm = step(pm, wm, q, pcm)
         torch.cuda.synchronize()
         modes[name] = {"solves_per_s": nf / (time.perf_counter() - tm), "iterations": sm["iterations"],
                        "true_residual_updates": sm["outer"], "initial_rel_resid": sm["initial_rel_resid"]}
@@ -318,7 +338,9 @@ def main():
                                f"{nf} frames x {m} ions",
                    "n_electrode": geo.n, "frames_per_step": nf, "ions": m,
                    "n_kvec": desc["n_kvec"], "tol": args.tol, "precision": args.precision,
-                   "warm_start": warm},
+                   "warm_start": warm, "preconditioner": args.precond,
+                   "dc_g": args.dc_g if args.precond == "dc" else None,
+                   "dc_rcut": args.dc_rcut if args.precond == "dc" else None},
         "fp64_cg_solves_per_s": nf / (fp64_ms * 1e-3),
         "fp64_cg_iterations": st64["iterations"],
         "speedup_vs_fp64_cg": value / (nf / (fp64_ms * 1e-3)),
@@ -328,7 +350,7 @@ def main():
         "charge_rel_err_vs_fp64_gpu": rel_vs_fp64,
         "e_assembly_gflops": asm_gflops, "e_assembly_ms": prof_build["ms"],
         "e_assembly_frac_fp64_peak": (asm_gflops / 1e3 / FP64_PEAK_TFLOPS) if asm_gflops else None,
-        "e_build_s": build_s,
+        "e_build_s": build_s, "precond_build_s": precond_build_s,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

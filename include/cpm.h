@@ -120,6 +120,7 @@ cpm_status cpm_rhs(cpm_system *s, const double *ion_pos_dev, const double *ion_q
 
 enum { CPM_PREC_F64 = 0, CPM_PREC_F32 = 1, CPM_PREC_BF16 = 2 };
 enum { CPM_WARM_ZERO = 0, CPM_WARM_CHI = 1, CPM_WARM_MLP = 2 };
+enum { CPM_PRECOND_JACOBI = 0, CPM_PRECOND_DC = 1 };
 
 typedef struct {
   double tol;          /* stop when |b - E q_b|_2 <= tol |b|_2 (true FP64 residual) */
@@ -129,8 +130,13 @@ typedef struct {
                           FP64 residual b - E q on the FP64 E                      */
   int warm_start;      /* CPM_WARM_*: zero, the no-electrolyte solution q_chi, or
                           the network prediction                                   */
-  double inner_tol;    /* relative tolerance of each inner solve (mixed), e.g. 1e-3 */
-  int check_every;     /* host convergence check period in iterations (>= 1)       */
+  double inner_tol;    /* reliable-update factor (mixed): the FP64 true residual
+                          replaces the recursive one once the latter has fallen by
+                          this factor, e.g. 1e-2                                   */
+  int check_every;     /* iterations between the device-side convergence checks
+                          (>= 1)                                                   */
+  int preconditioner;  /* CPM_PRECOND_JACOBI (diag E) or CPM_PRECOND_DC (the PCG-DC
+                          matrix of cpm_precond_dc, Sec. III.B.2)                   */
 } cpm_solve_opts;
 
 typedef struct {
@@ -151,11 +157,31 @@ typedef struct {
  *   b_dev (f, n), qsol_dev (f,), q_out_dev (f, n): device pointers.
  * q_out[f] = q_b - (1^T q_b + Q_sol[f]) d with E q_b = b[f] (Eq. 35),
  * d = d' / 1^T d'. Errors: CPM_EINVAL (pointers, f < 1, tol <= 0, unknown
- * precision, precision not stored), CPM_ESTATE (CPM_WARM_MLP without a
- * network), CPM_ENOTSPD (breakdown), CPM_ENOTCONV (q_out then holds the
- * projected last iterate). info may be NULL. */
+ * precision or preconditioner, precision not stored), CPM_ESTATE
+ * (CPM_WARM_MLP without a network, CPM_PRECOND_DC before cpm_precond_dc),
+ * CPM_ENOTSPD (breakdown), CPM_ENOTCONV (q_out then holds the projected last
+ * iterate). info may be NULL. */
 cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
                      const cpm_solve_opts *opts, double *q_out_dev, cpm_solve_info *info);
+
+/* ---- PCG-DC preconditioner (Sec. III.B.2, Eq. 36) --------------------------
+ * For every atom tau: the local matrix M_tau of Eq. 36 over tau and every atom
+ * image within rcut of it (distance <= rcut),
+ *   m_ii = sqrt(2/pi) a_i,
+ *   m_ij = [erfc(g r_ij) - erfc(g rcut)] / r_ij  (r_ij < rcut), 0 otherwise,
+ * with r_ij the distance of the two images; the column of M_tau^-1 belonging
+ * to tau becomes column tau of P (entries of images of one atom add up, zero
+ * beyond rcut). The solver uses the symmetric part (P + P^T) / 2. Built once
+ * per system (local FP64 Cholesky factorisations on host threads), kept on
+ * the device in ELL form; cpm_solve applies it with CPM_PRECOND_DC. The
+ * paper's choice for graphene electrodes is g = 0.083 / A, rcut = 8 A.
+ * Errors: CPM_EINVAL (g or rcut not finite and > 0, point-charge atoms),
+ * CPM_ENOTSPD (a local matrix is not positive definite), CPM_ENOMEM. */
+cpm_status cpm_precond_dc(cpm_system *s, double screening_g, double rcut);
+
+/* z = P r for f vectors, r_dev and z_dev (f, n) device arrays: the solver's
+   own apply kernel (tests). CPM_ESTATE before cpm_precond_dc. */
+cpm_status cpm_precond_apply(cpm_system *s, const double *r_dev, int64_t f, double *z_dev);
 
 /* Copy E (caller's atom order) into dst_dev with leading dimension ld >= n,
    in the requested precision (FP64 double, FP32 float, BF16 uint16 bits).

@@ -20,6 +20,7 @@ CPM_OK, CPM_EINVAL, CPM_ENOMEM, CPM_EDEVICE, CPM_ENOTSPD, CPM_ENOTCONV, CPM_ESTA
 STORE_F32, STORE_BF16 = 1, 2
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 WARM_ZERO, WARM_CHI, WARM_MLP = 0, 1, 2
+PRECOND_JACOBI, PRECOND_DC = 0, 1
 MLP_IN, MLP_HIDDEN = 26, 64
 MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 
@@ -28,7 +29,8 @@ EXPORTS = [
     "cpm_get_E", "cpm_get_dprime", "cpm_matvec", "cpm_mlp_init", "cpm_mlp_neighbours",
     "cpm_mlp_set_params", "cpm_mlp_get_params", "cpm_mlp_features", "cpm_mlp_forward",
     "cpm_mlp_loss_grad", "cpm_mlp_train_step", "cpm_mlp_train_epoch", "cpm_set_warm_chi",
-    "cpm_profile_enable", "cpm_profile_read", "cpm_status_str", "cpm_last_error",
+    "cpm_profile_enable", "cpm_profile_read", "cpm_precond_dc", "cpm_precond_apply",
+    "cpm_status_str", "cpm_last_error",
 ]
 PROFILE_BUILD = 4
 
@@ -47,7 +49,8 @@ class Params(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int),
-                ("warm_start", C.c_int), ("inner_tol", C.c_double), ("check_every", C.c_int)]
+                ("warm_start", C.c_int), ("inner_tol", C.c_double), ("check_every", C.c_int),
+                ("preconditioner", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -213,14 +216,15 @@ class System:
         return b_out, qsol_out
 
     def solve(self, b, qsol, tol=1e-10, max_iter=5000, precision=PREC_F64, warm_start=WARM_ZERO,
-              inner_tol=1e-3, check_every=8, q_out=None, allow_notconv=False):
+              inner_tol=1e-3, check_every=8, q_out=None, allow_notconv=False,
+              preconditioner=PRECOND_JACOBI):
         """Electrode charges (F, N) and a dict of solve statistics."""
         import torch
         f = int(b.shape[0])
         if q_out is None:
             q_out = torch.empty_like(b)
         o = SolveOpts(tol=tol, max_iter=max_iter, precision=precision, warm_start=warm_start,
-                      inner_tol=inner_tol, check_every=check_every)
+                      inner_tol=inner_tol, check_every=check_every, preconditioner=preconditioner)
         fit = (C.c_int * f)()
         frr = (C.c_double * f)()
         info = SolveInfo()
@@ -257,10 +261,23 @@ class System:
                                 _ptr(v, torch.float64)), "cpm_matvec")
         return v
 
-    def set_warm_chi(self, chi, tol=1e-12, max_iter=5000):
+    def precond_dc(self, screening_g=0.083, rcut=8.0):
+        """Build the PCG-DC preconditioner (Sec. III.B.2, Eq. 36)."""
+        _check(lib().cpm_precond_dc(self._h, C.c_double(screening_g), C.c_double(rcut)),
+               "cpm_precond_dc")
+
+    def precond_apply(self, r):
+        """z = P r for vectors r (F, N) on the device."""
+        import torch
+        z = torch.empty_like(r)
+        _check(lib().cpm_precond_apply(self._h, _ptr(r, torch.float64), int(r.shape[0]),
+                                       _ptr(z, torch.float64)), "cpm_precond_apply")
+        return z
+
+    def set_warm_chi(self, chi, tol=1e-12, max_iter=5000, preconditioner=PRECOND_JACOBI):
         import torch
         o = SolveOpts(tol=tol, max_iter=max_iter, precision=PREC_F64, warm_start=WARM_ZERO,
-                      inner_tol=1e-3, check_every=8)
+                      inner_tol=1e-3, check_every=8, preconditioner=preconditioner)
         _check(lib().cpm_set_warm_chi(self._h, _ptr(chi, torch.float64), C.byref(o)), "cpm_set_warm_chi")
 
     # ---- learned warm start

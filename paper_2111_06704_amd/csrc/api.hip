@@ -137,6 +137,7 @@ void free_system(cpm_system *s) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   release_workspace(s);
+  free_precond(s->pc);
   s->prof.reset();
   for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);
   if (s->prof.marks) (void)hipFree(s->prof.marks);
@@ -287,6 +288,7 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
   s->kset = make_kset(box_host, beta, kmax);
   s->prof.enabled = (params->store_mask & CPM_PROFILE_BUILD) != 0;
   s->pos_host = pos;
+  s->width_host = width;
   const int64_t ld = s->ld, nk = s->kset.nk;
   hipStream_t st = s->stream;
 
@@ -482,6 +484,14 @@ cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev,
   if (o.max_iter < 1) {
     set_error("max_iter must be >= 1");
     return CPM_EINVAL;
+  }
+  if (o.preconditioner != CPM_PRECOND_JACOBI && o.preconditioner != CPM_PRECOND_DC) {
+    set_error("unknown preconditioner");
+    return CPM_EINVAL;
+  }
+  if (o.preconditioner == CPM_PRECOND_DC && !s->pc.ready) {
+    set_error("CPM_PRECOND_DC: call cpm_precond_dc first");
+    return CPM_ESTATE;
   }
   if (o.precision == CPM_PREC_F32 && !s->E32) {
     set_error("FP32 copy of E not stored (store_mask)");

@@ -606,24 +606,31 @@ __global__ __launch_bounds__(RED_THREADS) void cg_refresh_kernel(
 }
 
 // Reduce (rr, rz) partials into the scalars of active columns.
-__global__ void set_scalars_kernel(const double *__restrict__ partial, int nblk, int cols,
-                                   double *__restrict__ scal, int slot,
-                                   const int *__restrict__ gate) {
+// one workgroup per column
+__global__ __launch_bounds__(RED_THREADS) void set_scalars_kernel(
+    const double *__restrict__ partial, int nblk, int cols, double *__restrict__ scal, int slot,
+    const int *__restrict__ gate) {
+  __shared__ double red[3][4];
   if (gate != nullptr && *gate == 0) return;
-  const int c = threadIdx.x;
-  if (c >= cols) return;
+  const int c = blockIdx.x;
   if (scal[S_ACT * cols + c] == 0.0) return;
   double rr = 0.0, rz = 0.0;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = threadIdx.x; b < nblk; b += RED_THREADS) {
     rr += partial[((int64_t)b * cols + c) * 2];
     rz += partial[((int64_t)b * cols + c) * 2 + 1];
   }
-  scal[S_RR * cols + c] = rr;
-  scal[(S_RZ0 + slot) * cols + c] = rz;
+  rr = block_sum(rr, red[0]);
+  rz = block_sum(rz, red[1]);
+  if (threadIdx.x == 0) {
+    scal[S_RR * cols + c] = rr;
+    scal[(S_RZ0 + slot) * cols + c] = rz;
+  }
 }
 
-// alpha = rz / p.v; x += alpha p; r -= alpha v; z = M^-1 r; partial rr, rz.
-template <typename VT>
+// alpha = rz / p.v; x += alpha p; r -= alpha v. Jacobi (JAC): also z = M^-1 r
+// and the partial rr, rz; otherwise the preconditioner kernel that follows
+// computes z and the partials.
+template <typename VT, bool JAC>
 __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
     double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
     const VT *__restrict__ p, const VT *__restrict__ vpart, int slices, int64_t stride,
@@ -658,17 +665,88 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
       x[idx] += alpha * (double)p[idx];
       const double ri = r[idx] - alpha * sum_slices(vpart, slices, stride, idx);
       r[idx] = ri;
-      const double zi = ri * dinv[i];
-      z[idx] = zi;
-      arr += ri * ri;
-      arz += ri * zi;
+      if constexpr (JAC) {
+        const double zi = ri * dinv[i];
+        z[idx] = zi;
+        arr += ri * ri;
+        arz += ri * zi;
+      }
     }
   }
-  arr = block_sum(arr, red[1]);
-  arz = block_sum(arz, red[2]);
-  if (threadIdx.x == 0) {
-    partial[((int64_t)blk * cols + c) * 2] = arr;
-    partial[((int64_t)blk * cols + c) * 2 + 1] = arz;
+  if constexpr (JAC) {
+    arr = block_sum(arr, red[1]);
+    arz = block_sum(arz, red[2]);
+    if (threadIdx.x == 0) {
+      partial[((int64_t)blk * cols + c) * 2] = arr;
+      partial[((int64_t)blk * cols + c) * 2 + 1] = arz;
+    }
+  }
+}
+
+// PCG-DC apply (Sec. III.B.2): z = P r with P in row-major ELL form (entry k
+// of row i at i * width + k). One wavefront per row (rows taken in the
+// spatial order), its lanes over the row's entries, 16 columns per wavefront
+// (grid.y = column group). Active columns only (scal == nullptr: all);
+// set_p: p = z. bpart (may be null): per workgroup and column (r.r, r.z),
+// summed by the kernels that need the totals.
+constexpr int PC_ROWS = RED_THREADS / 64;   // rows per workgroup
+
+template <typename VT>
+__global__ __launch_bounds__(RED_THREADS) void precond_kernel(
+    const double *__restrict__ r, double *__restrict__ z, VT *__restrict__ p,
+    const int32_t *__restrict__ pidx, const double *__restrict__ pval, int width,
+    const int32_t *__restrict__ order, int64_t ld, int64_t n, int cols,
+    const double *__restrict__ scal, double *__restrict__ bpart, int set_p,
+    const int *__restrict__ gate) {
+  __shared__ double red[PC_ROWS][kColGroup][2];
+  if (gate != nullptr && *gate == 0) return;
+  const int g = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * PC_ROWS + wave;
+  const int64_t i = t < n ? (int64_t)order[t] : -1;
+  const double *rg = r + (int64_t)g * kColGroup * ld;
+  double acc[kColGroup];
+#pragma unroll
+  for (int c = 0; c < kColGroup; ++c) acc[c] = 0.0;
+  if (i >= 0) {
+    for (int k = lane; k < width; k += 64) {
+      const int64_t j = pidx[i * width + k];
+      const double v = pval[i * width + k];
+#pragma unroll
+      for (int c = 0; c < kColGroup; ++c) acc[c] += v * rg[c * ld + j];
+    }
+  }
+  // lane c < 16 ends with column c's sum
+  double zc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kColGroup; ++c) {
+    const double sum = wave_sum(acc[c]);
+    if (lane == c) zc = sum;
+  }
+  double rr = 0.0, rz = 0.0;
+  if (lane < kColGroup && i >= 0) {
+    const int col = g * kColGroup + lane;
+    if (scal == nullptr || scal[S_ACT * cols + col] != 0.0) {
+      const int64_t idx = (int64_t)col * ld + i;
+      const double ri = r[idx];
+      z[idx] = zc;
+      if (set_p) p[idx] = (VT)zc;
+      rr = ri * ri;
+      rz = ri * zc;
+    }
+  }
+  if (bpart == nullptr) return;
+  if (lane < kColGroup) {
+    red[wave][lane][0] = rr;
+    red[wave][lane][1] = rz;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kColGroup) {
+    const int c = threadIdx.x >> 1, s2 = threadIdx.x & 1;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < PC_ROWS; ++w) v += red[w][c][s2];
+    bpart[((int64_t)blockIdx.x * cols + g * kColGroup + c) * 2 + s2] = v;
   }
 }
 
@@ -677,15 +755,17 @@ template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
     VT *__restrict__ p, const double *__restrict__ z, int64_t ld, int64_t n, int cols, int nblk,
     const double *__restrict__ partial, double *__restrict__ scal, int slot) {
+  __shared__ double red[3][4];
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
   if (scal[S_ACT * cols + c] == 0.0) return;
   double rr = 0.0, rzn = 0.0;
-#pragma unroll 8
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = threadIdx.x; b < nblk; b += RED_THREADS) {
     rr += partial[((int64_t)b * cols + c) * 2];
     rzn += partial[((int64_t)b * cols + c) * 2 + 1];
   }
+  rr = block_sum(rr, red[0]);
+  rzn = block_sum(rzn, red[1]);
   const double rz = scal[(S_RZ0 + slot) * cols + c];
   const double beta = (rz != 0.0) ? rzn / rz : 0.0;
   const int64_t i0 = (int64_t)blk * CHUNK;
@@ -998,7 +1078,7 @@ hipError_t launch_matvec(hipStream_t st, const T *E, int64_t ld, int64_t cols,
 
 void free_workspace(Workspace &w) {
   void *ptrs[] = {w.x, w.r, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.bx, w.bres, w.flags,
-                  w.xf, w.rf, w.pf, w.zf, w.vf};
+                  w.xf, w.rf, w.pf, w.zf, w.vf, w.bpart};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   if (w.hstat) (void)hipHostFree(w.hstat);
@@ -1033,6 +1113,8 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
             alloc(&w.pf, vec / 2) && alloc(&w.vf, vec / 2 * (size_t)nsl) &&
             alloc((void **)&w.partial, sizeof(double) * 2 * (size_t)(nblk + npv) * cols) &&
             alloc((void **)&w.scal, sizeof(double) * S_NFIELDS * cols) &&
+            alloc((void **)&w.bpart,
+                  sizeof(double) * 2 * (size_t)((s->n + PC_ROWS - 1) / PC_ROWS) * cols) &&
             alloc((void **)&w.flags, sizeof(int) * F_NWORDS);
   if (ok && hipHostMalloc((void **)&w.hstat, sizeof(int) * F_NWORDS * kStatusSlots,
                           hipHostMallocDefault) != hipSuccess) {
@@ -1092,8 +1174,10 @@ template <typename T> struct Solver {
   VT *p, *v;
   int *flags;
   int slot = 0;
+  const Precond *pc = nullptr;   // PCG-DC preconditioner (nullptr: Jacobi)
 
-  Solver(cpm_system *s_, const T *E_, int64_t cols_) : s(s_), st(s_->stream), E(E_) {
+  Solver(cpm_system *s_, const T *E_, int64_t cols_, const Precond *pc_)
+      : s(s_), st(s_->stream), E(E_), pc(pc_) {
     n = s->n;
     ld = s->ld;
     cols = cols_;
@@ -1128,12 +1212,29 @@ template <typename T> struct Solver {
     return hipGetLastError();
   }
 
+  // partial sums of r.r / r.z per column that the direction and set_scalars
+  // kernels add up: one per vector block (Jacobi) or per preconditioner
+  // workgroup (DC)
+  int npc() const { return (int)((n + PC_ROWS - 1) / PC_ROWS); }
+  int nred() const { return pc ? npc() : nblk; }
+  const double *dots() const { return pc ? s->ws.bpart : partial; }
+
+  // z = P r with the DC preconditioner
+  void precondition(bool set_p, const int *gate) {
+    hipLaunchKernelGGL(precond_kernel<VT>, dim3((unsigned)npc(), (unsigned)(cols / kColGroup)),
+                       dim3(RED_THREADS), 0, st, r, z, p, pc->idx, pc->val, pc->width,
+                       s->atom_order, ld, n, (int)cols, scal, s->ws.bpart, set_p ? 1 : 0, gate);
+  }
+
   // z = M^-1 r (and p = z when restarting); rz into the current slot
   hipError_t refresh(bool set_p, const int *gate) {
-    hipLaunchKernelGGL(cg_refresh_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, r, z, p, s->dinv,
-                       ld, n, (int)cols, scal, partial, set_p ? 1 : 0, gate);
-    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(MAX_COLS), 0, st, partial, nblk,
-                       (int)cols, scal, slot, gate);
+    if (pc)
+      precondition(set_p, gate);
+    else
+      hipLaunchKernelGGL(cg_refresh_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, r, z, p, s->dinv,
+                         ld, n, (int)cols, scal, partial, set_p ? 1 : 0, gate);
+    hipLaunchKernelGGL(set_scalars_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, dots(),
+                       nred(), (int)cols, scal, slot, gate);
     return hipGetLastError();
   }
 
@@ -1142,10 +1243,18 @@ template <typename T> struct Solver {
     int sl = 0;
     hipError_t e = launch_matvec<T>(st, E, ld, cols, p, v, pvp, sl, flags + F_ANY);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cg_update_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, x, r, z, p, v, sl,
-                       ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial, flags);
+    if (pc) {
+      hipLaunchKernelGGL((cg_update_kernel<VT, false>), grid(), dim3(RED_THREADS), 0, st, x, r, z, p,
+                         v, sl, ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial,
+                         flags);
+      precondition(false, flags + F_ANY);
+    } else {
+      hipLaunchKernelGGL((cg_update_kernel<VT, true>), grid(), dim3(RED_THREADS), 0, st, x, r, z, p,
+                         v, sl, ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial,
+                         flags);
+    }
     hipLaunchKernelGGL(cg_direction_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, p, z, ld, n,
-                       (int)cols, nblk, partial, scal, slot);
+                       (int)cols, nred(), dots(), scal, slot);
     slot ^= 1;
     return hipGetLastError();
   }
@@ -1170,7 +1279,7 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
                       cpm_solve_info *info, std::vector<int> &frame_iters,
                       std::vector<double> &frame_res, bool x_zero) {
   const int64_t cols = round_up(fc, kColGroup);
-  Solver<T> sv(s, E, cols);
+  Solver<T> sv(s, E, cols, o.preconditioner == CPM_PRECOND_DC ? &s->pc : nullptr);
   hipStream_t st = s->stream;
   Workspace &w = s->ws;
   const bool f64 = sizeof(T) == 8;
@@ -1312,6 +1421,7 @@ cpm_status solve_dprime(cpm_system *s, double tol, int max_iter) {
   o.max_iter = max_iter;
   o.precision = CPM_PREC_F64;
   o.check_every = 16;
+  o.preconditioner = s->pc.ready ? CPM_PRECOND_DC : CPM_PRECOND_JACOBI;
   std::vector<int> it(kColGroup, 0);
   std::vector<double> res(kColGroup, 0.0);
   stt = solve_columns(s, 1, o, nullptr, it, res, true);
@@ -1425,6 +1535,29 @@ cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_
     }
     out = res;
     CPM_HIP_CHECK(hipMemcpy2DAsync(v_dev + f0 * n, sizeof(double) * n, out, sizeof(double) * ld,
+                                   sizeof(double) * n, fc, hipMemcpyDeviceToDevice, st));
+  }
+  CPM_HIP_CHECK(hipGetLastError());
+  return CPM_OK;
+}
+
+cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z_dev) {
+  hipStream_t st = s->stream;
+  const int64_t ld = s->ld, n = s->n;
+  for (int64_t f0 = 0; f0 < f; f0 += MAX_COLS) {
+    const int fc = (int)std::min<int64_t>(MAX_COLS, f - f0);
+    const int64_t cols = round_up(fc, kColGroup);
+    cpm_status stt = ensure_workspace(s, cols);
+    if (stt != CPM_OK) return stt;
+    double *in = s->ws.bres, *out = s->ws.bx;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)cols), dim3(256),
+                       0, st, r_dev + f0 * n, n, (int64_t)fc, in, ld, cols);
+    hipLaunchKernelGGL(precond_kernel<double>,
+                       dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
+                       dim3(RED_THREADS), 0, st, (const double *)in, out, (double *)nullptr,
+                       s->pc.idx, s->pc.val, s->pc.width, s->atom_order, ld, n, (int)cols,
+                       (const double *)nullptr, (double *)nullptr, 0, (const int *)nullptr);
+    CPM_HIP_CHECK(hipMemcpy2DAsync(z_dev + f0 * n, sizeof(double) * n, out, sizeof(double) * ld,
                                    sizeof(double) * n, fc, hipMemcpyDeviceToDevice, st));
   }
   CPM_HIP_CHECK(hipGetLastError());

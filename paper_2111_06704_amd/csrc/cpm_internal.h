@@ -50,6 +50,7 @@ struct Workspace {            // CG scratch, grown on demand
   // padding rows (>= n) are always zero
   void *xf = nullptr, *rf = nullptr, *pf = nullptr, *zf = nullptr, *vf = nullptr;
   double *partial = nullptr;  // dot partial sums: 2*nblk*cols
+  double *bpart = nullptr;    // per-workgroup dot partials of the preconditioner apply
   double *scal = nullptr;     // per-column scalars, see cg.hip
   double *bx = nullptr;       // n_pad*cols double: right-hand sides / outer iterate
   double *bres = nullptr;     // n_pad*cols double: outer residual
@@ -59,6 +60,18 @@ struct Workspace {            // CG scratch, grown on demand
   size_t bytes = 0;
 };
 constexpr int kStatusSlots = 2;
+
+struct Precond {              // PCG-DC preconditioner (P + P^T) / 2 in ELL form
+  bool ready = false;
+  double g = 0, rcut = 0;     // screening and cutoff of Eq. 36
+  int width = 0;              // entries per row (padded with (i, 0))
+  int max_local = 0;          // largest local matrix
+  int64_t nnz = 0;
+  int32_t *idx = nullptr;     // n * width: column of entry k of row i at i * width + k
+  double *val = nullptr;      // width * n
+  int64_t bytes = 0;           // device memory held
+};
+void free_precond(Precond &p);
 
 struct Mlp {
   bool ready = false;
@@ -140,6 +153,8 @@ struct cpm_system {
   std::vector<double> pos_host;   // n*3 wrapped positions (host copy)
   cpm::Workspace ws;
   cpm::Mlp mlp;
+  cpm::Precond pc;
+  std::vector<double> width_host;   // n Gaussian inverse widths (host copy)
   cpm::Profile prof;
   int64_t device_bytes = 0;
 };
@@ -171,6 +186,8 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
 cpm_status solve_dprime(cpm_system *s, double tol, int max_iter);
 cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_t f,
                        double *v_dev);
+// z = P r (PCG-DC preconditioner) for f vectors (f, n), the CG's own apply kernel
+cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z_dev);
 hipError_t launch_diag_inverse(hipStream_t st, const double *E, int64_t n, int64_t ld,
                                double *dinv);
 

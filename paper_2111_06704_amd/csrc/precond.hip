@@ -1,0 +1,299 @@
+// PCG-DC preconditioner (Sec. III.B.2, Eq. 36): construction.
+//
+// For every atom tau the local matrix M_tau over tau and its neighbourhood
+// (every atom image within rcut) is formed from Eq. 36, factorised
+// (Cholesky, FP64), and the column of M_tau^-1 belonging to tau becomes
+// column tau of P; entries of different images of one atom add up. CG needs
+// a symmetric preconditioner, so the device copy holds (P + P^T) / 2 in
+// row-major ELL form: entry k of row i at i * width + k (column index,
+// value), rows padded with (i, 0). The construction runs once per system on host threads (a few
+// hundred local factorisations of size ~ 200 per thread); the apply z = P r
+// of every PCG iteration runs on the device (cg.hip).
+#include "cpm_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <string>
+#include <thread>
+
+namespace cpm {
+namespace {
+
+struct Image {
+  int32_t atom;
+  int32_t shift;   // packed periodic shift, 0-based per axis
+  double x, y, z;
+};
+
+// worker threads for the construction: at most 16 (the host share of one
+// GPU), fewer if OMP_NUM_THREADS or the hardware says so
+int build_threads() {
+  int t = (int)std::thread::hardware_concurrency();
+  if (t < 1) t = 1;
+  if (const char *e = std::getenv("OMP_NUM_THREADS")) {
+    const int v = std::atoi(e);
+    if (v >= 1) t = std::min(t, v);
+  }
+  return std::min(t, 16);
+}
+
+template <typename F> void parallel_for(int64_t count, F &&body) {
+  const int nt = (int)std::min<int64_t>(build_threads(), std::max<int64_t>(1, count));
+  std::atomic<int64_t> next{0};
+  auto worker = [&](int tid) {
+    for (;;) {
+      const int64_t i = next.fetch_add(1);
+      if (i >= count) break;
+      body(i, tid);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker, t);
+  worker(0);
+  for (std::thread &th : pool) th.join();
+}
+
+// Neighbourhood of every atom: all images within rc (distance <= rc), the
+// atom itself at zero shift excluded, ordered by atom index then shift.
+std::vector<std::vector<Image>> neighbourhoods(const std::vector<double> &pos, int64_t n,
+                                               const double box[3], double rc) {
+  int nr[3];
+  for (int d = 0; d < 3; ++d) nr[d] = (int)std::ceil(rc / box[d]) + 1;
+  const int w1 = 2 * nr[1] + 1, w2 = 2 * nr[2] + 1;
+  const int zero_shift = (nr[0] * w1 + nr[1]) * w2 + nr[2];
+  std::vector<Image> imgs;
+  for (int a = -nr[0]; a <= nr[0]; ++a)
+    for (int b = -nr[1]; b <= nr[1]; ++b)
+      for (int c = -nr[2]; c <= nr[2]; ++c)
+        for (int64_t i = 0; i < n; ++i) {
+          const double x = pos[3 * i] + a * box[0], y = pos[3 * i + 1] + b * box[1],
+                       z = pos[3 * i + 2] + c * box[2];
+          if (x < -rc || x > box[0] + rc || y < -rc || y > box[1] + rc || z < -rc ||
+              z > box[2] + rc)
+            continue;
+          imgs.push_back({(int32_t)i, (a + nr[0]) * w1 * w2 + (b + nr[1]) * w2 + (c + nr[2]), x, y, z});
+        }
+  // cells of edge >= rc over (-rc, L + rc)
+  int nc[3];
+  double cs[3];
+  for (int d = 0; d < 3; ++d) {
+    const double span = box[d] + 2 * rc;
+    nc[d] = std::max(1, std::min(512, (int)(span / rc)));
+    cs[d] = span / nc[d];
+  }
+  auto cell_index = [&](double v, int d) {
+    int ci = (int)((v + rc) / cs[d]);
+    return std::min(std::max(ci, 0), nc[d] - 1);
+  };
+  std::vector<int64_t> start((size_t)nc[0] * nc[1] * nc[2] + 1, 0);
+  std::vector<int64_t> cell_of(imgs.size());
+  for (size_t k = 0; k < imgs.size(); ++k) {
+    cell_of[k] = ((int64_t)cell_index(imgs[k].x, 0) * nc[1] + cell_index(imgs[k].y, 1)) * nc[2] +
+                 cell_index(imgs[k].z, 2);
+    ++start[cell_of[k] + 1];
+  }
+  for (size_t c = 1; c < start.size(); ++c) start[c] += start[c - 1];
+  std::vector<int64_t> fill(start.begin(), start.end() - 1), sorted(imgs.size());
+  for (size_t k = 0; k < imgs.size(); ++k) sorted[fill[cell_of[k]]++] = (int64_t)k;
+
+  std::vector<std::vector<Image>> out(n);
+  const double rc2 = rc * rc;
+  parallel_for(n, [&](int64_t i, int) {
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    const int ci[3] = {cell_index(x, 0), cell_index(y, 1), cell_index(z, 2)};
+    std::vector<Image> &nb = out[i];
+    for (int a = std::max(0, ci[0] - 1); a <= std::min(nc[0] - 1, ci[0] + 1); ++a)
+      for (int b = std::max(0, ci[1] - 1); b <= std::min(nc[1] - 1, ci[1] + 1); ++b)
+        for (int c = std::max(0, ci[2] - 1); c <= std::min(nc[2] - 1, ci[2] + 1); ++c) {
+          const int64_t cell = ((int64_t)a * nc[1] + b) * nc[2] + c;
+          for (int64_t s = start[cell]; s < start[cell + 1]; ++s) {
+            const Image &im = imgs[sorted[s]];
+            if (im.atom == i && im.shift == zero_shift) continue;
+            const double dx = im.x - x, dy = im.y - y, dz = im.z - z;
+            if (dx * dx + dy * dy + dz * dz <= rc2) nb.push_back(im);
+          }
+        }
+    std::sort(nb.begin(), nb.end(), [](const Image &p, const Image &q) {
+      return p.atom != q.atom ? p.atom < q.atom : p.shift < q.shift;
+    });
+  });
+  return out;
+}
+
+// In-place Cholesky of the m x m row-major matrix M (lower triangle used);
+// false if a pivot is not positive.
+bool cholesky(double *M, int m) {
+  for (int k = 0; k < m; ++k) {
+    double d = M[(size_t)k * m + k];
+    for (int l = 0; l < k; ++l) d -= M[(size_t)k * m + l] * M[(size_t)k * m + l];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    M[(size_t)k * m + k] = d;
+    const double inv = 1.0 / d;
+    for (int i = k + 1; i < m; ++i) {
+      double s = M[(size_t)i * m + k];
+      const double *ri = M + (size_t)i * m, *rk = M + (size_t)k * m;
+      for (int l = 0; l < k; ++l) s -= ri[l] * rk[l];
+      M[(size_t)i * m + k] = s * inv;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+void free_precond(Precond &p) {
+  if (p.idx) (void)hipFree(p.idx);
+  if (p.val) (void)hipFree(p.val);
+  p = Precond();
+}
+
+}  // namespace cpm
+
+using namespace cpm;
+
+extern "C" {
+
+cpm_status cpm_precond_dc(cpm_system *s, double g, double rcut) {
+  if (!s) {
+    set_error("NULL system");
+    return CPM_EINVAL;
+  }
+  if (!(g > 0.0) || !(rcut > 0.0) || !std::isfinite(g) || !std::isfinite(rcut)) {
+    set_error("screening g and rcut must be finite and > 0");
+    return CPM_EINVAL;
+  }
+  const int64_t n = s->n;
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(s->width_host[i])) {
+      set_error("the DC preconditioner needs Gaussian widths (atom " + std::to_string(i) +
+                " is a point charge)");
+      return CPM_EINVAL;
+    }
+  const std::vector<std::vector<Image>> nb = neighbourhoods(s->pos_host, n, s->box, rcut);
+  int mmax = 1;
+  for (const auto &v : nb) mmax = std::max(mmax, (int)v.size() + 1);
+
+  // column tau of P: (atom, value) pairs, images of one atom summed
+  std::vector<std::vector<std::pair<int32_t, double>>> col(n);
+  const int nt = build_threads();
+  std::vector<std::vector<double>> scratch(nt, std::vector<double>((size_t)mmax * mmax + 2 * mmax));
+  std::atomic<int64_t> bad{-1};
+  const double erfc_rc = std::erfc(g * rcut), self = std::sqrt(2.0 / M_PI);
+  parallel_for(n, [&](int64_t tau, int tid) {
+    const std::vector<Image> &v = nb[tau];
+    const int m = (int)v.size() + 1;
+    double *M = scratch[tid].data(), *y = M + (size_t)mmax * mmax, *x = y + mmax;
+    auto px = [&](int k, int d) {
+      if (k == 0) return s->pos_host[3 * tau + d];
+      return d == 0 ? v[k - 1].x : (d == 1 ? v[k - 1].y : v[k - 1].z);
+    };
+    auto width = [&](int k) { return s->width_host[k == 0 ? tau : v[k - 1].atom]; };
+    for (int k = 0; k < m; ++k) {
+      M[(size_t)k * m + k] = self * width(k);
+      for (int l = 0; l < k; ++l) {
+        const double dx = px(k, 0) - px(l, 0), dy = px(k, 1) - px(l, 1), dz = px(k, 2) - px(l, 2);
+        const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+        M[(size_t)k * m + l] = (r > 0.0 && r < rcut) ? (std::erfc(g * r) - erfc_rc) / r : 0.0;
+      }
+    }
+    if (!cholesky(M, m)) {
+      bad.store(tau);
+      return;
+    }
+    // M x = e_0: L y = e_0, L^T x = y
+    for (int i = 0; i < m; ++i) {
+      double t = (i == 0) ? 1.0 : 0.0;
+      for (int l = 0; l < i; ++l) t -= M[(size_t)i * m + l] * y[l];
+      y[i] = t / M[(size_t)i * m + i];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int l = i + 1; l < m; ++l) t -= M[(size_t)l * m + i] * x[l];
+      x[i] = t / M[(size_t)i * m + i];
+    }
+    std::vector<std::pair<int32_t, double>> &c = col[tau];
+    c.push_back({(int32_t)tau, x[0]});
+    for (int k = 1; k < m; ++k) {
+      const int32_t j = v[k - 1].atom;
+      auto it = std::lower_bound(c.begin(), c.end(), j,
+                                 [](const std::pair<int32_t, double> &e, int32_t a) { return e.first < a; });
+      if (it != c.end() && it->first == j)
+        it->second += x[k];
+      else
+        c.insert(it, {j, x[k]});
+    }
+  });
+  if (bad.load() >= 0) {
+    set_error("PCG-DC: the local matrix of atom " + std::to_string(bad.load()) +
+              " (Eq. 36) is not positive definite");
+    return CPM_ENOTSPD;
+  }
+  // symmetric part, row by row: P_s[i][j] = (C_i[j] + C_j[i]) / 2
+  auto entry = [&](int64_t c, int32_t r) {
+    const auto &v = col[c];
+    auto it = std::lower_bound(v.begin(), v.end(), r,
+                               [](const std::pair<int32_t, double> &e, int32_t a) { return e.first < a; });
+    return (it != v.end() && it->first == r) ? it->second : 0.0;
+  };
+  int width = 1;
+  for (const auto &v : col) width = std::max(width, (int)v.size());
+  std::vector<int32_t> idx((size_t)width * n);
+  std::vector<double> val((size_t)width * n, 0.0);
+  int64_t nnz = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const auto &v = col[i];   // the neighbour relation is symmetric: row i has the atoms of column i
+    for (int k = 0; k < width; ++k) {
+      if (k < (int)v.size()) {
+        idx[(size_t)i * width + k] = v[k].first;
+        val[(size_t)i * width + k] = 0.5 * (v[k].second + entry(v[k].first, (int32_t)i));
+      } else {
+        idx[(size_t)i * width + k] = (int32_t)i;
+      }
+    }
+    nnz += (int64_t)v.size();
+  }
+  Precond p;
+  p.g = g;
+  p.rcut = rcut;
+  p.width = width;
+  p.nnz = nnz;
+  p.max_local = mmax;
+  if (hipMalloc((void **)&p.idx, sizeof(int32_t) * idx.size()) != hipSuccess ||
+      hipMalloc((void **)&p.val, sizeof(double) * val.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    free_precond(p);
+    set_error("preconditioner allocation failed");
+    return CPM_ENOMEM;
+  }
+  CPM_HIP_CHECK(hipMemcpyAsync(p.idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice,
+                               s->stream));
+  CPM_HIP_CHECK(hipMemcpyAsync(p.val, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice,
+                               s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  s->device_bytes -= s->pc.bytes;
+  free_precond(s->pc);
+  p.ready = true;
+  p.bytes = (int64_t)(sizeof(int32_t) * idx.size() + sizeof(double) * val.size());
+  s->pc = p;
+  s->device_bytes += s->pc.bytes;
+  return CPM_OK;
+}
+
+cpm_status cpm_precond_apply(cpm_system *s, const double *r_dev, int64_t f, double *z_dev) {
+  if (!s || !r_dev || !z_dev || f < 1) {
+    set_error("invalid argument");
+    return CPM_EINVAL;
+  }
+  if (!s->pc.ready) {
+    set_error("cpm_precond_dc first");
+    return CPM_ESTATE;
+  }
+  cpm_status rc = precond_cols(s, r_dev, f, z_dev);
+  if (rc == CPM_OK) CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return rc;
+}
+
+}  // extern "C"

@@ -113,3 +113,26 @@ def test_mixed_matches_fp64(big):
     q, q64 = big["q"], big["q64"]
     rel = np.linalg.norm(q - q64, axis=1) / np.linalg.norm(q64, axis=1)
     assert rel.max() <= 1e-8
+
+
+def test_pcg_dc_at_full_size(big):
+    """PCG-DC (g = 0.083 / A, r_cut = 8 A) on the same frames: the charges of
+    the FP64 Jacobi solve to rel_2 <= 1e-8, stationarity at sampled atoms,
+    fewer iterations."""
+    cpm, S, geo = big["cpm"], big["S"], big["geo"]
+    S.precond_dc(0.083, 8.0)
+    b = torch.tensor(big["b"], device="cuda")
+    qsol = torch.tensor(big["qsol"], device="cuda")
+    q, st = S.solve(b, qsol, tol=1e-11, precision=cpm.PREC_F32, warm_start=cpm.WARM_CHI,
+                    inner_tol=1e-2, check_every=8, preconditioner=cpm.PRECOND_DC)
+    q = q.cpu().numpy()
+    print(f"[dc] workload 3: {st['iterations']} iterations vs {big['st']['iterations']} (Jacobi)")
+    rel = np.linalg.norm(q - big["q64"], axis=1) / np.linalg.norm(big["q64"], axis=1)
+    assert rel.max() <= 1e-8
+    assert st["iterations"] < big["st"]["iterations"]
+    at = _samples(geo.n, 8, 36)
+    u = ew.potentials(geo.pos, A, q[5], geo.box, BETA, RC, big["km"], at=at)
+    bo, _ = ew.rhs(geo.pos[at], A, big["ipos"][5], big["iq"][5], big["chi"][at], geo.box,
+                   BETA, RC, big["km"])
+    dev = u - bo
+    assert np.max(np.abs(dev - dev.mean())) <= 2e-10 * np.linalg.norm(big["b"][5])
