@@ -157,6 +157,19 @@ def ewald_matrix_literal(pos, box, a, beta, rcut, kmax):
     return E
 
 
+def slab_term(za, zb, box):
+    """Boundary correction of Eq. 39 between charges at heights za and zb
+    (cell coordinates in [0, L_z)): -(2 pi / V) [(z_a - z_b)^2 + L_z^2 / 6].
+    The first part cancels the net dipole of the periodic slab (Yeh and
+    Berkowitz), the second the non-neutral slab (Ballenegger); z is the
+    non-periodic direction (Sec. IV.A)."""
+    box = np.asarray(box, dtype=np.float64)
+    vol = float(np.prod(box))
+    za = np.mod(np.asarray(za, dtype=np.float64), box[2])
+    zb = np.mod(np.asarray(zb, dtype=np.float64), box[2])
+    return -(2.0 * math.pi / vol) * ((za - zb) ** 2 + box[2] ** 2 / 6.0)
+
+
 def real_space_pairs(pos_a, pos_b, box, rcut):
     """All (i, j, d) with d = |r_a,i - r_b,j + n L| < rcut over every image n.
 
@@ -198,8 +211,9 @@ def reciprocal_gram(pos_a, pos_b, K, w, chunk=2048):
     return out
 
 
-def ewald_matrix(pos, box, a, beta, rcut, kmax):
-    """The Gaussian Ewald matrix E of Eq. 22 for electrode atoms ``pos``.
+def ewald_matrix(pos, box, a, beta, rcut, kmax, slab=False):
+    """The Gaussian Ewald matrix E of Eq. 22 for electrode atoms ``pos``
+    (slab: plus the boundary correction of Eq. 39 on every entry).
 
     Same sum as ``ewald_matrix_literal``; the reciprocal part uses the half
     K set and the identity cos(K.(ri - rj)) = cos cos + sin sin."""
@@ -219,10 +233,12 @@ def ewald_matrix(pos, box, a, beta, rcut, kmax):
                                                         2.0 * np.where(np.isinf(aii), 0.0, aii)
                                                         / math.sqrt(math.pi))
     E[np.arange(n), np.arange(n)] += diag
+    if slab:
+        E += slab_term(pos[:, 2][:, None], pos[:, 2][None, :], box)
     return E
 
 
-def electrolyte_potential(pos, a, ion_pos, ion_q, box, beta, rcut, kmax):
+def electrolyte_potential(pos, a, ion_pos, ion_q, box, beta, rcut, kmax, slab=False):
     """b_sol,i = sum_I q_I e_iI(a_i) (Eq. 25).
 
     e_iI is Eq. 22 for a Gaussian electrode charge and a point ion: mixing
@@ -257,13 +273,15 @@ def electrolyte_potential(pos, a, ion_pos, ion_q, box, beta, rcut, kmax):
         i, I, d = real_space_pairs(pos, ion_pos[f], box, rcut)
         np.add.at(out[f], i, ion_q[f][I] * _pair_potential_real(d, beta, a[i]))
         out[f] -= math.pi / (vol * beta * beta) * float(np.sum(ion_q[f]))
+        if slab:
+            out[f] += slab_term(pos[:, 2][:, None], ion_pos[f][:, 2][None, :], box) @ ion_q[f]
     return out[0] if single else out
 
 
-def rhs(pos, a, ion_pos, ion_q, chi_volts, box, beta, rcut, kmax):
+def rhs(pos, a, ion_pos, ion_q, chi_volts, box, beta, rcut, kmax, slab=False):
     """b = chi - b_sol (Eq. 25) with chi converted from volts to e/A, and
     Q_sol = sum_I q_I, for one frame ((N,), float) or F frames ((F, N), (F,))."""
-    bsol = electrolyte_potential(pos, a, ion_pos, ion_q, box, beta, rcut, kmax)
+    bsol = electrolyte_potential(pos, a, ion_pos, ion_q, box, beta, rcut, kmax, slab)
     chi = np.asarray(chi_volts, dtype=np.float64) / K_E
     return chi - bsol, np.sum(np.asarray(ion_q, dtype=np.float64), axis=-1)
 

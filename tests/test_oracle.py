@@ -334,3 +334,81 @@ def test_workload_sizes(cfg, n):
     if n <= 4608:
         _, _, d = ew.real_space_pairs(geo.pos, geo.pos, geo.box, 1.5)
         assert abs(d.min() - wl.BOND) < 1e-9
+
+
+# --- slab geometry: boundary correction of Eq. 39 (Sec. IV.A)
+
+@pytest.mark.parametrize("a", [1.979, 2.93295072600296])
+def test_capacitor_charge_with_slab_correction(a):
+    """With the correction of Eq. 39 the field of the periodic replicas is
+    removed: only the inner gap d1 carries the field, q = (dV/k_e) /
+    (4 pi n d1 + 2 delta) with the same lattice term delta as in 3D
+    periodicity, and at a = a^0 the continuum eps0 dV / d1 per area. The
+    result does not depend on the vacuum: the same sheets in a cell twice as
+    tall give the same charge. E with the correction is solved by the
+    bordered system (Eq. 29), which does not need E to be definite."""
+    geo = wl.geometry(1)
+    b, rc, km = _params(0.3, 1e-12)
+    na = int(np.sum(geo.electrode == 0))
+    R = GOLD["gra_bond"]["value"]
+    aij = a / math.sqrt(2.0)
+    _, _, d = ew.real_space_pairs(geo.pos[:1], geo.pos[:na], geo.box, 12.0)
+    delta = math.sqrt(2 / math.pi) * a - GOLD["lattice_2d_unit_bond"]["gra"] / R - np.sum(erfc(aij * d) / d)
+    d1 = 40.0
+    qf = (1.0 / ew.K_E) / (4 * math.pi * geo.sheet_density * d1 + 2 * delta)
+    charges = []
+    for lz in (geo.box[2], 2 * geo.box[2]):
+        box = np.array([geo.box[0], geo.box[1], lz])
+        km = ew.kmax_from_eps(b, 1e-12)
+        E = ew.ewald_matrix(geo.pos, box, a, b, rc, km, slab=True)
+        bvec = wl.electrode_potential(geo) / ew.K_E
+        q, _ = cpm.bordered(E, bvec, 0.0)
+        qa, qb = q[:na], q[na:]
+        assert np.ptp(qa) / abs(qa.mean()) < 1e-9 and abs(qa.mean() + qb.mean()) < 1e-15
+        assert abs(qa.mean() / qf - 1) < 1e-8
+        charges.append(qa.mean())
+    assert abs(charges[1] / charges[0] - 1) < 1e-8
+    if a == GOLD["gra_alpha0"]["value"]:
+        eps0 = 1.0 / (4 * math.pi * ew.K_E)
+        assert abs(charges[0] / (eps0 / d1 / geo.sheet_density) - 1) < 1e-5
+
+
+def test_slab_correction_equals_dipole_energy():
+    """On neutral charge sets the correction of Eq. 39 adds (2 pi / V) M_z^2
+    (M_z the dipole along z) to the energy q^T E q / 2."""
+    rng = np.random.default_rng(21)
+    box = np.array([8.0, 9.0, 30.0])
+    pos = rng.random((9, 3)) * box
+    q = rng.standard_normal(9)
+    q -= q.mean()
+    B = ew.slab_term(pos[:, 2][:, None], pos[:, 2][None, :], box)
+    mz = float(q @ pos[:, 2])
+    assert abs(0.5 * q @ B @ q - 2 * math.pi / np.prod(box) * mz * mz) <= 1e-12 * mz * mz
+
+
+@pytest.mark.parametrize("qsol", [0.0, 2.0])
+def test_slab_correction_positive_definite_form(qsol):
+    """The charges of the literal Eq. 39 system (bordered solve) are those of
+    the definite form E + (4 pi / V) z z^T with right-hand side
+    chi/k_e - b_sol - (4 pi / V) M1 z, M1 = sum_I q_I z_I (the correction
+    restricted to sum q = -Q_sol), also for a charged electrolyte."""
+    geo = wl.geometry(1)
+    b, rc, km = _params(0.3, 1e-8)
+    rng = np.random.default_rng(5)
+    m = 20
+    ipos = np.stack([rng.random(m) * geo.box[0], rng.random(m) * geo.box[1],
+                     geo.ion_zlo + rng.random(m) * (geo.ion_zhi - geo.ion_zlo)], axis=1)
+    iq = np.where(np.arange(m) < m // 2, 1.0, -1.0)
+    iq[0] += qsol
+    chi = wl.electrode_potential(geo)
+    a = wl.GAUSS_INV_WIDTH
+    EL = ew.ewald_matrix(geo.pos, geo.box, a, b, rc, km, slab=True)
+    bl, qs = ew.rhs(geo.pos, a, ipos, iq, chi, geo.box, b, rc, km, slab=True)
+    ql, _ = cpm.bordered(EL, bl, qs)
+    vol = float(np.prod(geo.box))
+    z = np.mod(geo.pos[:, 2], geo.box[2])
+    E0 = ew.ewald_matrix(geo.pos, geo.box, a, b, rc, km)
+    b0, _ = ew.rhs(geo.pos, a, ipos, iq, chi, geo.box, b, rc, km)
+    m1 = float(iq @ np.mod(ipos[:, 2], geo.box[2]))
+    qs2 = cpm.solve(E0 + 4 * math.pi / vol * np.outer(z, z), b0 - 4 * math.pi / vol * m1 * z, qs)
+    assert np.max(np.abs(qs2 - ql)) <= 1e-10 * np.max(np.abs(ql))
