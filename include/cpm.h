@@ -70,6 +70,15 @@ typedef struct {
   double kspace_eps;     /* reciprocal cutoff K_max = 2 beta sqrt(ln(1/eps))     */
   double kmax_override;  /* > 0: use this K_max (1/A) instead of kspace_eps      */
   unsigned store_mask;   /* CPM_STORE_F32 | CPM_STORE_BF16: extra copies of E   */
+  /* 1: slab geometry, z not periodic: the boundary correction of Eq. 39,
+     e_ij += -(2 pi / V) [(z_i - z_j)^2 + L_z^2 / 6], on E and on the
+     electrode-ion terms of b. On the neutral subspace it equals the dipole
+     energy (2 pi / V) M_z^2, so the library stores the definite matrix
+     E + (4 pi / V) z z^T and cpm_rhs returns b - (4 pi / V) M1 z with
+     M1 = sum_I q_I z_I (z in [0, L_z)); cpm_solve then gives exactly the
+     charges of the Eq. 39 system (they differ from it only by multiples of
+     1 on the right-hand side and by terms that vanish for sum q = -Q_sol). */
+  int slab_correction;
 } cpm_params;
 
 /* Assemble E for n electrode atoms. The neutralising vector d' = E^-1 1

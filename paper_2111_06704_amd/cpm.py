@@ -44,7 +44,8 @@ class CpmError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("gauss_inv_width", C.c_double), ("gauss_inv_width_per_atom", C.POINTER(C.c_double)),
                 ("ewald_split", C.c_double), ("rcut", C.c_double), ("kspace_eps", C.c_double),
-                ("kmax_override", C.c_double), ("store_mask", C.c_uint)]
+                ("kmax_override", C.c_double), ("store_mask", C.c_uint),
+                ("slab_correction", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -139,7 +140,7 @@ class System:
 
     def __init__(self, pos, box, gauss_inv_width=1.979, ewald_split=0.3, rcut=12.0,
                  kspace_eps=1e-6, kmax_override=0.0, store=(), per_atom_width=None,
-                 profile_build=False):
+                 profile_build=False, slab=False):
         L = lib()
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         box = np.ascontiguousarray(box, dtype=np.float64)
@@ -158,6 +159,7 @@ class System:
         for s in store:
             mask |= {"f32": STORE_F32, "bf16": STORE_BF16}[s]
         p.store_mask = mask | (PROFILE_BUILD if profile_build else 0)
+        p.slab_correction = 1 if slab else 0
         self.store = tuple(store)
         h = C.c_void_p()
         st = L.cpm_build_E(pos.ctypes.data, self.n, box.ctypes.data, C.byref(p), _stream(), C.byref(h))

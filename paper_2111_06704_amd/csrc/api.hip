@@ -286,6 +286,7 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
   s->rcut = params->rcut;
   s->kmax = kmax;
   s->kset = make_kset(box_host, beta, kmax);
+  s->slab = params->slab_correction != 0;
   s->prof.enabled = (params->store_mask & CPM_PROFILE_BUILD) != 0;
   s->pos_host = pos;
   s->width_host = width;
@@ -378,8 +379,8 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
     BUILD_CHECK(hipStreamSynchronize(st));
     (void)hipFree(A);
   }
-  BUILD_CHECK(launch_finalize(st, s->pos, s->width, n, ld, s->box, beta, s->rcut, s->E64, s->E32,
-                              s->E16));
+  BUILD_CHECK(launch_finalize(st, s->pos, s->width, n, ld, s->box, beta, s->rcut, s->slab, s->E64,
+                              s->E32, s->E16));
   BUILD_CHECK(launch_diag_inverse(st, s->E64, n, ld, s->dinv));
   BUILD_CHECK(hipStreamSynchronize(st));
 #undef BUILD_CHECK

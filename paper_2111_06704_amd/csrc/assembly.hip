@@ -155,9 +155,9 @@ __device__ inline int64_t ifloor(double x) { return (int64_t)floor(x); }
 
 __global__ void finalize_kernel(const double *__restrict__ pos, const double *__restrict__ width,
                                 int64_t n, int64_t ld, double lx, double ly, double lz,
-                                double beta, double rcut, double c0, double *__restrict__ E64,
-                                float *__restrict__ E32, uint16_t *__restrict__ E16,
-                                int64_t jblocks) {
+                                double beta, double rcut, double c0, double slab,
+                                double *__restrict__ E64, float *__restrict__ E32,
+                                uint16_t *__restrict__ E16, int64_t jblocks) {
   const int64_t i = (int64_t)blockIdx.x / jblocks;
   const int64_t j = ((int64_t)blockIdx.x % jblocks) * blockDim.x + threadIdx.x;
   if (j >= n) return;
@@ -195,6 +195,8 @@ __global__ void finalize_kernel(const double *__restrict__ pos, const double *__
   }
   const int64_t idx = i * ld + j;
   double e = E64[idx] + real + c0;
+  // slab geometry (Eq. 39 in its definite form): (4 pi / V) z_i z_j
+  if (slab != 0.0) e += slab * (pos[3 * lo + 2] * pos[3 * hi + 2]);
   if (i == j) {
     // Gaussian self-energy 2 a_ii / sqrt(pi), a_ii = a_i / sqrt(2) (Eq. 6);
     // a point charge (a_i = inf) has none (end of Sec. II.C).
@@ -232,13 +234,14 @@ hipError_t launch_syrk_lower(hipStream_t st, const double *A, int64_t lda, int64
 }
 
 hipError_t launch_finalize(hipStream_t st, const double *pos, const double *width, int64_t n,
-                           int64_t ld, const double box[3], double beta, double rcut,
+                           int64_t ld, const double box[3], double beta, double rcut, bool slab,
                            double *E64, float *E32, uint16_t *E16) {
   const double vol = box[0] * box[1] * box[2];
   const double c0 = -M_PI / (vol * beta * beta);
+  const double cs = slab ? 4.0 * M_PI / vol : 0.0;
   const int64_t jblocks = (n + 255) / 256;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)(jblocks * n)), dim3(256), 0, st, pos, width,
-                     n, ld, box[0], box[1], box[2], beta, rcut, c0, E64, E32, E16, jblocks);
+                     n, ld, box[0], box[1], box[2], beta, rcut, c0, cs, E64, E32, E16, jblocks);
   return hipGetLastError();
 }
 

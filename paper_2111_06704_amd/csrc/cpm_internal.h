@@ -130,6 +130,7 @@ struct cpm_system {
   int64_t n = 0, ld = 0;      // ld = padded leading dimension (multiple of 128)
   double box[3] = {0, 0, 0};
   double vol = 0, beta = 0, rcut = 0, kmax = 0;
+  bool slab = false;          // boundary correction of Eq. 39 (definite form)
   cpm::Kset kset;
   double *pos = nullptr;      // n*3 device
   double *width = nullptr;    // n device (Gaussian inverse widths)
@@ -169,7 +170,7 @@ hipError_t launch_syrk_lower(hipStream_t st, const double *A, int64_t lda, int64
                              int64_t ld, double *E, int64_t lde, bool accumulate,
                              hipEvent_t ev_start, hipEvent_t ev_stop);
 hipError_t launch_finalize(hipStream_t st, const double *pos, const double *width, int64_t n,
-                           int64_t ld, const double box[3], double beta, double rcut,
+                           int64_t ld, const double box[3], double beta, double rcut, bool slab,
                            double *E64, float *E32, uint16_t *E16);
 
 // ---- rhs.hip

@@ -23,19 +23,37 @@ constexpr int FG = 16;        // frames per thread in the back-projection
 constexpr int BP_AT = 4;      // atoms per thread in the back-projection
 constexpr int BP_KCH = 32;    // k-vectors per LDS chunk in the back-projection
 
+// Q_sol[f] = sum_I q_I; with m1 != null also M1[f] = sum_I q_I z_I (z in [0, L_z)),
+// the ion dipole that the slab correction needs.
 __global__ __launch_bounds__(RB) void qsum_kernel(const double *__restrict__ q, int64_t m,
-                                                  double *__restrict__ qsol) {
-  __shared__ double red[RB];
+                                                  double *__restrict__ qsol,
+                                                  const double *__restrict__ ion_pos, double lz,
+                                                  double *__restrict__ m1) {
+  __shared__ double red[2][RB];
   const int64_t f = blockIdx.x;
-  double acc = 0.0;
-  for (int64_t I = threadIdx.x; I < m; I += RB) acc += q[f * m + I];
-  red[threadIdx.x] = acc;
+  double acc = 0.0, dip = 0.0;
+  for (int64_t I = threadIdx.x; I < m; I += RB) {
+    const double qi = q[f * m + I];
+    acc += qi;
+    if (m1 != nullptr) {
+      const double z = ion_pos[(f * m + I) * 3 + 2];
+      dip += qi * (z - lz * floor(z / lz));
+    }
+  }
+  red[0][threadIdx.x] = acc;
+  red[1][threadIdx.x] = dip;
   __syncthreads();
   for (int s = RB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) qsol[f] = red[0];
+  if (threadIdx.x == 0) {
+    qsol[f] = red[0][0];
+    if (m1 != nullptr) m1[f] = red[1][0];
+  }
 }
 
 // Ion structure factors of one group of ions, S_fK = sum_I q_I exp(i K.r_I).
@@ -221,12 +239,14 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
 }
 
 // b[f, i] = chi_i / k_e - sum_ks bp[ks][f][i] - sum_g rs[g][f][i] - c0 Q_f
-// (fixed order over the k splits and ion groups)
+// (fixed order over the k splits and ion groups); slab geometry (Eq. 39 in
+// its definite form): - (4 pi / V) M1_f z_i.
 __global__ void assemble_b_kernel(const double *__restrict__ bp, int ksplits,
                                   const double *__restrict__ rs, int rgroups, int64_t n,
                                   int64_t f_total, const double *__restrict__ chi,
                                   const double *__restrict__ qsol, double c0,
-                                  double *__restrict__ b) {
+                                  const double *__restrict__ m1, double cs,
+                                  const double *__restrict__ pos, double *__restrict__ b) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * f_total) return;
   const int64_t f = idx / n, i = idx % n;
@@ -234,7 +254,9 @@ __global__ void assemble_b_kernel(const double *__restrict__ bp, int ksplits,
   double s = 0.0;
   for (int ks = 0; ks < ksplits; ++ks) s += bp[ks * fn + idx];
   for (int g = 0; g < rgroups; ++g) s += rs[g * fn + idx];
-  b[idx] = chi[i] * (1.0 / kCoulombVA) - s - c0 * qsol[f];
+  double v = chi[i] * (1.0 / kCoulombVA) - s - c0 * qsol[f];
+  if (m1 != nullptr) v -= cs * m1[f] * pos[3 * i + 2];
+  b[idx] = v;
 }
 
 // Images of a displacement d (already reduced to the minimum image) along
@@ -345,7 +367,7 @@ namespace {
 //   rs  [rs_groups][f][n]      real-space partials
 struct RhsPlan {
   int64_t sf_groups = 1, sf_ipg = 0, ksplit = 0, kper = 0, rs_groups = 0, rs_ipg = 0;
-  int64_t off_sg = 0, off_bp = 0, off_rs = 0, total = 0;
+  int64_t off_sg = 0, off_bp = 0, off_rs = 0, off_m1 = 0, total = 0;
 };
 
 constexpr int64_t kTargetBlocks = 2048;          // workgroups that fill the chip several times
@@ -377,7 +399,8 @@ RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f) {
   p.off_sg = 2 * nk * f;
   p.off_bp = p.off_sg + (p.sf_groups > 1 ? p.sf_groups * 2 * nk * f : 0);
   p.off_rs = p.off_bp + p.ksplit * f * n;
-  p.total = p.off_rs + p.rs_groups * f * n;
+  p.off_m1 = p.off_rs + p.rs_groups * f * n;
+  p.total = p.off_m1 + f;
   return p;
 }
 
@@ -396,11 +419,17 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
   const RhsPlan p = rhs_plan(s, m, f);
   double *S = scratch, *bp = scratch + p.off_bp, *rs = scratch + p.off_rs;
   const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
+  double *m1 = s->slab ? scratch + p.off_m1 : nullptr;
   if (m > 0) {
-    hipLaunchKernelGGL(qsum_kernel, dim3((unsigned)f), dim3(RB), 0, st, ion_q, m, qsol_out);
+    hipLaunchKernelGGL(qsum_kernel, dim3((unsigned)f), dim3(RB), 0, st, ion_q, m, qsol_out, ion_pos,
+                       s->box[2], m1);
   } else {
     hipError_t e = hipMemsetAsync(qsol_out, 0, sizeof(double) * f, st);
     if (e != hipSuccess) return e;
+    if (m1) {
+      e = hipMemsetAsync(m1, 0, sizeof(double) * f, st);
+      if (e != hipSuccess) return e;
+    }
   }
   if (p.ksplit > 0) {
     double *Sg = p.sf_groups > 1 ? scratch + p.off_sg : S;
@@ -424,7 +453,8 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
                        p.rs_ipg, s->box[0], s->box[1], s->box[2], s->beta, s->rcut, f, rs);
   }
   hipLaunchKernelGGL(assemble_b_kernel, dim3((unsigned)((n * f + 255) / 256)), dim3(256), 0, st,
-                     bp, (int)p.ksplit, rs, (int)p.rs_groups, n, f, chi, qsol_out, c0, b_out);
+                     bp, (int)p.ksplit, rs, (int)p.rs_groups, n, f, chi, qsol_out, c0,
+                     (const double *)m1, 4.0 * M_PI / s->vol, s->pos, b_out);
   return hipGetLastError();
 }
 

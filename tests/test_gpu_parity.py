@@ -247,6 +247,44 @@ def test_capacitor_through_gpu():
     assert abs(q[:na].mean() / q_cont - 1) < 1e-5
 
 
+def test_capacitor_with_slab_correction_through_gpu():
+    """Slab geometry (Eq. 39): only the inner 40 A gap carries the field; at
+    a = a0 the charge is the continuum eps0 dV / d1 per area."""
+    cpm = _cpm()
+    dev = _dev()
+    geo = wl.geometry(1)
+    a0 = 2.93295072600296
+    S = cpm.System(geo.pos, geo.box, a0, 0.3, ew.rcut_from_eps(0.3, 1e-12), 1e-12, slab=True)
+    chi = torch.tensor(wl.electrode_potential(geo), device=dev)
+    b, qsol = S.rhs(None, None, chi)
+    q, _ = S.solve(b, qsol, tol=1e-13)
+    q = q.cpu().numpy()[0]
+    na = int(np.sum(geo.electrode == 0))
+    eps0 = 1.0 / (4 * math.pi * ew.K_E)
+    assert np.ptp(q[:na]) / abs(q[:na].mean()) < 1e-9
+    assert abs(q[:na].mean() / (eps0 / 40.0 / geo.sheet_density) - 1) < 1e-5
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_slab_correction_charges(cfg):
+    """Charges with the correction of Eq. 39 against the oracle's literal
+    Eq. 39 matrix solved as the bordered system (Eq. 29): rel_2 <= 1e-9."""
+    cpm = _cpm()
+    dev = _dev()
+    geo, ipos, iq, chi = wl.workload(cfg, frames=4)
+    km = ew.kmax_from_eps(BETA, EPS)
+    S = cpm.System(geo.pos, geo.box, A, BETA, RC, EPS, slab=True)
+    b, qsol = S.rhs(torch.tensor(ipos, device=dev), torch.tensor(iq, device=dev),
+                    torch.tensor(chi, device=dev))
+    q, st = S.solve(b, qsol, tol=1e-12)
+    EL = ew.ewald_matrix(geo.pos, geo.box, A, BETA, RC, km, slab=True)
+    bl, qs = ew.rhs(geo.pos, A, ipos, iq, chi, geo.box, BETA, RC, km, slab=True)
+    qo = np.array([ocpm.bordered(EL, bl[f], qs[f])[0] for f in range(len(qs))])
+    r2, _ = ocpm.rel_errors(q.cpu().numpy(), qo)
+    assert r2.max() <= 1e-9
+    assert st["max_abs_sum_q"] <= 1e-12
+
+
 def test_point_charge_madelung_through_gpu():
     """SC and BCC Wigner constants (Supplementary Note) with point charges."""
     cpm = _cpm()
