@@ -192,6 +192,21 @@ cpm_status cpm_precond_dc(cpm_system *s, double screening_g, double rcut);
    own apply kernel (tests). CPM_ESTATE before cpm_precond_dc. */
 cpm_status cpm_precond_apply(cpm_system *s, const double *r_dev, int64_t f, double *z_dev);
 
+/* ---- matrix-inversion path (Sec. III.B.1 MI; Eq. 33-35) -------------------
+ * cpm_mi_build forms S = E^-1 (I - 1 d^T) (Eq. 33), symmetric, whose column
+ * j is the two-step charge vector (Eq. 35) of the unit right-hand side e_j
+ * with Q_sol = 0: it runs cpm_solve on the n unit vectors, 64 at a time, with
+ * the caller's opts (tolerance, precision, preconditioner; the warm start is
+ * ignored), and keeps S on the device (n_pad^2 doubles). The error of S is
+ * that of those solves. cpm_mi_solve then gives q = S b - Q_sol d for f
+ * frames with one block product (b_dev, q_out_dev (f, n), qsol_dev (f,)
+ * device arrays; enqueued on the stream, not synchronised).
+ * Errors: CPM_EINVAL, CPM_ENOMEM, the solve's errors (build); CPM_ESTATE
+ * (cpm_mi_solve before cpm_mi_build). */
+cpm_status cpm_mi_build(cpm_system *s, const cpm_solve_opts *opts);
+cpm_status cpm_mi_solve(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
+                        double *q_out_dev);
+
 /* Copy E (caller's atom order) into dst_dev with leading dimension ld >= n,
    in the requested precision (FP64 double, FP32 float, BF16 uint16 bits).
    CPM_EINVAL if that precision is not stored. */

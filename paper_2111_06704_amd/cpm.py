@@ -30,6 +30,7 @@ EXPORTS = [
     "cpm_mlp_set_params", "cpm_mlp_get_params", "cpm_mlp_features", "cpm_mlp_forward",
     "cpm_mlp_loss_grad", "cpm_mlp_train_step", "cpm_mlp_train_epoch", "cpm_set_warm_chi",
     "cpm_profile_enable", "cpm_profile_read", "cpm_precond_dc", "cpm_precond_apply",
+    "cpm_mi_build", "cpm_mi_solve",
     "cpm_status_str", "cpm_last_error",
 ]
 PROFILE_BUILD = 4
@@ -275,6 +276,22 @@ class System:
         _check(lib().cpm_precond_apply(self._h, _ptr(r, torch.float64), int(r.shape[0]),
                                        _ptr(z, torch.float64)), "cpm_precond_apply")
         return z
+
+    def mi_build(self, tol=1e-13, max_iter=20000, precision=PREC_F64,
+                 preconditioner=PRECOND_JACOBI):
+        """Form S = E^-1 (I - 1 d^T) (Eq. 33) with the block solver."""
+        o = SolveOpts(tol=tol, max_iter=max_iter, precision=precision, warm_start=WARM_ZERO,
+                      inner_tol=1e-2, check_every=8, preconditioner=preconditioner)
+        _check(lib().cpm_mi_build(self._h, C.byref(o)), "cpm_mi_build")
+
+    def mi_solve(self, b, qsol, q_out=None):
+        """q = S b - Q_sol d (Eq. 35) for frames b (F, N); asynchronous."""
+        import torch
+        if q_out is None:
+            q_out = torch.empty_like(b)
+        _check(lib().cpm_mi_solve(self._h, _ptr(b, torch.float64), _ptr(qsol, torch.float64),
+                                  int(b.shape[0]), _ptr(q_out, torch.float64)), "cpm_mi_solve")
+        return q_out
 
     def set_warm_chi(self, chi, tol=1e-12, max_iter=5000, preconditioner=PRECOND_JACOBI):
         import torch

@@ -131,7 +131,7 @@ template <typename T> cpm_status dev_alloc(cpm_system *s, T **p, size_t count) {
 void free_system(cpm_system *s) {
   if (!s) return;
   void *ptrs[] = {s->pos, s->width, s->kn, s->kw, s->kinfo, s->krun, s->atom_order, s->E64, s->E32, s->E16, s->dinv, s->dprime,
-                  s->dvec, s->qchi, s->rhs_S, s->mlp.nbr, s->mlp.nbr_r, s->mlp.layer, s->mlp.params,
+                  s->dvec, s->qchi, s->rhs_S, s->S, s->mlp.nbr, s->mlp.nbr_r, s->mlp.layer, s->mlp.params,
                   s->mlp.adam_m, s->mlp.adam_v, s->mlp.grad, s->mlp.gpart, s->mlp.loss,
                   s->mlp.feat, s->mlp.yout};
   for (void *p : ptrs)

@@ -1503,8 +1503,14 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
 
 cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_t f,
                        double *v_dev) {
+  return matvec_cols_with(s, precision, nullptr, p_dev, f, v_dev);
+}
+
+cpm_status matvec_cols_with(cpm_system *s, int precision, const double *M64, const double *p_dev,
+                            int64_t f, double *v_dev) {
   t_prof = &s->prof;
   t_n = s->n;
+  if (M64 == nullptr) M64 = s->E64;
   hipStream_t st = s->stream;
   const int64_t ld = s->ld, n = s->n;
   for (int64_t f0 = 0; f0 < f; f0 += MAX_COLS) {
@@ -1519,7 +1525,7 @@ cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_
     int sl = 0;
     double *res = s->ws.bx;   // summed product (double)
     if (precision == CPM_PREC_F64) {
-      CPM_HIP_CHECK(launch_matvec<double>(st, s->E64, ld, cols, in, out, nullptr, sl));
+      CPM_HIP_CHECK(launch_matvec<double>(st, M64, ld, cols, in, out, nullptr, sl));
       hipLaunchKernelGGL(sum_slices_kernel<double>, elem_grid(ld * cols), dim3(256), 0, st,
                          (const double *)out, sl, ld * cols, res, ld * cols);
     } else {

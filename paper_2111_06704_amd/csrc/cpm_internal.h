@@ -148,6 +148,7 @@ struct cpm_system {
   double c_ele = 0;
   bool dprime_ready = false;
   double *qchi = nullptr;     // ld: neutral charges without electrolyte (warm start)
+  double *S = nullptr;        // ld*ld: S = E^-1 (I - 1 d^T) of the MI path (Eq. 33), or null
   bool qchi_ready = false;
   double *rhs_S = nullptr;    // structure-factor scratch
   int64_t rhs_S_elems = 0;
@@ -187,6 +188,9 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
 cpm_status solve_dprime(cpm_system *s, double tol, int max_iter);
 cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_t f,
                        double *v_dev);
+// V = M P with an ld x ld FP64 matrix M instead of E (precision CPM_PREC_F64)
+cpm_status matvec_cols_with(cpm_system *s, int precision, const double *M64, const double *p_dev,
+                            int64_t f, double *v_dev);
 // z = P r (PCG-DC preconditioner) for f vectors (f, n), the CG's own apply kernel
 cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z_dev);
 hipError_t launch_diag_inverse(hipStream_t st, const double *E, int64_t n, int64_t ld,
