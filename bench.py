@@ -32,9 +32,10 @@ FP64_PEAK_TFLOPS = 78.6
 # plain copy run after the timed region: its counter readings calibrate the
 # FETCH_SIZE / WRITE_SIZE counters (bytes moved are known exactly)
 CALIB_BYTES = 1 << 30
-KERNEL_OF_KIND = {"matvec_f64": "block_matvec_kernel<double, {ng}>",
-                  "matvec_f32": "block_matvec_kernel<float, {ng}>",
-                  "matvec_bf16": "block_matvec_kernel<unsigned short, {ng}>"}
+# 16 columns run on the row-split kernel
+KERNEL_OF_KIND = {"matvec_f64": "block_matvec_rows_kernel<double>",
+                  "matvec_f32": "block_matvec_rows_kernel<float>",
+                  "matvec_bf16": "block_matvec_rows_kernel<unsigned short>"}
 # 32..64 columns of an FP32 / BF16 E run on the split-bf16 kernel
 KERNEL_OF_KIND_WIDE = {"matvec_f64": "block_matvec_kernel<double, {ng}>",
                        "matvec_f32": "block_matvec_split_kernel<float, {ng}>",
@@ -121,13 +122,15 @@ def summarize_pmc(fetch_dir, write_dir, out_path):
                            "write_factor": CALIB_BYTES / (cw * 1024.0)},
            "cg_source_sha256": _sha256(CG_SOURCE), "kernels": {}}
     for name in sorted(set(fetch) | set(write)):
-        m = re.search(r"(block_matvec(?:_split)?_kernel)<([^>]*)>", name)
+        m = re.search(r"(block_matvec(?:_split|_rows)?_kernel)<([^>]*)>", name)
         if not m:
             continue
         key = m.group(1) + "<" + m.group(2) + ">"
+        # median over dispatches: launches that the device-side control
+        # turned into no-ops move no data and are not typical
         rec["kernels"][key] = {"dispatches": len(fetch.get(name, [])),
-                               "fetch_kib": float(np.mean(fetch[name])) if name in fetch else None,
-                               "write_kib": float(np.mean(write[name])) if name in write else None}
+                               "fetch_kib": float(np.median(fetch[name])) if name in fetch else None,
+                               "write_kib": float(np.median(write[name])) if name in write else None}
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")

@@ -274,6 +274,97 @@ __global__ __launch_bounds__(256) void block_matvec_kernel(
   }
 }
 
+// Block product for 16 columns with the rows split over the waves: grid
+// (row blocks of MR_WAVES x 16 rows, k slices). The workgroup first copies
+// its slice of P (16 columns x kslice) into LDS; each wave then streams its
+// own 16 rows of E over the slice (U load stages in flight) and takes the B
+// operands from LDS, so P is read from L2 once per workgroup and no
+// reduction across waves is needed:
+//   part[s][c][row] = sum_{k in slice s} E[row][k] P[c][k]
+//   pv_part[s][wave tile][c] = sum over the tile's 16 rows of P[c][row] part[s][c][row]
+constexpr int MR_WAVES = 8;
+extern __shared__ double mv_lds[];
+
+template <typename T> constexpr int mr_pad() { return 4; }   // keeps 32-byte alignment of LDS rows
+// longest k slice whose P copy fits 64 KB of LDS (a multiple of the k step)
+template <typename T> constexpr int64_t mr_kmax() {
+  constexpr int64_t kb = 4 * Mv<T>::VEC;
+  return ((65536 / (16 * (int64_t)sizeof(typename Mv<T>::VT))) - mr_pad<T>()) / kb * kb;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * MR_WAVES) void block_matvec_rows_kernel(
+    const T *__restrict__ E, int64_t ld, const typename Mv<T>::VT *__restrict__ P,
+    typename Mv<T>::VT *__restrict__ part, int64_t kslice, int64_t split_stride,
+    double *__restrict__ pv_part, const int *__restrict__ gate, int *__restrict__ mark) {
+  using M = Mv<T>;
+  using VT = typename M::VT;
+  using Acc = typename M::Acc;
+  constexpr int VEC = M::VEC;
+  constexpr int KB = 4 * VEC;
+  constexpr int U = 4;
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  if (gate != nullptr && *gate == 0) {
+    if (mark != nullptr && first) *mark = 0;
+    return;
+  }
+  if (mark != nullptr && first) *mark = 1;
+  VT *ps = reinterpret_cast<VT *>(mv_lds);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t wtile = (int64_t)blockIdx.x * MR_WAVES + wave;
+  const int64_t r0 = wtile * 16;
+  const int64_t sl = blockIdx.y;
+  const int64_t k0 = sl * kslice;
+  const int64_t kn = min(kslice, ld - k0);   // a multiple of KB
+  const int64_t pstride = kslice + mr_pad<T>();
+  const int64_t nsteps = kn / KB;
+  const T *erow = E + (r0 + lr) * ld + k0 + lg * VEC;
+  typename M::Raw ea[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (u < nsteps) M::load(erow + u * KB, ea[u]);
+  // P slice into LDS (16-byte pieces)
+  constexpr int PV = 16 / sizeof(VT);
+  const int64_t q = kn / PV;
+  for (int64_t t = threadIdx.x; t < 16 * q; t += 64 * MR_WAVES) {
+    const int64_t c = t / q, kk = (t % q) * PV;
+    *reinterpret_cast<uint4 *>(ps + c * pstride + kk) =
+        *reinterpret_cast<const uint4 *>(P + c * ld + k0 + kk);
+  }
+  __syncthreads();
+  Acc acc[2] = {Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}};
+  const VT *pl = ps + lr * pstride + lg * VEC;
+  for (int64_t st0 = 0; st0 < nsteps; st0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (st0 + u < nsteps) {
+        VT pb[VEC];
+        load_vec<VT, VEC>(pl + (st0 + u) * KB, pb);
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) acc[t & 1] = M::mfma(M::elem(ea[u], t), pb[t], acc[t & 1]);
+        const int64_t nxt = st0 + u + U;
+        if (nxt < nsteps) M::load(erow + nxt * KB, ea[u]);
+      }
+    }
+  }
+  // lane (lr, lg) holds rows out_row(lg, v) of column lr
+  VT *out = part + sl * split_stride + (int64_t)lr * ld + r0;
+  const VT *pc = P + (int64_t)lr * ld + r0;
+  double pv = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = M::out_row(lg, v);
+    const VT sv = acc[0][v] + acc[1][v];
+    out[row] = sv;
+    pv += (double)pc[row] * (double)sv;
+  }
+  if (pv_part == nullptr) return;
+  pv += __shfl_xor(pv, 16, 64);
+  pv += __shfl_xor(pv, 32, 64);
+  if (lg == 0) pv_part[(sl * (ld / 16) + wtile) * 16 + lr] = pv;
+}
+
 // ---- block product on bf16 matrix cores (32..64 columns, FP32 or BF16 E)
 //
 // v_mfma_f32_16x16x32_bf16: lane l supplies A[l % 16][8 (l / 16) + j] and
@@ -628,8 +719,9 @@ __global__ __launch_bounds__(RED_THREADS) void set_scalars_kernel(
 }
 
 // alpha = rz / p.v; x += alpha p; r -= alpha v. Jacobi (JAC): also z = M^-1 r
-// and the partial rr, rz; otherwise the preconditioner kernel that follows
-// computes z and the partials.
+// and the partial rr, rz; otherwise r is also written to its row-interleaved
+// copy rt and the preconditioner kernel that follows computes z and the
+// partials.
 template <typename VT, bool JAC>
 __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
     double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
@@ -637,7 +729,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
     const double *__restrict__ dinv, int64_t ld, int64_t n, int cols, int npv,
     const double *__restrict__ pv_part,
     const double *__restrict__ scal, int slot, double *__restrict__ partial,
-    int *__restrict__ flags) {
+    int *__restrict__ flags, double *__restrict__ rt) {
   __shared__ double red[3][4];
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
@@ -665,6 +757,8 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
       x[idx] += alpha * (double)p[idx];
       const double ri = r[idx] - alpha * sum_slices(vpart, slices, stride, idx);
       r[idx] = ri;
+      if constexpr (!JAC)
+        rt[((int64_t)(c / kColGroup) * ld + i) * kColGroup + (c % kColGroup)] = ri;
       if constexpr (JAC) {
         const double zi = ri * dinv[i];
         z[idx] = zi;
@@ -683,63 +777,128 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
   }
 }
 
+// Row-interleaved copy of the residual for the PCG-DC apply: column group g
+// (16 columns) holds entry (i, c) at rt[(g * ld + i) * 16 + c], so that the
+// 16 columns of one atom are one 128-byte line. src has column stride cs and
+// fc valid columns of n rows; rows >= n and columns >= fc are written as 0.
+// 64 rows x 16 columns per workgroup, transposed through LDS.
+constexpr int RT_ROWS = 64;
+__global__ __launch_bounds__(RED_THREADS) void rows_kernel(const double *__restrict__ src,
+                                                           int64_t cs, int64_t n, int fc,
+                                                           double *__restrict__ rt, int64_t ld,
+                                                           const int *__restrict__ gate) {
+  __shared__ double tile[kColGroup][RT_ROWS + 1];
+  if (gate != nullptr && *gate == 0) return;
+  const int64_t r0 = (int64_t)blockIdx.x * RT_ROWS;
+  const int g = blockIdx.y;
+  for (int t = threadIdx.x; t < kColGroup * RT_ROWS; t += RED_THREADS) {
+    const int c = t / RT_ROWS, rr = t % RT_ROWS;
+    const int64_t i = r0 + rr;
+    const int col = g * kColGroup + c;
+    tile[c][rr] = (col < fc && i < n) ? src[(int64_t)col * cs + i] : 0.0;
+  }
+  __syncthreads();
+  double *out = rt + ((int64_t)g * ld + r0) * kColGroup;
+  for (int t = threadIdx.x; t < kColGroup * RT_ROWS; t += RED_THREADS) {
+    const int rr = t / kColGroup, c = t % kColGroup;
+    if (r0 + rr < ld) out[t] = tile[c][rr];
+  }
+}
+
 // PCG-DC apply (Sec. III.B.2): z = P r with P in row-major ELL form (entry k
-// of row i at i * width + k). One wavefront per row (rows taken in the
-// spatial order), its lanes over the row's entries, 16 columns per wavefront
-// (grid.y = column group). Active columns only (scal == nullptr: all);
-// set_p: p = z. bpart (may be null): per workgroup and column (r.r, r.z),
-// summed by the kernels that need the totals.
+// of row i at i * width + k) and r in the row-interleaved layout of
+// rows_kernel. One wavefront per row (rows taken in the spatial order) and
+// column group (grid.y); lane = 8 e + h takes entries k = e, e + 8, ... and
+// the column pair (2h, 2h + 1), so every gather of the wavefront reads eight
+// whole 128-byte lines. The workgroup's rows of P are staged in LDS by
+// coalesced loads (PC_CHUNK entries per row at a time), so the vector memory
+// path serves only the gathers. The eight entry lanes of each pair are
+// summed by shuffles in a fixed order. Active columns only (scal == nullptr:
+// all); set_p: p = z. bpart (may be null): per workgroup and column (r.r,
+// r.z), summed by the kernels that need the totals.
 constexpr int PC_ROWS = RED_THREADS / 64;   // rows per workgroup
+constexpr int PC_CHUNK = 256;               // entries per row staged at a time
 
 template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void precond_kernel(
-    const double *__restrict__ r, double *__restrict__ z, VT *__restrict__ p,
+    const double *__restrict__ rt, double *__restrict__ z, VT *__restrict__ p,
     const int32_t *__restrict__ pidx, const double *__restrict__ pval, int width,
     const int32_t *__restrict__ order, int64_t ld, int64_t n, int cols,
     const double *__restrict__ scal, double *__restrict__ bpart, int set_p,
     const int *__restrict__ gate) {
   __shared__ double red[PC_ROWS][kColGroup][2];
+  __shared__ double sval[PC_ROWS][PC_CHUNK];
+  __shared__ int32_t sidx[PC_ROWS][PC_CHUNK];
   if (gate != nullptr && *gate == 0) return;
   const int g = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t t = (int64_t)blockIdx.x * PC_ROWS + wave;
-  const int64_t i = t < n ? (int64_t)order[t] : -1;
-  const double *rg = r + (int64_t)g * kColGroup * ld;
-  double acc[kColGroup];
+  const int e = lane >> 3, h = lane & 7;
+  int64_t rows[PC_ROWS];
 #pragma unroll
-  for (int c = 0; c < kColGroup; ++c) acc[c] = 0.0;
-  if (i >= 0) {
-    for (int k = lane; k < width; k += 64) {
-      const int64_t j = pidx[i * width + k];
-      const double v = pval[i * width + k];
-#pragma unroll
-      for (int c = 0; c < kColGroup; ++c) acc[c] += v * rg[c * ld + j];
+  for (int w = 0; w < PC_ROWS; ++w) {
+    const int64_t t = (int64_t)blockIdx.x * PC_ROWS + w;
+    rows[w] = t < n ? (int64_t)order[t] : -1;
+  }
+  const int64_t i = rows[wave];
+  const double *rg = rt + (int64_t)g * ld * kColGroup;
+  // the row's own residual and the columns' active flags, loaded early
+  const int c0 = g * kColGroup + 2 * h;
+  double2 ri = make_double2(0.0, 0.0);
+  if (i >= 0) ri = *reinterpret_cast<const double2 *>(rg + i * kColGroup + 2 * h);
+  const bool act0 = scal == nullptr || scal[S_ACT * cols + c0] != 0.0;
+  const bool act1 = scal == nullptr || scal[S_ACT * cols + c0 + 1] != 0.0;
+  double a0 = 0.0, a1 = 0.0;
+  for (int k0 = 0; k0 < width; k0 += PC_CHUNK) {
+    const int cw = min(PC_CHUNK, width - k0);
+    if (k0 > 0) __syncthreads();
+    for (int q = threadIdx.x; q < PC_ROWS * cw; q += RED_THREADS) {
+      const int w = q / cw, k = q % cw;
+      const int64_t r = rows[w];
+      sidx[w][k] = r >= 0 ? pidx[r * width + k0 + k] : 0;
+      sval[w][k] = r >= 0 ? pval[r * width + k0 + k] : 0.0;
+    }
+    __syncthreads();
+    if (i >= 0) {
+#pragma unroll 4
+      for (int k = e; k < cw; k += 8) {
+        const int64_t j = sidx[wave][k];
+        const double v = sval[wave][k];
+        const double2 x = *reinterpret_cast<const double2 *>(rg + j * kColGroup + 2 * h);
+        a0 += v * x.x;
+        a1 += v * x.y;
+      }
     }
   }
-  // lane c < 16 ends with column c's sum
-  double zc = 0.0;
 #pragma unroll
-  for (int c = 0; c < kColGroup; ++c) {
-    const double sum = wave_sum(acc[c]);
-    if (lane == c) zc = sum;
+  for (int off = 8; off < 64; off <<= 1) {
+    a0 += __shfl_xor(a0, off, 64);
+    a1 += __shfl_xor(a1, off, 64);
   }
-  double rr = 0.0, rz = 0.0;
-  if (lane < kColGroup && i >= 0) {
-    const int col = g * kColGroup + lane;
-    if (scal == nullptr || scal[S_ACT * cols + col] != 0.0) {
-      const int64_t idx = (int64_t)col * ld + i;
-      const double ri = r[idx];
-      z[idx] = zc;
-      if (set_p) p[idx] = (VT)zc;
-      rr = ri * ri;
-      rz = ri * zc;
+  // lanes 0..7 hold columns (2h, 2h + 1)
+  if (lane < 8) {
+    double d[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    if (i >= 0) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double zi = u ? a1 : a0, rv = u ? ri.y : ri.x;
+        if (u ? act1 : act0) {
+          const int64_t idx = (int64_t)(c0 + u) * ld + i;
+          z[idx] = zi;
+          if (set_p) p[idx] = (VT)zi;
+          d[u][0] = rv * rv;
+          d[u][1] = rv * zi;
+        }
+      }
+    }
+    if (bpart != nullptr) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        red[wave][2 * h + u][0] = d[u][0];
+        red[wave][2 * h + u][1] = d[u][1];
+      }
     }
   }
   if (bpart == nullptr) return;
-  if (lane < kColGroup) {
-    red[wave][lane][0] = rr;
-    red[wave][lane][1] = rz;
-  }
   __syncthreads();
   if (threadIdx.x < 2 * kColGroup) {
     const int c = threadIdx.x >> 1, s2 = threadIdx.x & 1;
@@ -1015,11 +1174,23 @@ template <typename T> constexpr bool uses_split(int64_t cols) {
   return sizeof(T) <= 4 && cols >= 32;
 }
 
+// k slices of the row-split kernel (16 columns): about 432 workgroups, each
+// slice a multiple of the k step and short enough for its P copy in LDS
+template <typename T> int64_t rows_slices(int64_t ld, int64_t &kslice) {
+  constexpr int64_t kb = 4 * Mv<T>::VEC;
+  const int64_t blocks = ld / (16 * MR_WAVES);
+  const int64_t want = std::max<int64_t>(1, (432 + blocks - 1) / std::max<int64_t>(1, blocks));
+  kslice = (ld / want + kb - 1) / kb * kb;
+  kslice = std::min<int64_t>(std::max<int64_t>(kslice, kb), mr_kmax<T>());
+  return (ld + kslice - 1) / kslice;
+}
+
 // (slice, tile) pairs of the block product for cols columns: entries of p.v
 // partials per column
 template <typename T> int64_t matvec_npv(int64_t ld, int64_t cols) {
   int64_t k = 0;
   if (uses_split<T>(cols)) return split_slices(ld, k) * (ld / SP_ROWS);
+  if (cols == 16) return rows_slices<T>(ld, k) * (ld / 16);
   return matvec_slices<T>(ld, k) * matvec_tiles<T>(ld);
 }
 
@@ -1030,14 +1201,27 @@ int64_t max_slices(int64_t ld) {
                    matvec_slices<uint16_t>(ld, k), split_slices(ld, k)});
 }
 
+// elements of the partial-product buffer for up to cols columns: slices x
+// columns x ld for the widest case (the row-split kernel only serves 16
+// columns)
+int64_t vpart_elems(int64_t ld, int64_t cols) {
+  int64_t k = 0;
+  const int64_t rows = std::max({rows_slices<double>(ld, k), rows_slices<float>(ld, k),
+                                 rows_slices<uint16_t>(ld, k)});
+  return ld * std::max(cols * max_slices(ld), (int64_t)kColGroup * rows);
+}
+
 template <typename T, int NG>
 hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typename Mv<T>::VT *P,
                            typename Mv<T>::VT *part, double *pv_part, int &slices,
                            const int *gate) {
   constexpr bool split = uses_split<T>(NG * 16);
+  constexpr bool rows = NG == 1;
   int64_t kslice = 0;
-  slices = split ? (int)split_slices(ld, kslice) : (int)matvec_slices<T>(ld, kslice);
-  const int64_t tiles = split ? ld / SP_ROWS : matvec_tiles<T>(ld);
+  slices = split  ? (int)split_slices(ld, kslice)
+           : rows ? (int)rows_slices<T>(ld, kslice)
+                  : (int)matvec_slices<T>(ld, kslice);
+  const int64_t tiles = split ? ld / SP_ROWS : rows ? ld / (16 * MR_WAVES) : matvec_tiles<T>(ld);
   hipEvent_t ea = nullptr, eb = nullptr;
   int *mark = nullptr;
   if (t_prof && t_prof->enabled) {
@@ -1049,7 +1233,12 @@ hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typenam
     eb = r.b;
     if (gate) mark = t_prof->take_mark(r);
   }
-  if constexpr (split) {
+  if constexpr (rows) {
+    const size_t lds = sizeof(typename Mv<T>::VT) * 16 * (size_t)(kslice + mr_pad<T>());
+    hipExtLaunchKernelGGL((block_matvec_rows_kernel<T>), dim3((unsigned)tiles, (unsigned)slices),
+                          dim3(64 * MR_WAVES), lds, st, ea, eb, 0, E, ld, P, part, kslice,
+                          (int64_t)16 * ld, pv_part, gate, mark);
+  } else if constexpr (split) {
     hipExtLaunchKernelGGL((block_matvec_split_kernel<T, NG>),
                           dim3((unsigned)tiles, (unsigned)slices), dim3(256), 0, st, ea, eb, 0, E,
                           ld, P, part, kslice, (int64_t)(NG * 16) * ld, pv_part, gate, mark);
@@ -1077,7 +1266,7 @@ hipError_t launch_matvec(hipStream_t st, const T *E, int64_t ld, int64_t cols,
 }
 
 void free_workspace(Workspace &w) {
-  void *ptrs[] = {w.x, w.r, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.bx, w.bres, w.flags,
+  void *ptrs[] = {w.x, w.r, w.rt, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.bx, w.bres, w.flags,
                   w.xf, w.rf, w.pf, w.zf, w.vf, w.bpart};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -1095,8 +1284,11 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
   const int64_t ld = s->ld;
   const size_t vec = sizeof(double) * (size_t)ld * (size_t)cols;
   const int64_t nblk = (s->n + CHUNK - 1) / CHUNK;
-  const int64_t nsl = max_slices(ld);
-  const int64_t npv = nsl * (ld / 16);   // most (slice, tile) pairs of the block product
+  const int64_t vpe = vpart_elems(ld, cols);
+  // most (slice, tile) pairs of the block product per column
+  int64_t k = 0;
+  const int64_t npv = std::max({max_slices(ld), rows_slices<double>(ld, k), rows_slices<float>(ld, k),
+                                rows_slices<uint16_t>(ld, k)}) * (ld / 16);
   size_t total = 0;
   auto alloc = [&](void **p, size_t bytes) -> bool {
     if (hipMalloc(p, bytes) != hipSuccess) {
@@ -1107,10 +1299,11 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
     return true;
   };
   // x, r, z, b, v (FP64); p (FP64) and pf, vf (FP32) for the mixed modes
-  bool ok = alloc(&w.x, vec) && alloc(&w.r, vec) && alloc(&w.p, vec) && alloc(&w.z, vec) &&
-            alloc(&w.v, vec * (size_t)nsl) && alloc((void **)&w.bx, vec) &&
+  bool ok = alloc(&w.x, vec) && alloc(&w.r, vec) && alloc((void **)&w.rt, vec) &&
+            alloc(&w.p, vec) && alloc(&w.z, vec) &&
+            alloc(&w.v, sizeof(double) * (size_t)vpe) && alloc((void **)&w.bx, vec) &&
             alloc((void **)&w.bres, vec) &&
-            alloc(&w.pf, vec / 2) && alloc(&w.vf, vec / 2 * (size_t)nsl) &&
+            alloc(&w.pf, vec / 2) && alloc(&w.vf, sizeof(float) * (size_t)vpe) &&
             alloc((void **)&w.partial, sizeof(double) * 2 * (size_t)(nblk + npv) * cols) &&
             alloc((void **)&w.scal, sizeof(double) * S_NFIELDS * cols) &&
             alloc((void **)&w.bpart,
@@ -1138,14 +1331,14 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
     set_error("workspace memset failed");
     return CPM_EDEVICE;
   }
-  void *zs[] = {w.x, w.r, w.p, w.z, w.bx, w.bres};
+  void *zs[] = {w.x, w.r, w.rt, w.p, w.z, w.bx, w.bres};
   for (void *q : zs)
     if (hipMemset(q, 0, vec) != hipSuccess) {
       set_error("workspace memset failed");
       return CPM_EDEVICE;
     }
-  if (hipMemset(w.v, 0, vec * (size_t)nsl) != hipSuccess ||
-      hipMemset(w.vf, 0, vec / 2 * (size_t)nsl) != hipSuccess) {
+  if (hipMemset(w.v, 0, sizeof(double) * (size_t)vpe) != hipSuccess ||
+      hipMemset(w.vf, 0, sizeof(float) * (size_t)vpe) != hipSuccess) {
     set_error("workspace memset failed");
     return CPM_EDEVICE;
   }
@@ -1170,7 +1363,7 @@ template <typename T> struct Solver {
   const T *E;
   int64_t n, ld, cols;
   int nblk, npv;
-  double *x, *r, *z, *b, *v64, *partial, *pvp, *scal;
+  double *x, *r, *z, *b, *v64, *partial, *pvp, *scal, *rt;
   VT *p, *v;
   int *flags;
   int slot = 0;
@@ -1185,6 +1378,7 @@ template <typename T> struct Solver {
     npv = (int)matvec_npv<T>(ld, cols);
     Workspace &w = s->ws;
     x = (double *)w.x; r = (double *)w.r; z = (double *)w.z; b = w.bx; v64 = (double *)w.v;
+    rt = w.rt;
     partial = w.partial;
     pvp = w.partial + 2 * (int64_t)nblk * cols;
     scal = w.scal;
@@ -1219,17 +1413,22 @@ template <typename T> struct Solver {
   int nred() const { return pc ? npc() : nblk; }
   const double *dots() const { return pc ? s->ws.bpart : partial; }
 
-  // z = P r with the DC preconditioner
-  void precondition(bool set_p, const int *gate) {
+  // z = P r with the DC preconditioner; to_rows: r was written by another
+  // kernel than the update, so its row-interleaved copy is made first
+  void precondition(bool set_p, const int *gate, bool to_rows) {
+    if (to_rows)
+      hipLaunchKernelGGL(rows_kernel, dim3((unsigned)(ld / RT_ROWS), (unsigned)(cols / kColGroup)),
+                         dim3(RED_THREADS), 0, st, (const double *)r, ld, n, (int)cols, rt, ld,
+                         gate);
     hipLaunchKernelGGL(precond_kernel<VT>, dim3((unsigned)npc(), (unsigned)(cols / kColGroup)),
-                       dim3(RED_THREADS), 0, st, r, z, p, pc->idx, pc->val, pc->width,
+                       dim3(RED_THREADS), 0, st, (const double *)rt, z, p, pc->idx, pc->val, pc->width,
                        s->atom_order, ld, n, (int)cols, scal, s->ws.bpart, set_p ? 1 : 0, gate);
   }
 
   // z = M^-1 r (and p = z when restarting); rz into the current slot
   hipError_t refresh(bool set_p, const int *gate) {
     if (pc)
-      precondition(set_p, gate);
+      precondition(set_p, gate, true);
     else
       hipLaunchKernelGGL(cg_refresh_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, r, z, p, s->dinv,
                          ld, n, (int)cols, scal, partial, set_p ? 1 : 0, gate);
@@ -1246,12 +1445,12 @@ template <typename T> struct Solver {
     if (pc) {
       hipLaunchKernelGGL((cg_update_kernel<VT, false>), grid(), dim3(RED_THREADS), 0, st, x, r, z, p,
                          v, sl, ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial,
-                         flags);
-      precondition(false, flags + F_ANY);
+                         flags, rt);
+      precondition(false, flags + F_ANY, false);
     } else {
       hipLaunchKernelGGL((cg_update_kernel<VT, true>), grid(), dim3(RED_THREADS), 0, st, x, r, z, p,
                          v, sl, ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial,
-                         flags);
+                         flags, (double *)nullptr);
     }
     hipLaunchKernelGGL(cg_direction_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, p, z, ld, n,
                        (int)cols, nred(), dots(), scal, slot);
@@ -1555,9 +1754,10 @@ cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z
     const int64_t cols = round_up(fc, kColGroup);
     cpm_status stt = ensure_workspace(s, cols);
     if (stt != CPM_OK) return stt;
-    double *in = s->ws.bres, *out = s->ws.bx;
-    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)cols), dim3(256),
-                       0, st, r_dev + f0 * n, n, (int64_t)fc, in, ld, cols);
+    double *in = s->ws.rt, *out = s->ws.bx;
+    hipLaunchKernelGGL(rows_kernel, dim3((unsigned)(ld / RT_ROWS), (unsigned)(cols / kColGroup)),
+                       dim3(RED_THREADS), 0, st, r_dev + f0 * n, n, n, fc, in, ld,
+                       (const int *)nullptr);
     hipLaunchKernelGGL(precond_kernel<double>,
                        dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
                        dim3(RED_THREADS), 0, st, (const double *)in, out, (double *)nullptr,

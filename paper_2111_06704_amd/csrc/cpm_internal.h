@@ -49,6 +49,7 @@ struct Workspace {            // CG scratch, grown on demand
   // FP32 vectors of the inner CG, separate from the FP64 ones so that their
   // padding rows (>= n) are always zero
   void *xf = nullptr, *rf = nullptr, *pf = nullptr, *zf = nullptr, *vf = nullptr;
+  double *rt = nullptr;       // n_pad*cols double: r with the 16 columns of a group interleaved
   double *partial = nullptr;  // dot partial sums: 2*nblk*cols
   double *bpart = nullptr;    // per-workgroup dot partials of the preconditioner apply
   double *scal = nullptr;     // per-column scalars, see cg.hip
