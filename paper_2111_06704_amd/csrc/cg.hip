@@ -7,20 +7,24 @@
 // contiguous array of ld values; rows >= n stay zero (E's padded columns
 // are zero, and 0 * NaN would not be).
 //
-// One iteration is three kernels:
-//   block_matvec_kernel  v = E p as k-slice partials: workgroup (tile, slice)
-//     owns 16*RT rows and one k slice split over its 4 waves, each
-//     accumulating 16x16 MFMA blocks
+// One Jacobi-preconditioned iteration is three kernels:
+//   block product        v = E p as k-slice partials (16 columns: the
+//     row-split kernel, waves over rows, the P slice in LDS; 32..64 columns
+//     of an FP64 E: block_matvec_kernel, workgroup (tile, slice) owning
+//     16*RT rows and one k slice split over its 4 waves; 32..64 columns of
+//     an FP32 / BF16 E: the split-bf16 kernel). MFMA blocks of 16x16
 //     (v_mfma_f64_16x16x4f64 for FP64 E, v_mfma_f32_16x16x4f32 for FP32 and
 //     BF16 E, products accumulated in FP32). Lane l supplies A[l % 16][l / 16]
 //     and B[l / 16][l % 16]; the k slots of the MFMA are mapped to 32
 //     contiguous bytes of an E row per lane, so E and P are read with wide,
-//     coalesced loads. The waves' partial tiles are summed in LDS in a fixed
-//     order and the workgroup's share of p.v is reduced.
+//     coalesced loads. Each workgroup also reduces its share of p.v.
 //   cg_update_kernel     v = sum of the slices; alpha = r.z / p.v;
 //                        x += alpha p; r -= alpha v;
 //                        z = M^-1 r (Jacobi, M = diag E); partial r.r, r.z.
 //   cg_direction_kernel  beta = r'.z' / r.z; p = z + beta p.
+// With PCG-DC (Sec. III.B.2) the update is cg_update_pc_kernel (it also
+// writes the row-interleaved copy of r) and precond_kernel computes z = P r
+// and the partial r.r, r.z before the direction kernel.
 // All dots are FP64 and reduced in a fixed order (bitwise reproducible).
 //
 // Control runs on the device: every check_every iterations a one-wave
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(256) void block_matvec_kernel(
 // operands from LDS, so P is read from L2 once per workgroup and no
 // reduction across waves is needed:
 //   part[s][c][row] = sum_{k in slice s} E[row][k] P[c][k]
-//   pv_part[s][wave tile][c] = sum over the tile's 16 rows of P[c][row] part[s][c][row]
+//   pv_part[s][workgroup][c] = sum over the workgroup's rows of P[c][row] part[s][c][row]
 constexpr int MR_WAVES = 8;
 extern __shared__ double mv_lds[];
 
@@ -362,7 +366,15 @@ __global__ __launch_bounds__(64 * MR_WAVES) void block_matvec_rows_kernel(
   if (pv_part == nullptr) return;
   pv += __shfl_xor(pv, 16, 64);
   pv += __shfl_xor(pv, 32, 64);
-  if (lg == 0) pv_part[(sl * (ld / 16) + wtile) * 16 + lr] = pv;
+  __shared__ double pvs[MR_WAVES][16];
+  if (lg == 0) pvs[wave][lr] = pv;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < MR_WAVES; ++w) t += pvs[w][threadIdx.x];
+    pv_part[(sl * gridDim.x + blockIdx.x) * 16 + threadIdx.x] = t;
+  }
 }
 
 // ---- block product on bf16 matrix cores (32..64 columns, FP32 or BF16 E)
@@ -601,12 +613,41 @@ __device__ inline double block_sum(double v, double *red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// sum of v[b * stride + off] over b = b0, b0 + step, ... < nb in a fixed
+// order, sixteen loads in flight (clamped indices keep the loads unconditional)
+__device__ inline double strided_sum(const double *__restrict__ v, int nb, int b0, int step,
+                                     int64_t stride, int64_t off) {
+  double s = 0.0;
+  for (int b = b0; b < nb; b += 16 * step) {
+    double t[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int bb = b + m * step;
+      t[m] = v[(int64_t)(bb < nb ? bb : nb - 1) * stride + off];
+      if (bb >= nb) t[m] = 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) s += t[m];
+  }
+  return s;
+}
+
 // sum of the k-slice partial products of element idx (fixed order)
 template <typename VT>
 __device__ inline double sum_slices(const VT *__restrict__ part, int slices, int64_t stride,
                                     int64_t idx) {
-  double v = (double)part[idx];
-  for (int sl = 1; sl < slices; ++sl) v += (double)part[sl * stride + idx];
+  double v = 0.0;
+  for (int s0 = 0; s0 < slices; s0 += 8) {
+    VT t[8];   // eight loads in flight; clamped indices keep them unconditional
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int sl = s0 + m;
+      t[m] = part[(int64_t)(sl < slices ? sl : slices - 1) * stride + idx];
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+      if (s0 + m < slices) v += (double)t[m];
+  }
   return v;
 }
 
@@ -718,18 +759,16 @@ __global__ __launch_bounds__(RED_THREADS) void set_scalars_kernel(
   }
 }
 
-// alpha = rz / p.v; x += alpha p; r -= alpha v. Jacobi (JAC): also z = M^-1 r
-// and the partial rr, rz; otherwise r is also written to its row-interleaved
-// copy rt and the preconditioner kernel that follows computes z and the
-// partials.
-template <typename VT, bool JAC>
+// Jacobi path: alpha = rz / p.v; x += alpha p; r -= alpha v; z = M^-1 r and
+// the partial rr, rz.
+template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
     double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
     const VT *__restrict__ p, const VT *__restrict__ vpart, int slices, int64_t stride,
     const double *__restrict__ dinv, int64_t ld, int64_t n, int cols, int npv,
     const double *__restrict__ pv_part,
     const double *__restrict__ scal, int slot, double *__restrict__ partial,
-    int *__restrict__ flags, double *__restrict__ rt) {
+    int *__restrict__ flags) {
   __shared__ double red[3][4];
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
@@ -757,24 +796,82 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
       x[idx] += alpha * (double)p[idx];
       const double ri = r[idx] - alpha * sum_slices(vpart, slices, stride, idx);
       r[idx] = ri;
-      if constexpr (!JAC)
-        rt[((int64_t)(c / kColGroup) * ld + i) * kColGroup + (c % kColGroup)] = ri;
-      if constexpr (JAC) {
-        const double zi = ri * dinv[i];
-        z[idx] = zi;
-        arr += ri * ri;
-        arz += ri * zi;
+      const double zi = ri * dinv[i];
+      z[idx] = zi;
+      arr += ri * ri;
+      arz += ri * zi;
+    }
+  }
+  arr = block_sum(arr, red[1]);
+  arz = block_sum(arz, red[2]);
+  if (threadIdx.x == 0) {
+    partial[((int64_t)blk * cols + c) * 2] = arr;
+    partial[((int64_t)blk * cols + c) * 2 + 1] = arz;
+  }
+}
+
+// PCG-DC path of the update: alpha = rz / p.v; x += alpha p; r -= alpha v,
+// and r also into its row-interleaved copy rt (layout of rows_kernel).
+// Workgroup = 16 rows x one column group of 16; thread t takes column t / 16
+// and row t % 16 (column-major accesses in 128-byte pieces); the tile goes
+// through LDS so that its rt rows are written as 2 KB of whole lines.
+constexpr int UP_ROWS = 16;
+template <typename VT>
+__global__ __launch_bounds__(RED_THREADS) void cg_update_pc_kernel(
+    double *__restrict__ x, double *__restrict__ r, const VT *__restrict__ p,
+    const VT *__restrict__ vpart, int slices, int64_t stride, int64_t ld, int64_t n, int cols,
+    int npv, const double *__restrict__ pv_part, const double *__restrict__ scal, int slot,
+    int *__restrict__ flags, double *__restrict__ rt) {
+  __shared__ double pvr[16][kColGroup + 1];
+  __shared__ double alpha_s[kColGroup];
+  __shared__ double tile[UP_ROWS][kColGroup + 1];
+  const int g = blockIdx.y;
+  const int64_t r0 = (int64_t)blockIdx.x * UP_ROWS;
+  // p.v of the group's columns: 16 threads per column over the partials
+  {
+    const int c = threadIdx.x & 15, part = threadIdx.x >> 4;
+    const int col = g * kColGroup + c;
+    pvr[part][c] = strided_sum(pv_part, npv, part, 16, cols, col);
+  }
+  __syncthreads();
+  if (threadIdx.x < kColGroup) {
+    const int c = threadIdx.x, col = g * kColGroup + c;
+    double pv = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pv += pvr[q][c];
+    const double rz = scal[(S_RZ0 + slot) * cols + col];
+    double alpha = 0.0;
+    if (scal[S_ACT * cols + col] != 0.0) {
+      if (pv > 0.0 && isfinite(pv)) {
+        alpha = rz / pv;
+      } else if (blockIdx.x == 0) {
+        flags[0] = 1;   // breakdown: p^T E p <= 0
+        flags[1] = col;
+        double *dbg = reinterpret_cast<double *>(flags + 2);
+        dbg[0] = pv;
+        dbg[1] = rz;
       }
     }
+    alpha_s[c] = alpha;
   }
-  if constexpr (JAC) {
-    arr = block_sum(arr, red[1]);
-    arz = block_sum(arz, red[2]);
-    if (threadIdx.x == 0) {
-      partial[((int64_t)blk * cols + c) * 2] = arr;
-      partial[((int64_t)blk * cols + c) * 2 + 1] = arz;
+  __syncthreads();
+  const int c = threadIdx.x >> 4, rr = threadIdx.x & 15;
+  const int col = g * kColGroup + c;
+  const int64_t i = r0 + rr;
+  const int64_t idx = (int64_t)col * ld + i;
+  double ri = 0.0;
+  if (i < n) {
+    ri = r[idx];
+    if (scal[S_ACT * cols + col] != 0.0) {
+      const double alpha = alpha_s[c];
+      x[idx] += alpha * (double)p[idx];
+      ri -= alpha * sum_slices(vpart, slices, stride, idx);
+      r[idx] = ri;
     }
   }
+  tile[rr][c] = ri;
+  __syncthreads();
+  rt[((int64_t)g * ld + r0) * kColGroup + threadIdx.x] = tile[threadIdx.x >> 4][threadIdx.x & 15];
 }
 
 // Row-interleaved copy of the residual for the PCG-DC apply: column group g
@@ -816,11 +913,12 @@ __global__ __launch_bounds__(RED_THREADS) void rows_kernel(const double *__restr
 // summed by shuffles in a fixed order. Active columns only (scal == nullptr:
 // all); set_p: p = z. bpart (may be null): per workgroup and column (r.r,
 // r.z), summed by the kernels that need the totals.
-constexpr int PC_ROWS = RED_THREADS / 64;   // rows per workgroup
+constexpr int PC_ROWS = 4;                  // rows (waves) per workgroup
+constexpr int PC_THREADS = 64 * PC_ROWS;
 constexpr int PC_CHUNK = 256;               // entries per row staged at a time
 
 template <typename VT>
-__global__ __launch_bounds__(RED_THREADS) void precond_kernel(
+__global__ __launch_bounds__(PC_THREADS) void precond_kernel(
     const double *__restrict__ rt, double *__restrict__ z, VT *__restrict__ p,
     const int32_t *__restrict__ pidx, const double *__restrict__ pval, int width,
     const int32_t *__restrict__ order, int64_t ld, int64_t n, int cols,
@@ -851,7 +949,7 @@ __global__ __launch_bounds__(RED_THREADS) void precond_kernel(
   for (int k0 = 0; k0 < width; k0 += PC_CHUNK) {
     const int cw = min(PC_CHUNK, width - k0);
     if (k0 > 0) __syncthreads();
-    for (int q = threadIdx.x; q < PC_ROWS * cw; q += RED_THREADS) {
+    for (int q = threadIdx.x; q < PC_ROWS * cw; q += PC_THREADS) {
       const int w = q / cw, k = q % cw;
       const int64_t r = rows[w];
       sidx[w][k] = r >= 0 ? pidx[r * width + k0 + k] : 0;
@@ -1190,7 +1288,7 @@ template <typename T> int64_t rows_slices(int64_t ld, int64_t &kslice) {
 template <typename T> int64_t matvec_npv(int64_t ld, int64_t cols) {
   int64_t k = 0;
   if (uses_split<T>(cols)) return split_slices(ld, k) * (ld / SP_ROWS);
-  if (cols == 16) return rows_slices<T>(ld, k) * (ld / 16);
+  if (cols == 16) return rows_slices<T>(ld, k) * (ld / (16 * MR_WAVES));
   return matvec_slices<T>(ld, k) * matvec_tiles<T>(ld);
 }
 
@@ -1421,7 +1519,7 @@ template <typename T> struct Solver {
                          dim3(RED_THREADS), 0, st, (const double *)r, ld, n, (int)cols, rt, ld,
                          gate);
     hipLaunchKernelGGL(precond_kernel<VT>, dim3((unsigned)npc(), (unsigned)(cols / kColGroup)),
-                       dim3(RED_THREADS), 0, st, (const double *)rt, z, p, pc->idx, pc->val, pc->width,
+                       dim3(PC_THREADS), 0, st, (const double *)rt, z, p, pc->idx, pc->val, pc->width,
                        s->atom_order, ld, n, (int)cols, scal, s->ws.bpart, set_p ? 1 : 0, gate);
   }
 
@@ -1443,14 +1541,14 @@ template <typename T> struct Solver {
     hipError_t e = launch_matvec<T>(st, E, ld, cols, p, v, pvp, sl, flags + F_ANY);
     if (e != hipSuccess) return e;
     if (pc) {
-      hipLaunchKernelGGL((cg_update_kernel<VT, false>), grid(), dim3(RED_THREADS), 0, st, x, r, z, p,
-                         v, sl, ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial,
-                         flags, rt);
+      hipLaunchKernelGGL(cg_update_pc_kernel<VT>, dim3((unsigned)(ld / UP_ROWS), (unsigned)(cols / kColGroup)),
+                         dim3(RED_THREADS), 0, st, x, r, (const VT *)p, (const VT *)v, sl, ld * cols,
+                         ld, n, (int)cols, npv, pvp, scal, slot, flags, rt);
       precondition(false, flags + F_ANY, false);
     } else {
-      hipLaunchKernelGGL((cg_update_kernel<VT, true>), grid(), dim3(RED_THREADS), 0, st, x, r, z, p,
+      hipLaunchKernelGGL(cg_update_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, x, r, z, p,
                          v, sl, ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial,
-                         flags, (double *)nullptr);
+                         flags);
     }
     hipLaunchKernelGGL(cg_direction_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, p, z, ld, n,
                        (int)cols, nred(), dots(), scal, slot);
@@ -1760,7 +1858,7 @@ cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z
                        (const int *)nullptr);
     hipLaunchKernelGGL(precond_kernel<double>,
                        dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
-                       dim3(RED_THREADS), 0, st, (const double *)in, out, (double *)nullptr,
+                       dim3(PC_THREADS), 0, st, (const double *)in, out, (double *)nullptr,
                        s->pc.idx, s->pc.val, s->pc.width, s->atom_order, ld, n, (int)cols,
                        (const double *)nullptr, (double *)nullptr, 0, (const int *)nullptr);
     CPM_HIP_CHECK(hipMemcpy2DAsync(z_dev + f0 * n, sizeof(double) * n, out, sizeof(double) * ld,
