@@ -62,6 +62,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int RED_THREADS = 256;
 constexpr int MAX_COLS = 64;
 constexpr int64_t CHUNK = 256;    // rows per block of the vector kernels
+// partial sums that the workgroups of one vector kernel may re-reduce in
+// total before a separate reduction launch is cheaper
+constexpr int64_t kRedLoads = (int64_t)1 << 22;
 
 // scalar fields (struct of arrays, cols entries each): r.z (two slots), r.r,
 // |b|^2, active flag, last true residual norm, relative true residual,
@@ -737,6 +740,23 @@ __global__ __launch_bounds__(RED_THREADS) void cg_refresh_kernel(
   }
 }
 
+// out[c][w] = sum over b of part[b][c][w] (w < width) in a fixed order: one
+// workgroup per column. Serves the update and direction kernels when
+// re-reducing all partials in each of their workgroups would cost more
+// than this extra launch (large systems).
+__global__ __launch_bounds__(RED_THREADS) void sum_cols_kernel(const double *__restrict__ part,
+                                                               int nb, int cols, int width,
+                                                               double *__restrict__ out) {
+  __shared__ double red[3][4];
+  const int c = blockIdx.x;
+  for (int w = 0; w < width; ++w) {
+    const double v = strided_sum(part, nb, threadIdx.x, RED_THREADS, (int64_t)cols * width,
+                                 (int64_t)c * width + w);
+    const double t = block_sum(v, red[w % 3]);
+    if (threadIdx.x == 0) out[c * width + w] = t;
+  }
+}
+
 // Reduce (rr, rz) partials into the scalars of active columns.
 // one workgroup per column
 __global__ __launch_bounds__(RED_THREADS) void set_scalars_kernel(
@@ -1364,7 +1384,7 @@ hipError_t launch_matvec(hipStream_t st, const T *E, int64_t ld, int64_t cols,
 }
 
 void free_workspace(Workspace &w) {
-  void *ptrs[] = {w.x, w.r, w.rt, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.bx, w.bres, w.flags,
+  void *ptrs[] = {w.x, w.r, w.rt, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.red, w.bx, w.bres, w.flags,
                   w.xf, w.rf, w.pf, w.zf, w.vf, w.bpart};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -1404,6 +1424,7 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
             alloc(&w.pf, vec / 2) && alloc(&w.vf, sizeof(float) * (size_t)vpe) &&
             alloc((void **)&w.partial, sizeof(double) * 2 * (size_t)(nblk + npv) * cols) &&
             alloc((void **)&w.scal, sizeof(double) * S_NFIELDS * cols) &&
+            alloc((void **)&w.red, sizeof(double) * 3 * MAX_COLS) &&
             alloc((void **)&w.bpart,
                   sizeof(double) * 2 * (size_t)((s->n + PC_ROWS - 1) / PC_ROWS) * cols) &&
             alloc((void **)&w.flags, sizeof(int) * F_NWORDS);
@@ -1540,18 +1561,37 @@ template <typename T> struct Solver {
     int sl = 0;
     hipError_t e = launch_matvec<T>(st, E, ld, cols, p, v, pvp, sl, flags + F_ANY);
     if (e != hipSuccess) return e;
+    // p.v partials: reduced once up front when every update workgroup
+    // re-reducing them would read more than kRedLoads values
+    const double *pvs = pvp;
+    int npvs = npv;
+    const int64_t upd_loads = pc ? (int64_t)npv * ld * cols / kColGroup : (int64_t)npv * nblk * cols;
+    if (upd_loads > kRedLoads) {
+      hipLaunchKernelGGL(sum_cols_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, pvp, npv,
+                         (int)cols, 1, s->ws.red);
+      pvs = s->ws.red;
+      npvs = 1;
+    }
     if (pc) {
       hipLaunchKernelGGL(cg_update_pc_kernel<VT>, dim3((unsigned)(ld / UP_ROWS), (unsigned)(cols / kColGroup)),
                          dim3(RED_THREADS), 0, st, x, r, (const VT *)p, (const VT *)v, sl, ld * cols,
-                         ld, n, (int)cols, npv, pvp, scal, slot, flags, rt);
+                         ld, n, (int)cols, npvs, pvs, scal, slot, flags, rt);
       precondition(false, flags + F_ANY, false);
     } else {
       hipLaunchKernelGGL(cg_update_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, x, r, z, p,
-                         v, sl, ld * cols, s->dinv, ld, n, (int)cols, npv, pvp, scal, slot, partial,
+                         v, sl, ld * cols, s->dinv, ld, n, (int)cols, npvs, pvs, scal, slot, partial,
                          flags);
     }
+    const double *ds = dots();
+    int nds = nred();
+    if (2 * (int64_t)nds * nblk * cols > kRedLoads) {
+      hipLaunchKernelGGL(sum_cols_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, ds, nds,
+                         (int)cols, 2, s->ws.red + MAX_COLS);
+      ds = s->ws.red + MAX_COLS;
+      nds = 1;
+    }
     hipLaunchKernelGGL(cg_direction_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, p, z, ld, n,
-                       (int)cols, nred(), dots(), scal, slot);
+                       (int)cols, nds, ds, scal, slot);
     slot ^= 1;
     return hipGetLastError();
   }

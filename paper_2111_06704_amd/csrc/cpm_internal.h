@@ -53,6 +53,7 @@ struct Workspace {            // CG scratch, grown on demand
   double *partial = nullptr;  // dot partial sums: 2*nblk*cols
   double *bpart = nullptr;    // per-workgroup dot partials of the preconditioner apply
   double *scal = nullptr;     // per-column scalars, see cg.hip
+  double *red = nullptr;      // 3*64 doubles: reduced dot partials (p.v; r.r and r.z)
   double *bx = nullptr;       // n_pad*cols double: right-hand sides / outer iterate
   double *bres = nullptr;     // n_pad*cols double: outer residual
   int *flags = nullptr;       // device status words
