@@ -183,20 +183,6 @@ __device__ inline void load_rows(TileLds &L, const float *__restrict__ feat, int
   }
 }
 
-__global__ __launch_bounds__(TT) void mlp_forward_kernel(const float *__restrict__ prm,
-                                                         const float *__restrict__ feat,
-                                                         int64_t rows, float *__restrict__ y) {
-  extern __shared__ unsigned char smem[];
-  TileLds &L = *reinterpret_cast<TileLds *>(smem);
-  const int64_t r0 = (int64_t)blockIdx.x * TR;
-  const int nrows = (int)std::min<int64_t>(TR, rows - r0);
-  load_params(L, prm);
-  load_rows(L, feat, r0, nrows);
-  __syncthreads();
-  tile_forward(L, nrows);
-  if ((int)threadIdx.x < nrows) y[r0 + threadIdx.x] = L.y[threadIdx.x];
-}
-
 // Forward + backward of one tile; writes the tile's gradient (sum over its
 // rows of d/dtheta of (y - t)^2 / rows_total) and its loss sum.
 __global__ __launch_bounds__(TT) void mlp_grad_kernel(const float *__restrict__ prm,
@@ -466,11 +452,136 @@ cpm_status build_neighbours(const cpm_system *s, std::vector<int32_t> &nbr,
 
 }  // namespace
 
+// Inference of many rows: each workgroup copies the parameters into LDS
+// once and then runs tiles of IR rows (grid-stride over tiles). Thread t
+// owns rows 4 (t / 16) .. + 3 and units 4 (t % 16) .. + 3 of each layer;
+// SiLU is applied once per hidden value; the output layer is reduced over
+// the 16 threads of a row group by shuffles in a fixed order. FROM_B: the
+// inputs are formed from b in the kernel (same definition as
+// features_kernel), otherwise read from feat.
+constexpr int IR = 64;   // rows per inference tile
+struct InferLds {
+  float w1[NIN][NH];
+  float w2[NH][NH];
+  float b1[NH], b2[NH], w3[NH];
+  float x[IR][NIN + 1];
+  float h1[IR][NH + 1];
+};
+
+template <bool FROM_B>
+__global__ __launch_bounds__(TT) void mlp_infer_kernel(
+    const float *__restrict__ prm, const float *__restrict__ feat, const double *__restrict__ b,
+    const double *__restrict__ mean, int64_t n, const int32_t *__restrict__ nbr,
+    const float *__restrict__ nbr_r, const int32_t *__restrict__ layer, float inv_layers,
+    float inv_bs, float inv_rs, int64_t rows, float *__restrict__ y) {
+  __shared__ InferLds L;
+  const int t = threadIdx.x;
+  for (int q = t; q < NIN * NH; q += TT) L.w1[q / NH][q % NH] = prm[OW1 + q];
+  for (int q = t; q < NH * NH; q += TT) L.w2[q / NH][q % NH] = prm[OW2 + q];
+  for (int q = t; q < NH; q += TT) {
+    L.b1[q] = prm[OB1 + q];
+    L.b2[q] = prm[OB2 + q];
+    L.w3[q] = prm[OW3 + q];
+  }
+  const float b3 = prm[OB3];
+  const int rg = t >> 4, ug = t & 15;
+  const int64_t tiles = (rows + IR - 1) / IR;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t r0 = tile * IR;
+    __syncthreads();   // parameters loaded / previous tile done with x and h1
+    if constexpr (FROM_B) {
+      if (t < IR) {
+        const int64_t r = r0 + t;
+        if (r < rows) {
+          const int64_t f = r / n, i = r % n;
+          const double mb = mean[f];
+          const double *bf = b + f * n;
+          L.x[t][0] = (float)((bf[i] - mb) * (double)inv_bs);
+          L.x[t][1] = (float)layer[i] * inv_layers;
+#pragma unroll
+          for (int k = 0; k < NNB; ++k) {
+            L.x[t][2 + k] = (float)((bf[nbr[i * NNB + k]] - mb) * (double)inv_bs);
+            L.x[t][2 + NNB + k] = nbr_r[i * NNB + k] * inv_rs;
+          }
+        } else {
+          for (int k = 0; k < NIN; ++k) L.x[t][k] = 0.0f;
+        }
+      }
+    } else {
+      for (int q = t; q < IR * NIN; q += TT) {
+        const int r = q / NIN, k = q % NIN;
+        L.x[r][k] = (r0 + r < rows) ? feat[(r0 + r) * NIN + k] : 0.0f;
+      }
+    }
+    __syncthreads();
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = L.b1[ug * 4 + c];
+    for (int k = 0; k < NIN; ++k) {
+      float xv[4], wv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xv[a] = L.x[rg * 4 + a][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) wv[c] = L.w1[k][ug * 4 + c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xv[a], wv[c], acc[a][c]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float z = acc[a][c];
+        L.h1[rg * 4 + a][ug * 4 + c] = z * sigm(z);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = L.b2[ug * 4 + c];
+    for (int k = 0; k < NH; ++k) {
+      float hv[4], wv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) hv[a] = L.h1[rg * 4 + a][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) wv[c] = L.w2[k][ug * 4 + c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(hv[a], wv[c], acc[a][c]);
+    }
+    // y = sum_j silu(a2_j) w3_j + b3: four units here, then the 16 unit groups
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      float sp = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float z = acc[a][c];
+        sp = fmaf(z * sigm(z), L.w3[ug * 4 + c], sp);
+      }
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) sp += __shfl_xor(sp, off, 16);
+      const int64_t r = r0 + rg * 4 + a;
+      if (ug == 0 && r < rows) y[r] = sp + b3;
+    }
+  }
+}
+
+// workgroups of the inference kernel: about two per CU, at most one per tile
+unsigned infer_blocks(int64_t rows) {
+  const int64_t tiles = (rows + IR - 1) / IR;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, 512));
+}
+
 hipError_t launch_mlp_forward(hipStream_t st, const float *params, const float *feat,
                               int64_t rows, float *y) {
-  const int64_t tiles = (rows + TR - 1) / TR;
-  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)tiles), dim3(TT), tile_lds_bytes(), st,
-                     params, feat, rows, y);
+  hipLaunchKernelGGL(mlp_infer_kernel<false>, dim3(infer_blocks(rows)), dim3(TT), 0, st, params,
+                     feat, (const double *)nullptr, (const double *)nullptr, (int64_t)1,
+                     (const int32_t *)nullptr, (const float *)nullptr, (const int32_t *)nullptr,
+                     0.0f, 0.0f, 0.0f, rows, y);
   return hipGetLastError();
 }
 
@@ -568,20 +679,26 @@ cpm_status warm_start_impl(cpm_system *s, bool use_mlp, const double *b, const d
   CPM_HIP_CHECK(hipMallocAsync((void **)&mean, sizeof(double) * f, st));
   if (use_mlp) {
     cpm_status rc = ensure_rows(s, f * n);
-    if (rc == CPM_OK) rc = features_impl(s, b, f, nullptr, 0, f * n, s->mlp.feat, mean, true);
     if (rc != CPM_OK) {
       (void)hipFreeAsync(mean, st);
       return rc;
     }
-    CPM_HIP_CHECK(launch_mlp_forward(st, s->mlp.params, s->mlp.feat, f * n, s->mlp.yout));
+    const Mlp &M = s->mlp;
+    hipLaunchKernelGGL(frame_mean_kernel, dim3((unsigned)f), dim3(256), 0, st, b, n, mean);
+    const float inv_layers = M.n_layers > 1 ? 1.0f / (float)(M.n_layers - 1) : 0.0f;
+    hipLaunchKernelGGL(mlp_infer_kernel<true>, dim3(infer_blocks(f * n)), dim3(TT), 0, st,
+                       (const float *)M.params, (const float *)nullptr, b, (const double *)mean, n,
+                       (const int32_t *)M.nbr, (const float *)M.nbr_r, (const int32_t *)M.layer,
+                       inv_layers, 1.0f / M.b_scale, 1.0f / M.r_scale, f * n, M.yout);
     y = s->mlp.yout;
   }
   hipLaunchKernelGGL(neutral_shift_kernel, dim3((unsigned)f), dim3(256), 0, st, y, s->qchi, n,
                      (double)s->mlp.q_scale, qsol, x0);
-  // E q0 (FP64) for the Lagrange shift
+  // E q0 for the Lagrange shift: the FP32 copy of E when there is one (the
+  // shift only sets the start; the solver's first residual is FP64)
   double *eq = nullptr;
   CPM_HIP_CHECK(hipMallocAsync((void **)&eq, sizeof(double) * f * n, st));
-  cpm_status rc = matvec_cols(s, CPM_PREC_F64, x0, f, eq);
+  cpm_status rc = matvec_cols(s, s->E32 ? CPM_PREC_F32 : CPM_PREC_F64, x0, f, eq);
   if (rc == CPM_OK)
     hipLaunchKernelGGL(lagrange_shift_kernel, dim3((unsigned)f), dim3(256), 0, st, b, eq,
                        s->dprime, n, x0);

@@ -20,8 +20,9 @@ namespace {
 
 constexpr int RB = 256;       // threads per block
 constexpr int FG = 16;        // frames per thread in the back-projection
-constexpr int BP_AT = 4;      // atoms per thread in the back-projection
+constexpr int BP_AT = 2;      // atoms per thread in the back-projection
 constexpr int BP_KCH = 32;    // k-vectors per LDS chunk in the back-projection
+constexpr double kErfcZero = 6.5;   // erfc(x) < 4e-20 beyond: below any FP64 sum it enters
 
 // Q_sol[f] = sum_I q_I; with m1 != null also M1[f] = sum_I q_I z_I (z in [0, L_z)),
 // the ion dipole that the slab correction needs.
@@ -222,7 +223,10 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
       for (int g = 0; g < FG; ++g) {
         const double2 sv = ss[kk][g];
 #pragma unroll
-        for (int a = 0; a < AT; ++a) acc[a][g] += wc[a] * sv.x + ws[a] * sv.y;
+        for (int a = 0; a < AT; ++a) {
+          acc[a][g] = fma(wc[a], sv.x, acc[a][g]);
+          acc[a][g] = fma(ws[a], sv.y, acc[a][g]);
+        }
       }
     }
     __syncthreads();
@@ -340,7 +344,10 @@ __global__ __launch_bounds__(RB) void real_space_ions_kernel(
               if (d2 < rc2) {
                 if (d2 > 0.0) {
                   const double d = sqrt(d2);
-                  acc += q * ((erfc(beta * d) - erfc(ai * d)) / d);
+                  // erfc(a d) < 4e-20 for a d >= 6.5: taken as zero there
+                  const double t = ai * d;
+                  const double eg = t < kErfcZero ? erfc(t) : 0.0;
+                  acc += q * ((erfc(beta * d) - eg) / d);
                 } else {
                   acc += q * lim0;
                 }
