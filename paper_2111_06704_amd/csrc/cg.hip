@@ -75,9 +75,10 @@ enum {
 };
 // status words (ints): breakdown flag and column, debug doubles (ints 2..5),
 // true residual due, any column active, non-finite residual seen, number of
-// true-residual updates, a start was discarded
+// true-residual updates, a start was discarded, largest recursive residual
 enum {
   F_BREAK = 0, F_COL = 1, F_NEED = 6, F_ANY = 7, F_NONFINITE = 8, F_UPDATES = 9, F_FELLBACK = 10,
+  F_RMAX = 12,   // (double, words 12-13) largest relative recursive residual at the last check
   F_NWORDS = 16
 };
 
@@ -1027,6 +1028,112 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
   }
 }
 
+// Tiled PCG-DC apply: workgroup = one tile of kPcTile rows (consecutive in
+// the spatial order) and one column group. The residual rows of the tile's
+// halo (every atom its rows touch, 16 columns = 128 bytes each in rt) and
+// the tile's ELL values and halo positions are staged in LDS by coalesced
+// loads; the rows then gather from LDS only. Lane = 8 e + h as in
+// precond_kernel, so each z is summed in the same order as there. Each of
+// the 4 waves takes rows wave, wave + 4; bpart gets one (r.r, r.z) pair per
+// tile and column.
+extern __shared__ double pc_lds[];
+
+template <typename VT>
+__global__ __launch_bounds__(RED_THREADS) void precond_tile_kernel(
+    const double *__restrict__ rt, double *__restrict__ z, VT *__restrict__ p,
+    const int32_t *__restrict__ tile_off, const int32_t *__restrict__ tile_idx,
+    const uint16_t *__restrict__ lidx, const double *__restrict__ pval, int width, int umax,
+    const int32_t *__restrict__ order, int64_t ld, int64_t n, int cols,
+    const double *__restrict__ scal, double *__restrict__ bpart, int set_p,
+    const int *__restrict__ gate) {
+  __shared__ double red[PC_ROWS][kColGroup][2];
+  if (gate != nullptr && *gate == 0) return;
+  double *hal = pc_lds;                                   // [umax][kPcHaloStride]
+  double *sval = hal + (size_t)umax * kPcHaloStride;      // [kPcTile][width]
+  uint16_t *slid = reinterpret_cast<uint16_t *>(sval + (size_t)kPcTile * width);
+  const int g = blockIdx.y;
+  const int64_t tile = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = lane >> 3, h = lane & 7;
+  const double *rg = rt + (int64_t)g * ld * kColGroup;
+  const int h0 = tile_off[tile], hu = tile_off[tile + 1] - h0;
+  for (int q = threadIdx.x; q < hu * 8; q += RED_THREADS) {
+    const int a = q >> 3, pc = q & 7;
+    const int64_t j = tile_idx[h0 + a];
+    *reinterpret_cast<double2 *>(hal + a * kPcHaloStride + 2 * pc) =
+        *reinterpret_cast<const double2 *>(rg + j * kColGroup + 2 * pc);
+  }
+  int64_t rows[kPcTile];
+#pragma unroll
+  for (int r = 0; r < kPcTile; ++r) {
+    const int64_t t = tile * kPcTile + r;
+    rows[r] = t < n ? (int64_t)order[t] : -1;
+  }
+  for (int q = threadIdx.x; q < kPcTile * width; q += RED_THREADS) {
+    const int r = q / width, k = q % width;
+    const int64_t row = rows[r];
+    sval[q] = row >= 0 ? pval[row * width + k] : 0.0;
+    slid[q] = row >= 0 ? lidx[row * width + k] : (uint16_t)0;
+  }
+  const int c0 = g * kColGroup + 2 * h;
+  const bool act0 = scal == nullptr || scal[S_ACT * cols + c0] != 0.0;
+  const bool act1 = scal == nullptr || scal[S_ACT * cols + c0 + 1] != 0.0;
+  __syncthreads();
+  double d00 = 0.0, d01 = 0.0, d10 = 0.0, d11 = 0.0;   // (r.r, r.z) of columns c0, c0 + 1
+  for (int rr = wave; rr < kPcTile; rr += PC_ROWS) {
+    const int64_t i = rows[rr];
+    double a0 = 0.0, a1 = 0.0;
+    if (i >= 0) {
+      const uint16_t *lp = slid + rr * width;
+      const double *vp = sval + rr * width;
+#pragma unroll 4
+      for (int k = e; k < width; k += 8) {
+        const double v = vp[k];
+        const double2 x = *reinterpret_cast<const double2 *>(hal + (int)lp[k] * kPcHaloStride + 2 * h);
+        a0 += v * x.x;
+        a1 += v * x.y;
+      }
+    }
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1) {
+      a0 += __shfl_xor(a0, off, 64);
+      a1 += __shfl_xor(a1, off, 64);
+    }
+    if (lane < 8 && i >= 0) {
+      const double2 ri = *reinterpret_cast<const double2 *>(rg + i * kColGroup + 2 * h);
+      if (act0) {
+        const int64_t idx = (int64_t)c0 * ld + i;
+        z[idx] = a0;
+        if (set_p) p[idx] = (VT)a0;
+        d00 += ri.x * ri.x;
+        d01 += ri.x * a0;
+      }
+      if (act1) {
+        const int64_t idx = (int64_t)(c0 + 1) * ld + i;
+        z[idx] = a1;
+        if (set_p) p[idx] = (VT)a1;
+        d10 += ri.y * ri.y;
+        d11 += ri.y * a1;
+      }
+    }
+  }
+  if (bpart == nullptr) return;
+  if (lane < 8) {
+    red[wave][2 * h][0] = d00;
+    red[wave][2 * h][1] = d01;
+    red[wave][2 * h + 1][0] = d10;
+    red[wave][2 * h + 1][1] = d11;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kColGroup) {
+    const int c = threadIdx.x >> 1, s2 = threadIdx.x & 1;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < PC_ROWS; ++w) v += red[w][c][s2];
+    bpart[((int64_t)blockIdx.x * cols + g * kColGroup + c) * 2 + s2] = v;
+  }
+}
+
 // beta = rz' / rz; p = z + beta p; block 0 stores rz' in the other slot and rr.
 template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
@@ -1127,6 +1234,7 @@ __global__ void ctl_check_kernel(double *__restrict__ scal, int cols, int it_aft
                                  int max_iter, double tol, double ru, int *__restrict__ flags) {
   const int c = threadIdx.x;
   bool need = false, bad = false;
+  double rel = 0.0;
   if (c < cols && scal[S_ACT * cols + c] != 0.0) {
     scal[S_IT * cols + c] += (double)todo;
     const double bn = sqrt(scal[S_BN2 * cols + c]);
@@ -1134,11 +1242,15 @@ __global__ void ctl_check_kernel(double *__restrict__ scal, int cols, int it_aft
     if (!isfinite(rn)) bad = true;
     need = rn <= 0.5 * tol * bn || (ru > 0.0 && rn <= ru * scal[S_RT * cols + c]) ||
            it_after >= max_iter;
+    rel = bn > 0.0 ? rn / bn : 0.0;
   }
   const bool any_need = __any(need), any_bad = __any(bad);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) rel = fmax(rel, __shfl_xor(rel, off, 64));
   if (threadIdx.x == 0) {
     flags[F_NEED] = any_need ? 1 : 0;
     if (any_bad) flags[F_NONFINITE] = 1;
+    *reinterpret_cast<double *>(flags + F_RMAX) = rel;
   }
 }
 
@@ -1257,13 +1369,19 @@ template <typename T> constexpr int prec_of() {
 
 template <typename T> int64_t matvec_tiles(int64_t ld) { return ld / (16 * Mv<T>::RT); }
 
-// k slices of the block product: enough workgroups (~1024) to fill the chip;
-// each slice is a multiple of 4 waves x KB columns.
-template <typename T> int64_t matvec_slices(int64_t ld, int64_t &kslice) {
+// k slices of the block product for cols columns: enough workgroups (~1024)
+// to fill the chip, and slices short enough that the cols x kslice block of
+// P (<= 1 MB) stays in L2 while the row tiles of one slice pass over it
+// (workgroups are dispatched tile-fastest, so those of one slice run
+// together); each slice a multiple of 4 waves x KB columns.
+template <typename T> int64_t matvec_slices(int64_t ld, int64_t cols, int64_t &kslice) {
   constexpr int64_t unit = 4 * 4 * Mv<T>::VEC;
   const int64_t tiles = matvec_tiles<T>(ld);
   const int64_t units = ld / unit;   // ld is a multiple of 128 >= unit
+  const int64_t kcap = std::max<int64_t>(
+      unit, ((int64_t)1 << 20) / (cols * (int64_t)sizeof(typename Mv<T>::VT)) / unit * unit);
   int64_t want = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
+  want = std::max<int64_t>(want, (ld + kcap - 1) / kcap);
   want = std::min<int64_t>(want, std::max<int64_t>(1, units));
   // prefer a slice count near want that splits the k range evenly
   int64_t best = want;
@@ -1309,24 +1427,33 @@ template <typename T> int64_t matvec_npv(int64_t ld, int64_t cols) {
   int64_t k = 0;
   if (uses_split<T>(cols)) return split_slices(ld, k) * (ld / SP_ROWS);
   if (cols == 16) return rows_slices<T>(ld, k) * (ld / (16 * MR_WAVES));
-  return matvec_slices<T>(ld, k) * matvec_tiles<T>(ld);
+  return matvec_slices<T>(ld, cols, k) * matvec_tiles<T>(ld);
 }
 
-// largest slice count of any kernel (buffer sizing)
-int64_t max_slices(int64_t ld) {
+// slices of the kernel that serves c columns of an E of type T
+template <typename T> int64_t slices_for(int64_t ld, int64_t c) {
   int64_t k = 0;
-  return std::max({matvec_slices<double>(ld, k), matvec_slices<float>(ld, k),
-                   matvec_slices<uint16_t>(ld, k), split_slices(ld, k)});
+  if (uses_split<T>(c)) return split_slices(ld, k);
+  if (c == kColGroup) return rows_slices<T>(ld, k);
+  return matvec_slices<T>(ld, c, k);
 }
 
-// elements of the partial-product buffer for up to cols columns: slices x
-// columns x ld for the widest case (the row-split kernel only serves 16
-// columns)
+// elements of the partial-product buffer for up to cols columns (slices x
+// columns x ld of the widest case) and the most (slice, tile) pairs of p.v
+// partials per column
 int64_t vpart_elems(int64_t ld, int64_t cols) {
-  int64_t k = 0;
-  const int64_t rows = std::max({rows_slices<double>(ld, k), rows_slices<float>(ld, k),
-                                 rows_slices<uint16_t>(ld, k)});
-  return ld * std::max(cols * max_slices(ld), (int64_t)kColGroup * rows);
+  int64_t e = 0;
+  for (int64_t c = kColGroup; c <= cols; c += kColGroup)
+    e = std::max({e, c * slices_for<double>(ld, c), c * slices_for<float>(ld, c),
+                  c * slices_for<uint16_t>(ld, c)});
+  return ld * e;
+}
+int64_t max_npv(int64_t ld, int64_t cols) {
+  int64_t e = 0;
+  for (int64_t c = kColGroup; c <= cols; c += kColGroup)
+    e = std::max({e, matvec_npv<double>(ld, c), matvec_npv<float>(ld, c),
+                  matvec_npv<uint16_t>(ld, c)});
+  return e;
 }
 
 template <typename T, int NG>
@@ -1338,7 +1465,7 @@ hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typenam
   int64_t kslice = 0;
   slices = split  ? (int)split_slices(ld, kslice)
            : rows ? (int)rows_slices<T>(ld, kslice)
-                  : (int)matvec_slices<T>(ld, kslice);
+                  : (int)matvec_slices<T>(ld, NG * 16, kslice);
   const int64_t tiles = split ? ld / SP_ROWS : rows ? ld / (16 * MR_WAVES) : matvec_tiles<T>(ld);
   hipEvent_t ea = nullptr, eb = nullptr;
   int *mark = nullptr;
@@ -1403,10 +1530,7 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
   const size_t vec = sizeof(double) * (size_t)ld * (size_t)cols;
   const int64_t nblk = (s->n + CHUNK - 1) / CHUNK;
   const int64_t vpe = vpart_elems(ld, cols);
-  // most (slice, tile) pairs of the block product per column
-  int64_t k = 0;
-  const int64_t npv = std::max({max_slices(ld), rows_slices<double>(ld, k), rows_slices<float>(ld, k),
-                                rows_slices<uint16_t>(ld, k)}) * (ld / 16);
+  const int64_t npv = max_npv(ld, cols);   // most p.v partials per column
   size_t total = 0;
   auto alloc = [&](void **p, size_t bytes) -> bool {
     if (hipMalloc(p, bytes) != hipSuccess) {
@@ -1473,6 +1597,26 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
   return CPM_OK;
 }
 
+// z = P r (PCG-DC) for cols columns of the row-interleaved residual rt: the
+// tiled kernel when the tile's halo fits in LDS, else the row kernel.
+// bpart gets one (r.r, r.z) pair per workgroup and column.
+template <typename VT>
+void launch_precond(hipStream_t st, const cpm_system *s, const Precond &pc, const double *rt,
+                    double *z, VT *p, int64_t cols, const double *scal, double *bpart, bool set_p,
+                    const int *gate) {
+  const int64_t ld = s->ld, n = s->n;
+  if (pc.tiled) {
+    hipLaunchKernelGGL(precond_tile_kernel<VT>, dim3((unsigned)pc.ntiles, (unsigned)(cols / kColGroup)),
+                       dim3(RED_THREADS), pc_tile_lds(pc.umax, pc.width), st, rt, z, p, pc.tile_off,
+                       pc.tile_idx, pc.lidx, pc.val, pc.width, pc.umax, s->atom_order, ld, n,
+                       (int)cols, scal, bpart, set_p ? 1 : 0, gate);
+  } else {
+    hipLaunchKernelGGL(precond_kernel<VT>, dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
+                       dim3(PC_THREADS), 0, st, rt, z, p, pc.idx, pc.val, pc.width, s->atom_order,
+                       ld, n, (int)cols, scal, bpart, set_p ? 1 : 0, gate);
+  }
+}
+
 // The solver over one block of cols columns. VT is the vector type of p and
 // v (double for FP64 E, float for FP32 / BF16 E); x, r, z, b are FP64.
 template <typename T> struct Solver {
@@ -1528,7 +1672,7 @@ template <typename T> struct Solver {
   // partial sums of r.r / r.z per column that the direction and set_scalars
   // kernels add up: one per vector block (Jacobi) or per preconditioner
   // workgroup (DC)
-  int npc() const { return (int)((n + PC_ROWS - 1) / PC_ROWS); }
+  int npc() const { return pc && pc->tiled ? (int)pc->ntiles : (int)((n + PC_ROWS - 1) / PC_ROWS); }
   int nred() const { return pc ? npc() : nblk; }
   const double *dots() const { return pc ? s->ws.bpart : partial; }
 
@@ -1539,9 +1683,7 @@ template <typename T> struct Solver {
       hipLaunchKernelGGL(rows_kernel, dim3((unsigned)(ld / RT_ROWS), (unsigned)(cols / kColGroup)),
                          dim3(RED_THREADS), 0, st, (const double *)r, ld, n, (int)cols, rt, ld,
                          gate);
-    hipLaunchKernelGGL(precond_kernel<VT>, dim3((unsigned)npc(), (unsigned)(cols / kColGroup)),
-                       dim3(PC_THREADS), 0, st, (const double *)rt, z, p, pc->idx, pc->val, pc->width,
-                       s->atom_order, ld, n, (int)cols, scal, s->ws.bpart, set_p ? 1 : 0, gate);
+    launch_precond<VT>(st, s, *pc, rt, z, p, cols, scal, s->ws.bpart, set_p, gate);
   }
 
   // z = M^-1 r (and p = z when restarting); rz into the current slot
@@ -1656,6 +1798,13 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
   const int check = std::max(1, o.check_every);
   int it = 0, pending = -1, batch = 0;
   auto status_of = [&](int slot) { return w.hstat + slot * F_NWORDS; };
+  auto finished = [](const int *fl) { return fl[F_BREAK] || fl[F_NONFINITE] || fl[F_ANY] == 0; };
+  auto rmax_of = [](const int *fl) {
+    double v;
+    std::memcpy(&v, fl + F_RMAX, sizeof(v));
+    return v;
+  };
+  double rhist[2] = {0.0, 0.0};   // largest recursive residual of the last two batches read
   while (it < o.max_iter) {
     const int todo = std::min(check, o.max_iter - it);
     for (int k = 0; k < todo; ++k) CPM_HIP_CHECK(sv.iterate());
@@ -1675,7 +1824,21 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
     if (pending >= 0) {
       CPM_HIP_CHECK(hipEventSynchronize(w.ev[pending]));
       const int *fl = status_of(pending);
-      if (fl[F_BREAK] || fl[F_NONFINITE] || fl[F_ANY] == 0) break;
+      if (finished(fl)) break;
+      rhist[0] = rhist[1];
+      rhist[1] = rmax_of(fl);
+      // when the batch just enqueued is expected to reach the tolerance (its
+      // residual extrapolated from the last two), read its status before
+      // enqueuing another one, which would only run gated off
+      if (rhist[0] > 0.0 && rhist[1] * (rhist[1] / rhist[0]) <= 0.5 * tol) {
+        CPM_HIP_CHECK(hipEventSynchronize(w.ev[slot]));
+        const int *fl2 = status_of(slot);
+        if (finished(fl2)) break;
+        rhist[0] = rhist[1];
+        rhist[1] = rmax_of(fl2);
+        pending = -1;
+        continue;
+      }
     }
     pending = slot;
   }
@@ -1896,11 +2059,8 @@ cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z
     hipLaunchKernelGGL(rows_kernel, dim3((unsigned)(ld / RT_ROWS), (unsigned)(cols / kColGroup)),
                        dim3(RED_THREADS), 0, st, r_dev + f0 * n, n, n, fc, in, ld,
                        (const int *)nullptr);
-    hipLaunchKernelGGL(precond_kernel<double>,
-                       dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
-                       dim3(PC_THREADS), 0, st, (const double *)in, out, (double *)nullptr,
-                       s->pc.idx, s->pc.val, s->pc.width, s->atom_order, ld, n, (int)cols,
-                       (const double *)nullptr, (double *)nullptr, 0, (const int *)nullptr);
+    launch_precond<double>(st, s, s->pc, in, out, (double *)nullptr, cols, nullptr, nullptr, false,
+                           nullptr);
     CPM_HIP_CHECK(hipMemcpy2DAsync(z_dev + f0 * n, sizeof(double) * n, out, sizeof(double) * ld,
                                    sizeof(double) * n, fc, hipMemcpyDeviceToDevice, st));
   }

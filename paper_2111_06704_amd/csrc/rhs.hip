@@ -20,7 +20,7 @@ namespace {
 
 constexpr int RB = 256;       // threads per block
 constexpr int FG = 16;        // frames per thread in the back-projection
-constexpr int BP_AT = 2;      // atoms per thread in the back-projection
+constexpr int BP_AT = 4;      // atoms per thread in the back-projection
 constexpr int BP_KCH = 32;    // k-vectors per LDS chunk in the back-projection
 constexpr double kErfcZero = 6.5;   // erfc(x) < 4e-20 beyond: below any FP64 sum it enters
 
@@ -60,9 +60,10 @@ __global__ __launch_bounds__(RB) void qsum_kernel(const double *__restrict__ q, 
 // Ion structure factors of one group of ions, S_fK = sum_I q_I exp(i K.r_I).
 // One thread per (run, frame): a run is up to kRun vectors of one (n_x, n_y)
 // column with consecutive n_z. The phase of the run's first vector is
-// evaluated directly (sincospi of the fractional phase); each following one
-// is the previous times exp(2 pi i z_I / L_z), so kRun vectors cost one
-// sincospi and kRun complex products per ion. Ions stream through LDS.
+// evaluated directly (sincospi of the fractional phase), the second by one
+// complex product with exp(2 pi i z_I / L_z), the following ones by the
+// three-term recurrence of the cosine and sine, so kRun vectors cost one
+// sincospi and about kRun FMAs per part and ion. Ions stream through LDS.
 // Output layout: Sg[((g * nk + k) * f_total + f) * 2 + {0: Re, 1: Im}].
 __global__ __launch_bounds__(RB) void structure_factor_kernel(
     const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m, int64_t ipg,
@@ -109,13 +110,23 @@ __global__ __launch_bounds__(RB) void structure_factor_kernel(
       double sn, cs;
       sincospi(2.0 * t, &sn, &cs);
       const double q = su[j][3], zc = su[j][4], zs = su[j][5];
+      // q exp(i (phi + s theta)) for s = 0, 1, ... by the three-term
+      // recurrence x_{s+1} = 2 cos(theta) x_s - x_{s-1} (one FMA per part;
+      // a rounding error made at step m enters step s with the factor
+      // sin((s - m) theta) / sin(theta), at most s - m)
+      double c0 = q * cs, s0 = q * sn;
+      double c1 = c0 * zc - s0 * zs, s1 = s0 * zc + c0 * zs;
+      const double tz = 2.0 * zc;
 #pragma unroll
-      for (int st = 0; st < kRun; ++st) {
-        ar[st] += q * cs;
-        ai[st] += q * sn;
-        const double c2 = cs * zc - sn * zs;
-        sn = cs * zs + sn * zc;
-        cs = c2;
+      for (int st = 0; st < kRun; st += 2) {
+        ar[st] += c0;
+        ai[st] += s0;
+        ar[st + 1] += c1;
+        ai[st + 1] += s1;
+        c0 = fma(tz, c1, -c0);
+        s0 = fma(tz, s1, -s0);
+        c1 = fma(tz, c0, -c1);
+        s1 = fma(tz, s0, -s1);
       }
     }
     __syncthreads();
@@ -143,12 +154,16 @@ __global__ void sum_groups_kernel(const double *__restrict__ Sg, int groups, int
 
 // Back-projection of the ion structure factors onto the electrode atoms,
 // split over k ranges: part[ks][f][i] = sum_{K in range ks} w_K (c_iK Re S_fK
-// + s_iK Im S_fK). Each thread takes AT atoms (i = block base + thread +
-// RB a) and FG frames; K data and S_f.K of BP_KCH vectors at a time are
-// staged in LDS and read by all lanes at the same address. The phase of
-// (i, K) is evaluated directly at the start of every run (and of the range)
-// and by the n_z recurrence inside a run. Grid (atom blocks, k splits,
+// + s_iK Im S_fK). The two half-waves of a wavefront take the same atoms
+// and frames [0, 8) and [8, 16) of the group: each thread holds AT atoms
+// (slot + BP_SLOTS a) x 8 frames. K data and S_f.K of BP_KCH vectors at a
+// time are staged in LDS; every LDS read serves a half-wave at one address.
+// The phase of (i, K) is evaluated directly at the start of every run (and
+// of the range) and by the n_z recurrence inside a run (each atom's phase is
+// computed by its two half-wave threads). Grid (atom blocks, k splits,
 // frame groups).
+constexpr int BP_FH = FG / 2;               // frames per thread
+constexpr int BP_SLOTS = RB / 2;            // atom slots per workgroup
 template <int AT>
 __global__ __launch_bounds__(RB) void backproject_kernel(
     const double *__restrict__ pos, int64_t n, const int32_t *__restrict__ kinfo,
@@ -157,15 +172,18 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
   __shared__ int4 sk[BP_KCH];
   __shared__ double sw[BP_KCH];
   __shared__ double2 ss[BP_KCH][FG];
-  const int64_t ibase = (int64_t)blockIdx.x * RB * AT + threadIdx.x;
+  const int half = (threadIdx.x >> 5) & 1;
+  const int slot = (threadIdx.x >> 6) * 32 + (threadIdx.x & 31);
+  const int64_t ibase = (int64_t)blockIdx.x * BP_SLOTS * AT + slot;
   const int64_t kbeg = (int64_t)blockIdx.y * kper;
   const int64_t kend = min(nk, kbeg + kper);
   const int64_t f0 = (int64_t)blockIdx.z * FG;
   const int nf = (int)((f_total - f0) < FG ? (f_total - f0) : FG);
+  const int gh = half * BP_FH;   // first frame of this thread within the group
   double ux[AT], uy[AT], uz[AT], zs[AT], zc[AT], cs[AT], sn[AT];
 #pragma unroll
   for (int a = 0; a < AT; ++a) {
-    const int64_t i = ibase + RB * a;
+    const int64_t i = ibase + BP_SLOTS * a;
     ux[a] = uy[a] = uz[a] = 0.0;
     if (i < n) {
       ux[a] = pos[3 * i] * inv_lx;
@@ -176,11 +194,11 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
     cs[a] = 1.0;
     sn[a] = 0.0;
   }
-  double acc[AT][FG];
+  double acc[AT][BP_FH];
 #pragma unroll
   for (int a = 0; a < AT; ++a)
 #pragma unroll
-    for (int g = 0; g < FG; ++g) acc[a][g] = 0.0;
+    for (int g = 0; g < BP_FH; ++g) acc[a][g] = 0.0;
   const int4 *ki4 = reinterpret_cast<const int4 *>(kinfo);
   for (int64_t k0 = kbeg; k0 < kend; k0 += BP_KCH) {
     const int cnt = (int)((kend - k0) < BP_KCH ? (kend - k0) : BP_KCH);
@@ -220,8 +238,8 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
         ws[a] = w * sn[a];
       }
 #pragma unroll
-      for (int g = 0; g < FG; ++g) {
-        const double2 sv = ss[kk][g];
+      for (int g = 0; g < BP_FH; ++g) {
+        const double2 sv = ss[kk][gh + g];
 #pragma unroll
         for (int a = 0; a < AT; ++a) {
           acc[a][g] = fma(wc[a], sv.x, acc[a][g]);
@@ -233,11 +251,11 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
   }
 #pragma unroll
   for (int a = 0; a < AT; ++a) {
-    const int64_t i = ibase + RB * a;
+    const int64_t i = ibase + BP_SLOTS * a;
     if (i < n) {
 #pragma unroll
-      for (int g = 0; g < FG; ++g)
-        if (g < nf) part[((int64_t)blockIdx.y * f_total + f0 + g) * n + i] = acc[a][g];
+      for (int g = 0; g < BP_FH; ++g)
+        if (gh + g < nf) part[((int64_t)blockIdx.y * f_total + f0 + gh + g) * n + i] = acc[a][g];
     }
   }
 }
@@ -395,7 +413,7 @@ RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f) {
   const int64_t n = s->n, nk = std::max<int64_t>(s->kset.nk, 1);
   const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
   const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
-  const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
+  const int64_t bblocks = (n + RB / 2 * BP_AT - 1) / (RB / 2 * BP_AT);
   if (m > 0 && s->kset.nk > 0) {
     p.sf_groups = groups_for(std::max<int64_t>(1, rblocks) * f, m, kPartialCap / (2 * nk * f), p.sf_ipg);
     int64_t kper = 0;
@@ -449,7 +467,7 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
       hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
                          Sg, (int)p.sf_groups, len, S);
     }
-    const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
+    const int64_t bblocks = (n + RB / 2 * BP_AT - 1) / (RB / 2 * BP_AT);
     hipLaunchKernelGGL(backproject_kernel<BP_AT>, dim3((unsigned)bblocks, (unsigned)p.ksplit, (unsigned)fgroups),
                        dim3(RB), 0, st, s->pos, n, s->kinfo, s->kw, nk, p.kper, ilx, ily, ilz, S, f,
                        bp);
