@@ -1028,112 +1028,6 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
   }
 }
 
-// Tiled PCG-DC apply: workgroup = one tile of kPcTile rows (consecutive in
-// the spatial order) and one column group. The residual rows of the tile's
-// halo (every atom its rows touch, 16 columns = 128 bytes each in rt) and
-// the tile's ELL values and halo positions are staged in LDS by coalesced
-// loads; the rows then gather from LDS only. Lane = 8 e + h as in
-// precond_kernel, so each z is summed in the same order as there. Each of
-// the 4 waves takes rows wave, wave + 4; bpart gets one (r.r, r.z) pair per
-// tile and column.
-extern __shared__ double pc_lds[];
-
-template <typename VT>
-__global__ __launch_bounds__(RED_THREADS) void precond_tile_kernel(
-    const double *__restrict__ rt, double *__restrict__ z, VT *__restrict__ p,
-    const int32_t *__restrict__ tile_off, const int32_t *__restrict__ tile_idx,
-    const uint16_t *__restrict__ lidx, const double *__restrict__ pval, int width, int umax,
-    const int32_t *__restrict__ order, int64_t ld, int64_t n, int cols,
-    const double *__restrict__ scal, double *__restrict__ bpart, int set_p,
-    const int *__restrict__ gate) {
-  __shared__ double red[PC_ROWS][kColGroup][2];
-  if (gate != nullptr && *gate == 0) return;
-  double *hal = pc_lds;                                   // [umax][kPcHaloStride]
-  double *sval = hal + (size_t)umax * kPcHaloStride;      // [kPcTile][width]
-  uint16_t *slid = reinterpret_cast<uint16_t *>(sval + (size_t)kPcTile * width);
-  const int g = blockIdx.y;
-  const int64_t tile = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int e = lane >> 3, h = lane & 7;
-  const double *rg = rt + (int64_t)g * ld * kColGroup;
-  const int h0 = tile_off[tile], hu = tile_off[tile + 1] - h0;
-  for (int q = threadIdx.x; q < hu * 8; q += RED_THREADS) {
-    const int a = q >> 3, pc = q & 7;
-    const int64_t j = tile_idx[h0 + a];
-    *reinterpret_cast<double2 *>(hal + a * kPcHaloStride + 2 * pc) =
-        *reinterpret_cast<const double2 *>(rg + j * kColGroup + 2 * pc);
-  }
-  int64_t rows[kPcTile];
-#pragma unroll
-  for (int r = 0; r < kPcTile; ++r) {
-    const int64_t t = tile * kPcTile + r;
-    rows[r] = t < n ? (int64_t)order[t] : -1;
-  }
-  for (int q = threadIdx.x; q < kPcTile * width; q += RED_THREADS) {
-    const int r = q / width, k = q % width;
-    const int64_t row = rows[r];
-    sval[q] = row >= 0 ? pval[row * width + k] : 0.0;
-    slid[q] = row >= 0 ? lidx[row * width + k] : (uint16_t)0;
-  }
-  const int c0 = g * kColGroup + 2 * h;
-  const bool act0 = scal == nullptr || scal[S_ACT * cols + c0] != 0.0;
-  const bool act1 = scal == nullptr || scal[S_ACT * cols + c0 + 1] != 0.0;
-  __syncthreads();
-  double d00 = 0.0, d01 = 0.0, d10 = 0.0, d11 = 0.0;   // (r.r, r.z) of columns c0, c0 + 1
-  for (int rr = wave; rr < kPcTile; rr += PC_ROWS) {
-    const int64_t i = rows[rr];
-    double a0 = 0.0, a1 = 0.0;
-    if (i >= 0) {
-      const uint16_t *lp = slid + rr * width;
-      const double *vp = sval + rr * width;
-#pragma unroll 4
-      for (int k = e; k < width; k += 8) {
-        const double v = vp[k];
-        const double2 x = *reinterpret_cast<const double2 *>(hal + (int)lp[k] * kPcHaloStride + 2 * h);
-        a0 += v * x.x;
-        a1 += v * x.y;
-      }
-    }
-#pragma unroll
-    for (int off = 8; off < 64; off <<= 1) {
-      a0 += __shfl_xor(a0, off, 64);
-      a1 += __shfl_xor(a1, off, 64);
-    }
-    if (lane < 8 && i >= 0) {
-      const double2 ri = *reinterpret_cast<const double2 *>(rg + i * kColGroup + 2 * h);
-      if (act0) {
-        const int64_t idx = (int64_t)c0 * ld + i;
-        z[idx] = a0;
-        if (set_p) p[idx] = (VT)a0;
-        d00 += ri.x * ri.x;
-        d01 += ri.x * a0;
-      }
-      if (act1) {
-        const int64_t idx = (int64_t)(c0 + 1) * ld + i;
-        z[idx] = a1;
-        if (set_p) p[idx] = (VT)a1;
-        d10 += ri.y * ri.y;
-        d11 += ri.y * a1;
-      }
-    }
-  }
-  if (bpart == nullptr) return;
-  if (lane < 8) {
-    red[wave][2 * h][0] = d00;
-    red[wave][2 * h][1] = d01;
-    red[wave][2 * h + 1][0] = d10;
-    red[wave][2 * h + 1][1] = d11;
-  }
-  __syncthreads();
-  if (threadIdx.x < 2 * kColGroup) {
-    const int c = threadIdx.x >> 1, s2 = threadIdx.x & 1;
-    double v = 0.0;
-#pragma unroll
-    for (int w = 0; w < PC_ROWS; ++w) v += red[w][c][s2];
-    bpart[((int64_t)blockIdx.x * cols + g * kColGroup + c) * 2 + s2] = v;
-  }
-}
-
 // beta = rz' / rz; p = z + beta p; block 0 stores rz' in the other slot and rr.
 template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
@@ -1597,24 +1491,16 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
   return CPM_OK;
 }
 
-// z = P r (PCG-DC) for cols columns of the row-interleaved residual rt: the
-// tiled kernel when the tile's halo fits in LDS, else the row kernel.
+// z = P r (PCG-DC) for cols columns of the row-interleaved residual rt;
 // bpart gets one (r.r, r.z) pair per workgroup and column.
 template <typename VT>
 void launch_precond(hipStream_t st, const cpm_system *s, const Precond &pc, const double *rt,
                     double *z, VT *p, int64_t cols, const double *scal, double *bpart, bool set_p,
                     const int *gate) {
   const int64_t ld = s->ld, n = s->n;
-  if (pc.tiled) {
-    hipLaunchKernelGGL(precond_tile_kernel<VT>, dim3((unsigned)pc.ntiles, (unsigned)(cols / kColGroup)),
-                       dim3(RED_THREADS), pc_tile_lds(pc.umax, pc.width), st, rt, z, p, pc.tile_off,
-                       pc.tile_idx, pc.lidx, pc.val, pc.width, pc.umax, s->atom_order, ld, n,
-                       (int)cols, scal, bpart, set_p ? 1 : 0, gate);
-  } else {
-    hipLaunchKernelGGL(precond_kernel<VT>, dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
-                       dim3(PC_THREADS), 0, st, rt, z, p, pc.idx, pc.val, pc.width, s->atom_order,
-                       ld, n, (int)cols, scal, bpart, set_p ? 1 : 0, gate);
-  }
+  hipLaunchKernelGGL(precond_kernel<VT>, dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
+                     dim3(PC_THREADS), 0, st, rt, z, p, pc.idx, pc.val, pc.width, s->atom_order, ld,
+                     n, (int)cols, scal, bpart, set_p ? 1 : 0, gate);
 }
 
 // The solver over one block of cols columns. VT is the vector type of p and
@@ -1672,7 +1558,7 @@ template <typename T> struct Solver {
   // partial sums of r.r / r.z per column that the direction and set_scalars
   // kernels add up: one per vector block (Jacobi) or per preconditioner
   // workgroup (DC)
-  int npc() const { return pc && pc->tiled ? (int)pc->ntiles : (int)((n + PC_ROWS - 1) / PC_ROWS); }
+  int npc() const { return (int)((n + PC_ROWS - 1) / PC_ROWS); }
   int nred() const { return pc ? npc() : nblk; }
   const double *dots() const { return pc ? s->ws.bpart : partial; }
 

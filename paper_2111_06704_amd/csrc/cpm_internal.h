@@ -63,9 +63,6 @@ struct Workspace {            // CG scratch, grown on demand
 };
 constexpr int kStatusSlots = 2;
 
-constexpr int kPcTile = 8;     // rows per tile of the PCG-DC apply (consecutive in the spatial order)
-constexpr int kPcHaloStride = 18;   // doubles per staged halo row (16 columns + padding)
-
 struct Precond {              // PCG-DC preconditioner (P + P^T) / 2 in ELL form
   bool ready = false;
   double g = 0, rcut = 0;     // screening and cutoff of Eq. 36
@@ -74,21 +71,8 @@ struct Precond {              // PCG-DC preconditioner (P + P^T) / 2 in ELL form
   int64_t nnz = 0;
   int32_t *idx = nullptr;     // n * width: column of entry k of row i at i * width + k
   double *val = nullptr;      // width * n
-  // tiles of kPcTile rows: the sorted atoms their entries touch (the halo,
-  // staged in LDS by the apply) and each entry's position in its tile's halo
-  bool tiled = false;         // the tile's halo and rows fit the LDS budget
-  int64_t ntiles = 0;
-  int umax = 0;               // largest halo
-  int32_t *tile_off = nullptr;  // ntiles + 1
-  int32_t *tile_idx = nullptr;  // halo atoms of all tiles
-  uint16_t *lidx = nullptr;     // n * width: position of entry (i, k) in the halo of i's tile
   int64_t bytes = 0;           // device memory held
 };
-// LDS bytes of the tiled apply for a halo of umax atoms and rows of width entries
-inline size_t pc_tile_lds(int umax, int width) {
-  return sizeof(double) * (size_t)umax * kPcHaloStride +
-         (sizeof(double) + sizeof(uint16_t)) * (size_t)kPcTile * width;
-}
 void free_precond(Precond &p);
 
 struct Mlp {

@@ -145,7 +145,7 @@ bool cholesky(double *M, int m) {
 }  // namespace
 
 void free_precond(Precond &p) {
-  void *ptrs[] = {p.idx, p.val, p.tile_off, p.tile_idx, p.lidx};
+  void *ptrs[] = {p.idx, p.val};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   p = Precond();
@@ -274,61 +274,6 @@ cpm_status cpm_precond_dc(cpm_system *s, double g, double rcut) {
   CPM_HIP_CHECK(hipMemcpyAsync(p.val, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice,
                                s->stream));
   p.bytes = (int64_t)(sizeof(int32_t) * idx.size() + sizeof(double) * val.size());
-  // tiles of kPcTile consecutive rows of the spatial order and their halos
-  {
-    std::vector<int32_t> order(n);
-    CPM_HIP_CHECK(hipMemcpyAsync(order.data(), s->atom_order, sizeof(int32_t) * n,
-                                 hipMemcpyDeviceToHost, s->stream));
-    CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
-    const int64_t ntiles = (n + kPcTile - 1) / kPcTile;
-    std::vector<int32_t> toff(ntiles + 1, 0), tidx;
-    std::vector<uint16_t> lidx((size_t)width * n, 0);
-    int umax = 0;
-    bool fits16 = true;
-    std::vector<int32_t> u;
-    for (int64_t t = 0; t < ntiles && fits16; ++t) {
-      u.clear();
-      const int64_t r0 = t * kPcTile, r1 = std::min<int64_t>(n, r0 + kPcTile);
-      for (int64_t r = r0; r < r1; ++r) {
-        const int64_t i = order[r];
-        u.insert(u.end(), idx.begin() + i * width, idx.begin() + (i + 1) * width);
-      }
-      std::sort(u.begin(), u.end());
-      u.erase(std::unique(u.begin(), u.end()), u.end());
-      if (u.size() > 65535) fits16 = false;
-      umax = std::max(umax, (int)u.size());
-      for (int64_t r = r0; r < r1; ++r) {
-        const int64_t i = order[r];
-        for (int k = 0; k < width; ++k)
-          lidx[(size_t)i * width + k] = (uint16_t)(std::lower_bound(u.begin(), u.end(),
-                                                                    idx[(size_t)i * width + k]) -
-                                                   u.begin());
-      }
-      tidx.insert(tidx.end(), u.begin(), u.end());
-      toff[t + 1] = (int32_t)tidx.size();
-    }
-    if (fits16 && pc_tile_lds(umax, width) <= 65536) {
-      if (hipMalloc((void **)&p.tile_off, sizeof(int32_t) * toff.size()) != hipSuccess ||
-          hipMalloc((void **)&p.tile_idx, sizeof(int32_t) * tidx.size()) != hipSuccess ||
-          hipMalloc((void **)&p.lidx, sizeof(uint16_t) * lidx.size()) != hipSuccess) {
-        (void)hipGetLastError();
-        free_precond(p);
-        set_error("preconditioner allocation failed");
-        return CPM_ENOMEM;
-      }
-      CPM_HIP_CHECK(hipMemcpyAsync(p.tile_off, toff.data(), sizeof(int32_t) * toff.size(),
-                                   hipMemcpyHostToDevice, s->stream));
-      CPM_HIP_CHECK(hipMemcpyAsync(p.tile_idx, tidx.data(), sizeof(int32_t) * tidx.size(),
-                                   hipMemcpyHostToDevice, s->stream));
-      CPM_HIP_CHECK(hipMemcpyAsync(p.lidx, lidx.data(), sizeof(uint16_t) * lidx.size(),
-                                   hipMemcpyHostToDevice, s->stream));
-      p.tiled = true;
-      p.ntiles = ntiles;
-      p.umax = umax;
-      p.bytes += (int64_t)(sizeof(int32_t) * (toff.size() + tidx.size()) +
-                           sizeof(uint16_t) * lidx.size());
-    }
-  }
   CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   s->device_bytes -= s->pc.bytes;
   free_precond(s->pc);

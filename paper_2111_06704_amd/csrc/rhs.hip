@@ -20,7 +20,7 @@ namespace {
 
 constexpr int RB = 256;       // threads per block
 constexpr int FG = 16;        // frames per thread in the back-projection
-constexpr int BP_AT = 4;      // atoms per thread in the back-projection
+constexpr int BP_AT = 2;      // atoms per thread in the back-projection
 constexpr int BP_KCH = 32;    // k-vectors per LDS chunk in the back-projection
 constexpr double kErfcZero = 6.5;   // erfc(x) < 4e-20 beyond: below any FP64 sum it enters
 
@@ -154,16 +154,12 @@ __global__ void sum_groups_kernel(const double *__restrict__ Sg, int groups, int
 
 // Back-projection of the ion structure factors onto the electrode atoms,
 // split over k ranges: part[ks][f][i] = sum_{K in range ks} w_K (c_iK Re S_fK
-// + s_iK Im S_fK). The two half-waves of a wavefront take the same atoms
-// and frames [0, 8) and [8, 16) of the group: each thread holds AT atoms
-// (slot + BP_SLOTS a) x 8 frames. K data and S_f.K of BP_KCH vectors at a
-// time are staged in LDS; every LDS read serves a half-wave at one address.
-// The phase of (i, K) is evaluated directly at the start of every run (and
-// of the range) and by the n_z recurrence inside a run (each atom's phase is
-// computed by its two half-wave threads). Grid (atom blocks, k splits,
+// + s_iK Im S_fK). Each thread takes AT atoms (i = block base + thread +
+// RB a) and FG frames; K data and S_f.K of BP_KCH vectors at a time are
+// staged in LDS and read by all lanes at the same address. The phase of
+// (i, K) is evaluated directly at the start of every run (and of the range)
+// and by the n_z recurrence inside a run. Grid (atom blocks, k splits,
 // frame groups).
-constexpr int BP_FH = FG / 2;               // frames per thread
-constexpr int BP_SLOTS = RB / 2;            // atom slots per workgroup
 template <int AT>
 __global__ __launch_bounds__(RB) void backproject_kernel(
     const double *__restrict__ pos, int64_t n, const int32_t *__restrict__ kinfo,
@@ -172,18 +168,15 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
   __shared__ int4 sk[BP_KCH];
   __shared__ double sw[BP_KCH];
   __shared__ double2 ss[BP_KCH][FG];
-  const int half = (threadIdx.x >> 5) & 1;
-  const int slot = (threadIdx.x >> 6) * 32 + (threadIdx.x & 31);
-  const int64_t ibase = (int64_t)blockIdx.x * BP_SLOTS * AT + slot;
+  const int64_t ibase = (int64_t)blockIdx.x * RB * AT + threadIdx.x;
   const int64_t kbeg = (int64_t)blockIdx.y * kper;
   const int64_t kend = min(nk, kbeg + kper);
   const int64_t f0 = (int64_t)blockIdx.z * FG;
   const int nf = (int)((f_total - f0) < FG ? (f_total - f0) : FG);
-  const int gh = half * BP_FH;   // first frame of this thread within the group
   double ux[AT], uy[AT], uz[AT], zs[AT], zc[AT], cs[AT], sn[AT];
 #pragma unroll
   for (int a = 0; a < AT; ++a) {
-    const int64_t i = ibase + BP_SLOTS * a;
+    const int64_t i = ibase + RB * a;
     ux[a] = uy[a] = uz[a] = 0.0;
     if (i < n) {
       ux[a] = pos[3 * i] * inv_lx;
@@ -194,11 +187,11 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
     cs[a] = 1.0;
     sn[a] = 0.0;
   }
-  double acc[AT][BP_FH];
+  double acc[AT][FG];
 #pragma unroll
   for (int a = 0; a < AT; ++a)
 #pragma unroll
-    for (int g = 0; g < BP_FH; ++g) acc[a][g] = 0.0;
+    for (int g = 0; g < FG; ++g) acc[a][g] = 0.0;
   const int4 *ki4 = reinterpret_cast<const int4 *>(kinfo);
   for (int64_t k0 = kbeg; k0 < kend; k0 += BP_KCH) {
     const int cnt = (int)((kend - k0) < BP_KCH ? (kend - k0) : BP_KCH);
@@ -238,8 +231,8 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
         ws[a] = w * sn[a];
       }
 #pragma unroll
-      for (int g = 0; g < BP_FH; ++g) {
-        const double2 sv = ss[kk][gh + g];
+      for (int g = 0; g < FG; ++g) {
+        const double2 sv = ss[kk][g];
 #pragma unroll
         for (int a = 0; a < AT; ++a) {
           acc[a][g] = fma(wc[a], sv.x, acc[a][g]);
@@ -251,11 +244,11 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
   }
 #pragma unroll
   for (int a = 0; a < AT; ++a) {
-    const int64_t i = ibase + BP_SLOTS * a;
+    const int64_t i = ibase + RB * a;
     if (i < n) {
 #pragma unroll
-      for (int g = 0; g < BP_FH; ++g)
-        if (gh + g < nf) part[((int64_t)blockIdx.y * f_total + f0 + gh + g) * n + i] = acc[a][g];
+      for (int g = 0; g < FG; ++g)
+        if (g < nf) part[((int64_t)blockIdx.y * f_total + f0 + g) * n + i] = acc[a][g];
     }
   }
 }
@@ -380,6 +373,180 @@ __global__ __launch_bounds__(RB) void real_space_ions_kernel(
   if (i >= 0) rs[(g * f_total + f) * n + i] = acc;
 }
 
+// ---- real space with the ions of each frame sorted by z
+//
+// ion_sort_kernel (one workgroup per frame): keys (z bin << 20 | ion) are
+// sorted in LDS (bitonic; the keys are unique, so the order is fixed), the
+// ions are written in that order as (x, y, z, q), and bin_start[b] is the
+// first sorted position of bin b (b = 0..NB). z is wrapped into [0, L_z).
+constexpr int kZBins = 256;
+constexpr int kSortThreads = 1024;
+constexpr int64_t kSortMaxIons = 32768;   // keys in LDS: 128 KB
+// below this many ions per frame the sort costs more than the window saves
+// (measured: 2000 ions, 4608 atoms: 195 us unsorted vs 30 + 207 us)
+constexpr int64_t kWinMinIons = 8192;
+extern __shared__ uint32_t sort_keys[];
+
+__global__ __launch_bounds__(kSortThreads) void ion_sort_kernel(
+    const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m, int p2,
+    double lz, double4 *__restrict__ sorted, int32_t *__restrict__ bin_start) {
+  const int64_t f = blockIdx.x;
+  const double bw = lz / kZBins;
+  const double *pf = ion_pos + f * m * 3;
+  for (int i = threadIdx.x; i < p2; i += kSortThreads) {
+    uint32_t key = 0xffffffffu;
+    if (i < m) {
+      const double z = pf[3 * i + 2];
+      const double zw = z - lz * floor(z / lz);
+      const int b = min(kZBins - 1, max(0, (int)floor(zw / bw)));
+      key = ((uint32_t)b << 20) | (uint32_t)i;
+    }
+    sort_keys[i] = key;
+  }
+  __syncthreads();
+  for (int k = 2; k <= p2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < p2; i += kSortThreads) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint32_t a = sort_keys[i], b = sort_keys[ixj];
+          if ((a > b) == ((i & k) == 0)) {
+            sort_keys[i] = b;
+            sort_keys[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const double *qf = ion_q + f * m;
+  for (int j = threadIdx.x; j < m; j += kSortThreads) {
+    const int i = (int)(sort_keys[j] & 0xfffffu);
+    sorted[f * m + j] = make_double4(pf[3 * i], pf[3 * i + 1], pf[3 * i + 2], qf[i]);
+  }
+  for (int b = threadIdx.x; b <= kZBins; b += kSortThreads) {
+    const uint32_t target = (uint32_t)b << 20;
+    int lo = 0, hi = (int)m;   // first j with key >= target
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sort_keys[mid] < target) lo = mid + 1;
+      else hi = mid;
+    }
+    bin_start[f * (kZBins + 1) + b] = lo;
+  }
+}
+
+// Real space over the z window of each wavefront's atoms: one wavefront per
+// (tile of 64 atoms in the spatial order, frame, ion group). The window is
+// [z_min - rcut, z_max + rcut] of the tile (z bins widened by one on both
+// sides, periodic in z); when L_z < 2 rcut or the window covers the box,
+// all ions. The window's ions (at most two ranges of the sorted list) are
+// split over the groups; the pair sum is that of real_space_ions_kernel.
+__global__ __launch_bounds__(64) void real_space_win_kernel(
+    const double *__restrict__ pos, const double *__restrict__ width,
+    const int32_t *__restrict__ order, int64_t n, const double4 *__restrict__ sorted,
+    const int32_t *__restrict__ bin_start, int64_t m, int groups, double lx, double ly, double lz,
+    double beta, double rcut, int64_t f_total, double *__restrict__ rs) {
+  __shared__ double4 si[64];
+  const int64_t f = blockIdx.y;
+  const int g = blockIdx.z;
+  const int lane = threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t i = t < n ? (int64_t)order[t] : -1;
+  double xi = 0, yi = 0, zi = 0, ai = 1.0;
+  if (i >= 0) {
+    xi = pos[3 * i];
+    yi = pos[3 * i + 1];
+    zi = pos[3 * i + 2];
+    ai = width[i];
+  }
+  const double ilx = 1.0 / lx, ily = 1.0 / ly, ilz = 1.0 / lz;
+  const bool wx = lx >= 2.0 * rcut, wy = ly >= 2.0 * rcut, wz = lz >= 2.0 * rcut;
+  // z extent of the tile about its first atom (lane 0 always holds one)
+  const double zref = __shfl(zi, 0, 64);
+  double dz0 = zi - zref;
+  dz0 -= lz * rint(dz0 * ilz);
+  if (i < 0) dz0 = 0.0;
+  double dmin = dz0, dmax = dz0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    dmin = fmin(dmin, __shfl_xor(dmin, off, 64));
+    dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+  }
+  const int32_t *bs = bin_start + f * (kZBins + 1);
+  const double bw = lz / kZBins;
+  const int64_t blo = (int64_t)floor((zref + dmin - rcut) / bw) - 1;
+  const int64_t bhi = (int64_t)floor((zref + dmax + rcut) / bw) + 1;
+  const int64_t nbins = bhi - blo + 1;
+  int64_t s1 = 0, e1 = m, s2 = 0, e2 = 0;   // candidate ranges [s1, e1) + [s2, e2)
+  if (wz && nbins < kZBins) {
+    const int64_t b0 = ((blo % kZBins) + kZBins) % kZBins;
+    if (b0 + nbins <= kZBins) {
+      s1 = bs[b0];
+      e1 = bs[b0 + nbins];
+    } else {
+      s1 = bs[b0];
+      e1 = bs[kZBins];
+      s2 = bs[0];
+      e2 = bs[b0 + nbins - kZBins];
+    }
+  }
+  const int64_t c1 = e1 - s1, cn = c1 + (e2 - s2);
+  const int64_t q0 = cn * g / groups, q1 = cn * (g + 1) / groups;
+  const double rc2 = rcut * rcut;
+  const double lim0 = 2.0 * (ai - beta) * 0.56418958354775628695;
+  const double4 *sf = sorted + f * m;
+  double acc = 0.0;
+  for (int64_t base = q0; base < q1; base += 64) {
+    const int64_t q = base + lane;
+    if (q < q1) si[lane] = sf[q < c1 ? s1 + q : s2 + (q - c1)];
+    __syncthreads();
+    const int cnt = (int)((q1 - base) < 64 ? (q1 - base) : 64);
+    if (i >= 0) {
+      for (int j = 0; j < cnt; ++j) {
+        const double4 ion = si[j];
+        double dz = zi - ion.z;
+        dz -= lz * rint(dz * ilz);
+        int za, zb;
+        image_range(dz, lz, ilz, rcut, wz, za, zb);
+        if (za > zb) continue;
+        double dx = xi - ion.x;
+        double dy = yi - ion.y;
+        dx -= lx * rint(dx * ilx);
+        dy -= ly * rint(dy * ily);
+        int xa, xb, ya, yb;
+        image_range(dx, lx, ilx, rcut, wx, xa, xb);
+        image_range(dy, ly, ily, rcut, wy, ya, yb);
+        const double qv = ion.w;
+        for (int a = xa; a <= xb; ++a) {
+          const double ex = dx + (double)a * lx;
+          for (int bb = ya; bb <= yb; ++bb) {
+            const double ey = dy + (double)bb * ly;
+            const double exy = ex * ex + ey * ey;
+            if (exy >= rc2) continue;
+            for (int c = za; c <= zb; ++c) {
+              const double ez = dz + (double)c * lz;
+              const double d2 = exy + ez * ez;
+              if (d2 < rc2) {
+                if (d2 > 0.0) {
+                  const double d = sqrt(d2);
+                  const double tt = ai * d;
+                  const double eg = tt < kErfcZero ? erfc(tt) : 0.0;
+                  acc += qv * ((erfc(beta * d) - eg) / d);
+                } else {
+                  acc += qv * lim0;
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (i >= 0) rs[((int64_t)g * f_total + f) * n + i] = acc;
+}
+
 }  // namespace
 
 namespace {
@@ -392,7 +559,9 @@ namespace {
 //   rs  [rs_groups][f][n]      real-space partials
 struct RhsPlan {
   int64_t sf_groups = 1, sf_ipg = 0, ksplit = 0, kper = 0, rs_groups = 0, rs_ipg = 0;
-  int64_t off_sg = 0, off_bp = 0, off_rs = 0, off_m1 = 0, total = 0;
+  bool rs_win = false;          // real space over z windows of the sorted ions
+  int p2 = 0;                   // sort size (power of two >= ions per frame)
+  int64_t off_sg = 0, off_bp = 0, off_rs = 0, off_m1 = 0, off_sorted = 0, off_bins = 0, total = 0;
 };
 
 constexpr int64_t kTargetBlocks = 2048;          // workgroups that fill the chip several times
@@ -413,19 +582,35 @@ RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f) {
   const int64_t n = s->n, nk = std::max<int64_t>(s->kset.nk, 1);
   const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
   const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
-  const int64_t bblocks = (n + RB / 2 * BP_AT - 1) / (RB / 2 * BP_AT);
+  const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
   if (m > 0 && s->kset.nk > 0) {
     p.sf_groups = groups_for(std::max<int64_t>(1, rblocks) * f, m, kPartialCap / (2 * nk * f), p.sf_ipg);
-    int64_t kper = 0;
-    p.ksplit = groups_for(bblocks * fgroups, s->kset.nk, kPartialCap / (f * n), kper);
-    p.kper = kper;
+    // k splits of the back-projection: as many as fill every SIMD with three
+    // wavefronts (its occupancy) without a fourth on some, at least 32 k each
+    const int64_t per = bblocks * fgroups * (RB / 64);
+    int64_t ks = std::max<int64_t>(1, (3 * 1024) / per);
+    ks = std::min<int64_t>({ks, std::max<int64_t>(1, nk / 32), std::max<int64_t>(1, kPartialCap / (f * n))});
+    p.kper = (nk + ks - 1) / ks;
+    p.ksplit = (nk + p.kper - 1) / p.kper;
   }
-  if (m > 0) p.rs_groups = groups_for(iblocks * f, m, kPartialCap / (f * n), p.rs_ipg);
+  if (m >= kWinMinIons && m <= kSortMaxIons) {
+    // windowed real space: enough wavefronts (tiles x frames x groups) to fill the chip
+    p.rs_win = true;
+    p.p2 = 1;
+    while (p.p2 < m) p.p2 <<= 1;
+    const int64_t tiles = (n + 63) / 64;
+    p.rs_groups = std::max<int64_t>(1, std::min<int64_t>(8, 3072 / std::max<int64_t>(1, tiles * f)));
+    p.rs_groups = std::max<int64_t>(1, std::min<int64_t>(p.rs_groups, kPartialCap / (f * n)));
+  } else if (m > 0) {
+    p.rs_groups = groups_for(iblocks * f, m, kPartialCap / (f * n), p.rs_ipg);
+  }
   p.off_sg = 2 * nk * f;
   p.off_bp = p.off_sg + (p.sf_groups > 1 ? p.sf_groups * 2 * nk * f : 0);
   p.off_rs = p.off_bp + p.ksplit * f * n;
   p.off_m1 = p.off_rs + p.rs_groups * f * n;
-  p.total = p.off_m1 + f;
+  p.off_sorted = (p.off_m1 + f + 3) / 4 * 4;   // 32-byte aligned (double4)
+  p.off_bins = p.off_sorted + (p.rs_win ? 4 * f * m : 0);
+  p.total = p.off_bins + (p.rs_win ? (f * (kZBins + 1) + 1) / 2 : 0);
   return p;
 }
 
@@ -467,12 +652,25 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
       hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
                          Sg, (int)p.sf_groups, len, S);
     }
-    const int64_t bblocks = (n + RB / 2 * BP_AT - 1) / (RB / 2 * BP_AT);
+    const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
     hipLaunchKernelGGL(backproject_kernel<BP_AT>, dim3((unsigned)bblocks, (unsigned)p.ksplit, (unsigned)fgroups),
                        dim3(RB), 0, st, s->pos, n, s->kinfo, s->kw, nk, p.kper, ilx, ily, ilz, S, f,
                        bp);
   }
-  if (p.rs_groups > 0) {
+  if (p.rs_win) {
+    double4 *sorted = reinterpret_cast<double4 *>(scratch + p.off_sorted);
+    int32_t *bins = reinterpret_cast<int32_t *>(scratch + p.off_bins);
+    const size_t lds = sizeof(uint32_t) * (size_t)p.p2;
+    if (lds > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(ion_sort_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(ion_sort_kernel, dim3((unsigned)f), dim3(kSortThreads), lds, st, ion_pos,
+                       ion_q, m, p.p2, s->box[2], sorted, bins);
+    hipLaunchKernelGGL(real_space_win_kernel, dim3((unsigned)((n + 63) / 64), (unsigned)f, (unsigned)p.rs_groups),
+                       dim3(64), 0, st, s->pos, s->width, s->atom_order, n, (const double4 *)sorted,
+                       (const int32_t *)bins, m, (int)p.rs_groups, s->box[0], s->box[1], s->box[2],
+                       s->beta, s->rcut, f, rs);
+  } else if (p.rs_groups > 0) {
     hipLaunchKernelGGL(real_space_ions_kernel, dim3((unsigned)iblocks, (unsigned)f, (unsigned)p.rs_groups),
                        dim3(RB), 0, st, s->pos, s->width, s->atom_order, n, ion_pos, ion_q, m,
                        p.rs_ipg, s->box[0], s->box[1], s->box[2], s->beta, s->rcut, f, rs);
