@@ -37,7 +37,7 @@ KERNEL_OF_KIND = {"matvec_f64": "block_matvec_rows_kernel<double>",
                   "matvec_f32": "block_matvec_rows_kernel<float>",
                   "matvec_bf16": "block_matvec_rows_kernel<unsigned short>"}
 # 32..64 columns of an FP32 / BF16 E run on the split-bf16 kernel
-KERNEL_OF_KIND_WIDE = {"matvec_f64": "block_matvec_kernel<double, {ng}>",
+KERNEL_OF_KIND_WIDE = {"matvec_f64": "block_matvec_f64s_kernel<{ng}>",
                        "matvec_f32": "block_matvec_split_kernel<float, {ng}>",
                        "matvec_bf16": "block_matvec_split_kernel<unsigned short, {ng}>"}
 
@@ -127,7 +127,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path):
                            "write_factor": CALIB_BYTES / (cw * 1024.0)},
            "cg_source_sha256": _sha256(CG_SOURCE), "kernels": {}}
     for name in sorted(set(fetch) | set(write)):
-        m = re.search(r"(block_matvec(?:_split|_rows)?_kernel)<([^>]*)>", name)
+        m = re.search(r"(block_matvec(?:_split|_rows|_f64s)?_kernel)<([^>]*)>", name)
         if not m:
             continue
         key = m.group(1) + "<" + m.group(2) + ">"

@@ -52,6 +52,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 namespace cpm {
 namespace {
@@ -379,6 +380,146 @@ __global__ __launch_bounds__(64 * MR_WAVES) void block_matvec_rows_kernel(
     for (int w = 0; w < MR_WAVES; ++w) t += pvs[w][threadIdx.x];
     pv_part[(sl * gridDim.x + blockIdx.x) * 16 + threadIdx.x] = t;
   }
+}
+
+// ---- FP64 block product for 32..64 columns: P streamed through LDS
+//
+// With 64 columns the FP64 product does 128 flops per E entry and is bound
+// by the FP64 matrix cores; what has to be avoided is re-reading P for every
+// 16-row tile. Workgroup = 4 waves x F64_RW row tiles of 16 rows (F64_ROWS
+// rows) and one k slice; per chunk of F64_KC columns of E the workgroup
+// copies the matching 16 NG x F64_KC block of P into LDS once (double
+// buffered, one barrier per chunk) and every wave takes its B operands from
+// there while its own E rows stream from HBM (F64_U chunks in flight).
+// v_mfma_f64_16x16x4f64: lane (lr, lg) supplies A = E[row lr][k 4 lg + t]
+// and B = P[column lr][k 4 lg + t] for t = 0..3 of each 16-k step.
+constexpr int F64_RW = 2;
+constexpr int F64_ROWS = 4 * 16 * F64_RW;   // rows per workgroup
+constexpr int F64_KC = 32;                  // k per chunk
+constexpr int F64_PR = F64_KC + 4;          // LDS row length of the P chunk (doubles)
+constexpr int F64_U = 2;                    // E chunks in flight per wave
+
+template <int NG>
+__global__ __launch_bounds__(256) void block_matvec_f64s_kernel(
+    const double *__restrict__ E, int64_t ld, const double *__restrict__ P,
+    double *__restrict__ part, int64_t kslice, int64_t split_stride,
+    double *__restrict__ pv_part, const int *__restrict__ gate, int *__restrict__ mark) {
+  constexpr int COLS = 16 * NG;
+  __shared__ __align__(16) double ps[2][COLS][F64_PR];
+  __shared__ double pvs[4][COLS];
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  if (gate != nullptr && *gate == 0) {
+    if (mark != nullptr && first) *mark = 0;
+    return;
+  }
+  if (mark != nullptr && first) *mark = 1;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t tile = blockIdx.x, sl = blockIdx.y;
+  const int64_t row0 = tile * F64_ROWS + wave * 16 * F64_RW;
+  const int64_t kbeg = sl * kslice;
+  const int64_t kend = min(ld, kbeg + kslice);
+  const int nch = (int)((kend - kbeg) / F64_KC);
+  // P loader: thread -> (column tid / 4, 8 consecutive k); 64 columns x 32 k per chunk
+  const int pcol = tid >> 2, pk = (tid & 3) * 8;
+  const bool ploader = pcol < COLS;
+  const double *pbase = P + (int64_t)(ploader ? pcol : 0) * ld + kbeg + pk;
+  // E: row tile a, chunk u holds k = 16 s + 4 lg + t for s = 0, 1
+  // row tile a starts erow_stride * a after erow0
+  const double *erow0 = E + (row0 + lr) * ld + kbeg + lg * 4;
+  const int64_t erow_stride = 16 * ld;
+  double4 ring[F64_U][F64_RW][2];
+#pragma unroll
+  for (int u = 0; u < F64_U; ++u)
+    if (u < nch)
+#pragma unroll
+      for (int a = 0; a < F64_RW; ++a)
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+          ring[u][a][st] = *reinterpret_cast<const double4 *>(erow0 + a * erow_stride + u * F64_KC + st * 16);
+  double4 pn0 = make_double4(0, 0, 0, 0), pn1 = pn0;
+  if (nch > 0 && ploader) {
+    pn0 = *reinterpret_cast<const double4 *>(pbase);
+    pn1 = *reinterpret_cast<const double4 *>(pbase + 4);
+    *reinterpret_cast<double4 *>(&ps[0][pcol][pk]) = pn0;
+    *reinterpret_cast<double4 *>(&ps[0][pcol][pk + 4]) = pn1;
+  }
+  __syncthreads();
+  d4 acc[F64_RW][NG];
+#pragma unroll
+  for (int a = 0; a < F64_RW; ++a)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[a][g] = d4{0, 0, 0, 0};
+  // one chunk with E from ring slot U (a compile-time index, so that the
+  // ring stays in registers)
+  auto chunk = [&](auto slot, int ch) {
+    constexpr int U = decltype(slot)::value;
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nch;
+    if (more && ploader) {
+      pn0 = *reinterpret_cast<const double4 *>(pbase + (int64_t)(ch + 1) * F64_KC);
+      pn1 = *reinterpret_cast<const double4 *>(pbase + (int64_t)(ch + 1) * F64_KC + 4);
+    }
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const double4 b = *reinterpret_cast<const double4 *>(&ps[buf][g * 16 + lr][st * 16 + lg * 4]);
+#pragma unroll
+        for (int a = 0; a < F64_RW; ++a) {
+          const double4 e = ring[U][a][st];
+          acc[a][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, b.x, acc[a][g], 0, 0, 0);
+          acc[a][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.y, b.y, acc[a][g], 0, 0, 0);
+          acc[a][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.z, b.z, acc[a][g], 0, 0, 0);
+          acc[a][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.w, b.w, acc[a][g], 0, 0, 0);
+        }
+      }
+    if (ch + F64_U < nch) {
+#pragma unroll
+      for (int a = 0; a < F64_RW; ++a)
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+          ring[U][a][st] =
+              *reinterpret_cast<const double4 *>(erow0 + a * erow_stride + (int64_t)(ch + F64_U) * F64_KC + st * 16);
+    }
+    if (more && ploader) {
+      *reinterpret_cast<double4 *>(&ps[buf ^ 1][pcol][pk]) = pn0;
+      *reinterpret_cast<double4 *>(&ps[buf ^ 1][pcol][pk + 4]) = pn1;
+    }
+    __syncthreads();
+  };
+  static_assert(F64_U == 2, "two ring slots");
+  for (int ch0 = 0; ch0 < nch; ch0 += F64_U) {
+    chunk(std::integral_constant<int, 0>(), ch0);
+    if (ch0 + 1 < nch) chunk(std::integral_constant<int, 1>(), ch0 + 1);
+  }
+  // lane (lr, lg) holds rows 4 v + lg of column lr of each tile
+  double *out = part + sl * split_stride;
+  double pv[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    pv[g] = 0.0;
+    const int64_t c = g * 16 + lr;
+#pragma unroll
+    for (int a = 0; a < F64_RW; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + a * 16 + 4 * v + lg;
+        out[c * ld + row] = acc[a][g][v];
+        if (pv_part) pv[g] += P[c * ld + row] * acc[a][g][v];
+      }
+  }
+  if (pv_part == nullptr) return;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    pv[g] += __shfl_xor(pv[g], 16, 64);
+    pv[g] += __shfl_xor(pv[g], 32, 64);
+    if (lg == 0) pvs[wave][g * 16 + lr] = pv[g];
+  }
+  __syncthreads();
+  if (tid < COLS)
+    pv_part[(sl * gridDim.x + tile) * COLS + tid] =
+        ((pvs[0][tid] + pvs[1][tid]) + pvs[2][tid]) + pvs[3][tid];
 }
 
 // ---- block product on bf16 matrix cores (32..64 columns, FP32 or BF16 E)
@@ -1304,6 +1445,22 @@ template <typename T> constexpr bool uses_split(int64_t cols) {
   return sizeof(T) <= 4 && cols >= 32;
 }
 
+// the streamed-P FP64 kernel serves an FP64 E with 32..64 columns
+template <typename T> constexpr bool uses_f64s(int64_t cols) {
+  return sizeof(T) == 8 && cols >= 32;
+}
+
+// k slices of the streamed-P FP64 kernel: about 1024 workgroups, slices of
+// whole chunks
+int64_t f64s_slices(int64_t ld, int64_t &kslice) {
+  const int64_t tiles = ld / F64_ROWS;
+  const int64_t units = ld / F64_KC;
+  int64_t want = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
+  want = std::min<int64_t>(want, units);
+  kslice = (units + want - 1) / want * F64_KC;
+  return (ld + kslice - 1) / kslice;
+}
+
 // k slices of the row-split kernel (16 columns): about 432 workgroups, each
 // slice a multiple of the k step and short enough for its P copy in LDS
 template <typename T> int64_t rows_slices(int64_t ld, int64_t &kslice) {
@@ -1320,6 +1477,7 @@ template <typename T> int64_t rows_slices(int64_t ld, int64_t &kslice) {
 template <typename T> int64_t matvec_npv(int64_t ld, int64_t cols) {
   int64_t k = 0;
   if (uses_split<T>(cols)) return split_slices(ld, k) * (ld / SP_ROWS);
+  if (uses_f64s<T>(cols)) return f64s_slices(ld, k) * (ld / F64_ROWS);
   if (cols == 16) return rows_slices<T>(ld, k) * (ld / (16 * MR_WAVES));
   return matvec_slices<T>(ld, cols, k) * matvec_tiles<T>(ld);
 }
@@ -1328,6 +1486,7 @@ template <typename T> int64_t matvec_npv(int64_t ld, int64_t cols) {
 template <typename T> int64_t slices_for(int64_t ld, int64_t c) {
   int64_t k = 0;
   if (uses_split<T>(c)) return split_slices(ld, k);
+  if (uses_f64s<T>(c)) return f64s_slices(ld, k);
   if (c == kColGroup) return rows_slices<T>(ld, k);
   return matvec_slices<T>(ld, c, k);
 }
@@ -1355,12 +1514,17 @@ hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typenam
                            typename Mv<T>::VT *part, double *pv_part, int &slices,
                            const int *gate) {
   constexpr bool split = uses_split<T>(NG * 16);
+  constexpr bool f64s = uses_f64s<T>(NG * 16);
   constexpr bool rows = NG == 1;
   int64_t kslice = 0;
   slices = split  ? (int)split_slices(ld, kslice)
+           : f64s ? (int)f64s_slices(ld, kslice)
            : rows ? (int)rows_slices<T>(ld, kslice)
                   : (int)matvec_slices<T>(ld, NG * 16, kslice);
-  const int64_t tiles = split ? ld / SP_ROWS : rows ? ld / (16 * MR_WAVES) : matvec_tiles<T>(ld);
+  const int64_t tiles = split ? ld / SP_ROWS
+                        : f64s ? ld / F64_ROWS
+                        : rows ? ld / (16 * MR_WAVES)
+                               : matvec_tiles<T>(ld);
   hipEvent_t ea = nullptr, eb = nullptr;
   int *mark = nullptr;
   if (t_prof && t_prof->enabled) {
@@ -1372,7 +1536,12 @@ hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typenam
     eb = r.b;
     if (gate) mark = t_prof->take_mark(r);
   }
-  if constexpr (rows) {
+  if constexpr (f64s) {
+    hipExtLaunchKernelGGL((block_matvec_f64s_kernel<NG>), dim3((unsigned)tiles, (unsigned)slices),
+                          dim3(256), 0, st, ea, eb, 0, reinterpret_cast<const double *>(E), ld,
+                          reinterpret_cast<const double *>(P), reinterpret_cast<double *>(part),
+                          kslice, (int64_t)(NG * 16) * ld, pv_part, gate, mark);
+  } else if constexpr (rows) {
     const size_t lds = sizeof(typename Mv<T>::VT) * 16 * (size_t)(kslice + mr_pad<T>());
     hipExtLaunchKernelGGL((block_matvec_rows_kernel<T>), dim3((unsigned)tiles, (unsigned)slices),
                           dim3(64 * MR_WAVES), lds, st, ea, eb, 0, E, ld, P, part, kslice,

@@ -338,3 +338,34 @@ def test_invalid_inputs():
     with pytest.raises(cpm.CpmError) as e:
         S.solve(b, torch.zeros(1, dtype=torch.float64, device="cuda"), warm_start=cpm.WARM_MLP)
     assert e.value.status == cpm.CPM_ESTATE
+
+
+def test_rhs_many_ions_z_windows():
+    """9000 ions per frame (the real-space sum then runs over z windows of the
+    z-sorted ions) on workload 1's geometry, with ions placed across the
+    periodic z boundary (z < 0, near 0, near L_z, > L_z): b of every atom
+    against the oracle's Eq. 25, <= 1e-12 max|b|."""
+    cpm = _cpm()
+    dev = _dev()
+    geo = wl.geometry(1)
+    km = ew.kmax_from_eps(BETA, EPS)
+    ipos, iq = wl.ion_frames(geo, 9000, [wl.frame_seed(1, 900 + f) for f in range(2)])
+    lz = geo.box[2]
+    rng = np.random.default_rng(77)
+    for f in range(2):
+        sel = rng.choice(9000, 800, replace=False)
+        ipos[f, sel[:200], 2] = rng.uniform(-3.0, 0.0, 200)
+        ipos[f, sel[200:400], 2] = rng.uniform(0.0, 3.0, 200)
+        ipos[f, sel[400:600], 2] = rng.uniform(lz - 3.0, lz, 200)
+        ipos[f, sel[600:], 2] = rng.uniform(lz, lz + 3.0, 200)
+    chi = wl.electrode_potential(geo)
+    print("[case] workload 1 geometry, 2 frames x 9000 ions", flush=True)
+    S = cpm.System(geo.pos, geo.box, A, BETA, RC, EPS, store=())
+    b, qsol = S.rhs(torch.tensor(ipos, device=dev), torch.tensor(iq, device=dev),
+                    torch.tensor(chi, device=dev))
+    bo, qso = ew.rhs(geo.pos, A, ipos, iq, chi, geo.box, BETA, RC, km)
+    assert np.max(np.abs(b.cpu().numpy() - bo)) <= 1e-12 * np.max(np.abs(bo))
+    assert np.array_equal(qsol.cpu().numpy(), qso)
+    b2, _ = S.rhs(torch.tensor(ipos, device=dev), torch.tensor(iq, device=dev),
+                  torch.tensor(chi, device=dev))
+    assert torch.equal(b, b2)   # the sorted order is fixed: bitwise reproducible
