@@ -288,14 +288,18 @@ cpm_status cpm_mlp_train_epoch(cpm_system *s, const double *b_dev, const double 
 cpm_status cpm_set_warm_chi(cpm_system *s, const double *chi_dev, const cpm_solve_opts *opts);
 
 /* ---- live kernel timing ----------------------------------------------------
- * While enabled, the library brackets every launch of the block matrix
- * product (per storage precision of E) and of the assembly contraction with
- * HIP events on its stream and records each launch's algorithmic work:
+ * While enabled, the library brackets launches of the block matrix product
+ * (per storage precision of E) and of the assembly contraction with HIP
+ * events on its stream and records each launch's algorithmic work:
  *   matvec: bytes s*n*n (E) + 2 * s_v * n * cols (P read, V written),
  *           s = 8/4/2 for FP64/FP32/BF16 E, s_v = 8 (FP64) or 4 (FP32 vectors);
  *   assembly: flops 4 * n_k * n (n + 1) / 2 for a chunk of n_k k-vectors.
- * cpm_profile_enable(s, 1) starts a new window (clears earlier records);
- * cpm_profile_read synchronises the stream and sums each kind. */
+ * cpm_profile_enable(s, on) starts a new window (clears earlier records):
+ * on = 0 stops timing, on = 1 times every launch, on = k > 1 times every
+ * k-th launch of the block product of each precision (the bracketing
+ * launch costs the host ~10 us more than a plain one; sampling keeps that
+ * out of the throughput being measured); cpm_profile_read synchronises the
+ * stream and sums each kind over the timed launches. */
 typedef struct {
   int64_t launches[4];   /* index: CPM_PREC_F64, CPM_PREC_F32, CPM_PREC_BF16, 3 = assembly */
   double ms[4];          /* summed kernel time (ms) between the events                    */

@@ -182,8 +182,10 @@ class System:
         except Exception:
             pass
 
-    def profile_enable(self, on=True):
-        _check(lib().cpm_profile_enable(self._h, 1 if on else 0), "cpm_profile_enable")
+    def profile_enable(self, on=True, stride=1):
+        """Time launches of the block product (every stride-th of each kind)."""
+        _check(lib().cpm_profile_enable(self._h, max(1, int(stride)) if on else 0),
+               "cpm_profile_enable")
 
     def profile_read(self):
         """Per kind (0 FP64, 1 FP32, 2 BF16 matvec, 3 assembly): launches, ms, work."""

@@ -603,6 +603,8 @@ cpm_status cpm_profile_enable(cpm_system *s, int on) {
     }
   }
   s->prof.enabled = on != 0;
+  s->prof.stride = on > 1 ? on : 1;
+  for (int64_t &c : s->prof.seen) c = 0;
   return CPM_OK;
 }
 

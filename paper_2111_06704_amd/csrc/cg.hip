@@ -10,9 +10,8 @@
 // One Jacobi-preconditioned iteration is three kernels:
 //   block product        v = E p as k-slice partials (16 columns: the
 //     row-split kernel, waves over rows, the P slice in LDS; 32..64 columns
-//     of an FP64 E: block_matvec_kernel, workgroup (tile, slice) owning
-//     16*RT rows and one k slice split over its 4 waves; 32..64 columns of
-//     an FP32 / BF16 E: the split-bf16 kernel). MFMA blocks of 16x16
+//     of an FP64 E: the streamed-P FP64 kernel; 32..64 columns of an FP32 /
+//     BF16 E: the split-bf16 kernel). MFMA blocks of 16x16
 //     (v_mfma_f64_16x16x4f64 for FP64 E, v_mfma_f32_16x16x4f32 for FP32 and
 //     BF16 E, products accumulated in FP32). Lane l supplies A[l % 16][l / 16]
 //     and B[l / 16][l % 16]; the k slots of the MFMA are mapped to 32
@@ -88,7 +87,6 @@ template <> struct Mv<double> {
   using VT = double;
   using Acc = d4;
   static constexpr int VEC = 4;
-  static constexpr int RT = 1;
   __device__ static inline Acc mfma(double a, double b, Acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -105,7 +103,6 @@ template <> struct Mv<float> {
   using VT = float;
   using Acc = f4;
   static constexpr int VEC = 8;
-  static constexpr int RT = 2;
   __device__ static inline Acc mfma(float a, float b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -124,7 +121,6 @@ template <> struct Mv<uint16_t> {   // bf16 storage, widened to FP32
   using VT = float;
   using Acc = f4;
   static constexpr int VEC = 16;
-  static constexpr int RT = 2;
   __device__ static inline Acc mfma(float a, float b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -152,133 +148,6 @@ template <typename VT, int VEC> __device__ inline void load_vec(const VT *p, VT 
     } else {
       const float4 v = *reinterpret_cast<const float4 *>(p + q);
       o[q] = v.x; o[q + 1] = v.y; o[q + 2] = v.z; o[q + 3] = v.w;
-    }
-  }
-}
-
-// Load stages kept in flight per wave (register budget <= 128 VGPRs).
-template <typename T, int NG> constexpr int mv_stages() {
-  return sizeof(T) == 8 ? (NG == 1 ? 4 : (NG == 2 ? 2 : 1))
-                        : (NG == 1 ? (sizeof(T) == 4 ? 4 : 3) : (NG == 2 ? 2 : 1));
-}
-
-// Partial block product over one k slice: grid (row tiles, k slices), one
-// workgroup of 4 waves per (tile, slice); the waves split the slice and
-// their 16*RT x 16*NG tiles are summed in LDS in a fixed order.
-//   part[s][c][row] = sum_{k in slice s} E[row][k] P[c][k]
-//   pv_part[s][tile][c] = sum over the tile's rows of P[c][row] part[s][c][row]
-// (p^T E p is linear in the partial products, so the slices' contributions
-// sum to p.v without any communication between workgroups). Each wave keeps
-// two independent accumulator chains per output tile and U load stages in
-// flight.
-template <typename T, int NG>
-__global__ __launch_bounds__(256) void block_matvec_kernel(
-    const T *__restrict__ E, int64_t ld, const typename Mv<T>::VT *__restrict__ P,
-    typename Mv<T>::VT *__restrict__ part, int64_t kslice, int64_t split_stride,
-    double *__restrict__ pv_part, const int *__restrict__ gate, int *__restrict__ mark) {
-  using M = Mv<T>;
-  // gate == 0: nothing to do (device-side control); mark records whether
-  // this launch did the product (for the live kernel timing)
-  const bool first = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
-  if (gate != nullptr && *gate == 0) {
-    if (mark != nullptr && first) *mark = 0;
-    return;
-  }
-  if (mark != nullptr && first) *mark = 1;
-  using VT = typename M::VT;
-  using Acc = typename M::Acc;
-  constexpr int W = 4;
-  constexpr int VEC = M::VEC;
-  constexpr int KB = 4 * VEC;
-  constexpr int RT = M::RT;
-  constexpr int ROWS = 16 * RT;
-  constexpr int COLS = 16 * NG;
-  __shared__ VT red[W][ROWS][COLS + 1];
-
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int lr = lane & 15, lg = lane >> 4;
-  const int64_t tile = blockIdx.x, sl = blockIdx.y;
-  const int64_t r0 = tile * ROWS;
-  const int64_t kq = kslice / W;   // multiple of KB by construction
-  const int64_t kbeg = sl * kslice + wave * kq;
-  const int64_t kend = min(ld, kbeg + kq);
-
-  Acc acc[2][RT][NG];
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int a = 0; a < RT; ++a)
-#pragma unroll
-      for (int g = 0; g < NG; ++g) acc[h][a][g] = Acc{0, 0, 0, 0};
-
-  const T *erow[RT];
-#pragma unroll
-  for (int a = 0; a < RT; ++a) erow[a] = E + (r0 + a * 16 + lr) * ld + lg * VEC;
-  const VT *pcol[NG];
-#pragma unroll
-  for (int g = 0; g < NG; ++g) pcol[g] = P + (int64_t)(g * 16 + lr) * ld + lg * VEC;
-
-  // software pipeline: U stages of E / P loads are in flight while the
-  // MFMAs of the oldest stage run
-  constexpr int U = mv_stages<T, NG>();
-  typename M::Raw ea[U][RT];
-  VT pb[U][NG][VEC];
-  const int64_t nsteps = kend > kbeg ? (kend - kbeg) / KB : 0;
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if (u < nsteps) {
-      const int64_t kb = kbeg + u * KB;
-#pragma unroll
-      for (int a = 0; a < RT; ++a) M::load(erow[a] + kb, ea[u][a]);
-#pragma unroll
-      for (int g = 0; g < NG; ++g) load_vec<VT, VEC>(pcol[g] + kb, pb[u][g]);
-    }
-  }
-  for (int64_t st0 = 0; st0 < nsteps; st0 += U) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (st0 + u < nsteps) {
-#pragma unroll
-        for (int t = 0; t < VEC; ++t)
-#pragma unroll
-          for (int a = 0; a < RT; ++a)
-#pragma unroll
-            for (int g = 0; g < NG; ++g)
-              acc[t & 1][a][g] = M::mfma(M::elem(ea[u][a], t), pb[u][g][t], acc[t & 1][a][g]);
-        const int64_t nxt = st0 + u + U;
-        if (nxt < nsteps) {
-          const int64_t kb = kbeg + nxt * KB;
-#pragma unroll
-          for (int a = 0; a < RT; ++a) M::load(erow[a] + kb, ea[u][a]);
-#pragma unroll
-          for (int g = 0; g < NG; ++g) load_vec<VT, VEC>(pcol[g] + kb, pb[u][g]);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int g = 0; g < NG; ++g)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        red[wave][a * 16 + M::out_row(lg, v)][g * 16 + lr] = acc[0][a][g][v] + acc[1][a][g][v];
-  __syncthreads();
-
-  // thread -> (row, column group); the ROWS threads of a group are adjacent lanes
-  constexpr int TPR = 64 * W / ROWS;
-  const int row = threadIdx.x % ROWS, cg0 = threadIdx.x / ROWS;
-  VT *out = part + sl * split_stride;
-#pragma unroll
-  for (int c = cg0; c < COLS; c += TPR) {
-    const VT sv = ((red[0][row][c] + red[1][row][c]) + red[2][row][c]) + red[3][row][c];
-    const int64_t idx = (int64_t)c * ld + r0 + row;
-    out[idx] = sv;
-    if (pv_part) {
-      double pv = (double)P[idx] * (double)sv;
-#pragma unroll
-      for (int off = ROWS / 2; off > 0; off >>= 1) pv += __shfl_xor(pv, off, ROWS);
-      if (row == 0) pv_part[(sl * gridDim.x + tile) * COLS + c] = pv;
     }
   }
 }
@@ -1289,14 +1158,19 @@ __global__ void ctl_check_kernel(double *__restrict__ scal, int cols, int it_aft
   }
 }
 
-// After a true residual (only when one was due): record it, retire the
-// columns that meet the tolerance, count the update.
-__global__ void ctl_update_kernel(double *__restrict__ scal, int cols, int fc, double tol,
+// After a true residual (only when one was due): |r|^2 from the residual
+// kernel's partials, record it, retire the columns that meet the tolerance,
+// count the update.
+__global__ void ctl_update_kernel(const double *__restrict__ partial, int nblk,
+                                  double *__restrict__ scal, int cols, int fc, double tol,
                                   int *__restrict__ flags) {
   if (flags[F_NEED] == 0) return;
   const int c = threadIdx.x;
   bool act = false;
   if (c < cols) {
+    double rr = 0.0;
+    for (int b = 0; b < nblk; ++b) rr += partial[((int64_t)b * cols + c) * 2];
+    scal[S_RR * cols + c] = rr;
     act = scal[S_ACT * cols + c] != 0.0;
     const double bn = sqrt(scal[S_BN2 * cols + c]);
     if (c < fc && bn != 0.0) {
@@ -1402,35 +1276,7 @@ template <typename T> constexpr int prec_of() {
   return sizeof(T) == 8 ? CPM_PREC_F64 : (sizeof(T) == 4 ? CPM_PREC_F32 : CPM_PREC_BF16);
 }
 
-template <typename T> int64_t matvec_tiles(int64_t ld) { return ld / (16 * Mv<T>::RT); }
-
-// k slices of the block product for cols columns: enough workgroups (~1024)
-// to fill the chip, and slices short enough that the cols x kslice block of
-// P (<= 1 MB) stays in L2 while the row tiles of one slice pass over it
-// (workgroups are dispatched tile-fastest, so those of one slice run
-// together); each slice a multiple of 4 waves x KB columns.
-template <typename T> int64_t matvec_slices(int64_t ld, int64_t cols, int64_t &kslice) {
-  constexpr int64_t unit = 4 * 4 * Mv<T>::VEC;
-  const int64_t tiles = matvec_tiles<T>(ld);
-  const int64_t units = ld / unit;   // ld is a multiple of 128 >= unit
-  const int64_t kcap = std::max<int64_t>(
-      unit, ((int64_t)1 << 20) / (cols * (int64_t)sizeof(typename Mv<T>::VT)) / unit * unit);
-  int64_t want = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
-  want = std::max<int64_t>(want, (ld + kcap - 1) / kcap);
-  want = std::min<int64_t>(want, std::max<int64_t>(1, units));
-  // prefer a slice count near want that splits the k range evenly
-  int64_t best = want;
-  for (int64_t c = want; c <= std::min<int64_t>(2 * want, units); ++c)
-    if (units % c == 0) {
-      best = c;
-      break;
-    }
-  kslice = (units + best - 1) / best * unit;
-  return (ld + kslice - 1) / kslice;
-}
-
-// k slices of the split-bf16 kernel: row tiles of SP_ROWS rows, ~1024
-// workgroups, slices a multiple of SP_KC
+// k slices of the split-bf16 kernel: about 1024 workgroups
 int64_t split_slices(int64_t ld, int64_t &kslice) {
   const int64_t tiles = ld / SP_ROWS;
   const int64_t units = ld / SP_KC;
@@ -1478,8 +1324,7 @@ template <typename T> int64_t matvec_npv(int64_t ld, int64_t cols) {
   int64_t k = 0;
   if (uses_split<T>(cols)) return split_slices(ld, k) * (ld / SP_ROWS);
   if (uses_f64s<T>(cols)) return f64s_slices(ld, k) * (ld / F64_ROWS);
-  if (cols == 16) return rows_slices<T>(ld, k) * (ld / (16 * MR_WAVES));
-  return matvec_slices<T>(ld, cols, k) * matvec_tiles<T>(ld);
+  return rows_slices<T>(ld, k) * (ld / (16 * MR_WAVES));   // 16 columns
 }
 
 // slices of the kernel that serves c columns of an E of type T
@@ -1487,8 +1332,7 @@ template <typename T> int64_t slices_for(int64_t ld, int64_t c) {
   int64_t k = 0;
   if (uses_split<T>(c)) return split_slices(ld, k);
   if (uses_f64s<T>(c)) return f64s_slices(ld, k);
-  if (c == kColGroup) return rows_slices<T>(ld, k);
-  return matvec_slices<T>(ld, c, k);
+  return rows_slices<T>(ld, k);   // 16 columns
 }
 
 // elements of the partial-product buffer for up to cols columns (slices x
@@ -1515,19 +1359,15 @@ hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typenam
                            const int *gate) {
   constexpr bool split = uses_split<T>(NG * 16);
   constexpr bool f64s = uses_f64s<T>(NG * 16);
-  constexpr bool rows = NG == 1;
+  static_assert(split || f64s || NG == 1, "16 columns or an FP32/BF16/FP64 wide kernel");
   int64_t kslice = 0;
-  slices = split  ? (int)split_slices(ld, kslice)
+  slices = split ? (int)split_slices(ld, kslice)
            : f64s ? (int)f64s_slices(ld, kslice)
-           : rows ? (int)rows_slices<T>(ld, kslice)
-                  : (int)matvec_slices<T>(ld, NG * 16, kslice);
-  const int64_t tiles = split ? ld / SP_ROWS
-                        : f64s ? ld / F64_ROWS
-                        : rows ? ld / (16 * MR_WAVES)
-                               : matvec_tiles<T>(ld);
+                  : (int)rows_slices<T>(ld, kslice);
+  const int64_t tiles = split ? ld / SP_ROWS : f64s ? ld / F64_ROWS : ld / (16 * MR_WAVES);
   hipEvent_t ea = nullptr, eb = nullptr;
   int *mark = nullptr;
-  if (t_prof && t_prof->enabled) {
+  if (t_prof && t_prof->sample(prec_of<T>())) {
     // algorithmic traffic: E (n x n) once, the n x cols block P read and V written
     const double n = (double)t_n;
     const double work = sizeof(T) * n * n + 2.0 * sizeof(typename Mv<T>::VT) * n * (NG * 16);
@@ -1541,19 +1381,15 @@ hipError_t launch_matvec_t(hipStream_t st, const T *E, int64_t ld, const typenam
                           dim3(256), 0, st, ea, eb, 0, reinterpret_cast<const double *>(E), ld,
                           reinterpret_cast<const double *>(P), reinterpret_cast<double *>(part),
                           kslice, (int64_t)(NG * 16) * ld, pv_part, gate, mark);
-  } else if constexpr (rows) {
-    const size_t lds = sizeof(typename Mv<T>::VT) * 16 * (size_t)(kslice + mr_pad<T>());
-    hipExtLaunchKernelGGL((block_matvec_rows_kernel<T>), dim3((unsigned)tiles, (unsigned)slices),
-                          dim3(64 * MR_WAVES), lds, st, ea, eb, 0, E, ld, P, part, kslice,
-                          (int64_t)16 * ld, pv_part, gate, mark);
   } else if constexpr (split) {
     hipExtLaunchKernelGGL((block_matvec_split_kernel<T, NG>),
                           dim3((unsigned)tiles, (unsigned)slices), dim3(256), 0, st, ea, eb, 0, E,
                           ld, P, part, kslice, (int64_t)(NG * 16) * ld, pv_part, gate, mark);
   } else {
-    hipExtLaunchKernelGGL((block_matvec_kernel<T, NG>), dim3((unsigned)tiles, (unsigned)slices),
-                          dim3(256), 0, st, ea, eb, 0, E, ld, P, part, kslice,
-                          (int64_t)(NG * 16) * ld, pv_part, gate, mark);
+    const size_t lds = sizeof(typename Mv<T>::VT) * 16 * (size_t)(kslice + mr_pad<T>());
+    hipExtLaunchKernelGGL((block_matvec_rows_kernel<T>), dim3((unsigned)tiles, (unsigned)slices),
+                          dim3(64 * MR_WAVES), lds, st, ea, eb, 0, E, ld, P, part, kslice,
+                          (int64_t)16 * ld, pv_part, gate, mark);
   }
   return hipGetLastError();
 }
@@ -1713,14 +1549,16 @@ template <typename T> struct Solver {
   const int *need() const { return flags + F_NEED; }
 
   // r = b - E64 x for all columns; scal RR = |r|^2 (gate: skipped when *gate == 0)
-  hipError_t true_residual(const int *gate) {
+  // (sum_rr: also reduce |r|^2 into the scalars; otherwise ctl_update_kernel does)
+  hipError_t true_residual(const int *gate, bool sum_rr = true) {
     int sl = 0;
     hipError_t e = launch_matvec<double>(st, s->E64, ld, cols, x, v64, nullptr, sl, gate);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(residual_kernel, grid(), dim3(RED_THREADS), 0, st, v64, sl, ld * cols, b,
                        r, ld, n, (int)cols, partial, gate);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, partial, nblk,
-                       (int)cols, scal, (int)S_RR, gate);
+    if (sum_rr)
+      hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, partial, nblk,
+                         (int)cols, scal, (int)S_RR, gate);
     return hipGetLastError();
   }
 
@@ -1866,8 +1704,9 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
     it += todo;
     hipLaunchKernelGGL(ctl_check_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.scal, (int)cols, it,
                        todo, o.max_iter, tol, ru, sv.flags);
-    CPM_HIP_CHECK(sv.true_residual(sv.need()));
-    hipLaunchKernelGGL(ctl_update_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.scal, (int)cols, fc,
+    CPM_HIP_CHECK(sv.true_residual(sv.need(), false));
+    hipLaunchKernelGGL(ctl_update_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.partial, sv.nblk,
+                       sv.scal, (int)cols, fc,
                        tol, sv.flags);
     CPM_HIP_CHECK(sv.refresh(restart, sv.need()));
     const int slot = batch % kStatusSlots;

@@ -100,6 +100,10 @@ struct Mlp {
 // contraction), enabled per system.
 struct Profile {
   bool enabled = false;
+  int stride = 1;            // time every stride-th block-product launch of each kind
+  int64_t seen[3] = {0, 0, 0};
+  // whether this launch of the block product (kind 0..2) is to be timed
+  bool sample(int kind) { return enabled && (seen[kind]++ % stride) == 0; }
   struct Rec {
     int kind;              // 0..2: matvec FP64/FP32/BF16, 3: assembly contraction
     double work;           // algorithmic bytes (matvec) or flops (assembly) of the launch
