@@ -207,6 +207,41 @@ cpm_status cpm_mi_build(cpm_system *s, const cpm_solve_opts *opts);
 cpm_status cpm_mi_solve(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
                         double *q_out_dev);
 
+/* ---- galvanostatic charge-discharge (Supplementary Note, Eq. S14-S24) -----
+ * Electrode a carries a prescribed total charge Q_a; minimising the energy of
+ * Eq. S14 under these constraints gives E q = b + Delta u, Delta u_i =
+ * Delta mu_a for the atoms i of electrode a (Eq. S15).
+ * cpm_gcd_build: labels_host (n,) int32, the electrode of each atom (caller's
+ * atom order), every one of the m electrodes (1 <= m <= 64) non-empty. Solves
+ * E a^h = b^h for the m indicator vectors b^h (Eq. S22-S23) with the block
+ * solver and the caller's opts (tolerance on |b^h - E a^h| / |b^h|,
+ * precision, preconditioner; the warm start is ignored), keeps
+ * A = (a^1 .. a^m) (m n doubles) on the device, sums it per electrode into
+ * the capacitance coefficients C_ab = sum over the atoms of a of a^b_i
+ * (Eq. S24), symmetrises C_E (it is symmetric up to the solve error), and
+ * factors it on the device. Outputs (host): C_out_host (m, m) row-major in
+ * units of e per (V / k_e); det_out = |C_E| and joint_out = C(Q, -Q) =
+ * |C_E| / sum_ab C_ab (Eq. S21; NaN unless m = 2), either may be NULL. A later
+ * build replaces the previous one. info as for cpm_solve (max_abs_sum_q 0).
+ * Errors: CPM_EINVAL (NULL, m, a label outside [0, m), an empty electrode,
+ * the opts), CPM_ESTATE (CPM_PRECOND_DC before cpm_precond_dc), CPM_ENOMEM,
+ * CPM_ENOTSPD (C_E not positive definite), the solve's errors.
+ * cpm_gcd_solve: b_dev (f, n), Q_dev (f, m) the totals Q_a per frame,
+ * q_out_dev (f, n), dmu_out_dev (f, m) or NULL: device arrays. q_b = E^-1 b
+ * by the block solver (opts as above), Delta mu = C_E^-1 (Q - L q_b)
+ * (Eq. S18-S20) and q = q_b + A Delta mu (Eq. S17). The system's E is used as
+ * built (with the boundary correction of Eq. 39 when it was requested; the
+ * constraint then fixes the totals, not the dipole). Synchronous.
+ * info->max_abs_sum_q = max over frames and electrodes of |sum_a q - Q_a|.
+ * Errors: CPM_EINVAL, CPM_ESTATE (before cpm_gcd_build), CPM_ENOTCONV (q_out
+ * then holds the shifted last iterate), the solve's errors. */
+cpm_status cpm_gcd_build(cpm_system *s, const int32_t *labels_host, int32_t m,
+                         const cpm_solve_opts *opts, double *C_out_host, double *det_out,
+                         double *joint_out, cpm_solve_info *info);
+cpm_status cpm_gcd_solve(cpm_system *s, const double *b_dev, const double *Q_dev, int64_t f,
+                         const cpm_solve_opts *opts, double *q_out_dev, double *dmu_out_dev,
+                         cpm_solve_info *info);
+
 /* Copy E (caller's atom order) into dst_dev with leading dimension ld >= n,
    in the requested precision (FP64 double, FP32 float, BF16 uint16 bits).
    CPM_EINVAL if that precision is not stored. */

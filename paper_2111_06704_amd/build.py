@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcpm.so")
-SOURCES = ["api.hip", "assembly.hip", "rhs.hip", "cg.hip", "mlp.hip", "precond.hip", "mi.hip"]
+SOURCES = ["api.hip", "assembly.hip", "rhs.hip", "cg.hip", "mlp.hip", "precond.hip", "mi.hip", "gcd.hip"]
 ARCH = os.environ.get("CPM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

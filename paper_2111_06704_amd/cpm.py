@@ -30,7 +30,7 @@ EXPORTS = [
     "cpm_mlp_set_params", "cpm_mlp_get_params", "cpm_mlp_features", "cpm_mlp_forward",
     "cpm_mlp_loss_grad", "cpm_mlp_train_step", "cpm_mlp_train_epoch", "cpm_set_warm_chi",
     "cpm_profile_enable", "cpm_profile_read", "cpm_precond_dc", "cpm_precond_apply",
-    "cpm_mi_build", "cpm_mi_solve",
+    "cpm_mi_build", "cpm_mi_solve", "cpm_gcd_build", "cpm_gcd_solve",
     "cpm_status_str", "cpm_last_error",
 ]
 PROFILE_BUILD = 4
@@ -98,6 +98,10 @@ def lib():
     L.cpm_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, f32, f32, f32, C.POINTER(dbl)]
     L.cpm_mlp_train_epoch.argtypes = [vp, vp, vp, i64, vp, i64, f32, f32, f32, f32, C.POINTER(dbl)]
     L.cpm_set_warm_chi.argtypes = [vp, vp, C.POINTER(SolveOpts)]
+    L.cpm_gcd_build.argtypes = [vp, vp, C.c_int32, C.POINTER(SolveOpts), vp, C.POINTER(dbl),
+                                C.POINTER(dbl), C.POINTER(SolveInfo)]
+    L.cpm_gcd_solve.argtypes = [vp, vp, vp, i64, C.POINTER(SolveOpts), vp, vp,
+                                C.POINTER(SolveInfo)]
     L.cpm_profile_enable.argtypes = [vp, C.c_int]
     L.cpm_profile_read.argtypes = [vp, C.POINTER(ProfileInfo)]
     L.cpm_status_str.argtypes = [C.c_int]
@@ -294,6 +298,54 @@ class System:
         _check(lib().cpm_mi_solve(self._h, _ptr(b, torch.float64), _ptr(qsol, torch.float64),
                                   int(b.shape[0]), _ptr(q_out, torch.float64)), "cpm_mi_solve")
         return q_out
+
+    def gcd_build(self, labels, m, tol=1e-12, max_iter=20000, precision=PREC_F64,
+                  preconditioner=PRECOND_JACOBI, check_every=8, inner_tol=1e-3):
+        """Capacitance coefficients C_E (Supplementary Eq. S22-S24) of the m
+        electrodes given by labels (N,); returns (C_E, |C_E|, C(Q, -Q), stats)."""
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        if labels.shape != (self.n,):
+            raise ValueError(f"labels must have shape ({self.n},)")
+        o = SolveOpts(tol=tol, max_iter=max_iter, precision=precision, warm_start=WARM_ZERO,
+                      inner_tol=inner_tol, check_every=check_every, preconditioner=preconditioner)
+        cmat = np.empty((int(m), int(m)), dtype=np.float64)
+        det, joint = C.c_double(), C.c_double()
+        info = SolveInfo()
+        _check(lib().cpm_gcd_build(self._h, labels.ctypes.data, int(m), C.byref(o),
+                                   cmat.ctypes.data, C.byref(det), C.byref(joint), C.byref(info)),
+               "cpm_gcd_build")
+        self._gcd_m = int(m)
+        stats = dict(iterations=info.iterations, max_rel_resid=info.max_rel_resid,
+                     solve_ms=info.solve_ms)
+        return cmat, det.value, joint.value, stats
+
+    def gcd_solve(self, b, Q, tol=1e-10, max_iter=5000, precision=PREC_F64,
+                  preconditioner=PRECOND_JACOBI, check_every=8, inner_tol=1e-3, q_out=None,
+                  dmu_out=None):
+        """Charges (F, N) under prescribed electrode totals Q (F, M) (Eq. S15-S20),
+        the multipliers Delta mu (F, M) and a dict of solve statistics."""
+        import torch
+        f = int(b.shape[0])
+        m = getattr(self, "_gcd_m", None)
+        if m is None:
+            raise RuntimeError("gcd_build first")
+        if tuple(b.shape) != (f, self.n) or tuple(Q.shape) != (f, m):
+            raise ValueError(f"need b ({f}, {self.n}) and Q ({f}, {m})")
+        if q_out is None:
+            q_out = torch.empty_like(b)
+        if dmu_out is None:
+            dmu_out = torch.empty_like(Q)
+        if tuple(q_out.shape) != (f, self.n) or tuple(dmu_out.shape) != (f, m):
+            raise ValueError("output shapes do not match b and Q")
+        o = SolveOpts(tol=tol, max_iter=max_iter, precision=precision, warm_start=WARM_ZERO,
+                      inner_tol=inner_tol, check_every=check_every, preconditioner=preconditioner)
+        info = SolveInfo()
+        _check(lib().cpm_gcd_solve(self._h, _ptr(b, torch.float64), _ptr(Q, torch.float64), f,
+                                   C.byref(o), _ptr(q_out, torch.float64),
+                                   _ptr(dmu_out, torch.float64), C.byref(info)), "cpm_gcd_solve")
+        stats = dict(iterations=info.iterations, max_rel_resid=info.max_rel_resid,
+                     max_abs_sum_q=info.max_abs_sum_q, solve_ms=info.solve_ms)
+        return q_out, dmu_out, stats
 
     def set_warm_chi(self, chi, tol=1e-12, max_iter=5000, preconditioner=PRECOND_JACOBI):
         import torch

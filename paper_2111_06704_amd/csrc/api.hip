@@ -138,6 +138,7 @@ void free_system(cpm_system *s) {
     if (p) (void)hipFree(p);
   release_workspace(s);
   free_precond(s->pc);
+  free_gcd(s->gcd);
   s->prof.reset();
   for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);
   if (s->prof.marks) (void)hipFree(s->prof.marks);
@@ -454,29 +455,10 @@ cpm_status cpm_rhs(cpm_system *s, const double *ion_pos_dev, const double *ion_q
   return CPM_OK;
 }
 
-namespace {
-cpm_status ensure_dprime(cpm_system *s) {
-  if (s->dprime_ready) return CPM_OK;
-  cpm_status rc = solve_dprime(s, 1e-13, 20000);
-  if (rc == CPM_OK) s->dprime_ready = true;
-  return rc;
-}
-}  // namespace
+}  // extern "C"
 
-cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
-                     const cpm_solve_opts *opts, double *q_out_dev, cpm_solve_info *info) {
-  if (!s || !b_dev || !qsol_dev || !opts || !q_out_dev) {
-    set_error("NULL argument");
-    return CPM_EINVAL;
-  }
-  {
-    cpm_status rd = ensure_dprime(s);
-    if (rd != CPM_OK) return rd;
-  }
-  if (f < 1) {
-    set_error("need f >= 1");
-    return CPM_EINVAL;
-  }
+cpm_status cpm::check_solve_opts(const cpm_system *s, const cpm_solve_opts *opts,
+                                  cpm_solve_opts *out) {
   cpm_solve_opts o = *opts;
   if (!(o.tol > 0.0) || !std::isfinite(o.tol)) {
     set_error("tol must be finite and > 0");
@@ -508,6 +490,40 @@ cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev,
   }
   if (o.precision != CPM_PREC_F64 && !(o.inner_tol > 0.0 && o.inner_tol < 1.0)) o.inner_tol = 1e-3;
   if (o.check_every < 1) o.check_every = 8;
+  *out = o;
+  return CPM_OK;
+}
+
+extern "C" {
+
+namespace {
+cpm_status ensure_dprime(cpm_system *s) {
+  if (s->dprime_ready) return CPM_OK;
+  cpm_status rc = solve_dprime(s, 1e-13, 20000);
+  if (rc == CPM_OK) s->dprime_ready = true;
+  return rc;
+}
+}  // namespace
+
+cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
+                     const cpm_solve_opts *opts, double *q_out_dev, cpm_solve_info *info) {
+  if (!s || !b_dev || !qsol_dev || !opts || !q_out_dev) {
+    set_error("NULL argument");
+    return CPM_EINVAL;
+  }
+  {
+    cpm_status rd = ensure_dprime(s);
+    if (rd != CPM_OK) return rd;
+  }
+  if (f < 1) {
+    set_error("need f >= 1");
+    return CPM_EINVAL;
+  }
+  cpm_solve_opts o;
+  {
+    cpm_status ro = check_solve_opts(s, opts, &o);
+    if (ro != CPM_OK) return ro;
+  }
   if (info) {
     int *fi = info->frame_iters;
     double *fr = info->frame_rel_resid;

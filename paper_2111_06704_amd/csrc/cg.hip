@@ -71,7 +71,8 @@ constexpr int64_t kRedLoads = (int64_t)1 << 22;
 // iterations, initial relative residual, start-discarded flag
 enum {
   S_RZ0 = 0, S_RZ1 = 1, S_RR = 2, S_BN2 = 3, S_ACT = 4, S_RT = 5, S_RES = 6, S_IT = 7,
-  S_INIT = 8, S_FB = 9, S_NFIELDS = 10
+  S_INIT = 8, S_FB = 9, S_HOLD0 = 10, S_HOLD1 = 11, S_RST = 12, S_RPREV = 13,
+  S_NFIELDS = 14
 };
 // status words (ints): breakdown flag and column, debug doubles (ints 2..5),
 // true residual due, any column active, non-finite residual seen, number of
@@ -729,6 +730,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_refresh_kernel(
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
   const bool act = scal[S_ACT * cols + c] != 0.0;
+  const bool sp = set_p || scal[S_RST * cols + c] != 0.0;
   double arr = 0.0, arz = 0.0;
   if (act) {
     const int64_t i0 = (int64_t)blk * CHUNK;
@@ -738,7 +740,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_refresh_kernel(
       const double ri = r[idx];
       const double zi = ri * dinv[i];
       z[idx] = zi;
-      if (set_p) p[idx] = (VT)zi;
+      if (sp) p[idx] = (VT)zi;
       arr += ri * ri;
       arz += ri * zi;
     }
@@ -777,6 +779,7 @@ __global__ __launch_bounds__(RED_THREADS) void set_scalars_kernel(
   if (gate != nullptr && *gate == 0) return;
   const int c = blockIdx.x;
   if (scal[S_ACT * cols + c] == 0.0) return;
+  if (threadIdx.x == 0) scal[S_RST * cols + c] = 0.0;   // the refresh has applied it
   double rr = 0.0, rz = 0.0;
   for (int b = threadIdx.x; b < nblk; b += RED_THREADS) {
     rr += partial[((int64_t)b * cols + c) * 2];
@@ -803,7 +806,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_kernel(
   __shared__ double red[3][4];
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
-  const bool act = scal[S_ACT * cols + c] != 0.0;
+  const bool act = scal[S_ACT * cols + c] != 0.0 && scal[(S_HOLD0 + slot) * cols + c] == 0.0;
   double arr = 0.0, arz = 0.0;
   if (act) {
     double pv = 0.0;
@@ -872,7 +875,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_pc_kernel(
     for (int q = 0; q < 16; ++q) pv += pvr[q][c];
     const double rz = scal[(S_RZ0 + slot) * cols + col];
     double alpha = 0.0;
-    if (scal[S_ACT * cols + col] != 0.0) {
+    if (scal[S_ACT * cols + col] != 0.0 && scal[(S_HOLD0 + slot) * cols + col] == 0.0) {
       if (pv > 0.0 && isfinite(pv)) {
         alpha = rz / pv;
       } else if (blockIdx.x == 0) {
@@ -893,7 +896,7 @@ __global__ __launch_bounds__(RED_THREADS) void cg_update_pc_kernel(
   double ri = 0.0;
   if (i < n) {
     ri = r[idx];
-    if (scal[S_ACT * cols + col] != 0.0) {
+    if (scal[S_ACT * cols + col] != 0.0 && scal[(S_HOLD0 + slot) * cols + col] == 0.0) {
       const double alpha = alpha_s[c];
       x[idx] += alpha * (double)p[idx];
       ri -= alpha * sum_slices(vpart, slices, stride, idx);
@@ -953,7 +956,7 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
     const double *__restrict__ rt, double *__restrict__ z, VT *__restrict__ p,
     const int32_t *__restrict__ pidx, const double *__restrict__ pval, int width,
     const int32_t *__restrict__ order, int64_t ld, int64_t n, int cols,
-    const double *__restrict__ scal, double *__restrict__ bpart, int set_p,
+    const double *__restrict__ scal, int slot, double *__restrict__ bpart, int set_p,
     const int *__restrict__ gate) {
   __shared__ double red[PC_ROWS][kColGroup][2];
   __shared__ double sval[PC_ROWS][PC_CHUNK];
@@ -974,8 +977,10 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
   const int c0 = g * kColGroup + 2 * h;
   double2 ri = make_double2(0.0, 0.0);
   if (i >= 0) ri = *reinterpret_cast<const double2 *>(rg + i * kColGroup + 2 * h);
-  const bool act0 = scal == nullptr || scal[S_ACT * cols + c0] != 0.0;
-  const bool act1 = scal == nullptr || scal[S_ACT * cols + c0 + 1] != 0.0;
+  const bool act0 = scal == nullptr || (scal[S_ACT * cols + c0] != 0.0 &&
+                                         scal[(S_HOLD0 + slot) * cols + c0] == 0.0);
+  const bool act1 = scal == nullptr || (scal[S_ACT * cols + c0 + 1] != 0.0 &&
+                                         scal[(S_HOLD0 + slot) * cols + c0 + 1] == 0.0);
   double a0 = 0.0, a1 = 0.0;
   for (int k0 = 0; k0 < width; k0 += PC_CHUNK) {
     const int cw = min(PC_CHUNK, width - k0);
@@ -1013,7 +1018,7 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
         if (u ? act1 : act0) {
           const int64_t idx = (int64_t)(c0 + u) * ld + i;
           z[idx] = zi;
-          if (set_p) p[idx] = (VT)zi;
+          if (set_p || (scal != nullptr && scal[S_RST * cols + c0 + u] != 0.0)) p[idx] = (VT)zi;
           d[u][0] = rv * rv;
           d[u][1] = rv * zi;
         }
@@ -1038,15 +1043,30 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
   }
 }
 
-// beta = rz' / rz; p = z + beta p; block 0 stores rz' in the other slot and rr.
+// beta = rz' / rz; p = z + beta p; block 0 stores rz' in the other slot and
+// rr, and counts the iteration.
+// Hold: a column whose recursive residual has fallen kHold below the level at
+// which the next control step takes a true residual (half the tolerance, or
+// the reliable-update factor below the last true residual) does no further
+// iteration until that step: below it the recursion only drifts (FP32 p
+// underflows, an exactly zero residual gives p = 0) and p^T E p can reach 0.
+// The hold flag of the next iteration goes to the other slot (S_HOLD0 +
+// slot ^ 1), so no workgroup reads a flag this launch writes; the control
+// step clears both.
+constexpr double kHold = 1e-3;
 template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
     VT *__restrict__ p, const double *__restrict__ z, int64_t ld, int64_t n, int cols, int nblk,
-    const double *__restrict__ partial, double *__restrict__ scal, int slot) {
+    const double *__restrict__ partial, double *__restrict__ scal, int slot, double tol,
+    double ru) {
   __shared__ double red[3][4];
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
   if (scal[S_ACT * cols + c] == 0.0) return;
+  if (scal[(S_HOLD0 + slot) * cols + c] != 0.0) {
+    if (blk == 0 && threadIdx.x == 0) scal[(S_HOLD0 + (slot ^ 1)) * cols + c] = 1.0;
+    return;
+  }
   double rr = 0.0, rzn = 0.0;
   for (int b = threadIdx.x; b < nblk; b += RED_THREADS) {
     rr += partial[((int64_t)b * cols + c) * 2];
@@ -1065,6 +1085,10 @@ __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
   if (blk == 0 && threadIdx.x == 0) {
     scal[(S_RZ0 + (slot ^ 1)) * cols + c] = rzn;
     scal[S_RR * cols + c] = rr;
+    scal[S_IT * cols + c] += 1.0;
+    const double bn = sqrt(scal[S_BN2 * cols + c]);
+    const double lim = kHold * fmax(0.5 * tol * bn, ru * scal[S_RT * cols + c]);
+    scal[(S_HOLD0 + (slot ^ 1)) * cols + c] = (sqrt(rr) <= lim) ? 1.0 : 0.0;
   }
 }
 
@@ -1105,6 +1129,10 @@ __global__ void ctl_init_kernel(double *__restrict__ scal, int cols, int fc, int
     scal[S_RES * cols + c] = res;
     scal[S_INIT * cols + c] = init;
     scal[S_IT * cols + c] = 0.0;
+    scal[S_HOLD0 * cols + c] = 0.0;
+    scal[S_HOLD1 * cols + c] = 0.0;
+    scal[S_RST * cols + c] = 0.0;
+    scal[S_RPREV * cols + c] = rn;
   }
   const bool any = __any(act), anyfb = __any(fb_any);
   if (threadIdx.x == 0) {
@@ -1129,23 +1157,23 @@ __global__ __launch_bounds__(RED_THREADS) void fallback_kernel(
   }
 }
 
-// After a batch of `todo` iterations (it_after in total): count iterations
-// of the active columns and decide whether the true residual is due — the
-// recursive residual met half the tolerance, fell by the reliable-update
-// factor ru below the last true residual (ru = 0: never), or the iteration
-// limit is reached.
+// After a batch of `todo` iterations (it_after in total): decide whether the
+// true residual is due — the recursive residual met half the tolerance, fell
+// by the reliable-update factor ru below the last true residual (ru = 0:
+// never), did not fall at all over the batch (a stalled recursion), or the
+// iteration limit is reached.
 __global__ void ctl_check_kernel(double *__restrict__ scal, int cols, int it_after, int todo,
                                  int max_iter, double tol, double ru, int *__restrict__ flags) {
   const int c = threadIdx.x;
   bool need = false, bad = false;
   double rel = 0.0;
   if (c < cols && scal[S_ACT * cols + c] != 0.0) {
-    scal[S_IT * cols + c] += (double)todo;
     const double bn = sqrt(scal[S_BN2 * cols + c]);
     const double rn = sqrt(scal[S_RR * cols + c]);
     if (!isfinite(rn)) bad = true;
     need = rn <= 0.5 * tol * bn || (ru > 0.0 && rn <= ru * scal[S_RT * cols + c]) ||
-           it_after >= max_iter;
+           rn > scal[S_RPREV * cols + c] || it_after >= max_iter;
+    scal[S_RPREV * cols + c] = rn;
     rel = bn > 0.0 ? rn / bn : 0.0;
   }
   const bool any_need = __any(need), any_bad = __any(bad);
@@ -1160,7 +1188,14 @@ __global__ void ctl_check_kernel(double *__restrict__ scal, int cols, int it_aft
 
 // After a true residual (only when one was due): |r|^2 from the residual
 // kernel's partials, record it, retire the columns that meet the tolerance,
-// count the update.
+// count the update. A column whose true residual exceeds kTrack times the
+// recursive one it replaces, or the previous true residual, is marked for a
+// restart (p = z at the refresh that follows): its recursion no longer
+// tracks the true residual, and the step length rz / p^T E p of a kept
+// direction assumes that it does (r orthogonal to the previous directions).
+// Left alone, such a column can diverge while its recursive residual stays
+// put.
+constexpr double kTrack = 4.0;
 __global__ void ctl_update_kernel(const double *__restrict__ partial, int nblk,
                                   double *__restrict__ scal, int cols, int fc, double tol,
                                   int *__restrict__ flags) {
@@ -1170,7 +1205,12 @@ __global__ void ctl_update_kernel(const double *__restrict__ partial, int nblk,
   if (c < cols) {
     double rr = 0.0;
     for (int b = 0; b < nblk; ++b) rr += partial[((int64_t)b * cols + c) * 2];
+    const double rec = sqrt(scal[S_RR * cols + c]);   // the recursive residual it replaces
+    const double last = scal[S_RT * cols + c];         // the previous true residual
     scal[S_RR * cols + c] = rr;
+    scal[S_HOLD0 * cols + c] = 0.0;
+    scal[S_HOLD1 * cols + c] = 0.0;
+    scal[S_RST * cols + c] = 0.0;
     act = scal[S_ACT * cols + c] != 0.0;
     const double bn = sqrt(scal[S_BN2 * cols + c]);
     if (c < fc && bn != 0.0) {
@@ -1178,9 +1218,12 @@ __global__ void ctl_update_kernel(const double *__restrict__ partial, int nblk,
       scal[S_RES * cols + c] = rn / bn;
       if (act) {
         scal[S_RT * cols + c] = rn;
+        scal[S_RPREV * cols + c] = rn;
         if (rn <= tol * bn) {
           act = false;
           scal[S_ACT * cols + c] = 0.0;
+        } else if (rn > kTrack * rec || rn > last) {
+          scal[S_RST * cols + c] = 1.0;
         }
       }
     }
@@ -1500,12 +1543,12 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
 // bpart gets one (r.r, r.z) pair per workgroup and column.
 template <typename VT>
 void launch_precond(hipStream_t st, const cpm_system *s, const Precond &pc, const double *rt,
-                    double *z, VT *p, int64_t cols, const double *scal, double *bpart, bool set_p,
-                    const int *gate) {
+                    double *z, VT *p, int64_t cols, const double *scal, int slot, double *bpart,
+                    bool set_p, const int *gate) {
   const int64_t ld = s->ld, n = s->n;
   hipLaunchKernelGGL(precond_kernel<VT>, dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
                      dim3(PC_THREADS), 0, st, rt, z, p, pc.idx, pc.val, pc.width, s->atom_order, ld,
-                     n, (int)cols, scal, bpart, set_p ? 1 : 0, gate);
+                     n, (int)cols, scal, slot, bpart, set_p ? 1 : 0, gate);
 }
 
 // The solver over one block of cols columns. VT is the vector type of p and
@@ -1522,6 +1565,7 @@ template <typename T> struct Solver {
   int *flags;
   int slot = 0;
   const Precond *pc = nullptr;   // PCG-DC preconditioner (nullptr: Jacobi)
+  double tol = 0.0, ru = 0.0;    // tolerance and reliable-update factor (hold test)
 
   Solver(cpm_system *s_, const T *E_, int64_t cols_, const Precond *pc_)
       : s(s_), st(s_->stream), E(E_), pc(pc_) {
@@ -1576,7 +1620,7 @@ template <typename T> struct Solver {
       hipLaunchKernelGGL(rows_kernel, dim3((unsigned)(ld / RT_ROWS), (unsigned)(cols / kColGroup)),
                          dim3(RED_THREADS), 0, st, (const double *)r, ld, n, (int)cols, rt, ld,
                          gate);
-    launch_precond<VT>(st, s, *pc, rt, z, p, cols, scal, s->ws.bpart, set_p, gate);
+    launch_precond<VT>(st, s, *pc, rt, z, p, cols, scal, slot, s->ws.bpart, set_p, gate);
   }
 
   // z = M^-1 r (and p = z when restarting); rz into the current slot
@@ -1626,7 +1670,7 @@ template <typename T> struct Solver {
       nds = 1;
     }
     hipLaunchKernelGGL(cg_direction_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, p, z, ld, n,
-                       (int)cols, nds, ds, scal, slot);
+                       (int)cols, nds, ds, scal, slot, tol, ru);
     slot ^= 1;
     return hipGetLastError();
   }
@@ -1664,6 +1708,8 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
   // residual (iterative refinement).
   const bool restart = sizeof(T) == 2;
   const double tol = o.tol;
+  sv.tol = tol;
+  sv.ru = ru;
 
   // |b|^2 and the start residual
   hipLaunchKernelGGL(sumsq_kernel, sv.grid(), dim3(RED_THREADS), 0, st, sv.b, sv.ld, sv.n,
@@ -1843,7 +1889,7 @@ cpm_status solve_dprime(cpm_system *s, double tol, int max_iter) {
 
 cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
                        const cpm_solve_opts &o, double *q_out_dev, cpm_solve_info *info,
-                       const double *x0_dev) {
+                       const double *x0_dev, bool project) {
   t_prof = &s->prof;
   t_n = s->n;
   const auto t0 = std::chrono::steady_clock::now();
@@ -1873,15 +1919,21 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
     stt = solve_columns(s, fc, o, info, fit, fres, x0_dev == nullptr);
     if (stt != CPM_OK && stt != CPM_ENOTCONV) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
     if (stt == CPM_ENOTCONV) result = CPM_ENOTCONV;
-    hipLaunchKernelGGL(project_kernel, dim3((unsigned)fc), dim3(RED_THREADS), 0, st,
-                       (const double *)s->ws.x, ld, n, s->dvec, qsol_dev + f0, q_out_dev + f0 * n,
-                       sum_err_dev);
-    CPM_HIP_CHECK(hipMemcpyAsync(sum_err.data(), sum_err_dev, sizeof(double) * fc,
-                                 hipMemcpyDeviceToHost, st));
+    if (project) {
+      hipLaunchKernelGGL(project_kernel, dim3((unsigned)fc), dim3(RED_THREADS), 0, st,
+                         (const double *)s->ws.x, ld, n, s->dvec, qsol_dev + f0,
+                         q_out_dev + f0 * n, sum_err_dev);
+      CPM_HIP_CHECK(hipMemcpyAsync(sum_err.data(), sum_err_dev, sizeof(double) * fc,
+                                   hipMemcpyDeviceToHost, st));
+    } else {
+      CPM_HIP_CHECK(hipMemcpy2DAsync(q_out_dev + f0 * n, sizeof(double) * n, s->ws.x,
+                                     sizeof(double) * ld, sizeof(double) * n, fc,
+                                     hipMemcpyDeviceToDevice, st));
+    }
     CPM_HIP_CHECK(hipStreamSynchronize(st));
     if (info) {
       for (int c = 0; c < fc; ++c) {
-        info->max_abs_sum_q = std::max(info->max_abs_sum_q, sum_err[c]);
+        if (project) info->max_abs_sum_q = std::max(info->max_abs_sum_q, sum_err[c]);
         if (info->frame_iters) info->frame_iters[f0 + c] = fit[c];
         if (info->frame_rel_resid) info->frame_rel_resid[f0 + c] = fres[c];
       }
@@ -1953,7 +2005,7 @@ cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z
     hipLaunchKernelGGL(rows_kernel, dim3((unsigned)(ld / RT_ROWS), (unsigned)(cols / kColGroup)),
                        dim3(RED_THREADS), 0, st, r_dev + f0 * n, n, n, fc, in, ld,
                        (const int *)nullptr);
-    launch_precond<double>(st, s, s->pc, in, out, (double *)nullptr, cols, nullptr, nullptr, false,
+    launch_precond<double>(st, s, s->pc, in, out, (double *)nullptr, cols, nullptr, 0, nullptr, false,
                            nullptr);
     CPM_HIP_CHECK(hipMemcpy2DAsync(z_dev + f0 * n, sizeof(double) * n, out, sizeof(double) * ld,
                                    sizeof(double) * n, fc, hipMemcpyDeviceToDevice, st));

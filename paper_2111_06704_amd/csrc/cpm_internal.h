@@ -75,6 +75,16 @@ struct Precond {              // PCG-DC preconditioner (P + P^T) / 2 in ELL form
 };
 void free_precond(Precond &p);
 
+struct Gcd {                 // capacitance coefficients (Supplementary Eq. S22-S24)
+  bool ready = false;
+  int m = 0;                  // electrodes
+  int32_t *labels = nullptr;  // n: electrode of each atom
+  double *A = nullptr;        // m * n: A[h * n + i] = (E^-1 b^h)_i
+  double *mats = nullptr;     // 2 m^2 + 4: C_E (symmetrised), C_E^-1, then |C_E|,
+                              // sum of C_E, C(Q, -Q), factor status
+  int64_t bytes = 0;
+};
+
 struct Mlp {
   bool ready = false;
   int32_t *nbr = nullptr;     // n*12
@@ -162,6 +172,7 @@ struct cpm_system {
   cpm::Workspace ws;
   cpm::Mlp mlp;
   cpm::Precond pc;
+  cpm::Gcd gcd;
   std::vector<double> width_host;   // n Gaussian inverse widths (host copy)
   cpm::Profile prof;
   int64_t device_bytes = 0;
@@ -188,9 +199,12 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
 
 // ---- cg.hip
 void release_workspace(cpm_system *s);
+// q_out = E^-1 b for f frames; with project the two-step neutralisation of
+// Eq. 35 follows (qsol_dev required), without it q_out is the raw solution
+// and qsol_dev is not read
 cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
                        const cpm_solve_opts &o, double *q_out_dev, cpm_solve_info *info,
-                       const double *x0_dev);
+                       const double *x0_dev, bool project = true);
 cpm_status solve_dprime(cpm_system *s, double tol, int max_iter);
 cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_t f,
                        double *v_dev);
@@ -201,6 +215,14 @@ cpm_status matvec_cols_with(cpm_system *s, int precision, const double *M64, con
 cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z_dev);
 hipError_t launch_diag_inverse(hipStream_t st, const double *E, int64_t n, int64_t ld,
                                double *dinv);
+
+// ---- api.hip
+// checks *opts against the system (tolerance, iterations, precision stored,
+// preconditioner built) and fills defaults; the warm start is not checked
+cpm_status check_solve_opts(const cpm_system *s, const cpm_solve_opts *opts, cpm_solve_opts *o);
+
+// ---- gcd.hip
+void free_gcd(Gcd &g);
 
 // ---- mlp.hip
 cpm_status warm_start_impl(cpm_system *s, bool use_mlp, const double *b, const double *qsol,

@@ -63,3 +63,5 @@ def test_build_rejects_bad_arguments_before_touching_the_device(libcpm):
     assert L.cpm_build_E(pos.ctypes.data, 2, box.ctypes.data, ctypes.byref(p), None, ctypes.byref(out)) == cpm.CPM_EINVAL
     assert not out.value
     assert L.cpm_solve(None, None, None, 1, None, None, None) == cpm.CPM_EINVAL
+    assert L.cpm_gcd_build(None, None, 2, None, None, None, None, None) == cpm.CPM_EINVAL
+    assert L.cpm_gcd_solve(None, None, None, 1, None, None, None, None) == cpm.CPM_EINVAL
