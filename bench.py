@@ -73,6 +73,10 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2111_06704_amd", "weights",
                                                       "warmstart_cfg2.npz"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--overlap", action=argparse.BooleanOptionalAction, default=False,
+                    help="compute the right-hand side of the next step on a second stream "
+                         "while the current step is solved (independent frames only: in MD "
+                         "the next frame's ions depend on this step's charges)")
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--traffic-record", default=None,
                     help="JSON written by --summarize-pmc (default: profiles/traffic_workload<W>.json)")
@@ -252,11 +256,49 @@ def main():
         precond_build_s = time.perf_counter() - t0
         log(f"PCG-DC preconditioner built in {precond_build_s:.2f} s")
 
+    def solver(precision, wm, qout, pcm=pcmode):
+        return lambda bb, qq: S.solve(bb, qq, tol=args.tol, precision=precision, warm_start=wm,
+                                      inner_tol=args.inner_tol, check_every=args.check_every,
+                                      q_out=qout, preconditioner=pcm)
+
+    # Steps: right-hand side of the batch, then its solve. With --overlap the
+    # right-hand side of step k + 1 is computed on a second stream (default
+    # priority) while step k is solved: the two share no memory in the
+    # library, the b buffers alternate, and events order each buffer's reuse.
+    main_stream = torch.cuda.current_stream()
+    rhs_stream = torch.cuda.Stream()
+    bufs = [(b, qsol), (torch.empty_like(b), torch.empty_like(qsol))]
+    ev_rhs = [torch.cuda.Event(), torch.cuda.Event()]
+    ev_used = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def enqueue_rhs(k):
+        bb, qq = bufs[k % 2]
+        with torch.cuda.stream(rhs_stream):
+            rhs_stream.wait_event(ev_used[k % 2])
+            S.set_stream()
+            S.rhs(t_ipos, t_iq, t_chi, b_out=bb, qsol_out=qq)
+            ev_rhs[k % 2].record(rhs_stream)
+        S.set_stream()
+
+    def run_steps(n, solve_fn, overlap=None):
+        """n steps; returns the last solve's result."""
+        last = None
+        if not (args.overlap if overlap is None else overlap):
+            for _ in range(n):
+                S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
+                last = solve_fn(b, qsol)
+            return last
+        enqueue_rhs(0)
+        for k in range(n):
+            if k + 1 < n:
+                enqueue_rhs(k + 1)
+            main_stream.wait_event(ev_rhs[k % 2])
+            last = solve_fn(*bufs[k % 2])
+            ev_used[k % 2].record(main_stream)
+        return last
+
     def step(precision, wm, qout, pcm=pcmode):
-        S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
-        return S.solve(b, qsol, tol=args.tol, precision=precision, warm_start=wm,
-                       inner_tol=args.inner_tol, check_every=args.check_every, q_out=qout,
-                       preconditioner=pcm)
+        return run_steps(1, solver(precision, wm, qout, pcm))
 
     # reference: plain FP64 CG from zero at the same tolerance
     q64 = torch.empty_like(b)
@@ -265,8 +307,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     n64 = max(3, args.steps // 2)
-    for _ in range(n64):
-        _, st64 = step(cpm.PREC_F64, cpm.WARM_ZERO, q64, cpm.PRECOND_JACOBI)
+    _, st64 = run_steps(n64, solver(cpm.PREC_F64, cpm.WARM_ZERO, q64, cpm.PRECOND_JACOBI))
     torch.cuda.synchronize()
     fp64_ms = (time.perf_counter() - t0) / n64 * 1e3
 
@@ -304,16 +345,12 @@ def main():
         mi_build_s = time.perf_counter() - t0
         qmi = torch.empty_like(b)
 
-        def mi_step():
-            S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
-            S.mi_solve(b, qsol, q_out=qmi)
-
-        mi_step()
+        mi_fn = lambda bb, qq: S.mi_solve(bb, qq, q_out=qmi)
+        run_steps(1, mi_fn)
         torch.cuda.synchronize()
         tm = time.perf_counter()
         nmi = max(3, args.steps)
-        for _ in range(nmi):
-            mi_step()
+        run_steps(nmi, mi_fn)
         torch.cuda.synchronize()
         mi_s = (time.perf_counter() - tm) / nmi
         qm = qmi.cpu().numpy()
@@ -331,14 +368,22 @@ def main():
     S.profile_enable(True, stride=PROFILE_STRIDE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st = step(prec, wmode, q)
+    _, st = run_steps(args.steps, solver(prec, wmode, q))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = S.profile_read()
     S.profile_enable(False)
     ms_per_step = elapsed / args.steps * 1e3
     value = nf * args.steps / elapsed
+    # the same steps with the right-hand side of step k + 1 overlapped with
+    # the solve of step k (for independent frames), for the record
+    run_steps(2, solver(prec, wmode, q), overlap=not args.overlap)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run_steps(args.steps, solver(prec, wmode, q), overlap=not args.overlap)
+    torch.cuda.synchronize()
+    other = {"overlap_rhs": not args.overlap,
+             "solves_per_s": nf * args.steps / (time.perf_counter() - t1)}
 
     # dominant kernel of the timed region: the block matrix product with the most time
     kinds = ["matvec_f64", "matvec_f32", "matvec_bf16"]
@@ -381,6 +426,7 @@ def main():
                    "n_electrode": geo.n, "frames_per_step": nf, "ions": m,
                    "n_kvec": desc["n_kvec"], "tol": args.tol, "check_every": args.check_every,
                    "inner_tol": args.inner_tol, "precision": args.precision,
+                   "overlap_rhs": bool(args.overlap),
                    "warm_start": warm, "preconditioner": args.precond,
                    "dc_g": args.dc_g if args.precond == "dc" else None,
                    "dc_rcut": args.dc_rcut if args.precond == "dc" else None},
@@ -388,6 +434,7 @@ def main():
         "fp64_cg_iterations": st64["iterations"],
         "speedup_vs_fp64_cg": value / (nf / (fp64_ms * 1e-3)),
         "iterations": st["iterations"], "true_residual_updates": st["outer"], "modes": modes,
+        "other_schedule": other,
         "initial_rel_resid": st["initial_rel_resid"], "max_rel_resid": st["max_rel_resid"],
         "max_abs_sum_q": st["max_abs_sum_q"],
         "charge_rel_err_vs_fp64_gpu": rel_vs_fp64,

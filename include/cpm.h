@@ -26,7 +26,10 @@
  *     what it keeps. A cpm_system owns its device memory until cpm_free.
  *   - Work is enqueued on the stream given to cpm_build_E (or cpm_set_stream).
  *     Calls that return host-side results (info structs, losses)
- *     synchronise that stream.
+ *     synchronise that stream. cpm_rhs shares no device memory with the
+ *     solve calls: a cpm_rhs enqueued on one stream may run while a solve
+ *     runs on another, but two cpm_rhs calls on one system must not overlap
+ *     (they share the structure-factor scratch).
  *   - Atom order in and out is the caller's order.
  *   - No exception or abort crosses the ABI. On failure a call returns a
  *     negative cpm_status and cpm_last_error() describes it (thread-local).

@@ -199,46 +199,71 @@ __global__ __launch_bounds__(64 * MR_WAVES) void block_matvec_rows_kernel(
   const int64_t pstride = kslice + mr_pad<T>();
   const int64_t nsteps = kn / KB;
   const T *erow = E + (r0 + lr) * ld + k0 + lg * VEC;
+  // E ring: slot u holds step st0 + u. The loads of the prologue and of the
+  // main loop are unconditional (the prologue's clamped to the last step) so
+  // that the loop body is one straight path: the compiler then waits only
+  // for the oldest slot (vmcnt 2 (U - 1)) instead of draining every load in
+  // flight at the top of each iteration.
   typename M::Raw ea[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u)
-    if (u < nsteps) M::load(erow + u * KB, ea[u]);
-  // P slice into LDS (16-byte pieces)
+  for (int u = 0; u < U; ++u) M::load(erow + min<int64_t>(u, nsteps - 1) * KB, ea[u]);
+  // P of the wave's own rows for the p.v partial, loaded now so that the
+  // loads are complete when the epilogue needs them
+  const VT *pc = P + (int64_t)lr * ld + r0;
+  VT pown[4];
+  if (pv_part != nullptr)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pown[v] = pc[M::out_row(lg, v)];
+  // P slice into LDS (16-byte pieces; kn / PV < 2^31)
   constexpr int PV = 16 / sizeof(VT);
-  const int64_t q = kn / PV;
-  for (int64_t t = threadIdx.x; t < 16 * q; t += 64 * MR_WAVES) {
-    const int64_t c = t / q, kk = (t % q) * PV;
+  const int q = (int)(kn / PV);
+  for (int t = threadIdx.x; t < 16 * q; t += 64 * MR_WAVES) {
+    const int c = t / q, kk = (t - c * q) * PV;
     *reinterpret_cast<uint4 *>(ps + c * pstride + kk) =
         *reinterpret_cast<const uint4 *>(P + c * ld + k0 + kk);
   }
   __syncthreads();
   Acc acc[2] = {Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}};
   const VT *pl = ps + lr * pstride + lg * VEC;
-  for (int64_t st0 = 0; st0 < nsteps; st0 += U) {
+  auto step = [&](const typename M::Raw &e, int64_t st) {
+    VT pb[VEC];
+    load_vec<VT, VEC>(pl + st * KB, pb);
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) acc[t & 1] = M::mfma(M::elem(e, t), pb[t], acc[t & 1]);
+  };
+  int64_t st0 = 0;
+  for (; st0 + 2 * U <= nsteps; st0 += U) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (st0 + u < nsteps) {
-        VT pb[VEC];
-        load_vec<VT, VEC>(pl + (st0 + u) * KB, pb);
-#pragma unroll
-        for (int t = 0; t < VEC; ++t) acc[t & 1] = M::mfma(M::elem(ea[u], t), pb[t], acc[t & 1]);
-        const int64_t nxt = st0 + u + U;
-        if (nxt < nsteps) M::load(erow + nxt * KB, ea[u]);
-      }
+      step(ea[u], st0 + u);
+      M::load(erow + (st0 + u + U) * KB, ea[u]);
+      // keep the refill here: scheduled after the last slot, all U refills
+      // would go out together and the ring would drain every iteration
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
+  // the last U .. 2U - 1 steps (fewer when nsteps < U)
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (st0 + u < nsteps) {
+      step(ea[u], st0 + u);
+      if (st0 + u + U < nsteps) M::load(erow + (st0 + u + U) * KB, ea[u]);
+    }
+  st0 += U;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (st0 + u < nsteps) step(ea[u], st0 + u);
   // lane (lr, lg) holds rows out_row(lg, v) of column lr
   VT *out = part + sl * split_stride + (int64_t)lr * ld + r0;
-  const VT *pc = P + (int64_t)lr * ld + r0;
+  VT sv[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sv[v] = acc[0][v] + acc[1][v];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[M::out_row(lg, v)] = sv[v];
+  if (pv_part == nullptr) return;
   double pv = 0.0;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = M::out_row(lg, v);
-    const VT sv = acc[0][v] + acc[1][v];
-    out[row] = sv;
-    pv += (double)pc[row] * (double)sv;
-  }
-  if (pv_part == nullptr) return;
+  for (int v = 0; v < 4; ++v) pv += (double)pown[v] * (double)sv[v];
   pv += __shfl_xor(pv, 16, 64);
   pv += __shfl_xor(pv, 32, 64);
   __shared__ double pvs[MR_WAVES][16];
