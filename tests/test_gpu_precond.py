@@ -47,6 +47,7 @@ class Case:
         km = ew.kmax_from_eps(BETA, EPS)
         E = ew.ewald_matrix(g.pos, g.box, A, BETA, RC, km)
         bo, qso = ew.rhs(g.pos, A, self.ipos, self.iq, self.chi, g.box, BETA, RC, km)
+        self.E = E
         self.qo = ocpm.solve(E, bo, qso)
         self.b, self.qsol = self.S.rhs(torch.tensor(self.ipos, device=self.dev),
                                        torch.tensor(self.iq, device=self.dev),
@@ -106,3 +107,28 @@ def test_dc_requires_build():
     with pytest.raises(cpm.CpmError) as ei:
         S.precond_dc(0.0, 8.0)
     assert ei.value.status == cpm.CPM_EINVAL
+
+
+@pytest.mark.parametrize("prec_name", ["f32", "bf16"])
+def test_mixed_dc_on_electrode_indicators(d2, prec_name):
+    """Right-hand sides that are nearly eigenvectors of E (the indicator of
+    each electrode: the FP64 solve converges in ~16 iterations) under FP32
+    or BF16 storage, PCG-DC, checks every 8 iterations and reliable-update
+    factor 1e-3. The recursive residual falls below the storage's accuracy
+    within one batch; the solver must notice that its recursion stopped
+    tracking the true residual (a stalled batch, a true residual above the
+    previous one) and restart the direction instead of diverging. Charges
+    against the oracle's Cholesky two-step solution (Eq. 35) with Q_sol = 0."""
+    c = d2
+    cpm = c.cpm
+    prec = {"f32": cpm.PREC_F32, "bf16": cpm.PREC_BF16}[prec_name]
+    ind = np.stack([(c.geo.electrode == a) for a in range(2)]).astype(np.float64)
+    b = torch.tensor(ind, device=c.dev)
+    qs = torch.zeros(2, dtype=torch.float64, device=c.dev)
+    q, st = c.S.solve(b, qs, tol=1e-11, precision=prec, inner_tol=1e-3, check_every=8,
+                      preconditioner=cpm.PRECOND_DC, max_iter=2000)
+    qo = ocpm.solve(c.E, ind, 0.0)
+    r2, _ = ocpm.rel_errors(q.cpu().numpy(), qo)
+    print(f"[indicator] {prec_name}: {st['iterations']} iterations, {st['outer']} true residuals")
+    assert r2.max() <= 1e-8
+    assert st["iterations"] < 200
