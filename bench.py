@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2111_06704_amd", "weights",
                                                       "warmstart_cfg2.npz"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--jitter", type=float, default=0.0,
+                    help="displace every electrode atom by U(-a, a) A per component (genericity check)")
     ap.add_argument("--overlap", action=argparse.BooleanOptionalAction, default=False,
                     help="compute the right-hand side of the next step on a second stream "
                          "while the current step is solved (independent frames only: in MD "
@@ -211,6 +213,10 @@ def main():
     torch.cuda.set_device(dev)
     cfg = args.workload
     geo, ipos, iq, chi = wl.workload(cfg)
+    if args.jitter > 0:
+        # genericity check: the same workload with every electrode atom displaced
+        # by U(-jitter, jitter) per component (no lattice structure to exploit)
+        geo = wl.jitter(geo, args.jitter, 7_000_000 + cfg)
     nf, m = ipos.shape[0], ipos.shape[1]
     log(f"workload {cfg}: N={geo.n} frames={nf} ions={m}")
 
@@ -426,7 +432,7 @@ def main():
                    "n_electrode": geo.n, "frames_per_step": nf, "ions": m,
                    "n_kvec": desc["n_kvec"], "tol": args.tol, "check_every": args.check_every,
                    "inner_tol": args.inner_tol, "precision": args.precision,
-                   "overlap_rhs": bool(args.overlap),
+                   "overlap_rhs": bool(args.overlap), "jitter_A": args.jitter,
                    "warm_start": warm, "preconditioner": args.precond,
                    "dc_g": args.dc_g if args.precond == "dc" else None,
                    "dc_rcut": args.dc_rcut if args.precond == "dc" else None},

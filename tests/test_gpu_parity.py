@@ -39,10 +39,12 @@ def _dev():
 
 
 class Case:
-    def __init__(self, cfg, frames, store=("f32", "bf16")):
+    def __init__(self, cfg, frames, store=("f32", "bf16"), jitter=0.0):
         cpm = _cpm()
         self.dev = _dev()
         self.geo, self.ipos, self.iq, self.chi = wl.workload(cfg, frames=frames)
+        if jitter > 0:
+            self.geo = wl.jitter(self.geo, jitter, 11 + cfg)
         self.km = ew.kmax_from_eps(BETA, EPS)
         g = self.geo
         print(f"[case] workload {cfg}: N={g.n} frames={frames}", flush=True)
@@ -195,6 +197,18 @@ def test_bench_step_workload2(c2):
     assert r2.max() <= 1e-8
     assert st["max_abs_sum_q"] <= 1e-12
     assert st["fell_back"] == 0 and st["initial_rel_resid"] < 0.5
+
+
+def test_jittered_geometry_workload1():
+    """Every electrode atom displaced by U(-0.01, 0.01) A: no lattice symmetry
+    left (the genericity check of the measurement). E, b and the FP64 and
+    mixed solves against the oracle built for the same positions."""
+    case = Case(1, 8, jitter=0.01)
+    assert np.ptp(case.geo.pos[:, 2][case.geo.electrode == 0]) > 0.005
+    _check_E(case)
+    _check_rhs(case)
+    _solve_and_check(case, _cpm().PREC_F64, 1e-12, 1e-9)
+    _solve_and_check(case, _cpm().PREC_F32, 1e-11, 1e-8, inner_tol=1e-3, check_every=4)
 
 
 def test_solve_ragged_frames(c1):
