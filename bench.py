@@ -329,6 +329,22 @@ def main():
                       ("f32_zero_dc", cpm.PREC_F32, cpm.WARM_ZERO, pcmode),
                       (f"f32_{warm}_dc", cpm.PREC_F32, wmode, pcmode),
                       (f"bf16_{warm}_dc", cpm.PREC_BF16, wmode, pcmode)]
+    # FP64 CG with one right-hand side per solve (the frames one after another)
+    S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
+    q1 = torch.empty_like(b)
+    S.solve(b[:1], qsol[:1], tol=args.tol, precision=cpm.PREC_F64, q_out=q1[:1])
+    torch.cuda.synchronize()
+    tm = time.perf_counter()
+    its = []
+    for f in range(nf):
+        _, s1 = S.solve(b[f:f + 1], qsol[f:f + 1], tol=args.tol, precision=cpm.PREC_F64,
+                        check_every=args.check_every, q_out=q1[f:f + 1])
+        its.append(s1["iterations"])
+    torch.cuda.synchronize()
+    modes["f64_zero_single_rhs"] = {"solves_per_s": nf / (time.perf_counter() - tm),
+                                    "iterations": max(its), "true_residual_updates": None,
+                                    "initial_rel_resid": 1.0}
+    log("f64_zero_single_rhs", modes["f64_zero_single_rhs"])
     for name, pm, wm, pcm in mode_list:
         if (pm == cpm.PREC_F32 and "f32" not in store) or (pm == cpm.PREC_BF16 and "bf16" not in store):
             continue
@@ -414,6 +430,16 @@ def main():
     for _ in range(3):
         torch.mul(src, 1.0, out=dst)   # an elementwise kernel, never a DMA copy
     torch.cuda.synchronize()
+    # the same copy timed: the bandwidth a plain streaming kernel reaches here
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * CALIB_BYTES * 5 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    roofline["copy_kernel_GBps"] = copy_gbs
+    roofline["frac_of_copy"] = achieved / copy_gbs
     del src, dst
 
     qg = q.cpu().numpy()
