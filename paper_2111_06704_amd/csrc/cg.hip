@@ -170,6 +170,15 @@ template <typename T> constexpr int64_t mr_kmax() {
   constexpr int64_t kb = 4 * Mv<T>::VEC;
   return ((65536 / (16 * (int64_t)sizeof(typename Mv<T>::VT))) - mr_pad<T>()) / kb * kb;
 }
+// the P copy plus the static p.v buffer stay far inside the 160 KB of LDS a
+// workgroup can hold (a launch asking for more than exists is not rejected
+// reliably)
+template <typename T> constexpr bool mr_lds_fits() {
+  return sizeof(typename Mv<T>::VT) * 16 * (mr_kmax<T>() + mr_pad<T>()) +
+             sizeof(double) * MR_WAVES * 16 <= 65536 + 4096;
+}
+static_assert(mr_lds_fits<double>() && mr_lds_fits<float>() && mr_lds_fits<uint16_t>(),
+              "LDS of the 16-column product");
 
 template <typename T>
 __global__ __launch_bounds__(64 * MR_WAVES) void block_matvec_rows_kernel(
