@@ -32,6 +32,7 @@ FP64_PEAK_TFLOPS = 78.6
 # plain copy run after the timed region: its counter readings calibrate the
 # FETCH_SIZE / WRITE_SIZE counters (bytes moved are known exactly)
 CALIB_BYTES = 1 << 30
+K_E = 14.3996454784   # V*A/e: cpm_rhs divides chi by it, so 1 V is 1/K_E in b units
 # 16 columns run on the row-split kernel
 KERNEL_OF_KIND = {"matvec_f64": "block_matvec_rows_kernel<double>",
                   "matvec_f32": "block_matvec_rows_kernel<float>",
@@ -382,6 +383,78 @@ def main():
                                                          / np.linalg.norm(q64n, axis=1)))}
         log("mi", mi)
 
+    # galvanostatic constraint (Supplementary Eq. S14-S24): C_E from the two
+    # electrode-indicator solves, then per step the charges under prescribed
+    # electrode totals, here the totals of the FP64 reference charges (so the
+    # constrained charges must come back equal to them)
+    gcd = None
+    if geo.n <= 10000:
+        labels = geo.electrode.astype(np.int32)
+        t0 = time.perf_counter()
+        cmat, cdet, cjoint, _ = S.gcd_build(labels, 2, tol=1e-12, precision=cpm.PREC_F64,
+                                            preconditioner=pcmode)
+        torch.cuda.synchronize()
+        gcd_build_s = time.perf_counter() - t0
+        q64n = q64.cpu().numpy()
+        qtot = torch.tensor(np.stack([q64n[:, labels == a].sum(axis=1) for a in range(2)], axis=1),
+                            device=dev)
+        qgcd = torch.empty_like(b)
+        dmu = torch.empty_like(qtot)
+        gcd_fn = lambda bb, qq: S.gcd_solve(bb, qtot, tol=args.tol, precision=prec,
+                                            preconditioner=pcmode, check_every=args.check_every,
+                                            inner_tol=args.inner_tol, q_out=qgcd, dmu_out=dmu)
+        run_steps(1, gcd_fn)
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        ngcd = max(3, args.steps)
+        _, _, gst = run_steps(ngcd, gcd_fn)
+        torch.cuda.synchronize()
+        gcd_s = (time.perf_counter() - tm) / ngcd
+        qgn = qgcd.cpu().numpy()
+        gcd = {"solves_per_s": nf / gcd_s, "ms_per_step": gcd_s * 1e3, "build_s": gcd_build_s,
+               "iterations": gst["iterations"], "max_abs_total_err": gst["max_abs_sum_q"],
+               "capacitance_matrix_e_per_V": (cmat / K_E).tolist(),
+               "joint_capacitance_e_per_V": cjoint / K_E,
+               "charge_rel_err_vs_fp64_gpu": float(np.max(np.linalg.norm(qgn - q64n, axis=1)
+                                                          / np.linalg.norm(q64n, axis=1)))}
+        log("gcd", gcd)
+
+    # boundary correction of Eq. 39 (slab geometry): its own E, the bench's
+    # precision and PCG-DC, zero start
+    slab = None
+    if geo.n <= 10000 and "f32" in store:
+        t0 = time.perf_counter()
+        S2 = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT,
+                        wl.KSPACE_EPS, store=("f32",), slab=True)
+        if pcmode == cpm.PRECOND_DC:
+            S2.precond_dc(args.dc_g, args.dc_rcut)
+        torch.cuda.synchronize()
+        slab_build_s = time.perf_counter() - t0
+        b2 = torch.empty_like(b)
+        qs2 = torch.empty_like(qsol)
+        q2 = torch.empty_like(b)
+
+        def slab_step():
+            S2.rhs(t_ipos, t_iq, t_chi, b_out=b2, qsol_out=qs2)
+            return S2.solve(b2, qs2, tol=args.tol, precision=cpm.PREC_F32, warm_start=cpm.WARM_ZERO,
+                            inner_tol=args.inner_tol, check_every=args.check_every, q_out=q2,
+                            preconditioner=pcmode)
+
+        slab_step()
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        nsl = max(3, args.steps)
+        for _ in range(nsl):
+            _, sst = slab_step()
+        torch.cuda.synchronize()
+        slab_s = (time.perf_counter() - tm) / nsl
+        slab = {"solves_per_s": nf / slab_s, "ms_per_step": slab_s * 1e3, "build_s": slab_build_s,
+                "precision": "f32+f64", "warm_start": "zero", "iterations": sst["iterations"],
+                "max_rel_resid": sst["max_rel_resid"], "max_abs_sum_q": sst["max_abs_sum_q"]}
+        log("slab", slab)
+        S2.close()
+        del S2
+
     for _ in range(args.warmup):
         step(prec, wmode, q)
     torch.cuda.synchronize()
@@ -473,6 +546,7 @@ def main():
         "e_assembly_gflops": asm_gflops, "e_assembly_ms": prof_build["ms"],
         "e_assembly_frac_fp64_peak": (asm_gflops / 1e3 / FP64_PEAK_TFLOPS) if asm_gflops else None,
         "e_build_s": build_s, "precond_build_s": precond_build_s, "matrix_inversion": mi,
+        "gcd": gcd, "slab_correction": slab,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
