@@ -131,7 +131,7 @@ template <typename T> cpm_status dev_alloc(cpm_system *s, T **p, size_t count) {
 void free_system(cpm_system *s) {
   if (!s) return;
   void *ptrs[] = {s->pos, s->width, s->kn, s->kw, s->kinfo, s->krun, s->atom_order, s->E64, s->E32, s->E16, s->dinv, s->dprime,
-                  s->dvec, s->qchi, s->rhs_S, s->S, s->mlp.nbr, s->mlp.nbr_r, s->mlp.layer, s->mlp.params,
+                  s->dvec, s->qchi, s->erfc_tab, s->rhs_S, s->S, s->mlp.nbr, s->mlp.nbr_r, s->mlp.layer, s->mlp.params,
                   s->mlp.adam_m, s->mlp.adam_v, s->mlp.grad, s->mlp.gpart, s->mlp.loss,
                   s->mlp.feat, s->mlp.yout};
   for (void *p : ptrs)
@@ -307,7 +307,7 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
       (rc = dev_alloc(s, &s->atom_order, n)) ||
       (rc = dev_alloc(s, &s->E64, (size_t)ld * ld)) || (rc = dev_alloc(s, &s->dinv, ld)) ||
       (rc = dev_alloc(s, &s->dprime, ld)) || (rc = dev_alloc(s, &s->dvec, ld)) ||
-      (rc = dev_alloc(s, &s->qchi, ld)))
+      (rc = dev_alloc(s, &s->qchi, ld)) || (rc = dev_alloc(s, &s->erfc_tab, kErfcTab)))
     return fail(rc);
   if ((params->store_mask & CPM_STORE_F32) && (rc = dev_alloc(s, &s->E32, (size_t)ld * ld)))
     return fail(rc);
@@ -323,6 +323,10 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
     }                                                                      \
   } while (0)
 
+  std::vector<double> etab(kErfcTab);
+  erfc_table(etab.data());
+  BUILD_CHECK(hipMemcpyAsync(s->erfc_tab, etab.data(), sizeof(double) * kErfcTab,
+                             hipMemcpyHostToDevice, st));
   BUILD_CHECK(hipMemcpyAsync(s->pos, pos.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
   BUILD_CHECK(hipMemcpyAsync(s->width, width.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
   if (nk > 0) {

@@ -164,6 +164,7 @@ struct cpm_system {
   double c_ele = 0;
   bool dprime_ready = false;
   double *qchi = nullptr;     // ld: neutral charges without electrolyte (warm start)
+  double *erfc_tab = nullptr; // piecewise polynomial of erfc (cpm::kErfcTab doubles)
   double *S = nullptr;        // ld*ld: S = E^-1 (I - 1 d^T) of the MI path (Eq. 33), or null
   bool qchi_ready = false;
   double *rhs_S = nullptr;    // structure-factor scratch
@@ -192,6 +193,12 @@ hipError_t launch_finalize(hipStream_t st, const double *pos, const double *widt
                            double *E64, float *E32, uint16_t *E16);
 
 // ---- rhs.hip
+// erfc on [0, 6.5): kErfcIntervals intervals of width 1/8, kErfcTerms
+// Taylor coefficients each (about the midpoint, in units of the width)
+constexpr int kErfcIntervals = 52;
+constexpr int kErfcTerms = 12;
+constexpr int kErfcTab = kErfcIntervals * kErfcTerms;
+void erfc_table(double *out);
 int64_t rhs_scratch_elems(const cpm_system *s, int64_t m, int64_t f);
 hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos,
                       const double *ion_q, int64_t m, int64_t f, const double *chi,
