@@ -1166,7 +1166,7 @@ __global__ void ctl_init_kernel(double *__restrict__ scal, int cols, int fc, int
     scal[S_HOLD0 * cols + c] = 0.0;
     scal[S_HOLD1 * cols + c] = 0.0;
     scal[S_RST * cols + c] = 0.0;
-    scal[S_RPREV * cols + c] = rn;
+    scal[S_RPREV * cols + c] = INFINITY;   // no stall test in the first batch
   }
   const bool any = __any(act), anyfb = __any(fb_any);
   if (threadIdx.x == 0) {
@@ -1194,7 +1194,9 @@ __global__ __launch_bounds__(RED_THREADS) void fallback_kernel(
 // After a batch of `todo` iterations (it_after in total): decide whether the
 // true residual is due — the recursive residual met half the tolerance, fell
 // by the reliable-update factor ru below the last true residual (ru = 0:
-// never), did not fall at all over the batch (a stalled recursion), or the
+// never), did not fall at all over the batch (a stalled recursion; not
+// tested in the first batch after a start or a true residual, where the
+// residual of a restarted recursion may rise for a few steps), or the
 // iteration limit is reached.
 __global__ void ctl_check_kernel(double *__restrict__ scal, int cols, int it_after, int todo,
                                  int max_iter, double tol, double ru, int *__restrict__ flags) {
@@ -1252,7 +1254,7 @@ __global__ void ctl_update_kernel(const double *__restrict__ partial, int nblk,
       scal[S_RES * cols + c] = rn / bn;
       if (act) {
         scal[S_RT * cols + c] = rn;
-        scal[S_RPREV * cols + c] = rn;
+        scal[S_RPREV * cols + c] = INFINITY;   // nor in the first batch after an update
         if (rn <= tol * bn) {
           act = false;
           scal[S_ACT * cols + c] = 0.0;
