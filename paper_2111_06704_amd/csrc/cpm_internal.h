@@ -36,7 +36,7 @@ struct Kset {
   std::vector<int32_t> info;
 };
 
-constexpr int kRun = 16;       // longest run of consecutive n_z (phase recurrence length)
+constexpr int kRun = 24;       // longest run of consecutive n_z (phase recurrence length)
 
 // Half-space reciprocal vectors with |K| <= kmax, K != 0 (host).
 Kset make_kset(const double box[3], double beta, double kmax);
