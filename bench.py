@@ -68,9 +68,10 @@ def parse():
     ap.add_argument("--warm", default="auto", choices=["auto", "zero", "chi", "mlp"])
     ap.add_argument("--precond", default="dc", choices=["jacobi", "dc"],
                     help="preconditioner of the timed solves (the FP64 reference is plain CG)")
-    ap.add_argument("--dc-g", type=float, default=0.12,
-                    help="PCG-DC screening g (1/A); 0.12 from a sweep on workload 2 (0.083 in the paper)")
-    ap.add_argument("--dc-rcut", type=float, default=8.0, help="PCG-DC cutoff (A)")
+    ap.add_argument("--dc-g", type=float, default=0.15,
+                    help="PCG-DC screening g (1/A); 0.15 with r_cut 7 from a sweep on workload 2 "
+                         "(the paper: 0.083 with 8)")
+    ap.add_argument("--dc-rcut", type=float, default=7.0, help="PCG-DC cutoff (A)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2111_06704_amd", "weights",
                                                       "warmstart_cfg2.npz"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
