@@ -331,19 +331,21 @@ def main():
                       ("f32_zero_dc", cpm.PREC_F32, cpm.WARM_ZERO, pcmode),
                       (f"f32_{warm}_dc", cpm.PREC_F32, wmode, pcmode),
                       (f"bf16_{warm}_dc", cpm.PREC_BF16, wmode, pcmode)]
-    # FP64 CG with one right-hand side per solve (the frames one after another)
+    # FP64 CG with one right-hand side per solve (up to 16 of the frames, one
+    # after another)
     S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
     q1 = torch.empty_like(b)
     S.solve(b[:1], qsol[:1], tol=args.tol, precision=cpm.PREC_F64, q_out=q1[:1])
     torch.cuda.synchronize()
     tm = time.perf_counter()
     its = []
-    for f in range(nf):
+    nsingle = min(nf, 16)
+    for f in range(nsingle):
         _, s1 = S.solve(b[f:f + 1], qsol[f:f + 1], tol=args.tol, precision=cpm.PREC_F64,
                         check_every=args.check_every, q_out=q1[f:f + 1])
         its.append(s1["iterations"])
     torch.cuda.synchronize()
-    modes["f64_zero_single_rhs"] = {"solves_per_s": nf / (time.perf_counter() - tm),
+    modes["f64_zero_single_rhs"] = {"solves_per_s": nsingle / (time.perf_counter() - tm),
                                     "iterations": max(its), "true_residual_updates": None,
                                     "initial_rel_resid": 1.0}
     log("f64_zero_single_rhs", modes["f64_zero_single_rhs"])
