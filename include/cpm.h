@@ -157,7 +157,8 @@ typedef struct {
   double max_rel_resid;/* max over frames of |b - E q_b| / |b| at exit             */
   double initial_rel_resid; /* max over frames of the relative residual at start   */
   double max_abs_sum_q;/* max over frames of |sum(q) + Q_sol| after projection     */
-  double warm_ms;      /* time of the warm start (network + shift)                 */
+  double warm_ms;      /* GPU time of the warm start (network, shifts and the FP64
+                          residual of the start), from HIP events               */
   double solve_ms;     /* wall time of the whole call                              */
   int fell_back;       /* 1 if the warm start was rejected (|r0| >= |b|)           */
   /* optional per-frame outputs (host arrays of length f, may be NULL) */

@@ -1729,7 +1729,7 @@ cpm_status breakdown_error(int it_done, const int *fl) {
 template <typename T>
 cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o,
                       cpm_solve_info *info, std::vector<int> &frame_iters,
-                      std::vector<double> &frame_res, bool x_zero) {
+                      std::vector<double> &frame_res, bool x_zero, bool r_given) {
   const int64_t cols = round_up(fc, kColGroup);
   Solver<T> sv(s, E, cols, o.preconditioner == CPM_PRECOND_DC ? &s->pc : nullptr);
   hipStream_t st = s->stream;
@@ -1752,9 +1752,11 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
                      (int)cols, sv.partial);
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.partial, sv.nblk,
                      (int)cols, sv.scal, (int)S_BN2, nullptr);
-  if (x_zero) {
-    CPM_HIP_CHECK(hipMemcpyAsync(sv.r, sv.b, sizeof(double) * sv.ld * cols,
-                                 hipMemcpyDeviceToDevice, st));
+  if (x_zero || r_given) {
+    // r = b (zero start) or the start's FP64 residual packed by the caller
+    if (x_zero)
+      CPM_HIP_CHECK(hipMemcpyAsync(sv.r, sv.b, sizeof(double) * sv.ld * cols,
+                                   hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(sumsq_kernel, sv.grid(), dim3(RED_THREADS), 0, st, sv.r, sv.ld, sv.n,
                        (int)cols, sv.partial);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.partial, sv.nblk,
@@ -1855,14 +1857,15 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
 
 cpm_status solve_columns(cpm_system *s, int fc, const cpm_solve_opts &o, cpm_solve_info *info,
                          std::vector<int> &frame_iters, std::vector<double> &frame_res,
-                         bool x_zero) {
+                         bool x_zero, bool r_given = false) {
   switch (o.precision) {
     case CPM_PREC_F64:
-      return run_solver<double>(s, s->E64, fc, o, info, frame_iters, frame_res, x_zero);
+      return run_solver<double>(s, s->E64, fc, o, info, frame_iters, frame_res, x_zero, r_given);
     case CPM_PREC_F32:
-      return run_solver<float>(s, s->E32, fc, o, info, frame_iters, frame_res, x_zero);
+      return run_solver<float>(s, s->E32, fc, o, info, frame_iters, frame_res, x_zero, r_given);
     default:
-      return run_solver<uint16_t>(s, s->E16, fc, o, info, frame_iters, frame_res, x_zero);
+      return run_solver<uint16_t>(s, s->E16, fc, o, info, frame_iters, frame_res, x_zero,
+                                  r_given);
   }
 }
 
@@ -1925,7 +1928,7 @@ cpm_status solve_dprime(cpm_system *s, double tol, int max_iter) {
 
 cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
                        const cpm_solve_opts &o, double *q_out_dev, cpm_solve_info *info,
-                       const double *x0_dev, bool project) {
+                       const double *x0_dev, bool project, const double *r0_dev) {
   t_prof = &s->prof;
   t_n = s->n;
   const auto t0 = std::chrono::steady_clock::now();
@@ -1946,13 +1949,18 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
       hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)cols),
                          dim3(256), 0, st, x0_dev + f0 * n, n, (int64_t)fc, (double *)s->ws.x, ld,
                          cols);
+      if (r0_dev)
+        hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)cols),
+                           dim3(256), 0, st, r0_dev + f0 * n, n, (int64_t)fc, (double *)s->ws.r,
+                           ld, cols);
     } else {
       hipLaunchKernelGGL(zero_kernel, elem_grid(ld * cols), dim3(256), 0, st, (double *)s->ws.x,
                          ld * cols);
     }
     std::vector<int> fit(cols, 0);
     std::vector<double> fres(cols, 0.0);
-    stt = solve_columns(s, fc, o, info, fit, fres, x0_dev == nullptr);
+    stt = solve_columns(s, fc, o, info, fit, fres, x0_dev == nullptr,
+                        x0_dev != nullptr && r0_dev != nullptr);
     if (stt != CPM_OK && stt != CPM_ENOTCONV) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
     if (stt == CPM_ENOTCONV) result = CPM_ENOTCONV;
     if (project) {

@@ -176,6 +176,7 @@ struct cpm_system {
   cpm::Gcd gcd;
   std::vector<double> width_host;   // n Gaussian inverse widths (host copy)
   cpm::Profile prof;
+  hipEvent_t warm_ev[2] = {nullptr, nullptr};   // brackets of the warm start (its time)
   int64_t device_bytes = 0;
 };
 
@@ -209,9 +210,10 @@ void release_workspace(cpm_system *s);
 // q_out = E^-1 b for f frames; with project the two-step neutralisation of
 // Eq. 35 follows (qsol_dev required), without it q_out is the raw solution
 // and qsol_dev is not read
+// r0_dev (with x0_dev, may be null): b - E x0 already known (FP64)
 cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_dev, int64_t f,
                        const cpm_solve_opts &o, double *q_out_dev, cpm_solve_info *info,
-                       const double *x0_dev, bool project = true);
+                       const double *x0_dev, bool project = true, const double *r0_dev = nullptr);
 cpm_status solve_dprime(cpm_system *s, double tol, int max_iter);
 cpm_status matvec_cols(cpm_system *s, int precision, const double *p_dev, int64_t f,
                        double *v_dev);
@@ -232,8 +234,9 @@ cpm_status check_solve_opts(const cpm_system *s, const cpm_solve_opts *opts, cpm
 void free_gcd(Gcd &g);
 
 // ---- mlp.hip
+// x0 (f, n): the start; r0 (f, n) or null: its FP64 residual b - E x0
 cpm_status warm_start_impl(cpm_system *s, bool use_mlp, const double *b, const double *qsol,
-                           int64_t f, double *x0);
+                           int64_t f, double *x0, double *r0 = nullptr);
 hipError_t launch_mlp_forward(hipStream_t st, const float *params, const float *feat,
                               int64_t rows, float *y);
 

@@ -345,10 +345,14 @@ __global__ __launch_bounds__(256) void neutral_shift_kernel(const float *__restr
 }
 
 // x0 = q0 + mu0 d' with mu0 = mean(b - E q0) (Eq = E q0 given in eq)
+// x0 += mu d' with mu = mean(b - E x0) (the Lagrange shift), and when r0 is
+// given also the residual of the shifted start, r0 = (b - E x0) - mu 1
+// (E d' = 1), so that the solver needs no product of its own for it.
 __global__ __launch_bounds__(256) void lagrange_shift_kernel(const double *__restrict__ b,
                                                              const double *__restrict__ eq,
                                                              const double *__restrict__ dprime,
-                                                             int64_t n, double *__restrict__ x0) {
+                                                             int64_t n, double *__restrict__ x0,
+                                                             double *__restrict__ r0) {
   __shared__ double red[256];
   const int64_t f = blockIdx.x;
   double s = 0.0;
@@ -362,6 +366,8 @@ __global__ __launch_bounds__(256) void lagrange_shift_kernel(const double *__res
   const double mu = red[0] / (double)n;
   __syncthreads();
   for (int64_t i = threadIdx.x; i < n; i += 256) x0[f * n + i] += mu * dprime[i];
+  if (r0 != nullptr)
+    for (int64_t i = threadIdx.x; i < n; i += 256) r0[f * n + i] = (b[f * n + i] - eq[f * n + i]) - mu;
 }
 
 size_t tile_lds_bytes() { return sizeof(TileLds); }
@@ -671,7 +677,7 @@ static cpm_status features_impl(cpm_system *s, const double *b, int64_t f,
 // x0 (f, n) for the warm start; mode from the system state: network if its
 // parameters are set and requested, else q_chi.
 cpm_status warm_start_impl(cpm_system *s, bool use_mlp, const double *b, const double *qsol,
-                           int64_t f, double *x0) {
+                           int64_t f, double *x0, double *r0) {
   hipStream_t st = s->stream;
   const int64_t n = s->n;
   const float *y = nullptr;
@@ -694,14 +700,16 @@ cpm_status warm_start_impl(cpm_system *s, bool use_mlp, const double *b, const d
   }
   hipLaunchKernelGGL(neutral_shift_kernel, dim3((unsigned)f), dim3(256), 0, st, y, s->qchi, n,
                      (double)s->mlp.q_scale, qsol, x0);
-  // E q0 for the Lagrange shift: the FP32 copy of E when there is one (the
-  // shift only sets the start; the solver's first residual is FP64)
+  // E q0 for the Lagrange shift: FP64 when the start's residual r0 is wanted
+  // too (it is then the solver's first residual), else the FP32 copy of E
+  // when there is one (the shift only sets the start)
   double *eq = nullptr;
   CPM_HIP_CHECK(hipMallocAsync((void **)&eq, sizeof(double) * f * n, st));
-  cpm_status rc = matvec_cols(s, s->E32 ? CPM_PREC_F32 : CPM_PREC_F64, x0, f, eq);
+  cpm_status rc =
+      matvec_cols(s, (r0 == nullptr && s->E32) ? CPM_PREC_F32 : CPM_PREC_F64, x0, f, eq);
   if (rc == CPM_OK)
     hipLaunchKernelGGL(lagrange_shift_kernel, dim3((unsigned)f), dim3(256), 0, st, b, eq,
-                       s->dprime, n, x0);
+                       s->dprime, n, x0, r0);
   (void)hipFreeAsync(eq, st);
   (void)hipFreeAsync(mean, st);
   CPM_HIP_CHECK(hipGetLastError());
