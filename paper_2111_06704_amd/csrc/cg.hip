@@ -1494,6 +1494,8 @@ void free_workspace(Workspace &w) {
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   if (w.hstat) (void)hipHostFree(w.hstat);
+  if (w.hfin) (void)hipHostFree(w.hfin);
+  if (w.hfl) (void)hipHostFree(w.hfl);
   for (hipEvent_t e : w.ev)
     if (e) (void)hipEventDestroy(e);
   w = Workspace();
@@ -1530,10 +1532,13 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
             alloc((void **)&w.bpart,
                   sizeof(double) * 2 * (size_t)((s->n + PC_ROWS - 1) / PC_ROWS) * cols) &&
             alloc((void **)&w.flags, sizeof(int) * F_NWORDS);
-  if (ok && hipHostMalloc((void **)&w.hstat, sizeof(int) * F_NWORDS * kStatusSlots,
-                          hipHostMallocDefault) != hipSuccess) {
+  if (ok && (hipHostMalloc((void **)&w.hstat, sizeof(int) * F_NWORDS * kStatusSlots,
+                           hipHostMallocDefault) != hipSuccess ||
+             hipHostMalloc((void **)&w.hfin, sizeof(double) * (S_NFIELDS + 1) * MAX_COLS,
+                           hipHostMallocDefault) != hipSuccess ||
+             hipHostMalloc((void **)&w.hfl, sizeof(int) * F_NWORDS, hipHostMallocDefault) !=
+                 hipSuccess)) {
     (void)hipGetLastError();
-    w.hstat = nullptr;
     ok = false;
   }
   for (hipEvent_t &e : w.ev)
@@ -1721,15 +1726,19 @@ cpm_status breakdown_error(int it_done, const int *fl) {
   return CPM_ENOTSPD;
 }
 
+cpm_status finish_solver(cpm_system *s, int fc, int64_t cols, double tol, cpm_solve_info *info,
+                         std::vector<int> &frame_iters, std::vector<double> &frame_res);
+
 // CG with reliable updates on columns [0, fc) of the workspace block: b in
-// ws.bx, start in ws.x (x_zero: it is zero). On return ws.x holds q_b.
-// Every decision is taken on the device (ctl_* kernels); the host enqueues
-// batches of check_every iterations and looks at the status words of the
-// batch before the one it has just enqueued.
+// ws.bx, start in ws.x (x_zero: it is zero; r_given: its residual is already
+// in ws.r). On return ws.x holds q_b. Every decision is taken on the device
+// (ctl_* kernels); the host enqueues batches of check_every iterations and
+// looks at the status words of the batch before the one it has just
+// enqueued.
 template <typename T>
 cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o,
                       cpm_solve_info *info, std::vector<int> &frame_iters,
-                      std::vector<double> &frame_res, bool x_zero, bool r_given) {
+                      std::vector<double> &frame_res, bool x_zero, bool r_given, bool sync) {
   const int64_t cols = round_up(fc, kColGroup);
   Solver<T> sv(s, E, cols, o.preconditioner == CPM_PRECOND_DC ? &s->pc : nullptr);
   hipStream_t st = s->stream;
@@ -1820,14 +1829,24 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
     }
     pending = slot;
   }
-  // final state
-  std::vector<double> hs(S_NFIELDS * cols);
-  int fl[F_NWORDS];
-  CPM_HIP_CHECK(hipMemcpyAsync(hs.data(), sv.scal, sizeof(double) * hs.size(),
+  // final state into pinned host memory; the caller may enqueue more work
+  // (the projection) before the one synchronisation, then call finish_solver
+  CPM_HIP_CHECK(hipMemcpyAsync(w.hfin, sv.scal, sizeof(double) * S_NFIELDS * cols,
                                hipMemcpyDeviceToHost, st));
-  CPM_HIP_CHECK(hipMemcpyAsync(fl, sv.flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+  CPM_HIP_CHECK(hipMemcpyAsync(w.hfl, sv.flags, sizeof(int) * F_NWORDS, hipMemcpyDeviceToHost, st));
+  w.hit = it;
+  if (!sync) return CPM_OK;
   CPM_HIP_CHECK(hipStreamSynchronize(st));
-  if (fl[F_BREAK]) return breakdown_error(it, fl);
+  return finish_solver(s, fc, cols, tol, info, frame_iters, frame_res);
+}
+
+// The outcome of the last solve from the pinned final state (after the
+// stream has been synchronised).
+cpm_status finish_solver(cpm_system *s, int fc, int64_t cols, double tol, cpm_solve_info *info,
+                         std::vector<int> &frame_iters, std::vector<double> &frame_res) {
+  const double *hs = s->ws.hfin;
+  const int *fl = s->ws.hfl;
+  if (fl[F_BREAK]) return breakdown_error(s->ws.hit, fl);
   if (fl[F_NONFINITE]) {
     set_error("CG produced a non-finite residual");
     return CPM_ENOTSPD;
@@ -1855,17 +1874,21 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
   return CPM_OK;
 }
 
+// sync = false: the final state is only enqueued; synchronise the stream,
+// then call finish_solver
 cpm_status solve_columns(cpm_system *s, int fc, const cpm_solve_opts &o, cpm_solve_info *info,
                          std::vector<int> &frame_iters, std::vector<double> &frame_res,
-                         bool x_zero, bool r_given = false) {
+                         bool x_zero, bool r_given = false, bool sync = true) {
   switch (o.precision) {
     case CPM_PREC_F64:
-      return run_solver<double>(s, s->E64, fc, o, info, frame_iters, frame_res, x_zero, r_given);
+      return run_solver<double>(s, s->E64, fc, o, info, frame_iters, frame_res, x_zero, r_given,
+                                sync);
     case CPM_PREC_F32:
-      return run_solver<float>(s, s->E32, fc, o, info, frame_iters, frame_res, x_zero, r_given);
+      return run_solver<float>(s, s->E32, fc, o, info, frame_iters, frame_res, x_zero, r_given,
+                               sync);
     default:
       return run_solver<uint16_t>(s, s->E16, fc, o, info, frame_iters, frame_res, x_zero,
-                                  r_given);
+                                  r_given, sync);
   }
 }
 
@@ -1935,7 +1958,6 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
   const int64_t ld = s->ld, n = s->n;
   hipStream_t st = s->stream;
   cpm_status result = CPM_OK;
-  std::vector<double> sum_err(MAX_COLS);
   double *sum_err_dev = nullptr;
   CPM_HIP_CHECK(hipMallocAsync((void **)&sum_err_dev, sizeof(double) * MAX_COLS, st));
   for (int64_t f0 = 0; f0 < f; f0 += MAX_COLS) {
@@ -1959,15 +1981,17 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
     }
     std::vector<int> fit(cols, 0);
     std::vector<double> fres(cols, 0.0);
+    // the solve, its final state and the projection are enqueued before
+    // the one synchronisation of this block
     stt = solve_columns(s, fc, o, info, fit, fres, x0_dev == nullptr,
-                        x0_dev != nullptr && r0_dev != nullptr);
-    if (stt != CPM_OK && stt != CPM_ENOTCONV) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
-    if (stt == CPM_ENOTCONV) result = CPM_ENOTCONV;
+                        x0_dev != nullptr && r0_dev != nullptr, false);
+    if (stt != CPM_OK) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
+    double *sum_err = s->ws.hfin + S_NFIELDS * MAX_COLS;   // pinned
     if (project) {
       hipLaunchKernelGGL(project_kernel, dim3((unsigned)fc), dim3(RED_THREADS), 0, st,
                          (const double *)s->ws.x, ld, n, s->dvec, qsol_dev + f0,
                          q_out_dev + f0 * n, sum_err_dev);
-      CPM_HIP_CHECK(hipMemcpyAsync(sum_err.data(), sum_err_dev, sizeof(double) * fc,
+      CPM_HIP_CHECK(hipMemcpyAsync(sum_err, sum_err_dev, sizeof(double) * fc,
                                    hipMemcpyDeviceToHost, st));
     } else {
       CPM_HIP_CHECK(hipMemcpy2DAsync(q_out_dev + f0 * n, sizeof(double) * n, s->ws.x,
@@ -1975,6 +1999,9 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
                                      hipMemcpyDeviceToDevice, st));
     }
     CPM_HIP_CHECK(hipStreamSynchronize(st));
+    stt = finish_solver(s, fc, cols, o.tol, info, fit, fres);
+    if (stt != CPM_OK && stt != CPM_ENOTCONV) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
+    if (stt == CPM_ENOTCONV) result = CPM_ENOTCONV;
     if (info) {
       for (int c = 0; c < fc; ++c) {
         if (project) info->max_abs_sum_q = std::max(info->max_abs_sum_q, sum_err[c]);

@@ -58,6 +58,10 @@ struct Workspace {            // CG scratch, grown on demand
   double *bres = nullptr;     // n_pad*cols double: outer residual
   int *flags = nullptr;       // device status words
   int *hstat = nullptr;       // pinned host copies of the status words (ring of kStatusSlots)
+  double *hfin = nullptr;     // pinned host copy of the final per-column scalars, then the
+                              // projection's |sum q + Q_sol| per column
+  int *hfl = nullptr;         // pinned host copy of the final status words
+  int hit = 0;                // iterations enqueued by the last solve (for messages)
   hipEvent_t ev[2] = {nullptr, nullptr};
   size_t bytes = 0;
 };
