@@ -787,18 +787,27 @@ __global__ __launch_bounds__(RED_THREADS) void cg_refresh_kernel(
   }
 }
 
-// out[c][w] = sum over b of part[b][c][w] (w < width) in a fixed order: one
+// Index of entry (block b, column c) of a partial array of nb blocks and
+// width values per entry: row-major part[b][c][width] (cmajor = 0) or
+// column-major part[c][b][width] (the PCG-DC dots). With nb = 1 both agree.
+__device__ inline int64_t part_at(int64_t b, int64_t c, int nb, int cols, int width, int cmajor) {
+  return cmajor ? (c * nb + b) * width : (b * cols + c) * width;
+}
+
+// out[c][w] = sum over b of part(b, c)[w] (w < width) in a fixed order: one
 // workgroup per column. Serves the update and direction kernels when
 // re-reducing all partials in each of their workgroups would cost more
 // than this extra launch (large systems).
 __global__ __launch_bounds__(RED_THREADS) void sum_cols_kernel(const double *__restrict__ part,
                                                                int nb, int cols, int width,
+                                                               int cmajor,
                                                                double *__restrict__ out) {
   __shared__ double red[3][4];
   const int c = blockIdx.x;
+  const int64_t bstride = cmajor ? width : (int64_t)cols * width;
   for (int w = 0; w < width; ++w) {
-    const double v = strided_sum(part, nb, threadIdx.x, RED_THREADS, (int64_t)cols * width,
-                                 (int64_t)c * width + w);
+    const double v = strided_sum(part, nb, threadIdx.x, RED_THREADS, bstride,
+                                 part_at(0, c, nb, cols, width, cmajor) + w);
     const double t = block_sum(v, red[w % 3]);
     if (threadIdx.x == 0) out[c * width + w] = t;
   }
@@ -807,8 +816,8 @@ __global__ __launch_bounds__(RED_THREADS) void sum_cols_kernel(const double *__r
 // Reduce (rr, rz) partials into the scalars of active columns.
 // one workgroup per column
 __global__ __launch_bounds__(RED_THREADS) void set_scalars_kernel(
-    const double *__restrict__ partial, int nblk, int cols, double *__restrict__ scal, int slot,
-    const int *__restrict__ gate) {
+    const double *__restrict__ partial, int nblk, int cols, int cmajor, double *__restrict__ scal,
+    int slot, const int *__restrict__ gate) {
   __shared__ double red[3][4];
   if (gate != nullptr && *gate == 0) return;
   const int c = blockIdx.x;
@@ -816,8 +825,9 @@ __global__ __launch_bounds__(RED_THREADS) void set_scalars_kernel(
   if (threadIdx.x == 0) scal[S_RST * cols + c] = 0.0;   // the refresh has applied it
   double rr = 0.0, rz = 0.0;
   for (int b = threadIdx.x; b < nblk; b += RED_THREADS) {
-    rr += partial[((int64_t)b * cols + c) * 2];
-    rz += partial[((int64_t)b * cols + c) * 2 + 1];
+    const int64_t o = part_at(b, c, nblk, cols, 2, cmajor);
+    rr += partial[o];
+    rz += partial[o + 1];
   }
   rr = block_sum(rr, red[0]);
   rz = block_sum(rz, red[1]);
@@ -970,20 +980,23 @@ __global__ __launch_bounds__(RED_THREADS) void rows_kernel(const double *__restr
   }
 }
 
-// PCG-DC apply (Sec. III.B.2): z = P r with P in row-major ELL form (entry k
-// of row i at i * width + k) and r in the row-interleaved layout of
-// rows_kernel. One wavefront per row (rows taken in the spatial order) and
-// column group (grid.y); lane = 8 e + h takes entries k = e, e + 8, ... and
-// the column pair (2h, 2h + 1), so every gather of the wavefront reads eight
-// whole 128-byte lines. The workgroup's rows of P are staged in LDS by
-// coalesced loads (PC_CHUNK entries per row at a time), so the vector memory
-// path serves only the gathers. The eight entry lanes of each pair are
-// summed by shuffles in a fixed order. Active columns only (scal == nullptr:
-// all); set_p: p = z. bpart (may be null): per workgroup and column (r.r,
-// r.z), summed by the kernels that need the totals.
+// PCG-DC apply (Sec. III.B.2): z = P r with P in row-major ELL form whose
+// row t is the row of atom order[t] (entry k at t * width + k), r in the
+// row-interleaved layout of rows_kernel. One wavefront per row (rows taken
+// in the spatial order) and column group (grid.y); lane = 8 e + h takes
+// entries k = e, e + 8, ... and the column pair (2h, 2h + 1), so every
+// gather of the wavefront reads eight whole 128-byte lines. Each wavefront
+// stages its row of P in LDS with all its loads in flight at once (the ELL
+// row does not depend on order[t], so that load overlaps them), and the
+// vector memory path then serves only the gathers. The eight entry lanes of
+// each pair are summed by shuffles in a fixed order. Active columns only
+// (scal == nullptr: all); set_p: p = z. bpart (may be null): per workgroup
+// and column (r.r, r.z), column-major (bpart[(c * gridDim.x + block) * 2 +
+// {0, 1}]) so that the kernels summing one column read it contiguously.
 constexpr int PC_ROWS = 4;                  // rows (waves) per workgroup
 constexpr int PC_THREADS = 64 * PC_ROWS;
 constexpr int PC_CHUNK = 256;               // entries per row staged at a time
+constexpr int PC_PER_LANE = PC_CHUNK / 64;
 
 template <typename VT>
 __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
@@ -999,31 +1012,42 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
   const int g = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int e = lane >> 3, h = lane & 7;
-  int64_t rows[PC_ROWS];
-#pragma unroll
-  for (int w = 0; w < PC_ROWS; ++w) {
-    const int64_t t = (int64_t)blockIdx.x * PC_ROWS + w;
-    rows[w] = t < n ? (int64_t)order[t] : -1;
-  }
-  const int64_t i = rows[wave];
+  const int64_t t = (int64_t)blockIdx.x * PC_ROWS + wave;
+  const bool live = t < n;
+  const int64_t i = live ? (int64_t)order[t] : -1;
+  const int32_t *ix = pidx + (live ? t : 0) * width;
+  const double *vx = pval + (live ? t : 0) * width;
   const double *rg = rt + (int64_t)g * ld * kColGroup;
-  // the row's own residual and the columns' active flags, loaded early
   const int c0 = g * kColGroup + 2 * h;
-  double2 ri = make_double2(0.0, 0.0);
-  if (i >= 0) ri = *reinterpret_cast<const double2 *>(rg + i * kColGroup + 2 * h);
   const bool act0 = scal == nullptr || (scal[S_ACT * cols + c0] != 0.0 &&
                                          scal[(S_HOLD0 + slot) * cols + c0] == 0.0);
   const bool act1 = scal == nullptr || (scal[S_ACT * cols + c0 + 1] != 0.0 &&
                                          scal[(S_HOLD0 + slot) * cols + c0 + 1] == 0.0);
+  double2 ri = make_double2(0.0, 0.0);
   double a0 = 0.0, a1 = 0.0;
   for (int k0 = 0; k0 < width; k0 += PC_CHUNK) {
     const int cw = min(PC_CHUNK, width - k0);
+    int32_t li[PC_PER_LANE];
+    double lv[PC_PER_LANE];
+#pragma unroll
+    for (int u = 0; u < PC_PER_LANE; ++u) {
+      const int k = lane + 64 * u;
+      li[u] = 0;
+      lv[u] = 0.0;
+      if (live && k < cw) {
+        li[u] = ix[k0 + k];
+        lv[u] = vx[k0 + k];
+      }
+    }
+    if (k0 == 0 && i >= 0) ri = *reinterpret_cast<const double2 *>(rg + i * kColGroup + 2 * h);
     if (k0 > 0) __syncthreads();
-    for (int q = threadIdx.x; q < PC_ROWS * cw; q += PC_THREADS) {
-      const int w = q / cw, k = q % cw;
-      const int64_t r = rows[w];
-      sidx[w][k] = r >= 0 ? pidx[r * width + k0 + k] : 0;
-      sval[w][k] = r >= 0 ? pval[r * width + k0 + k] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PC_PER_LANE; ++u) {
+      const int k = lane + 64 * u;
+      if (k < cw) {
+        sidx[wave][k] = li[u];
+        sval[wave][k] = lv[u];
+      }
     }
     __syncthreads();
     if (i >= 0) {
@@ -1073,7 +1097,7 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
     double v = 0.0;
 #pragma unroll
     for (int w = 0; w < PC_ROWS; ++w) v += red[w][c][s2];
-    bpart[((int64_t)blockIdx.x * cols + g * kColGroup + c) * 2 + s2] = v;
+    bpart[((int64_t)(g * kColGroup + c) * gridDim.x + blockIdx.x) * 2 + s2] = v;
   }
 }
 
@@ -1091,7 +1115,7 @@ constexpr double kHold = 1e-3;
 template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
     VT *__restrict__ p, const double *__restrict__ z, int64_t ld, int64_t n, int cols, int nblk,
-    const double *__restrict__ partial, double *__restrict__ scal, int slot, double tol,
+    const double *__restrict__ partial, int cmajor, double *__restrict__ scal, int slot, double tol,
     double ru) {
   __shared__ double red[3][4];
   const int c = blockIdx.y;
@@ -1103,8 +1127,9 @@ __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
   }
   double rr = 0.0, rzn = 0.0;
   for (int b = threadIdx.x; b < nblk; b += RED_THREADS) {
-    rr += partial[((int64_t)b * cols + c) * 2];
-    rzn += partial[((int64_t)b * cols + c) * 2 + 1];
+    const int64_t o = part_at(b, c, nblk, cols, 2, cmajor);
+    rr += partial[o];
+    rzn += partial[o + 1];
   }
   rr = block_sum(rr, red[0]);
   rzn = block_sum(rzn, red[1]);
@@ -1653,6 +1678,7 @@ template <typename T> struct Solver {
   int npc() const { return (int)((n + PC_ROWS - 1) / PC_ROWS); }
   int nred() const { return pc ? npc() : nblk; }
   const double *dots() const { return pc ? s->ws.bpart : partial; }
+  int dots_cmajor() const { return pc ? 1 : 0; }
 
   // z = P r with the DC preconditioner; to_rows: r was written by another
   // kernel than the update, so its row-interleaved copy is made first
@@ -1672,7 +1698,7 @@ template <typename T> struct Solver {
       hipLaunchKernelGGL(cg_refresh_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, r, z, p, s->dinv,
                          ld, n, (int)cols, scal, partial, set_p ? 1 : 0, gate);
     hipLaunchKernelGGL(set_scalars_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, dots(),
-                       nred(), (int)cols, scal, slot, gate);
+                       nred(), (int)cols, dots_cmajor(), scal, slot, gate);
     return hipGetLastError();
   }
 
@@ -1688,7 +1714,7 @@ template <typename T> struct Solver {
     const int64_t upd_loads = pc ? (int64_t)npv * ld * cols / kColGroup : (int64_t)npv * nblk * cols;
     if (upd_loads > kRedLoads) {
       hipLaunchKernelGGL(sum_cols_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, pvp, npv,
-                         (int)cols, 1, s->ws.red);
+                         (int)cols, 1, 0, s->ws.red);
       pvs = s->ws.red;
       npvs = 1;
     }
@@ -1706,12 +1732,12 @@ template <typename T> struct Solver {
     int nds = nred();
     if (2 * (int64_t)nds * nblk * cols > kRedLoads) {
       hipLaunchKernelGGL(sum_cols_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, ds, nds,
-                         (int)cols, 2, s->ws.red + MAX_COLS);
+                         (int)cols, 2, dots_cmajor(), s->ws.red + MAX_COLS);
       ds = s->ws.red + MAX_COLS;
       nds = 1;
     }
     hipLaunchKernelGGL(cg_direction_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, p, z, ld, n,
-                       (int)cols, nds, ds, scal, slot, tol, ru);
+                       (int)cols, nds, ds, dots_cmajor(), scal, slot, tol, ru);
     slot ^= 1;
     return hipGetLastError();
   }

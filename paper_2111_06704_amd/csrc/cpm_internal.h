@@ -73,7 +73,7 @@ struct Precond {              // PCG-DC preconditioner (P + P^T) / 2 in ELL form
   int width = 0;              // entries per row (padded with (i, 0))
   int max_local = 0;          // largest local matrix
   int64_t nnz = 0;
-  int32_t *idx = nullptr;     // n * width: column of entry k of row i at i * width + k
+  int32_t *idx = nullptr;     // n * width: column of entry k of the row of atom atom_order[t] at t * width + k
   double *val = nullptr;      // width * n
   int64_t bytes = 0;           // device memory held
 };

@@ -241,17 +241,24 @@ cpm_status cpm_precond_dc(cpm_system *s, double g, double rcut) {
   };
   int width = 1;
   for (const auto &v : col) width = std::max(width, (int)v.size());
+  // ELL row t holds the row of atom order[t], the order in which the apply
+  // kernel takes the rows
+  std::vector<int32_t> order(n);
+  CPM_HIP_CHECK(hipMemcpyAsync(order.data(), s->atom_order, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                               s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   std::vector<int32_t> idx((size_t)width * n);
   std::vector<double> val((size_t)width * n, 0.0);
   int64_t nnz = 0;
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t i = order[t];
     const auto &v = col[i];   // the neighbour relation is symmetric: row i has the atoms of column i
     for (int k = 0; k < width; ++k) {
       if (k < (int)v.size()) {
-        idx[(size_t)i * width + k] = v[k].first;
-        val[(size_t)i * width + k] = 0.5 * (v[k].second + entry(v[k].first, (int32_t)i));
+        idx[(size_t)t * width + k] = v[k].first;
+        val[(size_t)t * width + k] = 0.5 * (v[k].second + entry(v[k].first, (int32_t)i));
       } else {
-        idx[(size_t)i * width + k] = (int32_t)i;
+        idx[(size_t)t * width + k] = (int32_t)i;
       }
     }
     nnz += (int64_t)v.size();

@@ -121,29 +121,44 @@ __global__ __launch_bounds__(RB) void structure_factor_kernel(
     }
     __syncthreads();
     const int cnt = (int)((i1 - base) < RB ? (i1 - base) : RB);
-    for (int j = 0; j < cnt; ++j) {
-      double t = nx * su[j][0] + ny * su[j][1] + nz * su[j][2];
-      t -= rint(t);
-      double sn, cs;
-      sincospi(2.0 * t, &sn, &cs);
-      const double q = su[j][3], zc = su[j][4], zs = su[j][5];
+    // two ions per pass: their phase evaluations and recurrences are
+    // independent, so each thread keeps four FMA chains in flight; a missing
+    // second ion (odd count) enters with q = 0
+    for (int j = 0; j < cnt; j += 2) {
+      const int j2 = (j + 1 < cnt) ? j + 1 : j;
+      const double qb = (j + 1 < cnt) ? su[j2][3] : 0.0;
+      double ta = nx * su[j][0] + ny * su[j][1] + nz * su[j][2];
+      double tb = nx * su[j2][0] + ny * su[j2][1] + nz * su[j2][2];
+      ta -= rint(ta);
+      tb -= rint(tb);
+      double sna, csa, snb, csb;
+      sincospi(2.0 * ta, &sna, &csa);
+      sincospi(2.0 * tb, &snb, &csb);
+      const double qa = su[j][3];
+      const double zca = su[j][4], zsa = su[j][5], zcb = su[j2][4], zsb = su[j2][5];
       // q exp(i (phi + s theta)) for s = 0, 1, ... by the three-term
       // recurrence x_{s+1} = 2 cos(theta) x_s - x_{s-1} (one FMA per part;
       // a rounding error made at step m enters step s with the factor
       // sin((s - m) theta) / sin(theta), at most s - m)
-      double c0 = q * cs, s0 = q * sn;
-      double c1 = c0 * zc - s0 * zs, s1 = s0 * zc + c0 * zs;
-      const double tz = 2.0 * zc;
+      double c0 = qa * csa, s0 = qa * sna;
+      double c1 = c0 * zca - s0 * zsa, s1 = s0 * zca + c0 * zsa;
+      double d0 = qb * csb, e0 = qb * snb;
+      double d1 = d0 * zcb - e0 * zsb, e1 = e0 * zcb + d0 * zsb;
+      const double tza = 2.0 * zca, tzb = 2.0 * zcb;
 #pragma unroll
       for (int st = 0; st < kRun; st += 2) {
-        ar[st] += c0;
-        ai[st] += s0;
-        ar[st + 1] += c1;
-        ai[st + 1] += s1;
-        c0 = fma(tz, c1, -c0);
-        s0 = fma(tz, s1, -s0);
-        c1 = fma(tz, c0, -c1);
-        s1 = fma(tz, s0, -s1);
+        ar[st] += c0 + d0;
+        ai[st] += s0 + e0;
+        ar[st + 1] += c1 + d1;
+        ai[st + 1] += s1 + e1;
+        c0 = fma(tza, c1, -c0);
+        s0 = fma(tza, s1, -s0);
+        d0 = fma(tzb, d1, -d0);
+        e0 = fma(tzb, e1, -e0);
+        c1 = fma(tza, c0, -c1);
+        s1 = fma(tza, s0, -s1);
+        d1 = fma(tzb, d0, -d1);
+        e1 = fma(tzb, e0, -e1);
       }
     }
     __syncthreads();
