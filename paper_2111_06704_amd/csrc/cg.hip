@@ -79,7 +79,8 @@ enum {
 // true-residual updates, a start was discarded, largest recursive residual
 enum {
   F_BREAK = 0, F_COL = 1, F_NEED = 6, F_ANY = 7, F_NONFINITE = 8, F_UPDATES = 9, F_FELLBACK = 10,
-  F_RMAX = 12,   // (double, words 12-13) largest relative recursive residual at the last check
+  F_RMAX = 12,   // (double, words 12-13) largest relative residual of the active columns at the
+                 // last check: the true one when the check took it, else the recursive one
   F_NWORDS = 16
 };
 
@@ -1263,6 +1264,7 @@ __global__ void ctl_update_kernel(const double *__restrict__ partial, int nblk,
   if (flags[F_NEED] == 0) return;
   const int c = threadIdx.x;
   bool act = false;
+  double rel = 0.0;
   if (c < cols) {
     double rr = 0.0;
     for (int b = 0; b < nblk; ++b) rr += partial[((int64_t)b * cols + c) * 2];
@@ -1286,13 +1288,20 @@ __global__ void ctl_update_kernel(const double *__restrict__ partial, int nblk,
         } else if (rn > kTrack * rec || rn > last) {
           scal[S_RST * cols + c] = 1.0;
         }
+        if (act) rel = rn / bn;
       }
     }
   }
   const bool any = __any(act);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) rel = fmax(rel, __shfl_xor(rel, off, 64));
   if (threadIdx.x == 0) {
     flags[F_ANY] = any ? 1 : 0;
     flags[F_UPDATES] += 1;
+    // the host's convergence forecast then extrapolates from the true
+    // residual of the columns still active, not from the recursive one it
+    // replaced (which in FP32 / BF16 runs ahead of it)
+    *reinterpret_cast<double *>(flags + F_RMAX) = rel;
   }
 }
 
