@@ -459,18 +459,32 @@ cpm_status build_neighbours(const cpm_system *s, std::vector<int32_t> &nbr,
 }  // namespace
 
 // Inference of many rows: each workgroup copies the parameters into LDS
-// once and then runs tiles of IR rows (grid-stride over tiles). Thread t
-// owns rows 4 (t / 16) .. + 3 and units 4 (t % 16) .. + 3 of each layer;
-// SiLU is applied once per hidden value; the output layer is reduced over
-// the 16 threads of a row group by shuffles in a fixed order. FROM_B: the
-// inputs are formed from b in the kernel (same definition as
-// features_kernel), otherwise read from feat.
-constexpr int IR = 64;   // rows per inference tile
+// once and then runs tiles of IR rows (grid-stride over tiles). The two
+// hidden layers are dense products and run on the matrix cores
+// (v_mfma_f32_16x16x4f32, FP32 in and out): wavefront w takes rows
+// 16 w .. 16 w + 15 of the tile and all NH units as NH / 16 output tiles;
+// lane (lr, lg) supplies A = X[row lr][k + lg] and B = W[k + lg][unit lr]
+// and receives D[row 4 lg + v][unit lr], v = 0..3. The input width is padded
+// with zero columns to a multiple of 4. SiLU is applied once per hidden
+// value; the output layer is reduced over the 16 lanes of a row group by
+// shuffles in a fixed order. FROM_B: the inputs are formed from b in the
+// kernel (same definition as features_kernel), otherwise read from feat.
+constexpr int IR = 64;                       // rows per inference tile (16 per wavefront)
+constexpr int NINP = (NIN + 3) / 4 * 4;      // input width padded for the k-steps of 4
+constexpr int NHT = NH / 16;                 // output tiles per layer
+static_assert(NH % 16 == 0 && TT == 4 * 64 && IR == 16 * (TT / 64) && TT == 4 * IR &&
+                  NNB % 4 == 0 && NIN == 2 + 2 * NNB, "inference tiling");
+static_assert(OW1 % 4 == 0 && OB1 % 4 == 0 && OW2 % 4 == 0 && OB2 % 4 == 0 && OW3 % 4 == 0 &&
+                  (NH * NH / 4) % TT == 0 && 3 * (NH / 4) <= TT,
+              "parameter offsets and sizes in whole float4 pieces");
+typedef float mf4 __attribute__((ext_vector_type(4)));
 struct InferLds {
-  float w1[NIN][NH];
-  float w2[NH][NH];
-  float b1[NH], b2[NH], w3[NH];
-  float x[IR][NIN + 1];
+  alignas(16) float w1[NINP][NH];
+  alignas(16) float w2[NH][NH];
+  alignas(16) float b1[NH];
+  alignas(16) float b2[NH];
+  alignas(16) float w3[NH];
+  float x[IR][NINP + 1];
   float h1[IR][NH + 1];
 };
 
@@ -482,104 +496,128 @@ __global__ __launch_bounds__(TT) void mlp_infer_kernel(
     float inv_bs, float inv_rs, int64_t rows, float *__restrict__ y) {
   __shared__ InferLds L;
   const int t = threadIdx.x;
-  for (int q = t; q < NIN * NH; q += TT) L.w1[q / NH][q % NH] = prm[OW1 + q];
-  for (int q = t; q < NH * NH; q += TT) L.w2[q / NH][q % NH] = prm[OW2 + q];
-  for (int q = t; q < NH; q += TT) {
-    L.b1[q] = prm[OB1 + q];
-    L.b2[q] = prm[OB2 + q];
-    L.w3[q] = prm[OW3 + q];
+  {
+    // parameters into LDS as float4 pieces, every load of a thread issued
+    // before its first store (the offsets are multiples of 4 floats)
+    constexpr int N1 = NIN * NH / 4, N2 = NH * NH / 4, NV = NH / 4;
+    constexpr int L1 = (N1 + TT - 1) / TT, L2 = N2 / TT;
+    const float4 *p4 = reinterpret_cast<const float4 *>(prm);
+    float4 v1[L1], v2[L2], vb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int u = 0; u < L1; ++u) {
+      const int q = t + u * TT;
+      if (q < N1) v1[u] = p4[OW1 / 4 + q];
+    }
+#pragma unroll
+    for (int u = 0; u < L2; ++u) v2[u] = p4[OW2 / 4 + t + u * TT];
+    if (t < 3 * NV) vb = p4[(t < NV ? OB1 : t < 2 * NV ? OB2 : OW3) / 4 + t % NV];
+    float4 *w1 = reinterpret_cast<float4 *>(&L.w1[0][0]);
+    float4 *w2 = reinterpret_cast<float4 *>(&L.w2[0][0]);
+#pragma unroll
+    for (int u = 0; u < L1; ++u) {
+      const int q = t + u * TT;
+      if (q < N1) w1[q] = v1[u];
+    }
+    for (int q = N1 + t; q < NINP * NH / 4; q += TT) w1[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int u = 0; u < L2; ++u) w2[t + u * TT] = v2[u];
+    if (t < 3 * NV) {
+      float *dst = t < NV ? L.b1 : t < 2 * NV ? L.b2 : L.w3;
+      reinterpret_cast<float4 *>(dst)[t % NV] = vb;
+    }
   }
   const float b3 = prm[OB3];
-  const int rg = t >> 4, ug = t & 15;
+  const int wave = t >> 6, lane = t & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int rw = 16 * wave;   // the wavefront's first row in the tile
   const int64_t tiles = (rows + IR - 1) / IR;
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t r0 = tile * IR;
     __syncthreads();   // parameters loaded / previous tile done with x and h1
     if constexpr (FROM_B) {
-      if (t < IR) {
-        const int64_t r = r0 + t;
-        if (r < rows) {
-          const int64_t f = r / n, i = r % n;
-          const double mb = mean[f];
-          const double *bf = b + f * n;
-          L.x[t][0] = (float)((bf[i] - mb) * (double)inv_bs);
-          L.x[t][1] = (float)layer[i] * inv_layers;
-#pragma unroll
-          for (int k = 0; k < NNB; ++k) {
-            L.x[t][2 + k] = (float)((bf[nbr[i * NNB + k]] - mb) * (double)inv_bs);
-            L.x[t][2 + NNB + k] = nbr_r[i * NNB + k] * inv_rs;
-          }
-        } else {
-          for (int k = 0; k < NIN; ++k) L.x[t][k] = 0.0f;
+      // four threads per row, each with a quarter of the neighbours
+      constexpr int NQ = NNB / 4;
+      const int row = t >> 2, part = t & 3;
+      const int64_t r = r0 + row;
+      if (r < rows) {
+        const int64_t f = r / n, i = r % n;
+        const double mb = mean[f];
+        const double *bf = b + f * n;
+        if (part == 0) {
+          L.x[row][0] = (float)((bf[i] - mb) * (double)inv_bs);
+          L.x[row][1] = (float)layer[i] * inv_layers;
+          for (int k = NIN; k < NINP; ++k) L.x[row][k] = 0.0f;
         }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int k = part * NQ + q;
+          L.x[row][2 + k] = (float)((bf[nbr[i * NNB + k]] - mb) * (double)inv_bs);
+          L.x[row][2 + NNB + k] = nbr_r[i * NNB + k] * inv_rs;
+        }
+      } else if (part == 0) {
+        for (int k = 0; k < NINP; ++k) L.x[row][k] = 0.0f;
       }
     } else {
-      for (int q = t; q < IR * NIN; q += TT) {
-        const int r = q / NIN, k = q % NIN;
-        L.x[r][k] = (r0 + r < rows) ? feat[(r0 + r) * NIN + k] : 0.0f;
+      for (int q = t; q < IR * NINP; q += TT) {
+        const int r = q / NINP, k = q % NINP;
+        L.x[r][k] = (r0 + r < rows && k < NIN) ? feat[(r0 + r) * NIN + k] : 0.0f;
       }
     }
     __syncthreads();
-    float acc[4][4];
+    // layer 1: a1 = X W1, h1 = silu(a1 + b1)
+    mf4 acc[NHT];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int u = 0; u < NHT; ++u) acc[u] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = L.b1[ug * 4 + c];
-    for (int k = 0; k < NIN; ++k) {
-      float xv[4], wv[4];
+    for (int k = 0; k < NINP; k += 4) {
+      const float a = L.x[rw + lr][k + lg];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) xv[a] = L.x[rg * 4 + a][k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) wv[c] = L.w1[k][ug * 4 + c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xv[a], wv[c], acc[a][c]);
+      for (int u = 0; u < NHT; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L.w1[k + lg][16 * u + lr], acc[u], 0, 0, 0);
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int u = 0; u < NHT; ++u) {
+      const float bu = L.b1[16 * u + lr];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const float z = acc[a][c];
-        L.h1[rg * 4 + a][ug * 4 + c] = z * sigm(z);
+      for (int v = 0; v < 4; ++v) {
+        const float z = acc[u][v] + bu;
+        L.h1[rw + 4 * lg + v][16 * u + lr] = z * sigm(z);
       }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = L.b2[ug * 4 + c];
-    for (int k = 0; k < NH; ++k) {
-      float hv[4], wv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) hv[a] = L.h1[rg * 4 + a][k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) wv[c] = L.w2[k][ug * 4 + c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(hv[a], wv[c], acc[a][c]);
     }
-    // y = sum_j silu(a2_j) w3_j + b3: four units here, then the 16 unit groups
+    __syncthreads();
+    // layer 2: a2 = h1 W2
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int u = 0; u < NHT; ++u) acc[u] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (int k = 0; k < NH; k += 4) {
+      const float a = L.h1[rw + lr][k + lg];
+#pragma unroll
+      for (int u = 0; u < NHT; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L.w2[k + lg][16 * u + lr], acc[u], 0, 0, 0);
+    }
+    // y = sum_j silu(a2_j + b2_j) w3_j + b3: the lane's NHT units, then the
+    // 16 lanes of the row group
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
       float sp = 0.0f;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const float z = acc[a][c];
-        sp = fmaf(z * sigm(z), L.w3[ug * 4 + c], sp);
+      for (int u = 0; u < NHT; ++u) {
+        const float z = acc[u][v] + L.b2[16 * u + lr];
+        sp = fmaf(z * sigm(z), L.w3[16 * u + lr], sp);
       }
 #pragma unroll
       for (int off = 1; off < 16; off <<= 1) sp += __shfl_xor(sp, off, 16);
-      const int64_t r = r0 + rg * 4 + a;
-      if (ug == 0 && r < rows) y[r] = sp + b3;
+      const int64_t r = r0 + rw + 4 * lg + v;
+      if (lr == 0 && r < rows) y[r] = sp + b3;
     }
   }
 }
 
-// workgroups of the inference kernel: about two per CU, at most one per tile
+// workgroups of the inference kernel: up to four per CU (three fit its
+// LDS at a time), at most one per tile
 unsigned infer_blocks(int64_t rows) {
   const int64_t tiles = (rows + IR - 1) / IR;
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, 512));
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, 1024));
 }
 
 hipError_t launch_mlp_forward(hipStream_t st, const float *params, const float *feat,
