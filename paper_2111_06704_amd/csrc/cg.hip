@@ -1350,10 +1350,14 @@ __global__ __launch_bounds__(RED_THREADS) void project_kernel(
   const double *xf = x + f * ld;
   double *qf = q + f * n;
   double s = 0.0;
+  // (unrolled so that a thread's loads are in flight together; the order of
+  // the additions is unchanged)
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) s += xf[i];
   s = block_sum(s, red[0]);
   const double shift = s + qsol[f];
   double t = 0.0;
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) {
     const double qi = xf[i] - shift * d[i];
     qf[i] = qi;
@@ -1362,6 +1366,7 @@ __global__ __launch_bounds__(RED_THREADS) void project_kernel(
   t = block_sum(t, red[1]);
   const double shift2 = t + qsol[f];
   double t2 = 0.0;
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) {   // each thread rereads its own q
     const double qi = qf[i] - shift2 * d[i];
     qf[i] = qi;

@@ -45,6 +45,7 @@ __global__ __launch_bounds__(256) void frame_mean_kernel(const double *__restric
   __shared__ double red[256];
   const int64_t f = blockIdx.x;
   double s = 0.0;
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < n; i += 256) s += b[f * n + i];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -328,6 +329,7 @@ __global__ __launch_bounds__(256) void neutral_shift_kernel(const float *__restr
   __shared__ double red[256];
   const int64_t f = blockIdx.x;
   double s = 0.0;
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < n; i += 256) {
     const double v = y ? qs * (double)y[f * n + i] : qchi[i];
     q0[f * n + i] = v;
@@ -341,6 +343,7 @@ __global__ __launch_bounds__(256) void neutral_shift_kernel(const float *__restr
   }
   const double shift = (red[0] + qsol[f]) / (double)n;
   __syncthreads();
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < n; i += 256) q0[f * n + i] -= shift;
 }
 
@@ -356,6 +359,7 @@ __global__ __launch_bounds__(256) void lagrange_shift_kernel(const double *__res
   __shared__ double red[256];
   const int64_t f = blockIdx.x;
   double s = 0.0;
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < n; i += 256) s += b[f * n + i] - eq[f * n + i];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -365,8 +369,10 @@ __global__ __launch_bounds__(256) void lagrange_shift_kernel(const double *__res
   }
   const double mu = red[0] / (double)n;
   __syncthreads();
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < n; i += 256) x0[f * n + i] += mu * dprime[i];
   if (r0 != nullptr)
+#pragma unroll 8
     for (int64_t i = threadIdx.x; i < n; i += 256) r0[f * n + i] = (b[f * n + i] - eq[f * n + i]) - mu;
 }
 

@@ -299,7 +299,9 @@ __global__ void assemble_b_kernel(const double *__restrict__ bp, int ksplits,
   const int64_t f = idx / n, i = idx % n;
   const int64_t fn = n * f_total;
   double s = 0.0;
+#pragma unroll 8
   for (int ks = 0; ks < ksplits; ++ks) s += bp[ks * fn + idx];
+#pragma unroll 8
   for (int g = 0; g < rgroups; ++g) s += rs[g * fn + idx];
   double v = chi[i] * (1.0 / kCoulombVA) - s - c0 * qsol[f];
   if (m1 != nullptr) v -= cs * m1[f] * pos[3 * i + 2];
