@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -344,30 +346,52 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
   const std::vector<int32_t> order = spatial_order(pos, n);
   BUILD_CHECK(hipMemcpyAsync(s->atom_order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
                              st));
-  BUILD_CHECK(hipMemsetAsync(s->E64, 0, sizeof(double) * ld * ld, st));
-  if (s->E32) BUILD_CHECK(hipMemsetAsync(s->E32, 0, sizeof(float) * ld * ld, st));
-  if (s->E16) BUILD_CHECK(hipMemsetAsync(s->E16, 0, sizeof(uint16_t) * ld * ld, st));
   BUILD_CHECK(hipMemsetAsync(s->qchi, 0, sizeof(double) * ld, st));
 
   // Reciprocal part A A^T in chunks of k-vectors whose phase matrix stays
-  // under ~4 GiB (or 1/8 of free memory).
+  // under 24 GiB (or a third of the free memory): every chunk but the first
+  // adds to the lower tiles of E, so larger chunks re-read E less often.
+  // finalize_kernel writes every entry of E (padding included), so E needs
+  // no clearing.
   if (nk > 0) {
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
-    size_t budget = std::min<size_t>((size_t)4 << 30, free_b / 8);
+    size_t budget = std::min<size_t>((size_t)24 << 30, free_b / 3);
     int64_t kc = (int64_t)(budget / (sizeof(double) * 2 * (size_t)ld));
     kc = std::max<int64_t>(8, kc / 8 * 8);
-    kc = std::min<int64_t>(kc, round_up(nk, 8));
+    // equal chunks (the last one is not padded with zero columns)
+    const int64_t nchunks = (nk + kc - 1) / kc;
+    kc = round_up((nk + nchunks - 1) / nchunks, 8);
     const int64_t lda = 2 * kc;
     double *A = nullptr;
-    if (hipMalloc((void **)&A, sizeof(double) * (size_t)ld * lda) != hipSuccess) {
+    int32_t *tiles = nullptr;
+    const std::vector<int32_t> order_t = syrk_tile_order(ld / 128);
+    if ((int64_t)order_t.size() != (ld / 128) * (ld / 128 + 1)) {
+      set_error("internal: tile list size");
+      return fail(CPM_EDEVICE);
+    }
+    // CPM_PROGRESS=1 in the environment: one line on stderr per finished
+    // chunk (long assemblies)
+    const char *prog_env = std::getenv("CPM_PROGRESS");
+    const bool progress = prog_env && prog_env[0] == '1';
+    const auto t_asm = std::chrono::steady_clock::now();
+    if (hipMalloc((void **)&A, sizeof(double) * (size_t)ld * lda) != hipSuccess ||
+        hipMalloc((void **)&tiles, sizeof(int32_t) * order_t.size()) != hipSuccess) {
       (void)hipGetLastError();
+      if (A) (void)hipFree(A);
       set_error("phase matrix allocation failed");
       return fail(CPM_ENOMEM);
     }
-    for (int64_t k0 = 0; k0 < nk; k0 += kc) {
+    auto release = [&]() {
+      (void)hipFree(A);
+      (void)hipFree(tiles);
+    };
+    hipError_t e = hipMemcpyAsync(tiles, order_t.data(), sizeof(int32_t) * order_t.size(),
+                                  hipMemcpyHostToDevice, st);
+    for (int64_t k0 = 0; k0 < nk && e == hipSuccess; k0 += kc) {
       const int64_t kcur = std::min(kc, nk - k0);
-      hipError_t e = launch_phase_matrix(st, s->pos, n, ld, s->box, s->kn, s->kw, k0, kcur, lda, A);
+      e = launch_phase_matrix(st, s->pos, n, ld, s->box, s->kn, s->kw, k0, kcur,
+                              round_up(2 * kcur, 16), A);
       // algorithmic flops of the contraction: 2 products (cos, sin) per
       // k-vector for each unique pair i <= j, 2 flops each
       hipEvent_t ea = nullptr, eb = nullptr;
@@ -376,15 +400,27 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
         ea = r.a;
         eb = r.b;
       }
-      if (e == hipSuccess) e = launch_syrk_lower(st, A, lda, lda, ld, s->E64, ld, k0 > 0, ea, eb);
-      if (e != hipSuccess) {
-        (void)hipFree(A);
-        set_error(std::string("E assembly launch failed: ") + hipGetErrorString(e));
-        return fail(CPM_EDEVICE);
+      if (e == hipSuccess)
+        e = launch_syrk_lower(st, A, round_up(2 * kcur, 16), tiles, ld, s->E64, ld, k0 > 0, ea,
+                              eb);
+      if (progress && e == hipSuccess) {
+        e = hipStreamSynchronize(st);
+        std::fprintf(stderr, "cpm_build_E: k-vectors %lld of %lld done (%.1f s)\n",
+                     (long long)(k0 + kcur), (long long)nk,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t_asm).count());
+        std::fflush(stderr);
       }
     }
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(st);
+      release();
+      set_error(std::string("E assembly launch failed: ") + hipGetErrorString(e));
+      return fail(CPM_EDEVICE);
+    }
     BUILD_CHECK(hipStreamSynchronize(st));
-    (void)hipFree(A);
+    release();
+  } else {
+    BUILD_CHECK(hipMemsetAsync(s->E64, 0, sizeof(double) * ld * ld, st));
   }
   BUILD_CHECK(launch_finalize(st, s->pos, s->width, n, ld, s->box, beta, s->rcut, s->slab, s->E64,
                               s->E32, s->E16));

@@ -187,12 +187,17 @@ struct cpm_system {
 namespace cpm {
 
 // ---- assembly.hip
+// A (ld rows, kdim = 2 * k-vectors-per-chunk columns, column-blocked by 16):
+// sqrt(w) cos / sin of the chunk's k-vectors k0 .. k0 + kc - 1
 hipError_t launch_phase_matrix(hipStream_t st, const double *pos, int64_t n, int64_t ld,
                                const double box[3], const int32_t *kn, const double *kw,
-                               int64_t k0, int64_t kc, int64_t lda, double *A);
-hipError_t launch_syrk_lower(hipStream_t st, const double *A, int64_t lda, int64_t kdim,
-                             int64_t ld, double *E, int64_t lde, bool accumulate,
-                             hipEvent_t ev_start, hipEvent_t ev_stop);
+                               int64_t k0, int64_t kc, int64_t kdim, double *A);
+// lower-triangular tile list of the contraction (pairs ti >= tj, in the
+// order the kernel walks them) for T = ld / 128 tile rows
+std::vector<int32_t> syrk_tile_order(int64_t T);
+hipError_t launch_syrk_lower(hipStream_t st, const double *A, int64_t kdim,
+                             const int32_t *tiles, int64_t ld, double *E, int64_t lde,
+                             bool accumulate, hipEvent_t ev_start, hipEvent_t ev_stop);
 hipError_t launch_finalize(hipStream_t st, const double *pos, const double *width, int64_t n,
                            int64_t ld, const double box[3], double beta, double rcut, bool slab,
                            double *E64, float *E32, uint16_t *E16);
