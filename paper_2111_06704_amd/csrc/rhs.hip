@@ -408,87 +408,194 @@ __global__ __launch_bounds__(RB) void real_space_ions_kernel(
   if (i >= 0) rs[(g * f_total + f) * n + i] = acc;
 }
 
-// ---- real space with the ions of each frame sorted by z
+// ---- real space over a cell list of the ions of each frame
 //
-// ion_sort_kernel (one workgroup per frame): keys (z bin << 20 | ion) are
-// sorted in LDS (bitonic; the keys are unique, so the order is fixed), the
-// ions are written in that order as (x, y, z, q), and bin_start[b] is the
-// first sorted position of bin b (b = 0..NB). z is wrapped into [0, L_z).
-constexpr int kZBins = 256;
-constexpr int kSortThreads = 1024;
-constexpr int64_t kSortMaxIons = 32768;   // keys in LDS: 128 KB
-// below this many ions per frame the sort costs more than the window saves
-// (measured: 2000 ions, 4608 atoms: 195 us unsorted vs 30 + 207 us)
-constexpr int64_t kWinMinIons = 8192;
-extern __shared__ uint32_t sort_keys[];
+// The box is cut into ncx x ncy x ncz cells (edges h_d = L_d / nc_d >=
+// rcut / 2, at most kMaxCells cells); cell (cx, cy, cz) has index
+// (cz ncy + cy) ncx + cx. Every frame's ions are put in cell order, ions of
+// one cell in index order (a stable counting sort), in three steps:
+//   cell_sort_chunk_kernel  per chunk of kChunk ions: keys (cell << 12 |
+//                           local index) sorted in LDS (bitonic; unique keys,
+//                           so the order is fixed), the chunk's count per cell
+//   cell_scan_kernel        per frame: prefix sums of the counts over the
+//                           chunks (per cell) and over the cells
+//   cell_scatter_kernel     every ion to cell start + earlier chunks' count +
+//                           its rank in its chunk, as (x, y, z, q)
+// real_space_cell_kernel then gives each wavefront of 64 spatially compact
+// atoms the cells that overlap its bounding box widened by rcut: one
+// contiguous range of the sorted ions per (cz, cy) row (two where the x
+// range wraps), so the sum runs in a fixed order.
+constexpr int kChunk = 4096;            // ions per sorting chunk (12-bit local index)
+constexpr int kChunkThreads = 1024;
+constexpr int kMaxCells = 8192;         // 13-bit cell index; counts of a chunk fit in LDS
 
-__global__ __launch_bounds__(kSortThreads) void ion_sort_kernel(
-    const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m, int p2,
-    double lz, double4 *__restrict__ sorted, int32_t *__restrict__ bin_start) {
-  const int64_t f = blockIdx.x;
-  const double bw = lz / kZBins;
-  const double *pf = ion_pos + f * m * 3;
-  for (int i = threadIdx.x; i < p2; i += kSortThreads) {
+__device__ inline int cell_coord(double x, double L, double invh, int nc) {
+  double xw = x - L * floor(x / L);
+  int c = (int)(xw * invh);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__global__ __launch_bounds__(kChunkThreads) void cell_sort_chunk_kernel(
+    const double *__restrict__ ion_pos, int64_t m, int64_t nchunks, double lx, double ly,
+    double lz, double ihx, double ihy, double ihz, int ncx, int ncy, int ncz,
+    uint32_t *__restrict__ skeys, int32_t *__restrict__ hist) {
+  __shared__ uint32_t keys[kChunk];
+  const int64_t chunk = blockIdx.x, f = blockIdx.y;
+  const int64_t i0 = chunk * kChunk;
+  const int cnt = (int)((m - i0) < kChunk ? (m - i0) : kChunk);
+  const double *pf = ion_pos + (f * m + i0) * 3;
+  for (int j = threadIdx.x; j < kChunk; j += kChunkThreads) {
     uint32_t key = 0xffffffffu;
-    if (i < m) {
-      const double z = pf[3 * i + 2];
-      const double zw = z - lz * floor(z / lz);
-      const int b = min(kZBins - 1, max(0, (int)floor(zw / bw)));
-      key = ((uint32_t)b << 20) | (uint32_t)i;
+    if (j < cnt) {
+      const int cx = cell_coord(pf[3 * j], lx, ihx, ncx);
+      const int cy = cell_coord(pf[3 * j + 1], ly, ihy, ncy);
+      const int cz = cell_coord(pf[3 * j + 2], lz, ihz, ncz);
+      key = ((uint32_t)((cz * ncy + cy) * ncx + cx) << 12) | (uint32_t)j;
     }
-    sort_keys[i] = key;
+    keys[j] = key;
   }
   __syncthreads();
-  for (int k = 2; k <= p2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < p2; i += kSortThreads) {
-        const int ixj = i ^ j;
+  for (int k = 2; k <= kChunk; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int i = threadIdx.x; i < kChunk; i += kChunkThreads) {
+        const int ixj = i ^ jj;
         if (ixj > i) {
-          const uint32_t a = sort_keys[i], b = sort_keys[ixj];
+          const uint32_t a = keys[i], b = keys[ixj];
           if ((a > b) == ((i & k) == 0)) {
-            sort_keys[i] = b;
-            sort_keys[ixj] = a;
+            keys[i] = b;
+            keys[ixj] = a;
           }
         }
       }
       __syncthreads();
     }
   }
-  const double *qf = ion_q + f * m;
-  for (int j = threadIdx.x; j < m; j += kSortThreads) {
-    const int i = (int)(sort_keys[j] & 0xfffffu);
-    sorted[f * m + j] = make_double4(pf[3 * i], pf[3 * i + 1], pf[3 * i + 2], qf[i]);
-  }
-  for (int b = threadIdx.x; b <= kZBins; b += kSortThreads) {
-    const uint32_t target = (uint32_t)b << 20;
-    int lo = 0, hi = (int)m;   // first j with key >= target
+  for (int j = threadIdx.x; j < cnt; j += kChunkThreads) skeys[f * m + i0 + j] = keys[j];
+  // count of cell c = first position of cell c + 1 - first position of c
+  const int ncell = ncx * ncy * ncz;
+  int32_t *h = hist + (f * nchunks + chunk) * ncell;
+  for (int c = threadIdx.x; c < ncell; c += kChunkThreads) {
+    int lo = 0, hi = cnt;
+    const uint32_t t0 = (uint32_t)c << 12;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (sort_keys[mid] < target) lo = mid + 1;
+      if (keys[mid] < t0) lo = mid + 1;
       else hi = mid;
     }
-    bin_start[f * (kZBins + 1) + b] = lo;
+    int lo2 = lo, hi2 = cnt;
+    const uint32_t t1 = (uint32_t)(c + 1) << 12;
+    while (lo2 < hi2) {
+      const int mid = (lo2 + hi2) >> 1;
+      if (keys[mid] < t1) lo2 = mid + 1;
+      else hi2 = mid;
+    }
+    h[c] = lo2 - lo;
   }
 }
 
-// Real space over the z window of each wavefront's atoms: one wavefront per
-// (tile of 64 atoms in the spatial order, frame, ion group). The window is
-// [z_min - rcut, z_max + rcut] of the tile (z bins widened by one on both
-// sides, periodic in z); when L_z < 2 rcut or the window covers the box,
-// all ions. The window's ions (at most two ranges of the sorted list) are
-// split over the groups; the pair sum is that of real_space_ions_kernel.
-__global__ __launch_bounds__(64) void real_space_win_kernel(
+// One workgroup per frame: off[f][chunk][c] = sum of the counts of cell c in
+// the earlier chunks; cstart[f][c] = number of ions in cells before c
+// (cstart[f][ncell] = m).
+__global__ __launch_bounds__(kChunkThreads) void cell_scan_kernel(
+    int32_t *__restrict__ hist, int64_t nchunks, int ncell, int64_t m,
+    int32_t *__restrict__ cstart) {
+  __shared__ int32_t tot[kMaxCells];
+  __shared__ int32_t part[kChunkThreads];
+  const int64_t f = blockIdx.x;
+  int32_t *h = hist + f * nchunks * ncell;
+  for (int c = threadIdx.x; c < ncell; c += kChunkThreads) {
+    int32_t run = 0;
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+      const int32_t v = h[ch * ncell + c];
+      h[ch * ncell + c] = run;
+      run += v;
+    }
+    tot[c] = run;
+  }
+  __syncthreads();
+  // exclusive scan of tot over the cells: each thread a contiguous slice
+  const int per = (ncell + kChunkThreads - 1) / kChunkThreads;
+  const int c0 = threadIdx.x * per, c1 = min(ncell, c0 + per);
+  int32_t sum = 0;
+  for (int c = c0; c < c1; ++c) sum += tot[c];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int t = 0; t < kChunkThreads; ++t) {
+      const int32_t v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int32_t run = part[threadIdx.x];
+  int32_t *cs = cstart + f * (ncell + 1);
+  for (int c = c0; c < c1; ++c) {
+    cs[c] = run;
+    run += tot[c];
+  }
+  if (threadIdx.x == 0) cs[ncell] = (int32_t)m;
+}
+
+__global__ __launch_bounds__(kChunkThreads) void cell_scatter_kernel(
+    const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m,
+    int64_t nchunks, int ncell, const uint32_t *__restrict__ skeys,
+    const int32_t *__restrict__ off, const int32_t *__restrict__ cstart,
+    double4 *__restrict__ sorted) {
+  __shared__ uint32_t keys[kChunk];
+  const int64_t chunk = blockIdx.x, f = blockIdx.y;
+  const int64_t i0 = chunk * kChunk;
+  const int cnt = (int)((m - i0) < kChunk ? (m - i0) : kChunk);
+  for (int j = threadIdx.x; j < cnt; j += kChunkThreads) keys[j] = skeys[f * m + i0 + j];
+  __syncthreads();
+  const int32_t *o = off + (f * nchunks + chunk) * ncell;
+  const int32_t *cs = cstart + f * (ncell + 1);
+  const double *pf = ion_pos + f * m * 3;
+  const double *qf = ion_q + f * m;
+  for (int j = threadIdx.x; j < cnt; j += kChunkThreads) {
+    const uint32_t key = keys[j];
+    const int c = (int)(key >> 12);
+    const int64_t I = i0 + (int64_t)(key & 0xfffu);
+    int lo = 0, hi = j;   // first position of cell c in the chunk
+    const uint32_t t0 = (uint32_t)c << 12;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (keys[mid] < t0) lo = mid + 1;
+      else hi = mid;
+    }
+    const int64_t dst = (int64_t)cs[c] + o[c] + (j - lo);
+    sorted[f * m + dst] = make_double4(pf[3 * I], pf[3 * I + 1], pf[3 * I + 2], qf[I]);
+  }
+}
+
+// Cells [a, b] (unwrapped, a <= b) along one edge of nc cells: all of them
+// once when the range covers the edge.
+__device__ inline void cell_span(double lo, double hi, double invh, int nc, int &a, int &b) {
+  a = (int)floor(lo * invh);
+  b = (int)floor(hi * invh);
+  if (b - a + 1 >= nc) {
+    a = 0;
+    b = nc - 1;
+  }
+}
+
+__device__ inline int wrap_cell(int c, int nc) {
+  c %= nc;
+  return c < 0 ? c + nc : c;
+}
+
+__global__ __launch_bounds__(64) void real_space_cell_kernel(
     const double *__restrict__ pos, const double *__restrict__ width,
     const int32_t *__restrict__ order, int64_t n, const double4 *__restrict__ sorted,
-    const int32_t *__restrict__ bin_start, int64_t m, int groups, double lx, double ly, double lz,
-    double beta, double rcut, int64_t f_total, const double *__restrict__ etab,
-    double *__restrict__ rs) {
+    const int32_t *__restrict__ cstart, int64_t m, int ncx, int ncy, int ncz, double lx,
+    double ly, double lz, double beta, double rcut, int64_t f_total,
+    const double *__restrict__ etab, double *__restrict__ rs) {
   __shared__ double4 si[64];
   __shared__ double et[kErfcTab];
   for (int q = threadIdx.x; q < kErfcTab; q += 64) et[q] = etab[q];
   __syncthreads();
   const int64_t f = blockIdx.y;
-  const int g = blockIdx.z;
   const int lane = threadIdx.x;
   const int64_t t = (int64_t)blockIdx.x * 64 + lane;
   const int64_t i = t < n ? (int64_t)order[t] : -1;
@@ -501,87 +608,100 @@ __global__ __launch_bounds__(64) void real_space_win_kernel(
   }
   const double ilx = 1.0 / lx, ily = 1.0 / ly, ilz = 1.0 / lz;
   const bool wx = lx >= 2.0 * rcut, wy = ly >= 2.0 * rcut, wz = lz >= 2.0 * rcut;
-  // z extent of the tile about its first atom (lane 0 always holds one)
-  const double zref = __shfl(zi, 0, 64);
-  double dz0 = zi - zref;
-  dz0 -= lz * rint(dz0 * ilz);
-  if (i < 0) dz0 = 0.0;
-  double dmin = dz0, dmax = dz0;
+  // bounding box of the tile about its first atom (lane 0 always holds one)
+  const double xr = __shfl(xi, 0, 64), yr = __shfl(yi, 0, 64), zr = __shfl(zi, 0, 64);
+  double ex0 = xi - xr, ey0 = yi - yr, ez0 = zi - zr;
+  ex0 -= lx * rint(ex0 * ilx);
+  ey0 -= ly * rint(ey0 * ily);
+  ez0 -= lz * rint(ez0 * ilz);
+  if (i < 0) ex0 = ey0 = ez0 = 0.0;
+  double xmin = ex0, xmax = ex0, ymin = ey0, ymax = ey0, zmin = ez0, zmax = ez0;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    dmin = fmin(dmin, __shfl_xor(dmin, off, 64));
-    dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+  for (int o = 32; o > 0; o >>= 1) {
+    xmin = fmin(xmin, __shfl_xor(xmin, o, 64));
+    xmax = fmax(xmax, __shfl_xor(xmax, o, 64));
+    ymin = fmin(ymin, __shfl_xor(ymin, o, 64));
+    ymax = fmax(ymax, __shfl_xor(ymax, o, 64));
+    zmin = fmin(zmin, __shfl_xor(zmin, o, 64));
+    zmax = fmax(zmax, __shfl_xor(zmax, o, 64));
   }
-  const int32_t *bs = bin_start + f * (kZBins + 1);
-  const double bw = lz / kZBins;
-  const int64_t blo = (int64_t)floor((zref + dmin - rcut) / bw) - 1;
-  const int64_t bhi = (int64_t)floor((zref + dmax + rcut) / bw) + 1;
-  const int64_t nbins = bhi - blo + 1;
-  int64_t s1 = 0, e1 = m, s2 = 0, e2 = 0;   // candidate ranges [s1, e1) + [s2, e2)
-  if (wz && nbins < kZBins) {
-    const int64_t b0 = ((blo % kZBins) + kZBins) % kZBins;
-    if (b0 + nbins <= kZBins) {
-      s1 = bs[b0];
-      e1 = bs[b0 + nbins];
-    } else {
-      s1 = bs[b0];
-      e1 = bs[kZBins];
-      s2 = bs[0];
-      e2 = bs[b0 + nbins - kZBins];
-    }
-  }
-  const int64_t c1 = e1 - s1, cn = c1 + (e2 - s2);
-  const int64_t q0 = cn * g / groups, q1 = cn * (g + 1) / groups;
+  // cells meeting the box widened by rcut (and a hair for rounding at cell
+  // edges; the distance test below is exact)
+  const double rw = rcut * (1.0 + 1e-9) + 1e-9;
+  int xa, xb, ya, yb, za, zb;
+  cell_span(xr + xmin - rw, xr + xmax + rw, ncx * ilx, ncx, xa, xb);
+  cell_span(yr + ymin - rw, yr + ymax + rw, ncy * ily, ncy, ya, yb);
+  cell_span(zr + zmin - rw, zr + zmax + rw, ncz * ilz, ncz, za, zb);
+  const int32_t *cs = cstart + f * ((int64_t)ncx * ncy * ncz + 1);
+  const double4 *sf = sorted + f * m;
   const double rc2 = rcut * rcut;
   const double lim0 = 2.0 * (ai - beta) * 0.56418958354775628695;
-  const double4 *sf = sorted + f * m;
+  const int xlen = xb - xa + 1, xw0 = wrap_cell(xa, ncx);
   double acc = 0.0;
-  for (int64_t base = q0; base < q1; base += 64) {
-    const int64_t q = base + lane;
-    if (q < q1) si[lane] = sf[q < c1 ? s1 + q : s2 + (q - c1)];
-    __syncthreads();
-    const int cnt = (int)((q1 - base) < 64 ? (q1 - base) : 64);
-    if (i >= 0) {
-      for (int j = 0; j < cnt; ++j) {
-        const double4 ion = si[j];
-        double dz = zi - ion.z;
-        dz -= lz * rint(dz * ilz);
-        int za, zb;
-        image_range(dz, lz, ilz, rcut, wz, za, zb);
-        if (za > zb) continue;
-        double dx = xi - ion.x;
-        double dy = yi - ion.y;
-        dx -= lx * rint(dx * ilx);
-        dy -= ly * rint(dy * ily);
-        int xa, xb, ya, yb;
-        image_range(dx, lx, ilx, rcut, wx, xa, xb);
-        image_range(dy, ly, ily, rcut, wy, ya, yb);
-        const double qv = ion.w;
-        for (int a = xa; a <= xb; ++a) {
-          const double ex = dx + (double)a * lx;
-          for (int bb = ya; bb <= yb; ++bb) {
-            const double ey = dy + (double)bb * ly;
-            const double exy = ex * ex + ey * ey;
-            if (exy >= rc2) continue;
-            for (int c = za; c <= zb; ++c) {
-              const double ez = dz + (double)c * lz;
-              const double d2 = exy + ez * ez;
-              if (d2 < rc2) {
-                if (d2 > 0.0) {
-                  const double d = sqrt(d2);
-                  acc += qv * ((erfc_pw(et, beta * d) - erfc_pw(et, ai * d)) / d);
-                } else {
-                  acc += qv * lim0;
+  for (int cz = za; cz <= zb; ++cz) {
+    const int czw = wrap_cell(cz, ncz);
+    for (int cy = ya; cy <= yb; ++cy) {
+      const int64_t row = ((int64_t)czw * ncy + wrap_cell(cy, ncy)) * ncx;
+      for (int part = 0; part < 2; ++part) {
+        int c0, c1;   // cells [c0, c1) of the row
+        if (part == 0) {
+          c0 = xw0;
+          c1 = min(ncx, xw0 + xlen);
+        } else {
+          c0 = 0;
+          c1 = xw0 + xlen - ncx;
+          if (c1 <= 0) break;
+        }
+        const int64_t s0 = cs[row + c0], s1 = cs[row + c1];
+        for (int64_t base = s0; base < s1; base += 64) {
+          const int64_t q = base + lane;
+          if (q < s1) si[lane] = sf[q];
+          __syncthreads();
+          const int cnt = (int)((s1 - base) < 64 ? (s1 - base) : 64);
+          if (i >= 0) {
+            for (int j = 0; j < cnt; ++j) {
+              const double4 ion = si[j];
+              double dz = zi - ion.z;
+              dz -= lz * rint(dz * ilz);
+              int iza, izb;
+              image_range(dz, lz, ilz, rcut, wz, iza, izb);
+              if (iza > izb) continue;
+              double dx = xi - ion.x;
+              double dy = yi - ion.y;
+              dx -= lx * rint(dx * ilx);
+              dy -= ly * rint(dy * ily);
+              int ixa, ixb, iya, iyb;
+              image_range(dx, lx, ilx, rcut, wx, ixa, ixb);
+              image_range(dy, ly, ily, rcut, wy, iya, iyb);
+              const double qv = ion.w;
+              for (int a = ixa; a <= ixb; ++a) {
+                const double ex = dx + (double)a * lx;
+                for (int bb = iya; bb <= iyb; ++bb) {
+                  const double ey = dy + (double)bb * ly;
+                  const double exy = ex * ex + ey * ey;
+                  if (exy >= rc2) continue;
+                  for (int c = iza; c <= izb; ++c) {
+                    const double ez = dz + (double)c * lz;
+                    const double d2 = exy + ez * ez;
+                    if (d2 < rc2) {
+                      if (d2 > 0.0) {
+                        const double d = sqrt(d2);
+                        acc += qv * ((erfc_pw(et, beta * d) - erfc_pw(et, ai * d)) / d);
+                      } else {
+                        acc += qv * lim0;
+                      }
+                    }
+                  }
                 }
               }
             }
           }
+          __syncthreads();
         }
       }
     }
-    __syncthreads();
   }
-  if (i >= 0) rs[((int64_t)g * f_total + f) * n + i] = acc;
+  if (i >= 0) rs[f * n + i] = acc;
 }
 
 }  // namespace
@@ -596,10 +716,30 @@ namespace {
 //   rs  [rs_groups][f][n]      real-space partials
 struct RhsPlan {
   int64_t sf_groups = 1, sf_ipg = 0, ksplit = 0, kper = 0, rs_groups = 0, rs_ipg = 0;
-  bool rs_win = false;          // real space over z windows of the sorted ions
-  int p2 = 0;                   // sort size (power of two >= ions per frame)
-  int64_t off_sg = 0, off_bp = 0, off_rs = 0, off_m1 = 0, off_sorted = 0, off_bins = 0, total = 0;
+  bool rs_cell = false;         // real space over the cell list of the ions
+  int nc[3] = {1, 1, 1};        // cells per box edge
+  int64_t nchunks = 0;          // sorting chunks per frame
+  int64_t off_sg = 0, off_bp = 0, off_rs = 0, off_m1 = 0, off_sorted = 0, off_keys = 0,
+          off_hist = 0, off_cstart = 0, total = 0;
 };
+
+// below this many ions per frame the cell list costs more than it saves
+// (measured: 2000 ions, 4608 atoms: the all-pairs kernel takes 126 us)
+constexpr int64_t kCellMinIons = 8192;
+
+// Cells of edge >= rcut / 2 (widened until there are at most kMaxCells).
+void cell_grid(const double box[3], double rcut, int nc[3]) {
+  double h = 0.5 * rcut;
+  for (;;) {
+    int64_t tot = 1;
+    for (int d = 0; d < 3; ++d) {
+      nc[d] = std::max(1, (int)std::floor(box[d] / h));
+      tot *= nc[d];
+    }
+    if (tot <= kMaxCells) return;
+    h *= 1.25;
+  }
+}
 
 constexpr int64_t kTargetBlocks = 2048;          // workgroups that fill the chip several times
 constexpr int64_t kPartialCap = (int64_t)1 << 27;  // doubles per partial buffer
@@ -630,24 +770,24 @@ RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f) {
     p.kper = (nk + ks - 1) / ks;
     p.ksplit = (nk + p.kper - 1) / p.kper;
   }
-  if (m >= kWinMinIons && m <= kSortMaxIons) {
-    // windowed real space: enough wavefronts (tiles x frames x groups) to fill the chip
-    p.rs_win = true;
-    p.p2 = 1;
-    while (p.p2 < m) p.p2 <<= 1;
-    const int64_t tiles = (n + 63) / 64;
-    p.rs_groups = std::max<int64_t>(1, std::min<int64_t>(8, 3072 / std::max<int64_t>(1, tiles * f)));
-    p.rs_groups = std::max<int64_t>(1, std::min<int64_t>(p.rs_groups, kPartialCap / (f * n)));
+  if (m >= kCellMinIons) {
+    p.rs_cell = true;
+    cell_grid(s->box, s->rcut, p.nc);
+    p.nchunks = (m + kChunk - 1) / kChunk;
+    p.rs_groups = 1;
   } else if (m > 0) {
     p.rs_groups = groups_for(iblocks * f, m, kPartialCap / (f * n), p.rs_ipg);
   }
+  const int64_t ncell = (int64_t)p.nc[0] * p.nc[1] * p.nc[2];
   p.off_sg = 2 * nk * f;
   p.off_bp = p.off_sg + (p.sf_groups > 1 ? p.sf_groups * 2 * nk * f : 0);
   p.off_rs = p.off_bp + p.ksplit * f * n;
   p.off_m1 = p.off_rs + p.rs_groups * f * n;
   p.off_sorted = (p.off_m1 + f + 3) / 4 * 4;   // 32-byte aligned (double4)
-  p.off_bins = p.off_sorted + (p.rs_win ? 4 * f * m : 0);
-  p.total = p.off_bins + (p.rs_win ? (f * (kZBins + 1) + 1) / 2 : 0);
+  p.off_keys = p.off_sorted + (p.rs_cell ? 4 * f * m : 0);
+  p.off_hist = p.off_keys + (p.rs_cell ? (f * m + 1) / 2 : 0);
+  p.off_cstart = p.off_hist + (p.rs_cell ? (f * p.nchunks * ncell + 1) / 2 : 0);
+  p.total = p.off_cstart + (p.rs_cell ? (f * (ncell + 1) + 1) / 2 : 0);
   return p;
 }
 
@@ -694,19 +834,27 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
                        dim3(RB), 0, st, s->pos, n, s->kinfo, s->kw, nk, p.kper, ilx, ily, ilz, S, f,
                        bp);
   }
-  if (p.rs_win) {
+  if (p.rs_cell) {
     double4 *sorted = reinterpret_cast<double4 *>(scratch + p.off_sorted);
-    int32_t *bins = reinterpret_cast<int32_t *>(scratch + p.off_bins);
-    const size_t lds = sizeof(uint32_t) * (size_t)p.p2;
-    if (lds > 65536)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(ion_sort_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(ion_sort_kernel, dim3((unsigned)f), dim3(kSortThreads), lds, st, ion_pos,
-                       ion_q, m, p.p2, s->box[2], sorted, bins);
-    hipLaunchKernelGGL(real_space_win_kernel, dim3((unsigned)((n + 63) / 64), (unsigned)f, (unsigned)p.rs_groups),
-                       dim3(64), 0, st, s->pos, s->width, s->atom_order, n, (const double4 *)sorted,
-                       (const int32_t *)bins, m, (int)p.rs_groups, s->box[0], s->box[1], s->box[2],
-                       s->beta, s->rcut, f, (const double *)s->erfc_tab, rs);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(scratch + p.off_keys);
+    int32_t *hist = reinterpret_cast<int32_t *>(scratch + p.off_hist);
+    int32_t *cstart = reinterpret_cast<int32_t *>(scratch + p.off_cstart);
+    const int ncell = p.nc[0] * p.nc[1] * p.nc[2];
+    hipLaunchKernelGGL(cell_sort_chunk_kernel, dim3((unsigned)p.nchunks, (unsigned)f),
+                       dim3(kChunkThreads), 0, st, ion_pos, m, p.nchunks, s->box[0], s->box[1],
+                       s->box[2], p.nc[0] * ilx, p.nc[1] * ily, p.nc[2] * ilz, p.nc[0], p.nc[1],
+                       p.nc[2], keys, hist);
+    hipLaunchKernelGGL(cell_scan_kernel, dim3((unsigned)f), dim3(kChunkThreads), 0, st, hist,
+                       p.nchunks, ncell, m, cstart);
+    hipLaunchKernelGGL(cell_scatter_kernel, dim3((unsigned)p.nchunks, (unsigned)f),
+                       dim3(kChunkThreads), 0, st, ion_pos, ion_q, m, p.nchunks, ncell,
+                       (const uint32_t *)keys, (const int32_t *)hist, (const int32_t *)cstart,
+                       sorted);
+    hipLaunchKernelGGL(real_space_cell_kernel, dim3((unsigned)((n + 63) / 64), (unsigned)f),
+                       dim3(64), 0, st, s->pos, s->width, s->atom_order, n,
+                       (const double4 *)sorted, (const int32_t *)cstart, m, p.nc[0], p.nc[1],
+                       p.nc[2], s->box[0], s->box[1], s->box[2], s->beta, s->rcut, f,
+                       (const double *)s->erfc_tab, rs);
   } else if (p.rs_groups > 0) {
     hipLaunchKernelGGL(real_space_ions_kernel, dim3((unsigned)iblocks, (unsigned)f, (unsigned)p.rs_groups),
                        dim3(RB), 0, st, s->pos, s->width, s->atom_order, n, ion_pos, ion_q, m,

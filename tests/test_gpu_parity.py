@@ -355,10 +355,10 @@ def test_invalid_inputs():
 
 
 def test_rhs_many_ions_z_windows():
-    """9000 ions per frame (the real-space sum then runs over z windows of the
-    z-sorted ions) on workload 1's geometry, with ions placed across the
-    periodic z boundary (z < 0, near 0, near L_z, > L_z): b of every atom
-    against the oracle's Eq. 25, <= 1e-12 max|b|."""
+    """9000 ions per frame (the real-space sum then runs over the cell list of
+    the ions) on workload 1's geometry, whose L_y = 14.76 A is below 2 r_cut,
+    with ions placed across the periodic z boundary (z < 0, near 0, near L_z,
+    > L_z): b of every atom against the oracle's Eq. 25, <= 1e-12 max|b|."""
     cpm = _cpm()
     dev = _dev()
     geo = wl.geometry(1)
@@ -383,3 +383,30 @@ def test_rhs_many_ions_z_windows():
     b2, _ = S.rhs(torch.tensor(ipos, device=dev), torch.tensor(iq, device=dev),
                   torch.tensor(chi, device=dev))
     assert torch.equal(b, b2)   # the sorted order is fixed: bitwise reproducible
+
+
+@pytest.mark.parametrize("cfg,m,frames", [(1, 40000, 2), (2, 40000, 1)])
+def test_rhs_beyond_one_sorting_workgroup(cfg, m, frames):
+    """More than 32768 ions per frame (workload 5 has 200000): the cell list
+    sorts each frame in several chunks. Ions are drawn over 1.5 box edges in
+    x, y and z (positions outside [0, L) wrap). b of every atom against the
+    oracle's Eq. 25, <= 1e-12 max|b|, Q_sol exact, and bitwise
+    reproducible."""
+    cpm = _cpm()
+    dev = _dev()
+    geo = wl.geometry(cfg)
+    km = ew.kmax_from_eps(BETA, EPS)
+    rng = np.random.default_rng(5000 + cfg)
+    ipos = rng.random((frames, m, 3)) * geo.box * 1.5 - 0.25 * geo.box
+    iq = np.where(np.arange(m) < m // 2, 1.0, -1.0)[None, :].repeat(frames, axis=0)
+    iq[:, :7] = 2.0   # a charged frame
+    chi = wl.electrode_potential(geo)
+    print(f"[case] workload {cfg} geometry, {frames} frames x {m} ions", flush=True)
+    S = cpm.System(geo.pos, geo.box, A, BETA, RC, EPS, store=())
+    t_ipos, t_iq, t_chi = (torch.tensor(x, device=dev) for x in (ipos, iq, chi))
+    b, qsol = S.rhs(t_ipos, t_iq, t_chi)
+    bo, qso = ew.rhs(geo.pos, A, ipos, iq, chi, geo.box, BETA, RC, km)
+    assert np.max(np.abs(b.cpu().numpy() - bo)) <= 1e-12 * np.max(np.abs(bo))
+    assert np.array_equal(qsol.cpu().numpy(), qso)
+    b2, _ = S.rhs(t_ipos, t_iq, t_chi)
+    assert torch.equal(b, b2)
