@@ -251,6 +251,13 @@ cpm_status cpm_gcd_solve(cpm_system *s, const double *b_dev, const double *Q_dev
    CPM_EINVAL if that precision is not stored. */
 cpm_status cpm_get_E(const cpm_system *s, int precision, void *dst_dev, int64_t ld);
 
+/* Copy the block E[row0 : row0 + rows, col0 : col0 + cols] into dst_dev
+   (rows x cols, leading dimension ld >= cols) in the requested precision:
+   inspection of matrices too large to copy whole (N = 131072: 137 GB).
+   CPM_EINVAL if the block leaves [0, n)^2 or that precision is not stored. */
+cpm_status cpm_get_E_block(const cpm_system *s, int precision, int64_t row0, int64_t col0,
+                           int64_t rows, int64_t cols, void *dst_dev, int64_t ld);
+
 /* Copy d' = E^-1 1 (S9) into dst_dev (n,) and return C_ele = 1^T d'. */
 cpm_status cpm_get_dprime(cpm_system *s, double *dst_dev, double *c_ele);
 

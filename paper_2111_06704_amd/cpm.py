@@ -26,7 +26,7 @@ MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HI
 
 EXPORTS = [
     "cpm_build_E", "cpm_free", "cpm_set_stream", "cpm_describe", "cpm_rhs", "cpm_solve",
-    "cpm_get_E", "cpm_get_dprime", "cpm_matvec", "cpm_mlp_init", "cpm_mlp_neighbours",
+    "cpm_get_E", "cpm_get_E_block", "cpm_get_dprime", "cpm_matvec", "cpm_mlp_init", "cpm_mlp_neighbours",
     "cpm_mlp_set_params", "cpm_mlp_get_params", "cpm_mlp_features", "cpm_mlp_forward",
     "cpm_mlp_loss_grad", "cpm_mlp_train_step", "cpm_mlp_train_epoch", "cpm_set_warm_chi",
     "cpm_profile_enable", "cpm_profile_read", "cpm_precond_dc", "cpm_precond_apply",
@@ -86,6 +86,7 @@ def lib():
     L.cpm_rhs.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp]
     L.cpm_solve.argtypes = [vp, vp, vp, i64, C.POINTER(SolveOpts), vp, C.POINTER(SolveInfo)]
     L.cpm_get_E.argtypes = [vp, C.c_int, vp, i64]
+    L.cpm_get_E_block.argtypes = [vp, C.c_int, i64, i64, i64, i64, vp, i64]
     L.cpm_get_dprime.argtypes = [vp, vp, C.POINTER(dbl)]
     L.cpm_matvec.argtypes = [vp, C.c_int, vp, i64, vp]
     L.cpm_mlp_init.argtypes = [vp, vp, C.c_int32, f32, f32, f32]
@@ -254,6 +255,16 @@ class System:
         dt = {PREC_F64: torch.float64, PREC_F32: torch.float32, PREC_BF16: torch.bfloat16}[precision]
         out = torch.empty((self.n, self.n), dtype=dt, device="cuda")
         _check(lib().cpm_get_E(self._h, precision, C.c_void_p(out.data_ptr()), self.n), "cpm_get_E")
+        return out
+
+    def get_E_block(self, row0, col0, rows, cols, precision=PREC_F64):
+        """E[row0:row0+rows, col0:col0+cols] as a device tensor."""
+        import torch
+        dt = {PREC_F64: torch.float64, PREC_F32: torch.float32, PREC_BF16: torch.bfloat16}[precision]
+        out = torch.empty((rows, cols), dtype=dt, device="cuda")
+        _check(lib().cpm_get_E_block(self._h, precision, int(row0), int(col0), int(rows),
+                                     int(cols), C.c_void_p(out.data_ptr()), int(cols)),
+               "cpm_get_E_block")
         return out
 
     def dprime(self):

@@ -643,6 +643,33 @@ cpm_status cpm_get_E(const cpm_system *s, int precision, void *dst_dev, int64_t 
   return CPM_OK;
 }
 
+cpm_status cpm_get_E_block(const cpm_system *s, int precision, int64_t row0, int64_t col0,
+                           int64_t rows, int64_t cols, void *dst_dev, int64_t ld) {
+  if (!s || !dst_dev) {
+    set_error("NULL argument");
+    return CPM_EINVAL;
+  }
+  if (row0 < 0 || col0 < 0 || rows < 1 || cols < 1 || row0 + rows > s->n || col0 + cols > s->n ||
+      ld < cols) {
+    set_error("block outside E or ld < cols");
+    return CPM_EINVAL;
+  }
+  const void *src = nullptr;
+  size_t es = 0;
+  if (precision == CPM_PREC_F64) { src = s->E64; es = 8; }
+  else if (precision == CPM_PREC_F32) { src = s->E32; es = 4; }
+  else if (precision == CPM_PREC_BF16) { src = s->E16; es = 2; }
+  if (!src) {
+    set_error("requested precision of E is not stored");
+    return CPM_EINVAL;
+  }
+  const char *base = static_cast<const char *>(src) + es * ((size_t)row0 * s->ld + col0);
+  CPM_HIP_CHECK(hipMemcpy2DAsync(dst_dev, es * ld, base, es * s->ld, es * cols, rows,
+                                 hipMemcpyDeviceToDevice, s->stream));
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return CPM_OK;
+}
+
 cpm_status cpm_get_dprime(cpm_system *s, double *dst_dev, double *c_ele) {
   if (!s) {
     set_error("NULL system");

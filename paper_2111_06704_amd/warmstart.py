@@ -10,6 +10,14 @@ order of each epoch) are drawn here from seeded generators and passed to the
 library.
 
     python -m paper_2111_06704_amd.warmstart --frames 10000 --epochs 8
+    python -m paper_2111_06704_amd.warmstart --workload 3 --ions 50000 --frames 4000 \
+        --out paper_2111_06704_amd/weights/warmstart_4layer.npz
+
+The second network serves the two 4-layer geometries (workloads 3 and 5):
+its inputs are per-atom and local (the atom's and its 12 neighbours'
+right-hand sides, its layer among the 8), so it transfers to the laterally
+larger workload 5 when trained at workload 5's ion density (200000 ions in
+its slit of 157.41 x 272.64 x 46 A, i.e. 50000 in workload 3's).
 """
 from __future__ import annotations
 
@@ -26,6 +34,13 @@ from . import cpm, workloads as wl
 NIN, NH = cpm.MLP_IN, cpm.MLP_HIDDEN
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
                             "warmstart_cfg2.npz")
+FOUR_LAYER_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                               "warmstart_4layer.npz")
+
+
+def weights_for(cfg: int) -> str:
+    """Committed network for a workload's electrode geometry."""
+    return DEFAULT_PATH if cfg in (1, 2, 4) else FOUR_LAYER_PATH
 
 
 def init_params(seed: int) -> np.ndarray:
@@ -111,6 +126,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
     ap.add_argument("--frames", type=int, default=10000)
+    ap.add_argument("--ions", type=int, default=None,
+                    help="ions per training frame (default: the workload's)")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -123,12 +140,13 @@ def main(argv=None):
 
     dev = torch.device("cuda:0")
     geo = wl.geometry(args.workload)
-    m = wl.CONFIGS[args.workload]["m"]
+    m = args.ions or wl.CONFIGS[args.workload]["m"]
     S = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, wl.KSPACE_EPS,
                    store=("f32",))
     chi = torch.tensor(wl.electrode_potential(geo), device=dev)
     seeds = [wl.train_seed(t) for t in range(args.frames)]
-    log(f"generating {args.frames} training frames (workload {args.workload}, N={geo.n})")
+    log(f"generating {args.frames} training frames (workload {args.workload}, N={geo.n}, "
+        f"{m} ions)")
     t0 = time.perf_counter()
     b_all, q_all = generate(S, geo, seeds, m, chi, log=log)
     t_gen = time.perf_counter() - t0
@@ -139,7 +157,8 @@ def main(argv=None):
     losses = train(S, b_all, q_all, args.epochs, args.batch, args.lr, seed=args.seed + 1, log=log)
     t_train = time.perf_counter() - t0
     params = S.mlp_get_params()
-    meta = dict(workload=args.workload, frames=args.frames, epochs=args.epochs, batch=args.batch,
+    meta = dict(workload=args.workload, ions=m, frames=args.frames, epochs=args.epochs,
+                batch=args.batch,
                 lr=args.lr, seed=args.seed, losses=losses, gen_s=t_gen, train_s=t_train,
                 train_seeds=f"{wl.train_seed(0)}..{wl.train_seed(args.frames - 1)}")
     save(args.out, params, bs, qs, wl.BOND, meta)

@@ -1,0 +1,118 @@
+"""Workload 5 at its full size (N = 131072 electrode atoms, ld = 131072, 32
+frames of 200000 ions) with a shortened reciprocal sum (K_max = 0.3 / A, about
+a thousand k-vectors), so that E is assembled in seconds; the oracle uses
+the same K_max. Every other part runs as at the full k-set: the cell list of
+200000 ions per frame in 49 sorting chunks, the FP64 and FP32 matrices of
+137 and 69 GB, the 32-column block products (FP64 matrix cores, split
+bf16 for FP32), PCG-DC and the projection.
+
+The truncated E keeps the real-space part (a sampled positive-definite
+kernel, [erf(a r) - erf(beta r)] / r, plus its self term) and a subset of the
+positive semi-definite reciprocal terms, so it is positive definite.
+
+Checks against the FP64 oracle:
+  * E: sampled entries (random, diagonal, neighbours) vs the literal Eq. 22
+    sum, <= 1e-12 max|E|; exact symmetry of sampled blocks; FP32 copy is
+    the rounding of the FP64 matrix;
+  * b: sampled atoms of frames 0 and 31, <= 1e-12 max|b|;
+  * q: stationarity of Eq. 28 (E q - b uniform over atoms, Eq. 29) at
+    sampled atoms of two frames with (E q)_i from the oracle's matrix-free
+    potentials, spread <= 2e-10 |b|_2; sum q + Q_sol <= 1e-12 e; the mixed
+    (FP32 + PCG-DC) and FP64 solves agree to rel_2 <= 1e-8.
+"""
+import numpy as np
+import pytest
+
+from oracle import ewald as ew
+from paper_2111_06704_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+A, BETA, RC = wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT
+KMAX = 0.3
+
+
+@pytest.fixture(scope="module")
+def w5():
+    from paper_2111_06704_amd import cpm
+    cpm.lib()
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dev = torch.device("cuda:0")
+    geo, ipos, iq, chi = wl.workload(5)
+    print(f"[case] workload 5, K_max {KMAX}: N={geo.n} frames={ipos.shape[0]} "
+          f"ions={ipos.shape[1]}", flush=True)
+    S = cpm.System(geo.pos, geo.box, A, BETA, RC, kmax_override=KMAX, store=("f32",))
+    print(f"[case] E built: {S.describe()}", flush=True)
+    t_chi = torch.tensor(chi, device=dev)
+    b, qsol = S.rhs(torch.tensor(ipos, device=dev), torch.tensor(iq, device=dev), t_chi)
+    q64, st64 = S.solve(b, qsol, tol=1e-11, precision=cpm.PREC_F64, check_every=8)
+    print(f"[case] FP64 CG: {st64['iterations']} iterations", flush=True)
+    S.precond_dc(0.15, 7.0)
+    S.set_warm_chi(t_chi)
+    q, st = S.solve(b, qsol, tol=1e-11, precision=cpm.PREC_F32, warm_start=cpm.WARM_CHI,
+                    inner_tol=1e-3, check_every=4, preconditioner=cpm.PRECOND_DC)
+    print(f"[case] FP32 + PCG-DC + q_chi start: {st['iterations']} iterations", flush=True)
+    out = dict(cpm=cpm, S=S, geo=geo, ipos=ipos, iq=iq, chi=chi, b=b.cpu().numpy(),
+               qsol=qsol.cpu().numpy(), q=q.cpu().numpy(), st=st, q64=q64.cpu().numpy(), st64=st64)
+    yield out
+    S.close()
+
+
+def _samples(n, k, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, k, replace=False))
+
+
+def test_matrix_sampled_entries(w5):
+    cpm, S, geo = w5["cpm"], w5["S"], w5["geo"]
+    rng = np.random.default_rng(51)
+    ii, jj = rng.integers(0, geo.n, 16), rng.integers(0, geo.n, 16)
+    diag, near = _samples(geo.n, 4, 52), _samples(geo.n - 1, 4, 53)
+    pairs = list(zip(ii, jj)) + [(i, i) for i in diag] + [(i, i + 1) for i in near]
+    vals = np.array([S.get_E_block(i, j, 1, 1).item() for i, j in pairs])
+    ref = np.array([ew.ewald_entry_literal(geo.pos[i], geo.pos[j], geo.box, A, A, BETA, RC, KMAX,
+                                           same_atom=(i == j)) for i, j in pairs])
+    assert np.max(np.abs(vals - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # exact symmetry of sampled blocks, the last block row and column included
+    for i0, j0 in ((0, 0), (98304, 4096), (131072 - 256, 65536), (131072 - 256, 131072 - 256)):
+        assert torch.equal(S.get_E_block(i0, j0, 256, 256), S.get_E_block(j0, i0, 256, 256).T)
+    # the FP32 copy is the rounding of the FP64 matrix
+    for r0 in (0, 65536, 131072 - 1024):
+        assert torch.equal(S.get_E_block(r0, 0, 1024, geo.n, cpm.PREC_F32),
+                           S.get_E_block(r0, 0, 1024, geo.n).float())
+
+
+def test_rhs_sampled_atoms(w5):
+    geo = w5["geo"]
+    at = _samples(geo.n, 8, 54)
+    for f in (0, 31):
+        bo, qso = ew.rhs(geo.pos[at], A, w5["ipos"][f], w5["iq"][f], w5["chi"][at], geo.box,
+                         BETA, RC, KMAX)
+        assert np.max(np.abs(w5["b"][f, at] - bo)) <= 1e-12 * np.max(np.abs(bo))
+        assert w5["qsol"][f] == qso
+
+
+def test_charges_stationary_and_neutral(w5):
+    geo = w5["geo"]
+    at = _samples(geo.n, 8, 55)
+    for f in (3, 30):
+        for q in (w5["q"][f], w5["q64"][f]):
+            u = ew.potentials(geo.pos, A, q, geo.box, BETA, RC, KMAX, at=at)
+            bo, _ = ew.rhs(geo.pos[at], A, w5["ipos"][f], w5["iq"][f], w5["chi"][at], geo.box,
+                           BETA, RC, KMAX)
+            dev = u - bo
+            spread = np.max(np.abs(dev - np.mean(dev)))
+            print(f"[kkt] frame {f}: spread {spread:.3e}, |b|_2 {np.linalg.norm(w5['b'][f]):.3e}")
+            assert spread <= 2e-10 * np.linalg.norm(w5["b"][f])
+    for q in (w5["q"], w5["q64"]):
+        assert np.max(np.abs(q.sum(axis=1) + w5["qsol"])) <= 1e-12
+    assert w5["st"]["max_abs_sum_q"] <= 1e-12
+
+
+def test_mixed_matches_fp64(w5):
+    q, q64 = w5["q"], w5["q64"]
+    rel = np.linalg.norm(q - q64, axis=1) / np.linalg.norm(q64, axis=1)
+    assert rel.max() <= 1e-8
+    assert w5["st"]["iterations"] < w5["st64"]["iterations"]
