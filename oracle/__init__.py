@@ -18,7 +18,11 @@ are in e/A; volts convert with k_e = e^2/(4 pi eps0).
 Modules:
   ewald    - k-vector set, the Gaussian Ewald matrix E (Eq. 22-23), the
              electrolyte potential b_sol (Eq. 25) and a matrix-free
-             potential evaluation (Eq. 21).
+             potential evaluation (Eq. 21); for systems too large for the
+             direct phase sums (N = 131072 with 200000 ions) the same
+             structure factors and reciprocal sums through per-axis factors
+             of exp(i K.r) and complex matrix products, pinned to the direct
+             routines.
   cpm      - the constrained solve: Cholesky, neutralising vector (S8-S9),
              two-step neutralisation (Eq. 35), bordered Lagrange system
              (Eq. 29) and the S matrix (Eq. 33); the matrix-inversion

@@ -320,3 +320,103 @@ def potentials(pos, a, q, box, beta, rcut, kmax, at=None):
                                                          / math.sqrt(math.pi))
     u += selfc * q[idx]
     return u
+
+
+def structure_factor(pos, q, box, n, chunk=16384):
+    """S(K) = sum_j q_j exp(i K.r_j) for the k-vectors K = 2 pi n / L of the
+    integer triplets n (M, 3) (Eq. 23's structure factor, the sum whose real
+    and imaginary parts the reciprocal terms of Eq. 21-22 and 25 contract).
+
+    Uses the exact identity exp(i K.r) = exp(2 pi i n_x x / L_x)
+    exp(2 pi i n_y y / L_y) exp(2 pi i n_z z / L_z): per-axis factor tables of
+    every particle, and for each chunk of particles one complex matrix
+    product over them,
+        T[n_y, (n_x, n_z)] = sum_j Y_j(n_y) [q_j X_j(n_x) Z_j(n_z)],
+    from which the entries of the requested triplets are read. Same sum as
+    the direct cos / sin evaluation of ``potentials``, in another order; it
+    costs particles x (distinct n_x) x (distinct n_z) products instead of
+    particles x k-vectors phases."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    n = np.asarray(n, dtype=np.int64)
+    vals = [np.unique(n[:, d]) for d in range(3)]
+    ix = [np.searchsorted(vals[d], n[:, d]) for d in range(3)]
+    nxv, nyv, nzv = (len(v) for v in vals)
+    T = np.zeros((nyv, nxv * nzv), dtype=np.complex128)
+    for j0 in range(0, len(pos), chunk):
+        u = pos[j0:j0 + chunk] / box
+        X, Y, Z = (np.exp(2j * math.pi * np.outer(u[:, d], vals[d])) for d in range(3))
+        XZ = (q[j0:j0 + chunk, None] * X)[:, :, None] * Z[:, None, :]
+        T += Y.T @ XZ.reshape(len(u), nxv * nzv)
+    return T[ix[1], ix[0] * nzv + ix[2]]
+
+
+def reciprocal_potential(pos_at, S, n, w, box, chunk=16384):
+    """sum_K w_K Re(exp(-i K.r) S(K)) at the points pos_at for the k-vectors of
+    the integer triplets n (the reciprocal sums of Eq. 21 and 25 given the
+    structure factor S), through the per-axis factors of exp(-i K.r):
+        G[r, n_y] = sum_{n_z} conj(Z_r(n_z)) W[n_x, n_y, n_z],  W = w S on the
+        (n_x, n_y, n_z) grid (zero off the k-set),
+    then the sums over n_y and n_x with conj(Y_r) and conj(X_r)."""
+    pos_at = np.asarray(pos_at, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    n = np.asarray(n, dtype=np.int64)
+    vals = [np.unique(n[:, d]) for d in range(3)]
+    ix = [np.searchsorted(vals[d], n[:, d]) for d in range(3)]
+    W = np.zeros((len(vals[0]), len(vals[1]), len(vals[2])), dtype=np.complex128)
+    W[ix[0], ix[1], ix[2]] = np.asarray(w) * np.asarray(S)
+    out = np.empty(len(pos_at))
+    for r0 in range(0, len(pos_at), chunk):
+        u = pos_at[r0:r0 + chunk] / box
+        X, Y, Z = (np.exp(-2j * math.pi * np.outer(u[:, d], vals[d])) for d in range(3))
+        acc = np.zeros(len(u), dtype=np.complex128)
+        for a in range(len(vals[0])):
+            G = Z @ W[a].T                      # (points, n_y)
+            acc += X[:, a] * np.sum(Y * G, axis=1)
+        out[r0:r0 + chunk] = acc.real
+    return out
+
+
+def potentials_factored(pos, a, q, box, beta, rcut, kmax, at=None):
+    """The potentials of ``potentials`` at the atoms ``at`` (default: all),
+    with the reciprocal part from ``structure_factor`` and
+    ``reciprocal_potential`` (large systems)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    n = len(pos)
+    idx = np.arange(n) if at is None else np.asarray(at, dtype=np.int64)
+    a = np.broadcast_to(np.asarray(a, dtype=np.float64), (n,))
+    vol = float(np.prod(box))
+    nv, _, w = kvectors(box, beta, kmax, half=True)
+    u = reciprocal_potential(pos[idx], structure_factor(pos, q, box, nv), nv, w, box)
+    i, j, d = real_space_pairs(pos[idx], pos, box, rcut)
+    u += np.bincount(i, weights=q[j] * _pair_potential_real(d, beta, mix_width(a[idx][i], a[j])),
+                     minlength=len(idx))
+    u -= math.pi / (vol * beta * beta) * float(np.sum(q))
+    aii = mix_width(a[idx], a[idx])
+    selfc = -2.0 * beta / math.sqrt(math.pi) + np.where(np.isinf(aii), 0.0,
+                                                         2.0 * np.where(np.isinf(aii), 0.0, aii)
+                                                         / math.sqrt(math.pi))
+    return u + selfc * q[idx]
+
+
+def rhs_factored(pos, a, ion_pos, ion_q, chi_volts, box, beta, rcut, kmax):
+    """b = chi - b_sol and Q_sol of ``rhs`` for one frame at the atoms ``pos``
+    (any subset of the electrode), with the ion structure factor from
+    ``structure_factor`` (large ion counts)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    ion_pos = np.asarray(ion_pos, dtype=np.float64)
+    ion_q = np.asarray(ion_q, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    a = np.broadcast_to(np.asarray(a, dtype=np.float64), (len(pos),))
+    vol = float(np.prod(box))
+    nv, _, w = kvectors(box, beta, kmax, half=True)
+    bsol = reciprocal_potential(pos, structure_factor(ion_pos, ion_q, box, nv), nv, w, box)
+    i, I, d = real_space_pairs(pos, ion_pos, box, rcut)
+    bsol += np.bincount(i, weights=ion_q[I] * _pair_potential_real(d, beta, a[i]),
+                        minlength=len(pos))
+    qsol = float(np.sum(ion_q))
+    bsol -= math.pi / (vol * beta * beta) * qsol
+    return np.asarray(chi_volts, dtype=np.float64) / K_E - bsol, qsol

@@ -412,3 +412,47 @@ def test_slab_correction_positive_definite_form(qsol):
     m1 = float(iq @ np.mod(ipos[:, 2], geo.box[2]))
     qs2 = cpm.solve(E0 + 4 * math.pi / vol * np.outer(z, z), b0 - 4 * math.pi / vol * m1 * z, qs)
     assert np.max(np.abs(qs2 - ql)) <= 1e-10 * np.max(np.abs(ql))
+
+
+# --- factored structure factor (exp(i K.r) as a product of per-axis factors)
+
+def test_structure_factor_matches_direct_sum():
+    """The structure factor of Eq. 23 from per-axis factor tables equals the
+    literal sum_j q_j exp(i K.r_j) over every k-vector of a box (positions
+    also outside [0, L), several particle chunks)."""
+    rng = np.random.default_rng(91)
+    box = np.array([13.0, 17.5, 31.0])
+    pos = rng.random((301, 3)) * box * 1.4 - 0.2 * box
+    q = rng.standard_normal(301)
+    n, K, _ = ew.kvectors(box, 0.3, ew.kmax_from_eps(0.3, 1e-6), half=True)
+    S = ew.structure_factor(pos, q, box, n, chunk=64)
+    direct = np.array([np.sum(q * np.exp(1j * (pos @ k))) for k in K])
+    assert np.max(np.abs(S - direct)) <= 1e-12 * np.max(np.abs(direct))
+    # and its back-projection sum_K w_K Re(exp(-i K.r) S_K) at other points
+    _, _, w = ew.kvectors(box, 0.3, ew.kmax_from_eps(0.3, 1e-6), half=True)
+    pts = rng.random((37, 3)) * box
+    back = ew.reciprocal_potential(pts, S, n, w, box, chunk=16)
+    lit = np.array([np.sum(w * (np.exp(-1j * (K @ r)) * direct).real) for r in pts])
+    assert np.max(np.abs(back - lit)) <= 1e-12 * np.max(np.abs(lit))
+
+
+def test_factored_potentials_and_rhs_match_direct_routines():
+    """At workload 1 the factored routines (used for workload 5 checks) give the
+    electrode potentials of ``potentials`` and the right-hand side of ``rhs``
+    at sampled atoms to 1e-12 of their scale."""
+    geo, ipos, iq, chi = wl.workload(1, frames=1)
+    rng = np.random.default_rng(92)
+    q = rng.standard_normal(geo.n)
+    q -= q.mean()
+    at = np.sort(rng.choice(geo.n, 20, replace=False))
+    p = (wl.EWALD_SPLIT, wl.RCUT, ew.kmax_from_eps(wl.EWALD_SPLIT, wl.KSPACE_EPS))
+    u = ew.potentials(geo.pos, wl.GAUSS_INV_WIDTH, q, geo.box, *p, at=at)
+    uf = ew.potentials_factored(geo.pos, wl.GAUSS_INV_WIDTH, q, geo.box, *p, at=at)
+    assert np.max(np.abs(uf - u)) <= 1e-12 * np.max(np.abs(u))
+    uall = ew.potentials(geo.pos, wl.GAUSS_INV_WIDTH, q, geo.box, *p)
+    ufall = ew.potentials_factored(geo.pos, wl.GAUSS_INV_WIDTH, q, geo.box, *p)
+    assert np.max(np.abs(ufall - uall)) <= 1e-12 * np.max(np.abs(uall))
+    b, qs = ew.rhs(geo.pos[at], wl.GAUSS_INV_WIDTH, ipos[0], iq[0], chi[at], geo.box, *p)
+    bf, qsf = ew.rhs_factored(geo.pos[at], wl.GAUSS_INV_WIDTH, ipos[0], iq[0], chi[at], geo.box, *p)
+    assert np.max(np.abs(bf - b)) <= 1e-12 * np.max(np.abs(b))
+    assert qsf == qs
