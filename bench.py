@@ -6,9 +6,11 @@ cpm_rhs (b = chi - b_sol for F electrolyte frames) followed by cpm_solve
 with E assembled once beforehand (its assembly is timed and reported
 separately as GFLOP/s). Inputs are resident in HBM before the timed region.
 
-Prints one JSON line. Default workload: two 3-layer AB-graphite electrodes,
-N = 4608 electrode atoms, 16 frames of 2000 random +-1 e ions, a = 1.979 /A,
-beta = 0.3 /A, rcut = 12 A, k-space accuracy 1e-6, 1 V.
+Prints one JSON line (progress on stderr). Default workload 5: two 4-layer
+AB-graphite electrodes, N = 131072 electrode atoms, 32 frames of 200000
+random +-1 e ions, a = 1.979 /A, beta = 0.3 /A, rcut = 12 A, k-space
+accuracy 1e-6 (482337 k-vectors), 1 V; E stored in FP64 (137 GB, the
+residual and the FP64 reference) and FP32 (69 GB, the inner solves).
 """
 from __future__ import annotations
 
@@ -47,6 +49,7 @@ def kernel_name(kind, ng):
     return (KERNEL_OF_KIND_WIDE if ng >= 2 else KERNEL_OF_KIND)[kind].format(ng=ng)
 CG_SOURCE = os.path.join(ROOT, "paper_2111_06704_amd", "csrc", "cg.hip")
 PROFILE_STRIDE = 5   # timed launches of the block product: every 5th (coprime to the check batches)
+MODE_STEPS = 5       # timed steps of every comparison mode (at most --steps)
 
 
 def log(*a):
@@ -58,7 +61,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--workload", type=int, default=5, choices=[1, 2, 3, 5])
     ap.add_argument("--tol", type=float, default=1e-11)
     ap.add_argument("--check-every", type=int, default=4,
                     help="iterations per device-side convergence check (all modes)")
@@ -66,23 +69,35 @@ def parse():
                     help="reliable-update factor of the FP32 / BF16 modes (default: "
                          "1e-4 for FP32 with PCG-DC at workload 2, 1e-3 otherwise)")
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
-    ap.add_argument("--warm", default="auto", choices=["auto", "zero", "chi", "mlp"])
+    ap.add_argument("--warm", default="mlp", choices=["zero", "chi", "mlp"])
     ap.add_argument("--precond", default="dc", choices=["jacobi", "dc"],
-                    help="preconditioner of the timed solves (the FP64 reference is plain CG)")
+                    help="preconditioner of the timed solves")
     ap.add_argument("--dc-g", type=float, default=0.15,
                     help="PCG-DC screening g (1/A); 0.15 with r_cut 7 from a sweep on workload 2 "
                          "(the paper: 0.083 with 8)")
     ap.add_argument("--dc-rcut", type=float, default=7.0, help="PCG-DC cutoff (A)")
-    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2111_06704_amd", "weights",
-                                                      "warmstart_cfg2.npz"))
+    ap.add_argument("--weights", default=None,
+                    help="warm-start network (default: the one for the workload's geometry)")
+    ap.add_argument("--kmax-override", type=float, default=0.0,
+                    help="K_max (1/A) instead of the 1e-6 accuracy rule (counter runs of the "
+                         "block products only: the reported step is then not the workload's)")
+    ap.add_argument("--mode-steps", type=int, default=MODE_STEPS,
+                    help="timed steps of each comparison mode")
+    ap.add_argument("--all-modes", action="store_true",
+                    help="also time the BF16 and Jacobi-preconditioned mixed modes")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the matrix-inversion, capacitance-matrix (GCD) and "
+                         "boundary-corrected paths (N <= 10000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--cpu-atoms", type=int, default=64,
+                    help="sampled atoms of the oracle's stationarity check (workloads 3 and 5)")
     ap.add_argument("--jitter", type=float, default=0.0,
                     help="displace every electrode atom by U(-a, a) A per component (genericity check)")
     ap.add_argument("--overlap", action=argparse.BooleanOptionalAction, default=False,
                     help="compute the right-hand side of the next step on a second stream "
                          "while the current step is solved (independent frames only: in MD "
                          "the next frame's ions depend on this step's charges)")
-    ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--traffic-record", default=None,
                     help="JSON written by --summarize-pmc (default: profiles/traffic_workload<W>.json)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
@@ -168,18 +183,23 @@ def traffic_bytes(record_path, kind, ng):
     return 1024.0 * (k["fetch_kib"] * c["fetch_factor"] + k["write_kib"] * c["write_factor"])
 
 
-def cpu_baseline(geo, ipos, iq, chi, nframes, q_gpu):
+
+
+def oracle_cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline_full(geo, ipos, iq, chi, nframes, q_gpu):
     """The FP64 oracle on the host: E and its Cholesky factor once, then per
     frame b and the two-step solve. Returns the baseline record and the
     charge error of the GPU result on the sampled frames."""
     from oracle import cpm as ocpm
     from oracle import ewald as ew
     from paper_2111_06704_amd import workloads as wl
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
     km = ew.kmax_from_eps(wl.EWALD_SPLIT, wl.KSPACE_EPS)
     t0 = time.perf_counter()
     E = ew.ewald_matrix(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, km)
@@ -188,18 +208,76 @@ def cpu_baseline(geo, ipos, iq, chi, nframes, q_gpu):
     t1 = time.perf_counter()
     b, qs = ew.rhs(geo.pos, wl.GAUSS_INV_WIDTH, ipos[:nframes], iq[:nframes], chi, geo.box,
                    wl.EWALD_SPLIT, wl.RCUT, km)
-    q = ocpm.two_step(fac, b, qs, d)
     t2 = time.perf_counter()
+    q = ocpm.two_step(fac, b, qs, d)
+    t3 = time.perf_counter()
     r2, rm = ocpm.rel_errors(q_gpu[:nframes], q)
-    rec = {"value": nframes / (t2 - t1), "unit": "solves/s", "cores": cores, "kind": "oracle",
+    rec = {"value": nframes / (t3 - t1), "unit": "solves/s", "cores": oracle_cores(),
+           "kind": "oracle",
            "sample": f"{nframes} frames of the same workload: b (direct Ewald) + Cholesky solve + "
                      f"two-step projection per frame; E assembly and its factorisation once "
                      f"({t1 - t0:.1f} s, not in the rate)",
            "setup_s": t1 - t0}
-    return rec, float(r2.max()), float(rm.max())
+    return rec, float(r2.max()), float(rm.max()), (t2 - t1) / nframes, (t3 - t2) / nframes
+
+
+def cpu_baseline_large(geo, ipos, iq, chi, q_gpu, b_gpu, natoms, nframes_w2):
+    """Workloads whose FP64 E does not fit a host factorisation (N = 32768:
+    8.6 GB and 2.6e14 flop to assemble; N = 131072: 137 GB, 1.7e16 flop).
+
+    Parity: the oracle evaluates, for frame 0 of the GPU result, (E q)_i
+    matrix-free and b_i by direct Ewald at sampled atoms; the constrained
+    minimum of Eq. 28 has E q - b uniform (Eq. 29), so the spread of
+    (E q)_i - b_i measures the solve error.
+    Rate: the oracle's per-frame work (b by direct Ewald, the Cholesky
+    two-step solve) timed on workload 2 and scaled by its operation counts,
+    (N + M) n_k for b and N^2 for the triangular solves: an extrapolation,
+    labelled as such."""
+    from oracle import ewald as ew
+    from paper_2111_06704_amd import workloads as wl
+    km = ew.kmax_from_eps(wl.EWALD_SPLIT, wl.KSPACE_EPS)
+    rng = np.random.default_rng(2024)
+    at = np.sort(rng.choice(geo.n, natoms, replace=False))
+    log(f"cpu leg: oracle stationarity of frame 0 at {natoms} sampled atoms")
+    t0 = time.perf_counter()
+    u = ew.potentials_factored(geo.pos, wl.GAUSS_INV_WIDTH, q_gpu[0], geo.box, wl.EWALD_SPLIT,
+                               wl.RCUT, km, at=at)
+    bo, qso = ew.rhs_factored(geo.pos[at], wl.GAUSS_INV_WIDTH, ipos[0], iq[0], chi[at], geo.box,
+                              wl.EWALD_SPLIT, wl.RCUT, km)
+    t_check = time.perf_counter() - t0
+    dev = u - bo
+    spread = float(np.max(np.abs(dev - dev.mean())))
+    bnorm = float(np.linalg.norm(b_gpu[0]))
+    parity = {"frame": 0, "atoms": natoms, "stationarity_spread": spread,
+              "stationarity_spread_over_b2": spread / bnorm,
+              "b_relmax_sampled": float(np.max(np.abs(b_gpu[0, at] - bo)) / np.max(np.abs(bo))),
+              "abs_sum_q_plus_qsol": float(abs(np.sum(q_gpu[0]) + qso)),
+              "check_s": t_check}
+    log(f"cpu leg: spread {spread:.3e} (|b|_2 {bnorm:.3e}) in {t_check:.1f} s; timing the oracle "
+        f"on workload 2")
+    geo2, ip2, iq2, chi2 = wl.workload(2, frames=nframes_w2)
+    rec2, _, _, tb2, ts2 = cpu_baseline_full(geo2, ip2, iq2, chi2, nframes_w2,
+                                             np.zeros((nframes_w2, geo2.n)))
+    nk = len(ew.kvectors(geo.box, wl.EWALD_SPLIT, km)[0])
+    nk2 = len(ew.kvectors(geo2.box, wl.EWALD_SPLIT, km)[0])
+    m, m2 = ipos.shape[1], ip2.shape[1]
+    fb = (geo.n + m) * nk / ((geo2.n + m2) * nk2)
+    fs = (geo.n / geo2.n) ** 2
+    t_frame = tb2 * fb + ts2 * fs
+    rec = {"value": 1.0 / t_frame, "unit": "solves/s", "cores": rec2["cores"], "kind": "oracle",
+           "extrapolated": True,
+           "sample": f"oracle timed on {nframes_w2} frames of workload 2 (b by direct Ewald "
+                     f"{tb2:.3f} s/frame, Cholesky two-step solve {ts2:.4f} s/frame, after "
+                     f"{rec2['setup_s']:.1f} s of E assembly and factorisation) and scaled to this "
+                     f"workload by (N + M) n_k (x{fb:.1f}) and N^2 (x{fs:.1f}); measured here: the "
+                     f"oracle's matrix-free stationarity check of 1 frame at {natoms} atoms "
+                     f"({t_check:.1f} s)",
+           "setup_s": rec2["setup_s"]}
+    return rec, parity
 
 
 def main():
+    t_start = time.perf_counter()
     args = parse()
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
@@ -209,8 +287,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (single-GPU build)")
         sys.exit(2)
+    # one line per assembled k chunk on stderr (workload 5 assembles for minutes)
+    os.environ.setdefault("CPM_PROGRESS", "1")
     import torch
-    from paper_2111_06704_amd import cpm, workloads as wl
+    from paper_2111_06704_amd import cpm, warmstart, workloads as wl
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -223,18 +303,20 @@ def main():
     nf, m = ipos.shape[0], ipos.shape[1]
     log(f"workload {cfg}: N={geo.n} frames={nf} ions={m}")
 
-    store = ("f32", "bf16") if cfg < 3 else (("f32",) if args.precision == "f32" else ("bf16",))
+    store = ("f32",)
+    if args.precision == "bf16" or (args.all_modes and cfg <= 3):
+        store = ("f32", "bf16")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, wl.KSPACE_EPS,
-                   store=store, profile_build=True)
+                   kmax_override=args.kmax_override, store=store, profile_build=True)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     prof_build = S.profile_read()[3]
     desc = S.describe()
     asm_gflops = prof_build["work"] / (prof_build["ms"] * 1e-3) / 1e9 if prof_build["ms"] > 0 else None
-    log(f"E built in {build_s:.3f} s; contraction {prof_build['ms']:.2f} ms, "
-        f"{asm_gflops:.1f} GFLOP/s; n_kvec={desc['n_kvec']}")
+    log(f"E built in {build_s:.1f} s; contraction {prof_build['ms']:.1f} ms, "
+        f"{asm_gflops:.1f} GFLOP/s; n_kvec={desc['n_kvec']}, device bytes {desc['device_bytes']}")
 
     t_ipos = torch.tensor(ipos, device=dev)
     t_iq = torch.tensor(iq, device=dev)
@@ -244,23 +326,22 @@ def main():
     q = torch.empty_like(b)
 
     prec = {"f64": cpm.PREC_F64, "f32": cpm.PREC_F32, "bf16": cpm.PREC_BF16}[args.precision]
-    warm = args.warm
-    if warm == "auto":
-        warm = "mlp" if (os.path.exists(args.weights) and cfg in (1, 2)) else "chi"
-    if warm == "chi":
-        S.set_warm_chi(t_chi)
-        wmode = cpm.WARM_CHI
-    elif warm == "mlp":
-        from paper_2111_06704_amd import warmstart
-        warmstart.load_into(S, geo, args.weights)
-        wmode = cpm.WARM_MLP
-    else:
-        wmode = cpm.WARM_ZERO
-
     pcmode = cpm.PRECOND_DC if args.precond == "dc" else cpm.PRECOND_JACOBI
-    precond_build_s = None
+    # PCG-DC is built in every run: the FP64 reference with the same
+    # preconditioner needs it, and d' is solved with it
+    t0 = time.perf_counter()
+    S.precond_dc(args.dc_g, args.dc_rcut)
+    precond_build_s = time.perf_counter() - t0
+    log(f"PCG-DC preconditioner built in {precond_build_s:.2f} s")
+    t0 = time.perf_counter()
+    S.set_warm_chi(t_chi, preconditioner=cpm.PRECOND_DC)
+    torch.cuda.synchronize()
+    log(f"d' and the q_chi start in {time.perf_counter() - t0:.2f} s")
+    weights = args.weights or warmstart.weights_for(cfg)
+    warmstart.load_into(S, geo, weights)
+    wmode = {"zero": cpm.WARM_ZERO, "chi": cpm.WARM_CHI, "mlp": cpm.WARM_MLP}[args.warm]
 
-    def inner_tol_for(precision, pcm=pcmode):
+    def inner_tol_for(precision, pcm):
         # reliable-update factor: 1e-4 for FP32 with PCG-DC at workload 2
         # (from a sweep: one true residual fewer at the same 32 iterations),
         # 1e-3 elsewhere (BF16, Jacobi and workload 3 need more iterations
@@ -268,16 +349,11 @@ def main():
         if args.inner_tol is not None:
             return args.inner_tol
         return 1e-4 if (precision == cpm.PREC_F32 and pcm == cpm.PRECOND_DC and cfg == 2) else 1e-3
-    if pcmode == cpm.PRECOND_DC:
-        t0 = time.perf_counter()
-        S.precond_dc(args.dc_g, args.dc_rcut)
-        precond_build_s = time.perf_counter() - t0
-        log(f"PCG-DC preconditioner built in {precond_build_s:.2f} s")
 
-    def solver(precision, wm, qout, pcm=pcmode):
+    def solver(precision, wm, qout, pcm):
         return lambda bb, qq: S.solve(bb, qq, tol=args.tol, precision=precision, warm_start=wm,
-                                      inner_tol=inner_tol_for(precision, pcm), check_every=args.check_every,
-                                      q_out=qout, preconditioner=pcm)
+                                      inner_tol=inner_tol_for(precision, pcm),
+                                      check_every=args.check_every, q_out=qout, preconditioner=pcm)
 
     # Steps: right-hand side of the batch, then its solve. With --overlap the
     # right-hand side of step k + 1 is computed on a second stream (default
@@ -298,13 +374,15 @@ def main():
             ev_rhs[k % 2].record(rhs_stream)
         S.set_stream()
 
-    def run_steps(n, solve_fn, overlap=None):
+    def run_steps(n, solve_fn, name=None):
         """n steps; returns the last solve's result."""
         last = None
-        if not (args.overlap if overlap is None else overlap):
-            for _ in range(n):
+        if not args.overlap:
+            for k in range(n):
                 S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
                 last = solve_fn(b, qsol)
+                if name and nf * geo.n > 1 << 22:
+                    log(f"  {name}: step {k + 1}/{n}, {last[1]['iterations']} iterations")
             return last
         enqueue_rhs(0)
         for k in range(n):
@@ -315,183 +393,68 @@ def main():
             ev_used[k % 2].record(main_stream)
         return last
 
-    def step(precision, wm, qout, pcm=pcmode):
-        return run_steps(1, solver(precision, wm, qout, pcm))
-
-    # reference: plain FP64 CG from zero at the same tolerance
-    q64 = torch.empty_like(b)
-    for _ in range(max(1, args.warmup)):
-        step(cpm.PREC_F64, cpm.WARM_ZERO, q64, cpm.PRECOND_JACOBI)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n64 = max(3, args.steps // 2)
-    _, st64 = run_steps(n64, solver(cpm.PREC_F64, cpm.WARM_ZERO, q64, cpm.PRECOND_JACOBI))
-    torch.cuda.synchronize()
-    fp64_ms = (time.perf_counter() - t0) / n64 * 1e3
-
-    # every precision mode once (same tolerance), for the record
-    modes = {}
-    mode_list = [("f64_zero", cpm.PREC_F64, cpm.WARM_ZERO, cpm.PRECOND_JACOBI),
-                 ("f32_zero", cpm.PREC_F32, cpm.WARM_ZERO, cpm.PRECOND_JACOBI),
-                 ("bf16_zero", cpm.PREC_BF16, cpm.WARM_ZERO, cpm.PRECOND_JACOBI),
-                 (f"f32_{warm}", cpm.PREC_F32, wmode, cpm.PRECOND_JACOBI),
-                 (f"bf16_{warm}", cpm.PREC_BF16, wmode, cpm.PRECOND_JACOBI)]
-    if pcmode == cpm.PRECOND_DC:
-        mode_list += [("f64_zero_dc", cpm.PREC_F64, cpm.WARM_ZERO, pcmode),
-                      ("f32_zero_dc", cpm.PREC_F32, cpm.WARM_ZERO, pcmode),
-                      (f"f32_{warm}_dc", cpm.PREC_F32, wmode, pcmode),
-                      (f"bf16_{warm}_dc", cpm.PREC_BF16, wmode, pcmode)]
-    # FP64 CG with one right-hand side per solve (up to 16 of the frames, one
-    # after another)
-    S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
-    q1 = torch.empty_like(b)
-    S.solve(b[:1], qsol[:1], tol=args.tol, precision=cpm.PREC_F64, q_out=q1[:1])
-    torch.cuda.synchronize()
-    tm = time.perf_counter()
-    its = []
-    nsingle = min(nf, 16)
-    for f in range(nsingle):
-        _, s1 = S.solve(b[f:f + 1], qsol[f:f + 1], tol=args.tol, precision=cpm.PREC_F64,
-                        check_every=args.check_every, q_out=q1[f:f + 1])
-        its.append(s1["iterations"])
-    torch.cuda.synchronize()
-    modes["f64_zero_single_rhs"] = {"solves_per_s": nsingle / (time.perf_counter() - tm),
-                                    "iterations": max(its), "true_residual_updates": None,
-                                    "initial_rel_resid": 1.0}
-    log("f64_zero_single_rhs", modes["f64_zero_single_rhs"])
-    for name, pm, wm, pcm in mode_list:
-        if (pm == cpm.PREC_F32 and "f32" not in store) or (pm == cpm.PREC_BF16 and "bf16" not in store):
-            continue
-        step(pm, wm, q, pcm)
-        torch.cuda.synchronize()
-        tm = time.perf_counter()
-        _, sm = step(pm, wm, q, pcm)
-        torch.cuda.synchronize()
-        modes[name] = {"solves_per_s": nf / (time.perf_counter() - tm), "iterations": sm["iterations"],
-                       "true_residual_updates": sm["outer"], "initial_rel_resid": sm["initial_rel_resid"]}
-        log(name, modes[name])
-
-    # matrix-inversion path (Sec. III.B.1 MI), the paper's choice for N < 1e4:
-    # S = E^-1 (I - 1 d^T) built once by the block solver, one product per step
-    mi = None
-    if geo.n <= 10000:
-        t0 = time.perf_counter()
-        S.mi_build(tol=1e-13, preconditioner=pcmode)
-        torch.cuda.synchronize()
-        mi_build_s = time.perf_counter() - t0
-        qmi = torch.empty_like(b)
-
-        mi_fn = lambda bb, qq: S.mi_solve(bb, qq, q_out=qmi)
-        run_steps(1, mi_fn)
-        torch.cuda.synchronize()
-        tm = time.perf_counter()
-        nmi = max(3, args.steps)
-        run_steps(nmi, mi_fn)
-        torch.cuda.synchronize()
-        mi_s = (time.perf_counter() - tm) / nmi
-        qm = qmi.cpu().numpy()
-        q64n = q64.cpu().numpy()
-        mi = {"solves_per_s": nf / mi_s, "ms_per_step": mi_s * 1e3, "build_s": mi_build_s,
-              "charge_rel_err_vs_fp64_gpu": float(np.max(np.linalg.norm(qm - q64n, axis=1)
-                                                         / np.linalg.norm(q64n, axis=1)))}
-        log("mi", mi)
-
-    # galvanostatic constraint (Supplementary Eq. S14-S24): C_E from the two
-    # electrode-indicator solves, then per step the charges under prescribed
-    # electrode totals, here the totals of the FP64 reference charges (so the
-    # constrained charges must come back equal to them)
-    gcd = None
-    if geo.n <= 10000:
-        labels = geo.electrode.astype(np.int32)
-        t0 = time.perf_counter()
-        cmat, cdet, cjoint, _ = S.gcd_build(labels, 2, tol=1e-12, precision=cpm.PREC_F64,
-                                            preconditioner=pcmode)
-        torch.cuda.synchronize()
-        gcd_build_s = time.perf_counter() - t0
-        q64n = q64.cpu().numpy()
-        qtot = torch.tensor(np.stack([q64n[:, labels == a].sum(axis=1) for a in range(2)], axis=1),
-                            device=dev)
-        qgcd = torch.empty_like(b)
-        dmu = torch.empty_like(qtot)
-        gcd_fn = lambda bb, qq: S.gcd_solve(bb, qtot, tol=args.tol, precision=prec,
-                                            preconditioner=pcmode, check_every=args.check_every,
-                                            inner_tol=inner_tol_for(prec), q_out=qgcd, dmu_out=dmu)
-        run_steps(1, gcd_fn)
-        torch.cuda.synchronize()
-        tm = time.perf_counter()
-        ngcd = max(3, args.steps)
-        _, _, gst = run_steps(ngcd, gcd_fn)
-        torch.cuda.synchronize()
-        gcd_s = (time.perf_counter() - tm) / ngcd
-        qgn = qgcd.cpu().numpy()
-        gcd = {"solves_per_s": nf / gcd_s, "ms_per_step": gcd_s * 1e3, "build_s": gcd_build_s,
-               "iterations": gst["iterations"], "max_abs_total_err": gst["max_abs_sum_q"],
-               "capacitance_matrix_e_per_V": (cmat / K_E).tolist(),
-               "joint_capacitance_e_per_V": cjoint / K_E,
-               "charge_rel_err_vs_fp64_gpu": float(np.max(np.linalg.norm(qgn - q64n, axis=1)
-                                                          / np.linalg.norm(q64n, axis=1)))}
-        log("gcd", gcd)
-
-    # boundary correction of Eq. 39 (slab geometry): its own E, the bench's
-    # precision and PCG-DC, zero start
-    slab = None
-    if geo.n <= 10000 and "f32" in store:
-        t0 = time.perf_counter()
-        S2 = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT,
-                        wl.KSPACE_EPS, store=("f32",), slab=True)
-        if pcmode == cpm.PRECOND_DC:
-            S2.precond_dc(args.dc_g, args.dc_rcut)
-        torch.cuda.synchronize()
-        slab_build_s = time.perf_counter() - t0
-        b2 = torch.empty_like(b)
-        qs2 = torch.empty_like(qsol)
-        q2 = torch.empty_like(b)
-
-        def slab_step():
-            S2.rhs(t_ipos, t_iq, t_chi, b_out=b2, qsol_out=qs2)
-            return S2.solve(b2, qs2, tol=args.tol, precision=cpm.PREC_F32, warm_start=cpm.WARM_ZERO,
-                            inner_tol=inner_tol_for(cpm.PREC_F32), check_every=args.check_every, q_out=q2,
-                            preconditioner=pcmode)
-
-        slab_step()
-        torch.cuda.synchronize()
-        tm = time.perf_counter()
-        nsl = max(3, args.steps)
-        for _ in range(nsl):
-            _, sst = slab_step()
-        torch.cuda.synchronize()
-        slab_s = (time.perf_counter() - tm) / nsl
-        slab = {"solves_per_s": nf / slab_s, "ms_per_step": slab_s * 1e3, "build_s": slab_build_s,
-                "precision": "f32+f64", "warm_start": "zero", "iterations": sst["iterations"],
-                "max_rel_resid": sst["max_rel_resid"], "max_abs_sum_q": sst["max_abs_sum_q"]}
-        log("slab", slab)
-        S2.close()
-        del S2
-
-    for _ in range(args.warmup):
-        step(prec, wmode, q)
+    hname = f"{args.precision}_{args.precond}_{args.warm}"
+    log(f"headline mode {hname}: {args.warmup} warm-up + {args.steps} timed steps")
+    run_steps(max(1, args.warmup), solver(prec, wmode, q, pcmode), "warm-up")
     torch.cuda.synchronize()
     # every PROFILE_STRIDE-th launch of the block product is bracketed with HIP
     # events (the bracketing launch costs the host ~10 us more than a plain one)
     S.profile_enable(True, stride=PROFILE_STRIDE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, st = run_steps(args.steps, solver(prec, wmode, q))
+    _, st = run_steps(args.steps, solver(prec, wmode, q, pcmode), hname)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = S.profile_read()
     S.profile_enable(False)
     ms_per_step = elapsed / args.steps * 1e3
     value = nf * args.steps / elapsed
-    # the same steps with the right-hand side of step k + 1 overlapped with
-    # the solve of step k (for independent frames), for the record
-    run_steps(2, solver(prec, wmode, q), overlap=not args.overlap)
+    log(f"headline: {value:.2f} solves/s, {st['iterations']} iterations")
+
+    # the right-hand side alone (the same in every mode)
+    nrhs = max(1, min(args.steps, args.mode_steps))
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    run_steps(args.steps, solver(prec, wmode, q), overlap=not args.overlap)
+    t0 = time.perf_counter()
+    for _ in range(nrhs):
+        S.rhs(t_ipos, t_iq, t_chi, b_out=b, qsol_out=qsol)
     torch.cuda.synchronize()
-    other = {"overlap_rhs": not args.overlap,
-             "solves_per_s": nf * args.steps / (time.perf_counter() - t1)}
+    rhs_ms = (time.perf_counter() - t0) / nrhs * 1e3
+
+    # comparison modes, each timed over the same number of steps
+    nmode = max(1, min(args.steps, args.mode_steps))
+    q64 = torch.empty_like(b)
+    mode_list = [("f64_jacobi_zero", cpm.PREC_F64, cpm.WARM_ZERO, cpm.PRECOND_JACOBI, q64),
+                 ("f64_dc_zero", cpm.PREC_F64, cpm.WARM_ZERO, cpm.PRECOND_DC, None),
+                 ("f32_dc_zero", cpm.PREC_F32, cpm.WARM_ZERO, cpm.PRECOND_DC, None),
+                 ("f32_dc_chi", cpm.PREC_F32, cpm.WARM_CHI, cpm.PRECOND_DC, None)]
+    if args.all_modes:
+        mode_list += [("f32_jacobi_zero", cpm.PREC_F32, cpm.WARM_ZERO, cpm.PRECOND_JACOBI, None),
+                      ("f32_jacobi_mlp", cpm.PREC_F32, cpm.WARM_MLP, cpm.PRECOND_JACOBI, None),
+                      ("f32_dc_mlp_again", cpm.PREC_F32, cpm.WARM_MLP, cpm.PRECOND_DC, None)]
+        if "bf16" in store:
+            mode_list += [("bf16_dc_zero", cpm.PREC_BF16, cpm.WARM_ZERO, cpm.PRECOND_DC, None),
+                          ("bf16_dc_mlp", cpm.PREC_BF16, cpm.WARM_MLP, cpm.PRECOND_DC, None)]
+    modes = {}
+    qm = torch.empty_like(b)
+    for name, pm, wm, pcm, qout in mode_list:
+        log(f"mode {name}: {nmode} timed steps")
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        _, sm = run_steps(nmode, solver(pm, wm, qout if qout is not None else qm, pcm), name)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - tm) / nmode
+        modes[name] = {"solves_per_s": nf / dt, "ms_per_step": dt * 1e3,
+                       "solve_only_solves_per_s": nf / (dt - rhs_ms * 1e-3),
+                       "iterations": sm["iterations"], "true_residual_updates": sm["outer"],
+                       "initial_rel_resid": sm["initial_rel_resid"], "steps": nmode}
+        log(name, modes[name])
+    fp64 = modes["f64_jacobi_zero"]
+    fp64dc = modes["f64_dc_zero"]
+
+    extras = {}
+    if args.extras and geo.n <= 10000:
+        extras = run_extras(S, cpm, wl, geo, args, b, qsol, q64, dev, t_ipos, t_iq, t_chi, nf,
+                            prec, pcmode, inner_tol_for, run_steps)
 
     # dominant kernel of the timed region: the block matrix product with the most time
     kinds = ["matvec_f64", "matvec_f32", "matvec_bf16"]
@@ -530,8 +493,8 @@ def main():
 
     qg = q.cpu().numpy()
     q64g = q64.cpu().numpy()
+    bg = b.cpu().numpy()
     rel_vs_fp64 = float(np.max(np.linalg.norm(qg - q64g, axis=1) / np.linalg.norm(q64g, axis=1)))
-
     out = {
         "metric": "charge solves/sec to 1e-8 rel (mixed+warm vs FP64 CG); E-assembly GFLOP/s",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -545,29 +508,133 @@ def main():
                    "n_kvec": desc["n_kvec"], "tol": args.tol, "check_every": args.check_every,
                    "inner_tol": inner_tol_for(prec, pcmode), "precision": args.precision,
                    "overlap_rhs": bool(args.overlap), "jitter_A": args.jitter,
-                   "warm_start": warm, "preconditioner": args.precond,
-                   "dc_g": args.dc_g if args.precond == "dc" else None,
-                   "dc_rcut": args.dc_rcut if args.precond == "dc" else None},
-        "fp64_cg_solves_per_s": nf / (fp64_ms * 1e-3),
-        "fp64_cg_iterations": st64["iterations"],
-        "speedup_vs_fp64_cg": value / (nf / (fp64_ms * 1e-3)),
+                   "warm_start": args.warm, "warm_start_weights": os.path.basename(weights),
+                   "preconditioner": args.precond, "dc_g": args.dc_g, "dc_rcut": args.dc_rcut,
+                   "kmax_override": args.kmax_override or None,
+                   "E_stored": ["f64"] + list(store), "device_bytes": desc["device_bytes"]},
+        "fp64_cg_solves_per_s": fp64["solves_per_s"],
+        "fp64_cg_iterations": fp64["iterations"],
+        "speedup_vs_fp64_cg": value / fp64["solves_per_s"],
+        "fp64_pcgdc_solves_per_s": fp64dc["solves_per_s"],
+        "fp64_pcgdc_iterations": fp64dc["iterations"],
+        "speedup_vs_fp64_pcgdc": value / fp64dc["solves_per_s"],
+        "rhs_ms_per_step": rhs_ms,
+        "solve_only_solves_per_s": nf / (ms_per_step * 1e-3 - rhs_ms * 1e-3),
         "iterations": st["iterations"], "true_residual_updates": st["outer"], "modes": modes,
-        "other_schedule": other,
         "initial_rel_resid": st["initial_rel_resid"], "max_rel_resid": st["max_rel_resid"],
         "max_abs_sum_q": st["max_abs_sum_q"],
         "charge_rel_err_vs_fp64_gpu": rel_vs_fp64,
         "e_assembly_gflops": asm_gflops, "e_assembly_ms": prof_build["ms"],
         "e_assembly_frac_fp64_peak": (asm_gflops / 1e3 / FP64_PEAK_TFLOPS) if asm_gflops else None,
-        "e_build_s": build_s, "precond_build_s": precond_build_s, "matrix_inversion": mi,
-        "gcd": gcd, "slab_correction": slab,
+        "e_build_s": build_s, "precond_build_s": precond_build_s,
         "roofline": roofline,
     }
+    out.update(extras)
     if not args.no_cpu_baseline:
-        rec, r2, rm = cpu_baseline(geo, ipos, iq, chi, args.cpu_frames, qg)
-        out["cpu_baseline"] = rec
-        out["charge_rel2_vs_oracle"] = r2
-        out["charge_relmax_vs_oracle"] = rm
+        if geo.n <= 10000:
+            rec, r2, rm, _, _ = cpu_baseline_full(geo, ipos, iq, chi, args.cpu_frames, qg)
+            out["cpu_baseline"] = rec
+            out["charge_rel2_vs_oracle"] = r2
+            out["charge_relmax_vs_oracle"] = rm
+        elif not args.kmax_override:
+            rec, parity = cpu_baseline_large(geo, ipos, iq, chi, qg, bg, args.cpu_atoms,
+                                             args.cpu_frames)
+            out["cpu_baseline"] = rec
+            out["oracle_stationarity"] = parity
+    out["wall_s"] = time.perf_counter() - t_start
     print(json.dumps(out))
+
+
+def run_extras(S, cpm, wl, geo, args, b, qsol, q64, dev, t_ipos, t_iq, t_chi, nf, prec, pcmode,
+               inner_tol_for, run_steps):
+    """Matrix inversion (Sec. III.B.1), the capacitance matrix with prescribed
+    electrode totals (Supplementary Eq. S14-S24) and the boundary-corrected
+    path (Eq. 39), each timed over --mode-steps steps (N <= 10000 only)."""
+    import torch
+    out = {}
+    nst = max(3, args.mode_steps)
+    q64n = q64.cpu().numpy()
+    # matrix-inversion path, the paper's choice for N < 1e4: S = E^-1 (I - 1 d^T)
+    # built once by the block solver, one product per step
+    t0 = time.perf_counter()
+    S.mi_build(tol=1e-13, preconditioner=pcmode)
+    torch.cuda.synchronize()
+    mi_build_s = time.perf_counter() - t0
+    qmi = torch.empty_like(b)
+    mi_fn = lambda bb, qq: S.mi_solve(bb, qq, q_out=qmi)
+    run_steps(1, mi_fn)
+    torch.cuda.synchronize()
+    tm = time.perf_counter()
+    run_steps(nst, mi_fn)
+    torch.cuda.synchronize()
+    mi_s = (time.perf_counter() - tm) / nst
+    qm = qmi.cpu().numpy()
+    out["matrix_inversion"] = {
+        "solves_per_s": nf / mi_s, "ms_per_step": mi_s * 1e3, "build_s": mi_build_s,
+        "charge_rel_err_vs_fp64_gpu": float(np.max(np.linalg.norm(qm - q64n, axis=1)
+                                                   / np.linalg.norm(q64n, axis=1)))}
+    log("mi", out["matrix_inversion"])
+    # galvanostatic constraint: C_E from the electrode-indicator solves, then
+    # per step the charges under prescribed electrode totals (here the totals
+    # of the FP64 reference charges, so they must come back equal to them)
+    labels = geo.electrode.astype(np.int32)
+    t0 = time.perf_counter()
+    cmat, cdet, cjoint, _ = S.gcd_build(labels, 2, tol=1e-12, precision=cpm.PREC_F64,
+                                        preconditioner=pcmode)
+    torch.cuda.synchronize()
+    gcd_build_s = time.perf_counter() - t0
+    qtot = torch.tensor(np.stack([q64n[:, labels == a].sum(axis=1) for a in range(2)], axis=1),
+                        device=dev)
+    qgcd = torch.empty_like(b)
+    dmu = torch.empty_like(qtot)
+    gcd_fn = lambda bb, qq: S.gcd_solve(bb, qtot, tol=args.tol, precision=prec,
+                                        preconditioner=pcmode, check_every=args.check_every,
+                                        inner_tol=inner_tol_for(prec, pcmode), q_out=qgcd,
+                                        dmu_out=dmu)
+    run_steps(1, gcd_fn)
+    torch.cuda.synchronize()
+    tm = time.perf_counter()
+    _, _, gst = run_steps(nst, gcd_fn)
+    torch.cuda.synchronize()
+    gcd_s = (time.perf_counter() - tm) / nst
+    qgn = qgcd.cpu().numpy()
+    out["gcd"] = {"solves_per_s": nf / gcd_s, "ms_per_step": gcd_s * 1e3, "build_s": gcd_build_s,
+                  "iterations": gst["iterations"], "max_abs_total_err": gst["max_abs_sum_q"],
+                  "capacitance_matrix_e_per_V": (cmat / K_E).tolist(),
+                  "joint_capacitance_e_per_V": cjoint / K_E,
+                  "charge_rel_err_vs_fp64_gpu": float(np.max(np.linalg.norm(qgn - q64n, axis=1)
+                                                             / np.linalg.norm(q64n, axis=1)))}
+    log("gcd", out["gcd"])
+    # boundary correction of Eq. 39 (slab geometry): its own E, FP32 + PCG-DC
+    t0 = time.perf_counter()
+    S2 = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT,
+                    wl.KSPACE_EPS, store=("f32",), slab=True)
+    S2.precond_dc(args.dc_g, args.dc_rcut)
+    torch.cuda.synchronize()
+    slab_build_s = time.perf_counter() - t0
+    b2, qs2, q2 = torch.empty_like(b), torch.empty_like(qsol), torch.empty_like(b)
+
+    def slab_step():
+        S2.rhs(t_ipos, t_iq, t_chi, b_out=b2, qsol_out=qs2)
+        return S2.solve(b2, qs2, tol=args.tol, precision=cpm.PREC_F32, warm_start=cpm.WARM_ZERO,
+                        inner_tol=inner_tol_for(cpm.PREC_F32, cpm.PRECOND_DC),
+                        check_every=args.check_every, q_out=q2, preconditioner=cpm.PRECOND_DC)
+
+    slab_step()
+    torch.cuda.synchronize()
+    tm = time.perf_counter()
+    for _ in range(nst):
+        _, sst = slab_step()
+    torch.cuda.synchronize()
+    slab_s = (time.perf_counter() - tm) / nst
+    out["slab_correction"] = {"solves_per_s": nf / slab_s, "ms_per_step": slab_s * 1e3,
+                              "build_s": slab_build_s, "precision": "f32+f64",
+                              "warm_start": "zero", "iterations": sst["iterations"],
+                              "max_rel_resid": sst["max_rel_resid"],
+                              "max_abs_sum_q": sst["max_abs_sum_q"]}
+    log("slab", out["slab_correction"])
+    S2.close()
+    return out
 
 
 if __name__ == "__main__":
