@@ -344,11 +344,15 @@ def main():
     def inner_tol_for(precision, pcm):
         # reliable-update factor: 1e-4 for FP32 with PCG-DC at workload 2
         # (from a sweep: one true residual fewer at the same 32 iterations),
-        # 1e-3 elsewhere (BF16, Jacobi and workload 3 need more iterations
-        # at 1e-4)
+        # 1e-2 at workload 5 (a sweep of 1e-1 .. 1e-5: 88 iterations at 1e-2,
+        # 96 at 1e-3, 116 at 1e-4, 252 at 1e-5; the FP32 recursion drifts
+        # from the true residual over long stretches), 1e-3 elsewhere (BF16,
+        # Jacobi and workload 3 need more iterations at 1e-4)
         if args.inner_tol is not None:
             return args.inner_tol
-        return 1e-4 if (precision == cpm.PREC_F32 and pcm == cpm.PRECOND_DC and cfg == 2) else 1e-3
+        if precision == cpm.PREC_F32 and pcm == cpm.PRECOND_DC and cfg == 2:
+            return 1e-4
+        return 1e-2 if cfg == 5 else 1e-3
 
     def solver(precision, wm, qout, pcm):
         return lambda bb, qq: S.solve(bb, qq, tol=args.tol, precision=precision, warm_start=wm,
