@@ -238,6 +238,22 @@ def ewald_matrix(pos, box, a, beta, rcut, kmax, slab=False):
     return E
 
 
+def ewald_matrix_point_self(pos, box, a, beta, rcut, kmax, slab=False):
+    """The point-charge simplification of Sec. III.C: the electrode charges
+    interact as classic point charges (the matrix of Eq. 15, i.e. Eq. 22
+    without its erfc(a_ij d) screening terms, which for graphene at a^0 are
+    below 3.2e-5 of the pair term, last column of Table 1), and each keeps
+    the non-singular self-energy sqrt(2/pi) a_i of a Gaussian charge on the
+    diagonal (U^GRA = sqrt(2/pi) a^0). The electrolyte acts on them as
+    point charges too: ``electrolyte_potential`` / ``rhs`` with a = inf."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = len(pos)
+    a = np.broadcast_to(np.asarray(a, dtype=np.float64), (n,))
+    E = ewald_matrix(pos, box, np.inf, beta, rcut, kmax, slab)
+    E[np.arange(n), np.arange(n)] += math.sqrt(2.0 / math.pi) * a
+    return E
+
+
 def electrolyte_potential(pos, a, ion_pos, ion_q, box, beta, rcut, kmax, slab=False):
     """b_sol,i = sum_I q_I e_iI(a_i) (Eq. 25).
 

@@ -456,3 +456,60 @@ def test_factored_potentials_and_rhs_match_direct_routines():
     bf, qsf = ew.rhs_factored(geo.pos[at], wl.GAUSS_INV_WIDTH, ipos[0], iq[0], chi[at], geo.box, *p)
     assert np.max(np.abs(bf - b)) <= 1e-12 * np.max(np.abs(b))
     assert qsf == qs
+
+
+# --- point-charge simplification with the Gaussian self-energy (Sec. III.C)
+
+@pytest.mark.parametrize("slab", [False, True])
+def test_point_charge_simplification_capacitor(slab):
+    """Point charges on graphene plus the self-energy sqrt(2/pi) a^0: the lattice
+    term of the capacitor, delta = sqrt(2/pi) a^0 - U^GRA / R (no screening
+    sum for point charges), vanishes exactly at a^0 (Table 1: U^GRA =
+    sqrt(2/pi) a^0 R / R), so each sheet carries the continuum charge:
+    eps0 dV (1/d1 + 1/d2) per area under 3D periodicity, eps0 dV / d1 with
+    the correction of Eq. 39."""
+    geo = wl.geometry(1)
+    b, rc, km = _params(0.3, 1e-12)
+    a0 = GOLD["gra_alpha0"]["value"]
+    R = GOLD["gra_bond"]["value"]
+    assert abs(math.sqrt(2 / math.pi) * a0 - GOLD["lattice_2d_unit_bond"]["gra"] / R) < 1e-12
+    E = ew.ewald_matrix_point_self(geo.pos, geo.box, a0, b, rc, km, slab=slab)
+    bvec = wl.electrode_potential(geo) / ew.K_E
+    q, _ = cpm.bordered(E, bvec, 0.0)
+    na = int(np.sum(geo.electrode == 0))
+    qa = q[:na]
+    assert np.ptp(qa) / abs(qa.mean()) < 1e-9 and abs(qa.mean() + q[na:].mean()) < 1e-15
+    eps0 = 1.0 / (4 * math.pi * ew.K_E)          # e / (V A)
+    lz, d1, d2 = geo.box[2], 40.0, 20.0
+    q_cont = eps0 * (1 / d1 if slab else (1 / d1 + 1 / d2)) / geo.sheet_density
+    assert abs(qa.mean() / q_cont - 1) < 1e-9
+
+
+def test_point_charge_simplification_is_unscreened_gaussian_matrix():
+    """The simplified matrix equals the Gaussian matrix of Eq. 22 plus the
+    screening terms sum_images erfc(a_ij d) / d that the point charges drop
+    (the literal entries of both), and equals the classic point-charge matrix
+    (a = inf) plus sqrt(2/pi) a_i on the diagonal."""
+    rng = np.random.default_rng(23)
+    box = np.array([6.0, 7.0, 8.0])
+    pos = rng.random((5, 3)) * box
+    a = rng.uniform(1.5, 3.0, 5)
+    p = _params(0.7, 1e-13)
+    Es = ew.ewald_matrix_point_self(pos, box, a, *p)
+    for i in range(5):
+        for j in range(5):
+            lit_g = ew.ewald_entry_literal(pos[i], pos[j], box, a[i], a[j], *p, same_atom=(i == j))
+            lit_p = ew.ewald_entry_literal(pos[i], pos[j], box, np.inf, np.inf, *p, same_atom=(i == j))
+            aij = 1.0 / math.sqrt(1 / a[i] ** 2 + 1 / a[j] ** 2)
+            screen = 0.0
+            for sx in range(-3, 4):
+                for sy in range(-3, 4):
+                    for sz in range(-3, 4):
+                        if i == j and sx == sy == sz == 0:
+                            continue
+                        d = np.linalg.norm(pos[i] - pos[j] + np.array([sx, sy, sz]) * box)
+                        if d < p[1]:
+                            screen += erfc(aij * d) / d
+            self_e = math.sqrt(2 / math.pi) * a[i] if i == j else 0.0
+            assert abs(Es[i, j] - (lit_p + self_e)) < 1e-12
+            assert abs(Es[i, j] - (lit_g + screen)) < 1e-11
