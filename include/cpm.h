@@ -82,6 +82,13 @@ typedef struct {
      charges of the Eq. 39 system (they differ from it only by multiples of
      1 on the right-hand side and by terms that vanish for sum q = -Q_sol). */
   int slab_correction;
+  /* 1: the point-charge simplification of Sec. III.C: electrode charges
+     interact with each other and with the ions as classic point charges
+     (the erfc(a d) screening terms of Eq. 22 and 25 are dropped) and keep
+     the Gaussian self-energy sqrt(2/pi) a_i on the diagonal of E (for
+     graphene, a_i = a^0 = 2.93295 /A makes it the lattice potential gap
+     U^GRA). Needs finite a_i. The PCG-DC matrices keep their Eq. 36 form. */
+  int point_charge_self;
 } cpm_params;
 
 /* Assemble E for n electrode atoms. The neutralising vector d' = E^-1 1
@@ -160,7 +167,8 @@ typedef struct {
   double warm_ms;      /* GPU time of the warm start (network, shifts and the FP64
                           residual of the start), from HIP events               */
   double solve_ms;     /* wall time of the whole call                              */
-  int fell_back;       /* 1 if the warm start was rejected (|r0| >= |b|)           */
+  int fell_back;       /* 1 if the warm start of some frame was rejected (it did not
+                          lower the energy x.E x / 2 - x.b below zero's)         */
   /* optional per-frame outputs (host arrays of length f, may be NULL) */
   int *frame_iters;
   double *frame_rel_resid;
@@ -275,8 +283,9 @@ cpm_status cpm_matvec(cpm_system *s, int precision, const double *p_dev, int64_t
  * minimum image; distances and angles are compared after rounding to 1e-6.
  * The prediction is shifted to sum(q0) = -Q_sol, and the CG start is
  * q_b0 = q0 + mu0 d' with mu0 = mean(b - E q0) (the Lagrange shift of
- * Eq. 29-31). A start whose residual is not below |b| is discarded (zero
- * start). Feature layout per atom: [b_i - mean, layer/(L-1),
+ * Eq. 29-31). A start that does not lower the energy x.E x / 2 - x.b below
+ * that of x = 0 (equivalently: whose E-norm error, the norm CG reduces, is
+ * not below the zero start's) is discarded (zero start). Feature layout per atom: [b_i - mean, layer/(L-1),
  * 12 x (b_j - mean), 12 x r_ij], with b scaled by 1/b_scale and r by 1/r_scale;
  * the output is multiplied by q_scale. */
 #define CPM_MLP_IN 26
@@ -332,6 +341,17 @@ cpm_status cpm_mlp_train_epoch(cpm_system *s, const double *b_dev, const double 
 /* Precompute q_chi, the neutral solution without electrolyte (b = chi / k_e,
    Q_sol = 0), used by CPM_WARM_CHI. chi_dev (n,) volts; opts as cpm_solve. */
 cpm_status cpm_set_warm_chi(cpm_system *s, const double *chi_dev, const cpm_solve_opts *opts);
+
+/* The CG start cpm_solve takes for warm_start (CPM_WARM_CHI or CPM_WARM_MLP)
+   and f frames of b (device, (f, n)) and Q_sol (device, (f,)), before its
+   acceptance test: x0_out_dev (f, n) = q0 + mu0 d' with q0 the network's
+   prediction (times q_scale) or q_chi, shifted to sum(q0) = -Q_sol, and
+   mu0 = mean(b - E q0) (Eq. 29-31); r0_out_dev (f, n) = b - E x0 in FP64.
+   The same kernels as cpm_solve (inspection and tests).
+   Errors: CPM_EINVAL, CPM_ESTATE (network or q_chi not set), d' errors. */
+cpm_status cpm_warm_start(cpm_system *s, int warm_start, const double *b_dev,
+                          const double *qsol_dev, int64_t f, double *x0_out_dev,
+                          double *r0_out_dev);
 
 /* ---- live kernel timing ----------------------------------------------------
  * While enabled, the library brackets launches of the block matrix product

@@ -25,10 +25,12 @@ MLP_IN, MLP_HIDDEN = 26, 64
 MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 
 EXPORTS = [
-    "cpm_build_E", "cpm_free", "cpm_set_stream", "cpm_describe", "cpm_rhs", "cpm_solve",
+    "cpm_build_E", "cpm_free", "cpm_set_stream", "cpm_describe", "cpm_rhs",
+    "cpm_solve",
     "cpm_get_E", "cpm_get_E_block", "cpm_get_dprime", "cpm_matvec", "cpm_mlp_init", "cpm_mlp_neighbours",
     "cpm_mlp_set_params", "cpm_mlp_get_params", "cpm_mlp_features", "cpm_mlp_forward",
     "cpm_mlp_loss_grad", "cpm_mlp_train_step", "cpm_mlp_train_epoch", "cpm_set_warm_chi",
+    "cpm_warm_start",
     "cpm_profile_enable", "cpm_profile_read", "cpm_precond_dc", "cpm_precond_apply",
     "cpm_mi_build", "cpm_mi_solve", "cpm_gcd_build", "cpm_gcd_solve",
     "cpm_status_str", "cpm_last_error",
@@ -46,7 +48,7 @@ class Params(C.Structure):
     _fields_ = [("gauss_inv_width", C.c_double), ("gauss_inv_width_per_atom", C.POINTER(C.c_double)),
                 ("ewald_split", C.c_double), ("rcut", C.c_double), ("kspace_eps", C.c_double),
                 ("kmax_override", C.c_double), ("store_mask", C.c_uint),
-                ("slab_correction", C.c_int)]
+                ("slab_correction", C.c_int), ("point_charge_self", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -99,6 +101,7 @@ def lib():
     L.cpm_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, f32, f32, f32, C.POINTER(dbl)]
     L.cpm_mlp_train_epoch.argtypes = [vp, vp, vp, i64, vp, i64, f32, f32, f32, f32, C.POINTER(dbl)]
     L.cpm_set_warm_chi.argtypes = [vp, vp, C.POINTER(SolveOpts)]
+    L.cpm_warm_start.argtypes = [vp, C.c_int, vp, vp, i64, vp, vp]
     L.cpm_gcd_build.argtypes = [vp, vp, C.c_int32, C.POINTER(SolveOpts), vp, C.POINTER(dbl),
                                 C.POINTER(dbl), C.POINTER(SolveInfo)]
     L.cpm_gcd_solve.argtypes = [vp, vp, vp, i64, C.POINTER(SolveOpts), vp, vp,
@@ -146,7 +149,7 @@ class System:
 
     def __init__(self, pos, box, gauss_inv_width=1.979, ewald_split=0.3, rcut=12.0,
                  kspace_eps=1e-6, kmax_override=0.0, store=(), per_atom_width=None,
-                 profile_build=False, slab=False):
+                 profile_build=False, slab=False, point_charge_self=False):
         L = lib()
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         box = np.ascontiguousarray(box, dtype=np.float64)
@@ -166,6 +169,7 @@ class System:
             mask |= {"f32": STORE_F32, "bf16": STORE_BF16}[s]
         p.store_mask = mask | (PROFILE_BUILD if profile_build else 0)
         p.slab_correction = 1 if slab else 0
+        p.point_charge_self = 1 if point_charge_self else 0
         self.store = tuple(store)
         h = C.c_void_p()
         st = L.cpm_build_E(pos.ctypes.data, self.n, box.ctypes.data, C.byref(p), _stream(), C.byref(h))
@@ -363,6 +367,17 @@ class System:
         o = SolveOpts(tol=tol, max_iter=max_iter, precision=PREC_F64, warm_start=WARM_ZERO,
                       inner_tol=1e-3, check_every=8, preconditioner=preconditioner)
         _check(lib().cpm_set_warm_chi(self._h, _ptr(chi, torch.float64), C.byref(o)), "cpm_set_warm_chi")
+
+    def warm_start(self, b, qsol, warm_start=WARM_MLP):
+        """The solver's start x0 (F, N) and its FP64 residual r0 = b - E x0."""
+        import torch
+        x0 = torch.empty_like(b)
+        r0 = torch.empty_like(b)
+        _check(lib().cpm_warm_start(self._h, int(warm_start), _ptr(b, torch.float64),
+                                    _ptr(qsol, torch.float64), int(b.shape[0]),
+                                    _ptr(x0, torch.float64), _ptr(r0, torch.float64)),
+               "cpm_warm_start")
+        return x0, r0
 
     # ---- learned warm start
     def mlp_init(self, layer, n_layers, b_scale, r_scale, q_scale):

@@ -138,6 +138,7 @@ void free_system(cpm_system *s) {
                   s->mlp.feat, s->mlp.yout};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  if (s->rs_width && s->rs_width != s->width) (void)hipFree(s->rs_width);
   for (hipEvent_t e : s->warm_ev)
     if (e) (void)hipEventDestroy(e);
   release_workspace(s);
@@ -217,11 +218,16 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
     return CPM_EINVAL;
   }
   std::vector<double> width(n);
+  const bool point_self = params->point_charge_self != 0;
   for (int64_t i = 0; i < n; ++i) {
     const double a = params->gauss_inv_width_per_atom ? params->gauss_inv_width_per_atom[i]
                                                       : params->gauss_inv_width;
     if (!(a > 0.0) || std::isnan(a)) {   // +inf is a point charge
       set_error("Gaussian inverse widths must be > 0 (inf = point charge)");
+      return CPM_EINVAL;
+    }
+    if (point_self && !std::isfinite(a)) {
+      set_error("point_charge_self needs finite widths (they set the self-energy)");
       return CPM_EINVAL;
     }
     width[i] = a;
@@ -292,6 +298,7 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
   s->kmax = kmax;
   s->kset = make_kset(box_host, beta, kmax);
   s->slab = params->slab_correction != 0;
+  s->point_self = point_self;
   s->prof.enabled = (params->store_mask & CPM_PROFILE_BUILD) != 0;
   s->pos_host = pos;
   s->width_host = width;
@@ -313,6 +320,11 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
       (rc = dev_alloc(s, &s->dprime, ld)) || (rc = dev_alloc(s, &s->dvec, ld)) ||
       (rc = dev_alloc(s, &s->qchi, ld)) || (rc = dev_alloc(s, &s->erfc_tab, kErfcTab)))
     return fail(rc);
+  if (point_self) {
+    if ((rc = dev_alloc(s, &s->rs_width, n))) return fail(rc);
+  } else {
+    s->rs_width = s->width;
+  }
   if ((params->store_mask & CPM_STORE_F32) && (rc = dev_alloc(s, &s->E32, (size_t)ld * ld)))
     return fail(rc);
   if ((params->store_mask & CPM_STORE_BF16) && (rc = dev_alloc(s, &s->E16, (size_t)ld * ld)))
@@ -333,6 +345,11 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
                              hipMemcpyHostToDevice, st));
   BUILD_CHECK(hipMemcpyAsync(s->pos, pos.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
   BUILD_CHECK(hipMemcpyAsync(s->width, width.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  if (point_self) {
+    const std::vector<double> unscreened(n, INFINITY);
+    BUILD_CHECK(hipMemcpyAsync(s->rs_width, unscreened.data(), sizeof(double) * n,
+                               hipMemcpyHostToDevice, st));
+  }
   if (nk > 0) {
     BUILD_CHECK(hipMemcpyAsync(s->kn, s->kset.n.data(), sizeof(int32_t) * 3 * nk,
                                hipMemcpyHostToDevice, st));
@@ -422,8 +439,8 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
   } else {
     BUILD_CHECK(hipMemsetAsync(s->E64, 0, sizeof(double) * ld * ld, st));
   }
-  BUILD_CHECK(launch_finalize(st, s->pos, s->width, n, ld, s->box, beta, s->rcut, s->slab, s->E64,
-                              s->E32, s->E16));
+  BUILD_CHECK(launch_finalize(st, s->pos, s->width, s->rs_width, n, ld, s->box, beta, s->rcut,
+                              s->slab, s->E64, s->E32, s->E16));
   BUILD_CHECK(launch_diag_inverse(st, s->E64, n, ld, s->dinv));
   BUILD_CHECK(hipStreamSynchronize(st));
 #undef BUILD_CHECK
@@ -617,6 +634,36 @@ cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev,
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call).count();
   }
   return rc;
+}
+
+cpm_status cpm_warm_start(cpm_system *s, int warm_start, const double *b_dev,
+                          const double *qsol_dev, int64_t f, double *x0_out_dev,
+                          double *r0_out_dev) {
+  if (!s || !b_dev || !qsol_dev || !x0_out_dev || !r0_out_dev || f < 1) {
+    set_error("invalid argument");
+    return CPM_EINVAL;
+  }
+  if (warm_start != CPM_WARM_CHI && warm_start != CPM_WARM_MLP) {
+    set_error("warm_start must be CPM_WARM_CHI or CPM_WARM_MLP");
+    return CPM_EINVAL;
+  }
+  if (warm_start == CPM_WARM_MLP && !(s->mlp.ready && s->mlp.params_set)) {
+    set_error("CPM_WARM_MLP needs cpm_mlp_init and cpm_mlp_set_params first");
+    return CPM_ESTATE;
+  }
+  if (warm_start == CPM_WARM_CHI && !s->qchi_ready) {
+    set_error("CPM_WARM_CHI needs cpm_set_warm_chi first");
+    return CPM_ESTATE;
+  }
+  {
+    cpm_status rd = ensure_dprime(s);
+    if (rd != CPM_OK) return rd;
+  }
+  cpm_status rc = warm_start_impl(s, warm_start == CPM_WARM_MLP, b_dev, qsol_dev, f, x0_out_dev,
+                                  r0_out_dev);
+  if (rc != CPM_OK) return rc;
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return CPM_OK;
 }
 
 cpm_status cpm_get_E(const cpm_system *s, int precision, void *dst_dev, int64_t ld) {

@@ -234,7 +234,8 @@ constexpr int FZ_B = 64;   // finalize block edge
 // above the diagonal, so both stores are row-contiguous and E is exactly
 // symmetric. FP32 / BF16 copies are the round-to-nearest of the FP64 value.
 __global__ __launch_bounds__(256) void finalize_kernel(
-    const double *__restrict__ pos, const double *__restrict__ width, int64_t n, int64_t ld,
+    const double *__restrict__ pos, const double *__restrict__ width,
+    const double *__restrict__ rs_width, int64_t n, int64_t ld,
     double lx, double ly, double lz, double beta, double rcut, double c0, double slab,
     double *__restrict__ E64, float *__restrict__ E32, uint16_t *__restrict__ E16) {
   __shared__ double tile[FZ_B][FZ_B + 1];
@@ -248,12 +249,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(
     double e = 0.0;
     if (i < n && j < n) {
       const int64_t idx = i * ld + j;
-      e = E64[idx] + c0 + real_space_entry(pos, width, j, i, lx, ly, lz, beta, rcut);
+      e = E64[idx] + c0 + real_space_entry(pos, rs_width, j, i, lx, ly, lz, beta, rcut);
       // slab geometry (Eq. 39 in its definite form): (4 pi / V) z_i z_j
       if (slab != 0.0) e += slab * (pos[3 * j + 2] * pos[3 * i + 2]);
       if (i == j) {
         // Gaussian self-energy 2 a_ii / sqrt(pi), a_ii = a_i / sqrt(2) (Eq. 6);
-        // a point charge (a_i = inf) has none (end of Sec. II.C).
+        // a point charge (a_i = inf) has none (end of Sec. II.C); the
+        // point-charge simplification keeps it (Sec. III.C)
         const double aii = width[i] * 0.70710678118654752440;
         e -= 2.0 * beta * 0.56418958354775628695;   // 1/sqrt(pi)
         if (isfinite(aii)) e += 2.0 * aii * 0.56418958354775628695;
@@ -320,16 +322,18 @@ hipError_t launch_syrk_lower(hipStream_t st, const double *A, int64_t kdim,
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(hipStream_t st, const double *pos, const double *width, int64_t n,
-                           int64_t ld, const double box[3], double beta, double rcut, bool slab,
-                           double *E64, float *E32, uint16_t *E16) {
+hipError_t launch_finalize(hipStream_t st, const double *pos, const double *width,
+                           const double *rs_width, int64_t n, int64_t ld, const double box[3],
+                           double beta, double rcut, bool slab, double *E64, float *E32,
+                           uint16_t *E16) {
   const double vol = box[0] * box[1] * box[2];
   const double c0 = -M_PI / (vol * beta * beta);
   const double cs = slab ? 4.0 * M_PI / vol : 0.0;
   if (ld % FZ_B != 0) return hipErrorInvalidValue;
   const int64_t B = ld / FZ_B;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)(B * (B + 1) / 2)), dim3(256), 0, st, pos,
-                     width, n, ld, box[0], box[1], box[2], beta, rcut, c0, cs, E64, E32, E16);
+                     width, rs_width, n, ld, box[0], box[1], box[2], beta, rcut, c0, cs, E64,
+                     E32, E16);
   return hipGetLastError();
 }
 

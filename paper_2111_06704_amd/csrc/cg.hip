@@ -72,7 +72,8 @@ constexpr int64_t kRedLoads = (int64_t)1 << 22;
 enum {
   S_RZ0 = 0, S_RZ1 = 1, S_RR = 2, S_BN2 = 3, S_ACT = 4, S_RT = 5, S_RES = 6, S_IT = 7,
   S_INIT = 8, S_FB = 9, S_HOLD0 = 10, S_HOLD1 = 11, S_RST = 12, S_RPREV = 13,
-  S_NFIELDS = 14
+  S_EN = 14,   // x0 . (b + r0) of a warm start: > 0 iff it lowers the energy
+  S_NFIELDS = 15
 };
 // status words (ints): breakdown flag and column, debug doubles (ints 2..5),
 // true residual due, any column active, non-finite residual seen, number of
@@ -741,6 +742,26 @@ __global__ __launch_bounds__(RED_THREADS) void sumsq_kernel(const double *__rest
   if (threadIdx.x == 0) partial[((int64_t)blk * cols + c) * 2] = acc;
 }
 
+// partial[blk][c][0] = block's share of x . (b + r): with r = b - E x,
+// x . (b + r) = 2 x.b - x.E x = -2 (x.E x / 2 - x.b), so it is positive
+// exactly when x lowers the energy x.E x / 2 - x.b below that of x = 0
+__global__ __launch_bounds__(RED_THREADS) void start_energy_kernel(
+    const double *__restrict__ x, const double *__restrict__ b, const double *__restrict__ r,
+    int64_t ld, int64_t n, int cols, double *__restrict__ partial) {
+  __shared__ double red[3][4];
+  const int c = blockIdx.y;
+  const int blk = blockIdx.x;
+  const int64_t i0 = (int64_t)blk * CHUNK;
+  const int64_t i1 = min(n, i0 + CHUNK);
+  double acc = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) {
+    const int64_t idx = (int64_t)c * ld + i;
+    acc += x[idx] * (b[idx] + r[idx]);
+  }
+  acc = block_sum(acc, red[0]);
+  if (threadIdx.x == 0) partial[((int64_t)blk * cols + c) * 2] = acc;
+}
+
 // scal[field][c] = sum over blocks of partial[blk][c][0]
 __global__ void sum_partials_kernel(const double *__restrict__ partial, int nblk, int cols,
                                     double *__restrict__ scal, int field,
@@ -1154,10 +1175,11 @@ __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
 
 // ---- device-side control (one wave, thread c = column)
 
-// After the start residual: |b| and |r| per column; a warm start that is not
-// better than zero (or not finite) is discarded (x = 0, r = b: applied by
-// fallback_kernel); b = 0 gives q_b = 0. Sets the active flags and clears
-// the status words.
+// After the start residual: |b| and |r| per column; a warm start that does
+// not lower the energy x.E x / 2 - x.b below that of zero (scal S_EN <= 0:
+// its E-norm error, which CG reduces, is not below the zero start's; or not
+// finite) is discarded (x = 0, r = b: applied by fallback_kernel); b = 0
+// gives q_b = 0. Sets the active flags and clears the status words.
 __global__ void ctl_init_kernel(double *__restrict__ scal, int cols, int fc, int x_zero, double tol,
                                 int *__restrict__ flags) {
   const int c = threadIdx.x;
@@ -1172,7 +1194,7 @@ __global__ void ctl_init_kernel(double *__restrict__ scal, int cols, int fc, int
         fb = !x_zero;
         rn = 0.0;
       } else {
-        if (!x_zero && !(rn < bn)) {
+        if (!x_zero && !(scal[S_EN * cols + c] > 0.0 && isfinite(rn))) {
           fb = true;
           fb_any = true;
           rn = bn;
@@ -1816,6 +1838,12 @@ cpm_status run_solver(cpm_system *s, const T *E, int fc, const cpm_solve_opts &o
                        (int)cols, sv.scal, (int)S_RR, nullptr);
   } else {
     CPM_HIP_CHECK(sv.true_residual(nullptr));
+  }
+  if (!x_zero) {
+    hipLaunchKernelGGL(start_energy_kernel, sv.grid(), dim3(RED_THREADS), 0, st, sv.x, sv.b, sv.r,
+                       sv.ld, sv.n, (int)cols, sv.partial);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.partial, sv.nblk,
+                       (int)cols, sv.scal, (int)S_EN, nullptr);
   }
   hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(MAX_COLS), 0, st, sv.scal, (int)cols, fc,
                      x_zero ? 1 : 0, tol, sv.flags);

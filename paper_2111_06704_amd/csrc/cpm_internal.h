@@ -154,6 +154,10 @@ struct cpm_system {
   cpm::Kset kset;
   double *pos = nullptr;      // n*3 device
   double *width = nullptr;    // n device (Gaussian inverse widths)
+  // n device: widths of the real-space pair screening erfc(a d) (width, or
+  // +inf everywhere under the point-charge simplification: then its own array)
+  double *rs_width = nullptr;
+  bool point_self = false;    // point-charge simplification (Sec. III.C)
   int32_t *kn = nullptr;      // nk*3 device
   double *kw = nullptr;       // nk device
   int32_t *kinfo = nullptr;   // nk*4 device (Kset::info)
@@ -198,9 +202,13 @@ std::vector<int32_t> syrk_tile_order(int64_t T);
 hipError_t launch_syrk_lower(hipStream_t st, const double *A, int64_t kdim,
                              const int32_t *tiles, int64_t ld, double *E, int64_t lde,
                              bool accumulate, hipEvent_t ev_start, hipEvent_t ev_stop);
-hipError_t launch_finalize(hipStream_t st, const double *pos, const double *width, int64_t n,
-                           int64_t ld, const double box[3], double beta, double rcut, bool slab,
-                           double *E64, float *E32, uint16_t *E16);
+// width: the Gaussian self-energy of the diagonal; rs_width: the screening
+// of the real-space pair terms (the same array unless the point-charge
+// simplification sets it to +inf)
+hipError_t launch_finalize(hipStream_t st, const double *pos, const double *width,
+                           const double *rs_width, int64_t n, int64_t ld, const double box[3],
+                           double beta, double rcut, bool slab, double *E64, float *E32,
+                           uint16_t *E16);
 
 // ---- rhs.hip
 // erfc on [0, 6.5): kErfcIntervals intervals of width 1/8, kErfcTerms
@@ -210,9 +218,13 @@ constexpr int kErfcTerms = 12;
 constexpr int kErfcTab = kErfcIntervals * kErfcTerms;
 void erfc_table(double *out);
 int64_t rhs_scratch_elems(const cpm_system *s, int64_t m, int64_t f);
+// scratch of the plan limited to limit doubles (fewer partial buffers)
+int64_t rhs_scratch_elems_capped(const cpm_system *s, int64_t m, int64_t f, int64_t limit);
+// limit > 0: the plan whose scratch fits limit doubles (as sized by
+// rhs_scratch_elems_capped)
 hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos,
                       const double *ion_q, int64_t m, int64_t f, const double *chi,
-                      double *S, double *b_out, double *qsol_out);
+                      double *S, double *b_out, double *qsol_out, int64_t limit = 0);
 
 // ---- cg.hip
 void release_workspace(cpm_system *s);

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace cpm {
 namespace {
@@ -39,6 +40,11 @@ __device__ inline double erfc_pw(const double *__restrict__ tab, double x) {
 #pragma unroll
   for (int k = kErfcTerms - 2; k >= 0; --k) p = fma(p, u, c[k]);
   return p;
+}
+
+__global__ void fill_zero_kernel(double *__restrict__ v, int64_t len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) v[i] = 0.0;
 }
 
 // Q_sol[f] = sum_I q_I; with m1 != null also M1[f] = sum_I q_I z_I (z in [0, L_z)),
@@ -754,19 +760,25 @@ int64_t groups_for(int64_t blocks, int64_t items, int64_t cap, int64_t &per) {
   return per > 0 ? (items + per - 1) / per : 1;
 }
 
-RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f) {
+// cap_* > 0 bound the ion groups of the structure factor, the k splits of
+// the back-projection and the ion groups of the real-space sum (fewer
+// partial buffers, less parallelism)
+RhsPlan rhs_plan_capped(const cpm_system *s, int64_t m, int64_t f, int64_t cap_sf,
+                        int64_t cap_ks, int64_t cap_rs) {
   RhsPlan p;
   const int64_t n = s->n, nk = std::max<int64_t>(s->kset.nk, 1);
   const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
   const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
   const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
   if (m > 0 && s->kset.nk > 0) {
-    p.sf_groups = groups_for(std::max<int64_t>(1, rblocks) * f, m, kPartialCap / (2 * nk * f), p.sf_ipg);
+    p.sf_groups = groups_for(std::max<int64_t>(1, rblocks) * f, m,
+                             std::min(cap_sf, kPartialCap / (2 * nk * f)), p.sf_ipg);
     // k splits of the back-projection: as many as fill every SIMD with three
     // wavefronts (its occupancy) without a fourth on some, at least 32 k each
     const int64_t per = bblocks * fgroups * (RB / 64);
     int64_t ks = std::max<int64_t>(1, (3 * 1024) / per);
-    ks = std::min<int64_t>({ks, std::max<int64_t>(1, nk / 32), std::max<int64_t>(1, kPartialCap / (f * n))});
+    ks = std::min<int64_t>({ks, std::max<int64_t>(1, nk / 32),
+                            std::max<int64_t>(1, kPartialCap / (f * n)), cap_ks});
     p.kper = (nk + ks - 1) / ks;
     p.ksplit = (nk + p.kper - 1) / p.kper;
   }
@@ -776,7 +788,7 @@ RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f) {
     p.nchunks = (m + kChunk - 1) / kChunk;
     p.rs_groups = 1;
   } else if (m > 0) {
-    p.rs_groups = groups_for(iblocks * f, m, kPartialCap / (f * n), p.rs_ipg);
+    p.rs_groups = groups_for(iblocks * f, m, std::min(cap_rs, kPartialCap / (f * n)), p.rs_ipg);
   }
   const int64_t ncell = (int64_t)p.nc[0] * p.nc[1] * p.nc[2];
   p.off_sg = 2 * nk * f;
@@ -791,35 +803,59 @@ RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f) {
   return p;
 }
 
+constexpr int64_t kNoCap = (int64_t)1 << 40;
+
+// the default plan, or with limit > 0 the most parallel plan whose scratch
+// holds at most limit doubles (halving the largest partial count first)
+RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f, int64_t limit = 0) {
+  RhsPlan p = rhs_plan_capped(s, m, f, kNoCap, kNoCap, kNoCap);
+  int64_t csf = p.sf_groups, cks = std::max<int64_t>(1, p.ksplit), crs = p.rs_groups;
+  while (limit > 0 && p.total > limit && (csf > 1 || cks > 1 || crs > 1)) {
+    const int64_t nk = std::max<int64_t>(s->kset.nk, 1);
+    const int64_t wsf = csf > 1 ? csf * 2 * nk * f : 0, wks = cks > 1 ? cks * f * s->n : 0,
+                  wrs = crs > 1 ? crs * f * s->n : 0;
+    if (wsf >= wks && wsf >= wrs) csf = std::max<int64_t>(1, csf / 2);
+    else if (wks >= wrs) cks = std::max<int64_t>(1, cks / 2);
+    else crs = std::max<int64_t>(1, crs / 2);
+    p = rhs_plan_capped(s, m, f, csf, cks, crs);
+  }
+  return p;
+}
+
 }  // namespace
+
 
 int64_t rhs_scratch_elems(const cpm_system *s, int64_t m, int64_t f) {
   return rhs_plan(s, m, f).total;
 }
 
+int64_t rhs_scratch_elems_capped(const cpm_system *s, int64_t m, int64_t f, int64_t limit) {
+  return rhs_plan(s, m, f, limit).total;
+}
+
 hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos,
-                      const double *ion_q, int64_t m, int64_t f, const double *chi, double *scratch,
-                      double *b_out, double *qsol_out) {
+                      const double *ion_q, int64_t m, int64_t f, const double *chi, double *buf,
+                      double *b_out, double *qsol_out, int64_t limit) {
   const double ilx = 1.0 / s->box[0], ily = 1.0 / s->box[1], ilz = 1.0 / s->box[2];
   const int64_t nk = s->kset.nk, n = s->n;
   const double c0 = -M_PI / (s->vol * s->beta * s->beta);
-  const RhsPlan p = rhs_plan(s, m, f);
-  double *S = scratch, *bp = scratch + p.off_bp, *rs = scratch + p.off_rs;
+  const RhsPlan p = rhs_plan(s, m, f, limit);
+  double *S = buf, *bp = buf + p.off_bp, *rs = buf + p.off_rs;
   const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
-  double *m1 = s->slab ? scratch + p.off_m1 : nullptr;
+  double *m1 = s->slab ? buf + p.off_m1 : nullptr;
   if (m > 0) {
     hipLaunchKernelGGL(qsum_kernel, dim3((unsigned)f), dim3(RB), 0, st, ion_q, m, qsol_out, ion_pos,
                        s->box[2], m1);
   } else {
-    hipError_t e = hipMemsetAsync(qsol_out, 0, sizeof(double) * f, st);
-    if (e != hipSuccess) return e;
-    if (m1) {
-      e = hipMemsetAsync(m1, 0, sizeof(double) * f, st);
-      if (e != hipSuccess) return e;
-    }
+    // zeros by a kernel (no memset node when the caller captures the stream)
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((f + 255) / 256)), dim3(256), 0, st,
+                       qsol_out, f);
+    if (m1)
+      hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((f + 255) / 256)), dim3(256), 0, st,
+                         m1, f);
   }
   if (p.ksplit > 0) {
-    double *Sg = p.sf_groups > 1 ? scratch + p.off_sg : S;
+    double *Sg = p.sf_groups > 1 ? buf + p.off_sg : S;
     const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
     hipLaunchKernelGGL(structure_factor_kernel, dim3((unsigned)rblocks, (unsigned)f, (unsigned)p.sf_groups),
                        dim3(RB), 0, st, ion_pos, ion_q, m, p.sf_ipg, s->kinfo, s->krun,
@@ -835,10 +871,10 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
                        bp);
   }
   if (p.rs_cell) {
-    double4 *sorted = reinterpret_cast<double4 *>(scratch + p.off_sorted);
-    uint32_t *keys = reinterpret_cast<uint32_t *>(scratch + p.off_keys);
-    int32_t *hist = reinterpret_cast<int32_t *>(scratch + p.off_hist);
-    int32_t *cstart = reinterpret_cast<int32_t *>(scratch + p.off_cstart);
+    double4 *sorted = reinterpret_cast<double4 *>(buf + p.off_sorted);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(buf + p.off_keys);
+    int32_t *hist = reinterpret_cast<int32_t *>(buf + p.off_hist);
+    int32_t *cstart = reinterpret_cast<int32_t *>(buf + p.off_cstart);
     const int ncell = p.nc[0] * p.nc[1] * p.nc[2];
     hipLaunchKernelGGL(cell_sort_chunk_kernel, dim3((unsigned)p.nchunks, (unsigned)f),
                        dim3(kChunkThreads), 0, st, ion_pos, m, p.nchunks, s->box[0], s->box[1],
@@ -851,13 +887,13 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
                        (const uint32_t *)keys, (const int32_t *)hist, (const int32_t *)cstart,
                        sorted);
     hipLaunchKernelGGL(real_space_cell_kernel, dim3((unsigned)((n + 63) / 64), (unsigned)f),
-                       dim3(64), 0, st, s->pos, s->width, s->atom_order, n,
+                       dim3(64), 0, st, s->pos, s->rs_width, s->atom_order, n,
                        (const double4 *)sorted, (const int32_t *)cstart, m, p.nc[0], p.nc[1],
                        p.nc[2], s->box[0], s->box[1], s->box[2], s->beta, s->rcut, f,
                        (const double *)s->erfc_tab, rs);
   } else if (p.rs_groups > 0) {
     hipLaunchKernelGGL(real_space_ions_kernel, dim3((unsigned)iblocks, (unsigned)f, (unsigned)p.rs_groups),
-                       dim3(RB), 0, st, s->pos, s->width, s->atom_order, n, ion_pos, ion_q, m,
+                       dim3(RB), 0, st, s->pos, s->rs_width, s->atom_order, n, ion_pos, ion_q, m,
                        p.rs_ipg, s->box[0], s->box[1], s->box[2], s->beta, s->rcut, f,
                        (const double *)s->erfc_tab, rs);
   }

@@ -60,7 +60,8 @@ def init_network(S: cpm.System, geo: wl.Geometry, b_scale: float, q_scale: float
 
 
 def generate(S: cpm.System, geo: wl.Geometry, seeds, m: int, chi, block: int = 64,
-             tol: float = 1e-10, precision: int = cpm.PREC_F32, log=None):
+             tol: float = 1e-10, precision: int = cpm.PREC_F32, log=None,
+             preconditioner: int = cpm.PRECOND_JACOBI):
     """(b, q) device tensors (T, N) for the electrolyte frames of ``seeds``."""
     import torch
     dev = chi.device
@@ -73,7 +74,8 @@ def generate(S: cpm.System, geo: wl.Geometry, seeds, m: int, chi, block: int = 6
         ipos, iq = wl.ion_frames(geo, m, ss)
         b, qsol = S.rhs(torch.tensor(ipos, device=dev), torch.tensor(iq, device=dev), chi,
                         b_out=b_all[s0:s0 + len(ss)])
-        S.solve(b, qsol, tol=tol, precision=precision, inner_tol=1e-2, q_out=q_all[s0:s0 + len(ss)])
+        S.solve(b, qsol, tol=tol, precision=precision, inner_tol=1e-2, q_out=q_all[s0:s0 + len(ss)],
+                preconditioner=preconditioner)
         if log and (s0 // block) % 20 == 0:
             log(f"  generated {s0 + len(ss)}/{T} frames ({time.perf_counter() - t0:.1f} s)")
     return b_all, q_all
@@ -124,7 +126,7 @@ def load_into(S: cpm.System, geo: wl.Geometry, path: str = DEFAULT_PATH):
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 5])
     ap.add_argument("--frames", type=int, default=10000)
     ap.add_argument("--ions", type=int, default=None,
                     help="ions per training frame (default: the workload's)")
@@ -144,11 +146,15 @@ def main(argv=None):
     S = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, wl.KSPACE_EPS,
                    store=("f32",))
     chi = torch.tensor(wl.electrode_potential(geo), device=dev)
+    pc = cpm.PRECOND_JACOBI
+    if geo.n > 10000:
+        S.precond_dc(0.15, 7.0)
+        pc = cpm.PRECOND_DC
     seeds = [wl.train_seed(t) for t in range(args.frames)]
     log(f"generating {args.frames} training frames (workload {args.workload}, N={geo.n}, "
         f"{m} ions)")
     t0 = time.perf_counter()
-    b_all, q_all = generate(S, geo, seeds, m, chi, log=log)
+    b_all, q_all = generate(S, geo, seeds, m, chi, log=log, preconditioner=pc)
     t_gen = time.perf_counter() - t0
     bs, qs = scales(b_all, q_all)
     init_network(S, geo, bs, qs)

@@ -156,3 +156,64 @@ def test_broken_network_falls_back(sys1):
     bo, qso = ew.rhs(geo.pos, A, ipos, iq, chi, geo.box, BETA, RC, km)
     r2, _ = ocpm.rel_errors(q.cpu().numpy(), ocpm.solve(E, bo, qso))
     assert r2.max() <= 1e-9
+
+
+def test_solver_warm_start_matches_oracle():
+    """The start cpm_solve takes with the network: the fused inference kernel
+    (inputs formed from b inside the kernel, both layers on the FP32 matrix
+    cores), the neutral shift sum(q0) = -Q_sol and the Lagrange shift
+    x0 = q0 + mu0 d', mu0 = mean(b - E q0) (Eq. 29-31), against the oracle's
+    features -> FP64 forward pass -> the same shifts with its Cholesky d'.
+    Workload 1 with 7 frames (2016 rows: the last 64-row tile is partial),
+    the committed workload-2 network. x0 within 2e-5 max|x0| (FP32 network);
+    r0 = b - E x0 of the GPU's own x0 within 1e-12 |b| (FP64)."""
+    cpm = _cpm()
+    from paper_2111_06704_amd import warmstart
+    geo, ipos, iq, chi = wl.workload(1, frames=7)
+    S = cpm.System(geo.pos, geo.box, A, BETA, RC, EPS, store=("f32",))
+    warmstart.load_into(S, geo, warmstart.DEFAULT_PATH)
+    z = np.load(warmstart.DEFAULT_PATH, allow_pickle=False)
+    b, qsol = S.rhs(torch.tensor(ipos, device="cuda"), torch.tensor(iq, device="cuda"),
+                    torch.tensor(chi, device="cuda"))
+    x0, r0 = S.warm_start(b, qsol, cpm.WARM_MLP)
+    x0, r0, bn, qs = (t.cpu().numpy() for t in (x0, r0, b, qsol))
+    km = ew.kmax_from_eps(BETA, EPS)
+    E = ew.ewald_matrix(geo.pos, geo.box, A, BETA, RC, km)
+    dprime, _, _ = ocpm.neutralising_vector(ocpm.cholesky(E), geo.n)
+    nbr, dist = ft.neighbours(geo.pos, geo.box)
+    X = ft.features(bn, nbr, dist, geo.layer, geo.n_layers, float(z["b_scale"]), float(z["r_scale"]))
+    q0 = omlp.forward(z["params"].astype(np.float64), X).reshape(7, geo.n) * float(z["q_scale"])
+    q0 -= ((q0.sum(axis=1) + qs) / geo.n)[:, None]
+    mu0 = np.mean(bn - q0 @ E, axis=1)
+    x0o = q0 + mu0[:, None] * dprime[None, :]
+    assert np.max(np.abs(x0 - x0o)) <= 2e-5 * np.max(np.abs(x0o))
+    assert np.max(np.abs(x0.sum(axis=1) + qs - mu0 * dprime.sum())) <= 1e-4 * np.max(np.abs(x0o))
+    assert np.max(np.linalg.norm(r0 - (bn - x0 @ E), axis=1) / np.linalg.norm(bn, axis=1)) <= 1e-12
+
+
+def test_learned_start_gain_workload2():
+    """What the trained network gains over the method without it, at the
+    settings bench.py times at workload 2 (FP32 E, PCG-DC g = 0.15 / A with
+    r_cut 7 A, reliable-update factor 1e-4, checks every 4 iterations, tol
+    1e-11), on the 16 evaluation frames (seeds disjoint from the training
+    frames): a smaller initial residual and strictly fewer iterations than
+    both the zero start and the free q_chi start."""
+    cpm = _cpm()
+    from paper_2111_06704_amd import warmstart
+    geo, ipos, iq, chi = wl.workload(2)
+    S = cpm.System(geo.pos, geo.box, A, BETA, RC, EPS, store=("f32",))
+    S.precond_dc(0.15, 7.0)
+    t_chi = torch.tensor(chi, device="cuda")
+    S.set_warm_chi(t_chi, preconditioner=cpm.PRECOND_DC)
+    warmstart.load_into(S, geo, warmstart.DEFAULT_PATH)
+    b, qsol = S.rhs(torch.tensor(ipos, device="cuda"), torch.tensor(iq, device="cuda"), t_chi)
+    st = {}
+    for name, ws in (("zero", cpm.WARM_ZERO), ("chi", cpm.WARM_CHI), ("mlp", cpm.WARM_MLP)):
+        _, st[name] = S.solve(b, qsol, tol=1e-11, precision=cpm.PREC_F32, warm_start=ws,
+                              inner_tol=1e-4, check_every=4, preconditioner=cpm.PRECOND_DC)
+        print(f"[gain] {name}: {st[name]['iterations']} iterations, initial residual "
+              f"{st[name]['initial_rel_resid']:.3f}")
+    assert st["mlp"]["fell_back"] == 0
+    for other in ("zero", "chi"):
+        assert st["mlp"]["initial_rel_resid"] < st[other]["initial_rel_resid"]
+        assert st["mlp"]["iterations"] < st[other]["iterations"]
