@@ -137,6 +137,23 @@ cpm_status cpm_rhs(cpm_system *s, const double *ion_pos_dev, const double *ion_q
                    int64_t m, int64_t f, const double *chi_dev, double *b_out_dev,
                    double *qsol_out_dev);
 
+/* cpm_rhs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result, with the scratch of the structure factors, partial sums and
+ * ion cell lists in a fixed device array of 4 Mi doubles (32 MiB) that the
+ * library holds on each GPU it runs on until the process ends, instead of
+ * memory allocated on the system. No hipMalloc, hipFree or allocating
+ * library call, and no memset node. The partial sums are then fewer when
+ * the usual split would not fit (a different summation order: b agrees
+ * with cpm_rhs to rounding, and bitwise when the usual split fits).
+ * Errors: those of cpm_rhs, and CPM_EINVAL when even the least split needs
+ * more scratch (the message gives both sizes; e.g. 2 n_k f doubles of
+ * structure factors alone). Calls that overlap on one GPU share the array
+ * and race: serialise them (one stream, or events). */
+cpm_status cpm_rhs_noalloc(cpm_system *s, const double *ion_pos_dev, const double *ion_q_dev,
+                           int64_t m, int64_t f, const double *chi_dev, double *b_out_dev,
+                           double *qsol_out_dev);
+
 enum { CPM_PREC_F64 = 0, CPM_PREC_F32 = 1, CPM_PREC_BF16 = 2 };
 enum { CPM_WARM_ZERO = 0, CPM_WARM_CHI = 1, CPM_WARM_MLP = 2 };
 enum { CPM_PRECOND_JACOBI = 0, CPM_PRECOND_DC = 1 };

@@ -25,7 +25,7 @@ MLP_IN, MLP_HIDDEN = 26, 64
 MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 
 EXPORTS = [
-    "cpm_build_E", "cpm_free", "cpm_set_stream", "cpm_describe", "cpm_rhs",
+    "cpm_build_E", "cpm_free", "cpm_set_stream", "cpm_describe", "cpm_rhs", "cpm_rhs_noalloc",
     "cpm_solve",
     "cpm_get_E", "cpm_get_E_block", "cpm_get_dprime", "cpm_matvec", "cpm_mlp_init", "cpm_mlp_neighbours",
     "cpm_mlp_set_params", "cpm_mlp_get_params", "cpm_mlp_features", "cpm_mlp_forward",
@@ -86,6 +86,7 @@ def lib():
     L.cpm_set_stream.argtypes = [vp, vp]
     L.cpm_describe.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(dbl), C.POINTER(i64)]
     L.cpm_rhs.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp]
+    L.cpm_rhs_noalloc.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp]
     L.cpm_solve.argtypes = [vp, vp, vp, i64, C.POINTER(SolveOpts), vp, C.POINTER(SolveInfo)]
     L.cpm_get_E.argtypes = [vp, C.c_int, vp, i64]
     L.cpm_get_E_block.argtypes = [vp, C.c_int, i64, i64, i64, i64, vp, i64]
@@ -227,6 +228,19 @@ class System:
                            _ptr(chi, torch.float64), _ptr(b_out, torch.float64),
                            _ptr(qsol_out, torch.float64))
         _check(st, "cpm_rhs")
+        return b_out, qsol_out
+
+    def rhs_noalloc(self, ion_pos, ion_q, chi, b_out, qsol_out):
+        """cpm_rhs with the library's static scratch (allocates nothing; b_out
+        (F, N) and qsol_out (F,) are the caller's)."""
+        import torch
+        f = int(ion_pos.shape[0]) if ion_pos is not None else int(b_out.shape[0])
+        m = int(ion_pos.shape[1]) if ion_pos is not None else 0
+        st = lib().cpm_rhs_noalloc(self._h, _ptr(ion_pos, torch.float64) if m else None,
+                                   _ptr(ion_q, torch.float64) if m else None, m, f,
+                                   _ptr(chi, torch.float64), _ptr(b_out, torch.float64),
+                                   _ptr(qsol_out, torch.float64))
+        _check(st, "cpm_rhs_noalloc")
         return b_out, qsol_out
 
     def solve(self, b, qsol, tol=1e-10, max_iter=5000, precision=PREC_F64, warm_start=WARM_ZERO,

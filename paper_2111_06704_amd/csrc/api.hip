@@ -514,6 +514,39 @@ cpm_status cpm_rhs(cpm_system *s, const double *ion_pos_dev, const double *ion_q
   return CPM_OK;
 }
 
+cpm_status cpm_rhs_noalloc(cpm_system *s, const double *ion_pos_dev, const double *ion_q_dev,
+                           int64_t m, int64_t f, const double *chi_dev, double *b_out_dev,
+                           double *qsol_out_dev) {
+  if (!s || !chi_dev || !b_out_dev || !qsol_out_dev || (m > 0 && (!ion_pos_dev || !ion_q_dev))) {
+    set_error("NULL argument");
+    return CPM_EINVAL;
+  }
+  if (f < 1 || m < 0) {
+    set_error("need f >= 1 and m >= 0");
+    return CPM_EINVAL;
+  }
+  const int64_t cap = rhs_static_scratch_elems();
+  const int64_t fchunk = 1024;
+  int64_t need = rhs_scratch_elems_capped(s, m, std::min(f, fchunk), cap);
+  if (f > fchunk && f % fchunk)
+    need = std::max(need, rhs_scratch_elems_capped(s, m, f % fchunk, cap));
+  if (need > cap) {
+    set_error("cpm_rhs_noalloc: " + std::to_string(m) + " ions x " + std::to_string(std::min(f, fchunk)) +
+              " frames need " + std::to_string(need) + " doubles of scratch; the static buffer holds " +
+              std::to_string(cap) + " (use cpm_rhs)");
+    return CPM_EINVAL;
+  }
+  double *buf = nullptr;
+  CPM_HIP_CHECK(rhs_static_scratch(&buf));
+  for (int64_t f0 = 0; f0 < f; f0 += fchunk) {
+    const int64_t fc = std::min(fchunk, f - f0);
+    CPM_HIP_CHECK(launch_rhs(s->stream, s, m > 0 ? ion_pos_dev + f0 * m * 3 : nullptr,
+                             m > 0 ? ion_q_dev + f0 * m : nullptr, m, fc, chi_dev, buf,
+                             b_out_dev + f0 * s->n, qsol_out_dev + f0, cap));
+  }
+  return CPM_OK;
+}
+
 }  // extern "C"
 
 cpm_status cpm::check_solve_opts(const cpm_system *s, const cpm_solve_opts *opts,

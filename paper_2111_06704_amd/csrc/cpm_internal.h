@@ -218,8 +218,11 @@ constexpr int kErfcTerms = 12;
 constexpr int kErfcTab = kErfcIntervals * kErfcTerms;
 void erfc_table(double *out);
 int64_t rhs_scratch_elems(const cpm_system *s, int64_t m, int64_t f);
-// scratch of the plan limited to limit doubles (fewer partial buffers)
+// scratch of the plan limited to limit doubles (fewer partial buffers), and
+// the static scratch of cpm_rhs_noalloc: its size and this device's address
 int64_t rhs_scratch_elems_capped(const cpm_system *s, int64_t m, int64_t f, int64_t limit);
+int64_t rhs_static_scratch_elems();
+hipError_t rhs_static_scratch(double **ptr);
 // limit > 0: the plan whose scratch fits limit doubles (as sized by
 // rhs_scratch_elems_capped)
 hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos,

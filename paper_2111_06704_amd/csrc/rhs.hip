@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 namespace cpm {
@@ -822,15 +823,44 @@ RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f, int64_t limit = 0) {
   return p;
 }
 
+// ---- cpm_rhs_noalloc: the scratch in a fixed device array
+//
+// kStaticRhsScratch doubles (32 MiB) per GPU, held by the code object until
+// the process ends. Host code takes its device address from
+// hipGetSymbolAddress (per device, on first use): the array's name in host
+// code is not a device address.
+constexpr int64_t kStaticRhsScratch = (int64_t)1 << 22;
+
 }  // namespace
 
+static __device__ __align__(256) double scratch[kStaticRhsScratch];
 
 int64_t rhs_scratch_elems(const cpm_system *s, int64_t m, int64_t f) {
   return rhs_plan(s, m, f).total;
 }
 
+int64_t rhs_static_scratch_elems() { return kStaticRhsScratch; }
+
 int64_t rhs_scratch_elems_capped(const cpm_system *s, int64_t m, int64_t f, int64_t limit) {
   return rhs_plan(s, m, f, limit).total;
+}
+
+hipError_t rhs_static_scratch(double **ptr) {
+  static std::mutex mu;
+  static std::vector<double *> per_device;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)per_device.size() <= dev) per_device.resize(dev + 1, nullptr);
+  if (!per_device[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    per_device[dev] = static_cast<double *>(p);
+  }
+  *ptr = per_device[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos,
