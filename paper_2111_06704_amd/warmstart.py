@@ -13,11 +13,14 @@ library.
     python -m paper_2111_06704_amd.warmstart --workload 3 --ions 50000 --frames 4000 \
         --out paper_2111_06704_amd/weights/warmstart_4layer.npz
 
-The second network serves the two 4-layer geometries (workloads 3 and 5):
-its inputs are per-atom and local (the atom's and its 12 neighbours'
-right-hand sides, its layer among the 8), so it transfers to the laterally
-larger workload 5 when trained at workload 5's ion density (200000 ions in
-its slit of 157.41 x 272.64 x 46 A, i.e. 50000 in workload 3's).
+    python -m paper_2111_06704_amd.warmstart --workload 5 --frames 1024 \
+        --out paper_2111_06704_amd/weights/warmstart_cfg5.npz
+
+The second network serves workload 3 (trained at workload 5's ion density,
+50000 ions in workload 3's slit), the third workload 5 itself (its inputs
+are per-atom and local, but the long-wavelength part of b grows with the
+lateral size, and the workload-3 network's starts raise the CG energy at
+workload 5).
 """
 from __future__ import annotations
 
@@ -36,11 +39,18 @@ DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights
                             "warmstart_cfg2.npz")
 FOUR_LAYER_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
                                "warmstart_4layer.npz")
+WORKLOAD5_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                              "warmstart_cfg5.npz")
 
 
 def weights_for(cfg: int) -> str:
-    """Committed network for a workload's electrode geometry."""
-    return DEFAULT_PATH if cfg in (1, 2, 4) else FOUR_LAYER_PATH
+    """Committed network for a workload's electrode geometry. Workload 5 has
+    its own: the workload-3 network, trained at the same ion density, gives
+    starts that raise the CG energy there (the long-wavelength part of b,
+    which a 12-neighbour network cannot map, grows with the lateral size)."""
+    if cfg in (1, 2, 4):
+        return DEFAULT_PATH
+    return WORKLOAD5_PATH if cfg == 5 else FOUR_LAYER_PATH
 
 
 def init_params(seed: int) -> np.ndarray:
