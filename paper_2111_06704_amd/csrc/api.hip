@@ -61,6 +61,36 @@ Kset make_kset(const double box[3], double beta, double kmax) {
     c0 = c1;
   }
   ks.nruns = (int64_t)ks.runs.size() / 2;
+  // columns: every (n_x, n_y) with n_x > 0 or n_y > 0 holds n_z = -m..m
+  // (|K| <= kmax is symmetric in n_z); (0, 0) holds n_z = 1..m
+  struct Col { int32_t nx, ny, m, kzero; };
+  std::vector<Col> cols;
+  for (int64_t c0 = 0; c0 < ks.nk;) {
+    int64_t c1 = c0 + 1;
+    while (c1 < ks.nk && ks.n[3 * c1] == ks.n[3 * c0] && ks.n[3 * c1 + 1] == ks.n[3 * c0 + 1]) ++c1;
+    Col c;
+    c.nx = ks.n[3 * c0];
+    c.ny = ks.n[3 * c0 + 1];
+    c.m = ks.n[3 * (c1 - 1) + 2];
+    c.kzero = (int32_t)(c1 - 1 - c.m);
+    cols.push_back(c);
+    ks.smax = std::max(ks.smax, (int)c.m);
+    c0 = c1;
+  }
+  std::stable_sort(cols.begin(), cols.end(), [](const Col &a, const Col &b) { return a.m > b.m; });
+  ks.ncols = (int64_t)cols.size();
+  ks.ncols_pad = round_up(std::max<int64_t>(ks.ncols, 1), kSfTile);
+  ks.cols.assign(4 * ks.ncols_pad, 0);
+  for (int64_t c = 0; c < ks.ncols_pad; ++c) {
+    if (c < ks.ncols) {
+      ks.cols[4 * c] = cols[c].nx;
+      ks.cols[4 * c + 1] = cols[c].ny;
+      ks.cols[4 * c + 2] = cols[c].m;
+      ks.cols[4 * c + 3] = cols[c].kzero;
+    } else {
+      ks.cols[4 * c + 2] = -1;
+    }
+  }
   return ks;
 }
 
@@ -132,7 +162,7 @@ template <typename T> cpm_status dev_alloc(cpm_system *s, T **p, size_t count) {
 
 void free_system(cpm_system *s) {
   if (!s) return;
-  void *ptrs[] = {s->pos, s->width, s->kn, s->kw, s->kinfo, s->krun, s->atom_order, s->E64, s->E32, s->E16, s->dinv, s->dprime,
+  void *ptrs[] = {s->pos, s->width, s->kn, s->kw, s->kinfo, s->krun, s->kcol, s->atom_order, s->E64, s->E32, s->E16, s->dinv, s->dprime,
                   s->dvec, s->qchi, s->erfc_tab, s->rhs_S, s->S, s->mlp.nbr, s->mlp.nbr_r, s->mlp.layer, s->mlp.params,
                   s->mlp.adam_m, s->mlp.adam_v, s->mlp.grad, s->mlp.gpart, s->mlp.loss,
                   s->mlp.feat, s->mlp.yout};
@@ -315,6 +345,7 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
       (rc = dev_alloc(s, &s->kw, std::max<int64_t>(nk, 1))) ||
       (rc = dev_alloc(s, &s->kinfo, 4 * std::max<int64_t>(nk, 1))) ||
       (rc = dev_alloc(s, &s->krun, 2 * std::max<int64_t>(s->kset.nruns, 1))) ||
+      (rc = dev_alloc(s, &s->kcol, 4 * s->kset.ncols_pad)) ||
       (rc = dev_alloc(s, &s->atom_order, n)) ||
       (rc = dev_alloc(s, &s->E64, (size_t)ld * ld)) || (rc = dev_alloc(s, &s->dinv, ld)) ||
       (rc = dev_alloc(s, &s->dprime, ld)) || (rc = dev_alloc(s, &s->dvec, ld)) ||
@@ -356,6 +387,8 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
     BUILD_CHECK(hipMemcpyAsync(s->kw, s->kset.w.data(), sizeof(double) * nk, hipMemcpyHostToDevice,
                                st));
     BUILD_CHECK(hipMemcpyAsync(s->kinfo, s->kset.info.data(), sizeof(int32_t) * 4 * nk,
+                               hipMemcpyHostToDevice, st));
+    BUILD_CHECK(hipMemcpyAsync(s->kcol, s->kset.cols.data(), sizeof(int32_t) * 4 * s->kset.ncols_pad,
                                hipMemcpyHostToDevice, st));
     BUILD_CHECK(hipMemcpyAsync(s->krun, s->kset.runs.data(), sizeof(int32_t) * 2 * s->kset.nruns,
                                hipMemcpyHostToDevice, st));

@@ -34,7 +34,17 @@ struct Kset {
   int64_t nruns = 0;
   // info[4k..4k+3] = n_x, n_y, n_z, 1 if k starts a run (else 0)
   std::vector<int32_t> info;
+  // (n_x, n_y) columns for the structure-factor product, sorted by their
+  // largest |n_z| (descending) and padded to a multiple of kSfTile:
+  // cols[4c..4c+3] = n_x, n_y, m = largest |n_z| (-1: padding), k index of
+  // n_z = 0 (the column (0, 0) holds n_z = 1..m only: k index of n_z = 0 is
+  // one before its first vector)
+  std::vector<int32_t> cols;
+  int64_t ncols = 0, ncols_pad = 0;
+  int smax = 0;                // largest |n_z|
 };
+
+constexpr int kSfTile = 64;    // columns per workgroup of the structure-factor product
 
 constexpr int kRun = 24;       // longest run of consecutive n_z (phase recurrence length)
 
@@ -162,6 +172,7 @@ struct cpm_system {
   double *kw = nullptr;       // nk device
   int32_t *kinfo = nullptr;   // nk*4 device (Kset::info)
   int32_t *krun = nullptr;    // nruns*2 device (Kset::runs)
+  int32_t *kcol = nullptr;    // ncols_pad*4 device (Kset::cols)
   int32_t *atom_order = nullptr;  // n device: atoms in compact spatial tiles (real-space sums)
   double *E64 = nullptr;      // ld*ld device (rows >= n and cols >= n are zero)
   float *E32 = nullptr;

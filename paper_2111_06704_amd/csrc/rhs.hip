@@ -20,6 +20,8 @@
 namespace cpm {
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 constexpr int RB = 256;       // threads per block
 constexpr int FG = 16;        // frames per thread in the back-projection
 constexpr int BP_AT = 2;      // atoms per thread in the back-projection
@@ -178,6 +180,116 @@ __global__ __launch_bounds__(RB) void structure_factor_kernel(
         out[st * f_total * 2] = ar[st];
         out[st * f_total * 2 + 1] = ai[st];
       }
+  }
+}
+
+// Ion structure factors as a product on the FP64 matrix cores. With
+// exp(i K.r) = exp(2 pi i (n_x x / L_x + n_y y / L_y)) exp(2 pi i n_z z / L_z)
+// = P_c(r) Z_s(r)^(+-1) for the column c = (n_x, n_y) and s = |n_z|,
+//   S(c, +s) = sum_I q_I P_c Z_s,   S(c, -s) = sum_I q_I P_c conj(Z_s).
+// With q P = a + i b and Z = z + i w these are four real products over the
+// ions, AZ = sum a z, BW = sum b w, AW = sum a w, BZ = sum b z:
+//   S(c, +s) = (AZ - BW) + i (AW + BZ),  S(c, -s) = (AZ + BW) + i (BZ - AW),
+// one pass over the ions for both signs of n_z. A workgroup takes 64
+// columns (a wave each 16: the A operand rows) and the s blocks of 16 its
+// largest |n_z| needs (columns sorted by it), and streams its ion group in
+// chunks: per chunk the Z_s of every ion go to LDS (sincospi of the reduced
+// fractional phase), per step of 4 ions each lane forms its (column, ion)
+// entry of q P the same way; v_mfma_f64_16x16x4f64 accumulates the four
+// products. Output: Sg as in structure_factor_kernel.
+constexpr int SG_CH = 32;      // ions per LDS chunk
+constexpr int SG_SB = 4;       // s blocks of 16 at most (|n_z| <= 63)
+
+__global__ __launch_bounds__(256, 2) void sf_gemm_kernel(
+    const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m, int64_t ipg,
+    const int4 *__restrict__ kcol, double inv_lx, double inv_ly, double inv_lz, int64_t nk,
+    int64_t f_total, double *__restrict__ Sg) {
+  __shared__ double2 zt[SG_CH][SG_SB * 16];
+  __shared__ double su[SG_CH][3];   // x / L_x, y / L_y, q
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t cbase = (int64_t)blockIdx.x * kSfTile;
+  const int64_t f = blockIdx.y, g = blockIdx.z;
+  // columns are sorted by their largest |n_z|: the first one sets the blocks
+  const int nsb = (kcol[cbase].z + 16) / 16;
+  const int4 mycol = kcol[cbase + wave * 16 + lr];
+  const double cnx = (double)mycol.x, cny = (double)mycol.y;
+  d4 acc[SG_SB][4];
+#pragma unroll
+  for (int sb = 0; sb < SG_SB; ++sb)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[sb][p] = d4{0.0, 0.0, 0.0, 0.0};
+  const double *pf = ion_pos + f * m * 3;
+  const double *qf = ion_q + f * m;
+  const int64_t i0 = g * ipg, i1 = min(m, i0 + ipg);
+  const int ns = nsb * 16;
+  for (int64_t base = i0; base < i1; base += SG_CH) {
+    const int cnt = (int)((i1 - base) < SG_CH ? (i1 - base) : SG_CH);
+    if (tid < SG_CH) {
+      double ux = 0.0, uy = 0.0, q = 0.0;   // missing ions enter with q = 0
+      if (tid < cnt) {
+        ux = pf[3 * (base + tid)] * inv_lx;
+        uy = pf[3 * (base + tid) + 1] * inv_ly;
+        q = qf[base + tid];
+      }
+      su[tid][0] = ux;
+      su[tid][1] = uy;
+      su[tid][2] = q;
+    }
+    for (int e = tid; e < SG_CH * ns; e += 256) {
+      const int ion = e / ns, sidx = e - ion * ns;
+      double t = 0.0;
+      if (ion < cnt) t = (double)sidx * (pf[3 * (base + ion) + 2] * inv_lz);
+      t -= rint(t);
+      double sn, cs;
+      sincospi(2.0 * t, &sn, &cs);
+      zt[ion][sidx] = make_double2(cs, sn);
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ks = 0; ks < SG_CH / 4; ++ks) {
+      const int ion = ks * 4 + lg;
+      double t = cnx * su[ion][0] + cny * su[ion][1];
+      t -= rint(t);
+      double sn, cs;
+      sincospi(2.0 * t, &sn, &cs);
+      const double a = su[ion][2] * cs, b = su[ion][2] * sn;
+#pragma unroll
+      for (int sb = 0; sb < SG_SB; ++sb) {
+        if (sb < nsb) {
+          const double2 z = zt[ion][sb * 16 + lr];
+          acc[sb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z.x, acc[sb][0], 0, 0, 0);
+          acc[sb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, z.y, acc[sb][1], 0, 0, 0);
+          acc[sb][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z.y, acc[sb][2], 0, 0, 0);
+          acc[sb][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, z.x, acc[sb][3], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // D[i][j] (column i, s = j of the block) in lane j + 16 (i % 4), register i / 4
+#pragma unroll
+  for (int sb = 0; sb < SG_SB; ++sb) {
+    if (sb >= nsb) break;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int4 col = kcol[cbase + wave * 16 + 4 * v + lg];
+      const int sv = sb * 16 + lr;
+      if (col.z < 0 || sv > col.z) continue;
+      const double AZ = acc[sb][0][v], BW = acc[sb][1][v], AW = acc[sb][2][v],
+                   BZ = acc[sb][3][v];
+      const bool half = col.x == 0 && col.y == 0;   // n_z = 1..m only
+      if (!(half && sv == 0)) {
+        double *o = Sg + ((g * nk + col.w + sv) * f_total + f) * 2;
+        o[0] = AZ - BW;
+        o[1] = AW + BZ;
+      }
+      if (!half && sv > 0) {
+        double *o = Sg + ((g * nk + col.w - sv) * f_total + f) * 2;
+        o[0] = AZ + BW;
+        o[1] = BZ - AW;
+      }
+    }
   }
 }
 
@@ -723,6 +835,7 @@ namespace {
 //   rs  [rs_groups][f][n]      real-space partials
 struct RhsPlan {
   int64_t sf_groups = 1, sf_ipg = 0, ksplit = 0, kper = 0, rs_groups = 0, rs_ipg = 0;
+  bool sf_gemm = false;         // structure factors on the matrix cores (|n_z| <= 63)
   bool rs_cell = false;         // real space over the cell list of the ions
   int nc[3] = {1, 1, 1};        // cells per box edge
   int64_t nchunks = 0;          // sorting chunks per frame
@@ -772,8 +885,10 @@ RhsPlan rhs_plan_capped(const cpm_system *s, int64_t m, int64_t f, int64_t cap_s
   const int64_t iblocks = (n + RB - 1) / RB, fgroups = (f + FG - 1) / FG;
   const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
   if (m > 0 && s->kset.nk > 0) {
-    p.sf_groups = groups_for(std::max<int64_t>(1, rblocks) * f, m,
-                             std::min(cap_sf, kPartialCap / (2 * nk * f)), p.sf_ipg);
+    p.sf_gemm = s->kset.smax < SG_SB * 16;
+    const int64_t sf_blocks = p.sf_gemm ? (s->kset.ncols_pad / kSfTile) * f
+                                        : std::max<int64_t>(1, rblocks) * f;
+    p.sf_groups = groups_for(sf_blocks, m, std::min(cap_sf, kPartialCap / (2 * nk * f)), p.sf_ipg);
     // k splits of the back-projection: as many as fill every SIMD with three
     // wavefronts (its occupancy) without a fourth on some, at least 32 k each
     const int64_t per = bblocks * fgroups * (RB / 64);
@@ -887,9 +1002,15 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
   if (p.ksplit > 0) {
     double *Sg = p.sf_groups > 1 ? buf + p.off_sg : S;
     const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
-    hipLaunchKernelGGL(structure_factor_kernel, dim3((unsigned)rblocks, (unsigned)f, (unsigned)p.sf_groups),
-                       dim3(RB), 0, st, ion_pos, ion_q, m, p.sf_ipg, s->kinfo, s->krun,
-                       s->kset.nruns, nk, ilx, ily, ilz, f, Sg);
+    if (p.sf_gemm)
+      hipLaunchKernelGGL(sf_gemm_kernel, dim3((unsigned)(s->kset.ncols_pad / kSfTile), (unsigned)f,
+                                              (unsigned)p.sf_groups),
+                         dim3(256), 0, st, ion_pos, ion_q, m, p.sf_ipg,
+                         reinterpret_cast<const int4 *>(s->kcol), ilx, ily, ilz, nk, f, Sg);
+    else
+      hipLaunchKernelGGL(structure_factor_kernel, dim3((unsigned)rblocks, (unsigned)f, (unsigned)p.sf_groups),
+                         dim3(RB), 0, st, ion_pos, ion_q, m, p.sf_ipg, s->kinfo, s->krun,
+                         s->kset.nruns, nk, ilx, ily, ilz, f, Sg);
     if (p.sf_groups > 1) {
       const int64_t len = 2 * nk * f;
       hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
