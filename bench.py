@@ -63,8 +63,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=5, choices=[1, 2, 3, 5])
     ap.add_argument("--tol", type=float, default=1e-11)
-    ap.add_argument("--check-every", type=int, default=4,
-                    help="iterations per device-side convergence check (all modes)")
+    ap.add_argument("--check-every", type=int, default=None,
+                    help="iterations per device-side convergence check (all modes; default 8 at "
+                         "workload 5, 4 elsewhere)")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="reliable-update factor of the FP32 / BF16 modes (default: "
                          "1e-4 for FP32 with PCG-DC at workload 2, 1e-3 otherwise)")
@@ -295,6 +296,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cfg = args.workload
+    if args.check_every is None:
+        args.check_every = 8 if cfg == 5 else 4
     geo, ipos, iq, chi = wl.workload(cfg)
     if args.jitter > 0:
         # genericity check: the same workload with every electrode atom displaced
@@ -344,15 +347,16 @@ def main():
     def inner_tol_for(precision, pcm):
         # reliable-update factor: 1e-4 for FP32 with PCG-DC at workload 2
         # (from a sweep: one true residual fewer at the same 32 iterations),
-        # 1e-2 at workload 5 (a sweep of 1e-1 .. 1e-5: 88 iterations at 1e-2,
-        # 96 at 1e-3, 116 at 1e-4, 252 at 1e-5; the FP32 recursion drifts
-        # from the true residual over long stretches), 1e-3 elsewhere (BF16,
-        # Jacobi and workload 3 need more iterations at 1e-4)
+        # 3e-3 with checks every 8 iterations at workload 5 (a sweep of
+        # 1e-1 .. 3e-3 and 4 / 8: 80 iterations at every factor, the fewest
+        # true residuals, 4, at 3e-3 with 8; factors of 1e-4 and below need
+        # more iterations, 1e-5 nearly three times as many), 1e-3 elsewhere
+        # (BF16, Jacobi and workload 3 need more iterations at 1e-4)
         if args.inner_tol is not None:
             return args.inner_tol
         if precision == cpm.PREC_F32 and pcm == cpm.PRECOND_DC and cfg == 2:
             return 1e-4
-        return 1e-2 if cfg == 5 else 1e-3
+        return 3e-3 if cfg == 5 else 1e-3
 
     def solver(precision, wm, qout, pcm):
         return lambda bb, qq: S.solve(bb, qq, tol=args.tol, precision=precision, warm_start=wm,

@@ -449,7 +449,9 @@ constexpr int SP_RW = 2;                     // row tiles per wave
 constexpr int SP_ROWS = 4 * 16 * SP_RW;      // rows per workgroup
 constexpr int SP_KC = 32;                    // k per chunk (one MFMA depth)
 constexpr int SP_PR = SP_KC + 8;             // LDS row length of a P part (bf16, padded)
-constexpr int SP_U = 4;                      // E chunks in flight per wave
+// E chunks in flight per wave: 2 up to 32 columns (three waves per SIMD fit
+// beside the FP64 sums: 12.3 ms against 14.4 with 4 at N = 131072), 4 for 64
+template <int NG> constexpr int sp_ring() { return NG <= 2 ? 2 : 4; }
 
 __device__ inline uint32_t cvt_bf16x2(float a, float b) {
   const f2v v = {a, b};
@@ -526,6 +528,7 @@ __global__ __launch_bounds__(256) void block_matvec_split_kernel(
     const int *__restrict__ gate, int *__restrict__ mark) {
   using SP = Sp<T>;
   constexpr int COLS = 16 * NG;
+  constexpr int SP_U = sp_ring<NG>();
   // one LDS buffer: the P parts during the k loop, the output tile after it
   constexpr int PS_BYTES = 2 * 3 * COLS * SP_PR * 2;
   constexpr int OUT_BYTES = COLS * (SP_ROWS + 1) * 4;
@@ -570,11 +573,18 @@ __global__ __launch_bounds__(256) void block_matvec_split_kernel(
 #pragma unroll
   for (int a = 0; a < SP_RW; ++a) erow[a] = E + (row0 + wave * 16 * SP_RW + a * 16 + lr) * ld + kbeg + lg * 8;
 
+  // the matrix cores accumulate in FP32 over SP_U chunks, then the sums move
+  // to FP64 registers: a running FP32 sum over a k slice of ~40000 would
+  // carry ~1e-6 of |v| in rounding (slower CG), the flushed one ~1e-7
   f4 acc[SP_RW][NG];
+  d4 accd[SP_RW][NG];
 #pragma unroll
   for (int a = 0; a < SP_RW; ++a)
 #pragma unroll
-    for (int g = 0; g < NG; ++g) acc[a][g] = f4{0, 0, 0, 0};
+    for (int g = 0; g < NG; ++g) {
+      acc[a][g] = f4{0, 0, 0, 0};
+      accd[a][g] = d4{0.0, 0.0, 0.0, 0.0};
+    }
 
   typename SP::Raw ring[SP_U][SP_RW];
 #pragma unroll
@@ -616,6 +626,14 @@ __global__ __launch_bounds__(256) void block_matvec_split_kernel(
         __syncthreads();
       }
     }
+#pragma unroll
+    for (int a = 0; a < SP_RW; ++a)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) accd[a][g][v] += (double)acc[a][g][v];
+        acc[a][g] = f4{0, 0, 0, 0};
+      }
   }
 
   // this workgroup's partial product through LDS: coalesced rows per column
@@ -625,7 +643,7 @@ __global__ __launch_bounds__(256) void block_matvec_split_kernel(
     for (int g = 0; g < NG; ++g)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        outs[g * 16 + lr][wave * 16 * SP_RW + a * 16 + 4 * lg + v] = acc[a][g][v];
+        outs[g * 16 + lr][wave * 16 * SP_RW + a * 16 + 4 * lg + v] = (float)accd[a][g][v];
   __syncthreads();
   float *out = part + sl * split_stride;
   for (int c = tid / SP_ROWS; c < COLS; c += 256 / SP_ROWS) {
