@@ -141,6 +141,34 @@ void Profile::reset() {
   next_mark = 0;
 }
 
+void *grow_buf(cpm_system *s, DevBuf &b, size_t bytes, cpm_status *rc) {
+  *rc = CPM_OK;
+  if (bytes <= b.bytes) return b.p;
+  // at least 1.5x the old size, so that a slowly growing caller reallocates
+  // a few times only
+  const size_t want = std::max(bytes, b.bytes + b.bytes / 2);
+  if (b.p) {
+    if (hipStreamSynchronize(s->stream) != hipSuccess) {
+      set_error("stream synchronisation before a scratch resize failed");
+      *rc = CPM_EDEVICE;
+      return nullptr;
+    }
+    (void)hipFree(b.p);
+    s->device_bytes -= (int64_t)b.bytes;
+    b = DevBuf();
+  }
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b = DevBuf();
+    set_error("device allocation of " + std::to_string(want) + " bytes of scratch failed");
+    *rc = CPM_ENOMEM;
+    return nullptr;
+  }
+  b.bytes = want;
+  s->device_bytes += (int64_t)want;
+  return b.p;
+}
+
 }  // namespace cpm
 
 using namespace cpm;
@@ -169,6 +197,8 @@ void free_system(cpm_system *s) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->rs_width && s->rs_width != s->width) (void)hipFree(s->rs_width);
+  for (DevBuf *b : {&s->buf_warm, &s->buf_eq, &s->buf_mean, &s->buf_aux})
+    if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : s->warm_ev)
     if (e) (void)hipEventDestroy(e);
   release_workspace(s);
@@ -673,14 +703,13 @@ cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev,
       CPM_HIP_CHECK(hipEventCreate(&s->warm_ev[1]));
     }
     // the start and its FP64 residual (the solver's first residual)
-    CPM_HIP_CHECK(hipMallocAsync((void **)&x0_buf, sizeof(double) * 2 * f * s->n, s->stream));
+    cpm_status rb = CPM_OK;
+    x0_buf = (double *)grow_buf(s, s->buf_warm, sizeof(double) * 2 * f * s->n, &rb);
+    if (rb != CPM_OK) return rb;
     CPM_HIP_CHECK(hipEventRecord(s->warm_ev[0], s->stream));
     cpm_status rc = warm_start_impl(s, o.warm_start == CPM_WARM_MLP, b_dev, qsol_dev, f, x0_buf,
                                     x0_buf + f * s->n);
-    if (rc != CPM_OK) {
-      (void)hipFreeAsync(x0_buf, s->stream);
-      return rc;
-    }
+    if (rc != CPM_OK) return rc;
     CPM_HIP_CHECK(hipEventRecord(s->warm_ev[1], s->stream));
     x0 = x0_buf;
     r0 = x0_buf + f * s->n;
@@ -689,7 +718,6 @@ cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev,
     return CPM_EINVAL;
   }
   cpm_status rc = solve_block(s, b_dev, qsol_dev, f, o, q_out_dev, info, x0, true, r0);
-  if (x0_buf) (void)hipFreeAsync(x0_buf, s->stream);
   if (info) {
     // the solve has synchronised the stream: the warm start's time from its
     // events, the call's from the host clock

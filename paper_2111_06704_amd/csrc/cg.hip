@@ -1572,7 +1572,7 @@ hipError_t launch_matvec(hipStream_t st, const T *E, int64_t ld, int64_t cols,
 }
 
 void free_workspace(Workspace &w) {
-  void *ptrs[] = {w.x, w.r, w.rt, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.red, w.bx, w.bres, w.flags,
+  void *ptrs[] = {w.x, w.r, w.rt, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.red, w.sum_err, w.bx, w.bres, w.flags,
                   w.xf, w.rf, w.pf, w.zf, w.vf, w.bpart};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -1612,6 +1612,7 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
             alloc((void **)&w.partial, sizeof(double) * 2 * (size_t)(nblk + npv) * cols) &&
             alloc((void **)&w.scal, sizeof(double) * S_NFIELDS * cols) &&
             alloc((void **)&w.red, sizeof(double) * 3 * MAX_COLS) &&
+            alloc((void **)&w.sum_err, sizeof(double) * MAX_COLS) &&
             alloc((void **)&w.bpart,
                   sizeof(double) * 2 * (size_t)((s->n + PC_ROWS - 1) / PC_ROWS) * cols) &&
             alloc((void **)&w.flags, sizeof(int) * F_NWORDS);
@@ -2048,13 +2049,11 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
   const int64_t ld = s->ld, n = s->n;
   hipStream_t st = s->stream;
   cpm_status result = CPM_OK;
-  double *sum_err_dev = nullptr;
-  CPM_HIP_CHECK(hipMallocAsync((void **)&sum_err_dev, sizeof(double) * MAX_COLS, st));
   for (int64_t f0 = 0; f0 < f; f0 += MAX_COLS) {
     const int fc = (int)std::min<int64_t>(MAX_COLS, f - f0);
     const int64_t cols = round_up(fc, kColGroup);
     cpm_status stt = ensure_workspace(s, cols);
-    if (stt != CPM_OK) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
+    if (stt != CPM_OK) return stt;
     hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)cols), dim3(256),
                        0, st, b_dev + f0 * n, n, (int64_t)fc, s->ws.bx, ld, cols);
     if (x0_dev) {
@@ -2075,13 +2074,13 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
     // the one synchronisation of this block
     stt = solve_columns(s, fc, o, info, fit, fres, x0_dev == nullptr,
                         x0_dev != nullptr && r0_dev != nullptr, false);
-    if (stt != CPM_OK) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
+    if (stt != CPM_OK) return stt;
     double *sum_err = s->ws.hfin + S_NFIELDS * MAX_COLS;   // pinned
     if (project) {
       hipLaunchKernelGGL(project_kernel, dim3((unsigned)fc), dim3(RED_THREADS), 0, st,
                          (const double *)s->ws.x, ld, n, s->dvec, qsol_dev + f0,
-                         q_out_dev + f0 * n, sum_err_dev);
-      CPM_HIP_CHECK(hipMemcpyAsync(sum_err, sum_err_dev, sizeof(double) * fc,
+                         q_out_dev + f0 * n, s->ws.sum_err);
+      CPM_HIP_CHECK(hipMemcpyAsync(sum_err, s->ws.sum_err, sizeof(double) * fc,
                                    hipMemcpyDeviceToHost, st));
     } else {
       CPM_HIP_CHECK(hipMemcpy2DAsync(q_out_dev + f0 * n, sizeof(double) * n, s->ws.x,
@@ -2090,7 +2089,7 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
     }
     CPM_HIP_CHECK(hipStreamSynchronize(st));
     stt = finish_solver(s, fc, cols, o.tol, info, fit, fres);
-    if (stt != CPM_OK && stt != CPM_ENOTCONV) { (void)hipFreeAsync(sum_err_dev, st); return stt; }
+    if (stt != CPM_OK && stt != CPM_ENOTCONV) return stt;
     if (stt == CPM_ENOTCONV) result = CPM_ENOTCONV;
     if (info) {
       for (int c = 0; c < fc; ++c) {
@@ -2100,7 +2099,6 @@ cpm_status solve_block(cpm_system *s, const double *b_dev, const double *qsol_de
       }
     }
   }
-  (void)hipFreeAsync(sum_err_dev, st);
   CPM_HIP_CHECK(hipStreamSynchronize(st));
   if (info)
     info->solve_ms +=

@@ -64,6 +64,7 @@ struct Workspace {            // CG scratch, grown on demand
   double *bpart = nullptr;    // per-workgroup dot partials of the preconditioner apply
   double *scal = nullptr;     // per-column scalars, see cg.hip
   double *red = nullptr;      // 3*64 doubles: reduced dot partials (p.v; r.r and r.z)
+  double *sum_err = nullptr;  // MAX_COLS doubles: |sum q + Q_sol| per column after the projection
   double *bx = nullptr;       // n_pad*cols double: right-hand sides / outer iterate
   double *bres = nullptr;     // n_pad*cols double: outer residual
   int *flags = nullptr;       // device status words
@@ -76,6 +77,13 @@ struct Workspace {            // CG scratch, grown on demand
   size_t bytes = 0;
 };
 constexpr int kStatusSlots = 2;
+
+// device buffer of a system that keeps its largest size: per-call scratch
+// (warm starts, per-frame means, error words) without an allocation per call
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
 
 struct Precond {              // PCG-DC preconditioner (P + P^T) / 2 in ELL form
   bool ready = false;
@@ -196,10 +204,20 @@ struct cpm_system {
   std::vector<double> width_host;   // n Gaussian inverse widths (host copy)
   cpm::Profile prof;
   hipEvent_t warm_ev[2] = {nullptr, nullptr};   // brackets of the warm start (its time)
+  // per-call scratch, grown on demand and kept: the warm start and its
+  // residual (2 f n), E q0 of its neutral shift (f n), per-frame means (f),
+  // and small values of one call (per-frame errors, flags, loss history,
+  // the right-hand side of q_chi)
+  cpm::DevBuf buf_warm, buf_eq, buf_mean, buf_aux;
   int64_t device_bytes = 0;
 };
 
 namespace cpm {
+
+// device pointer to at least `bytes` bytes of b, grown (after the stream has
+// drained, so no enqueued work still reads the old buffer) when too small;
+// nullptr with CPM_ENOMEM in *rc when the allocation fails
+void *grow_buf(cpm_system *s, DevBuf &b, size_t bytes, cpm_status *rc);
 
 // ---- assembly.hip
 // A (ld rows, kdim = 2 * k-vectors-per-chunk columns, column-blocked by 16):

@@ -330,15 +330,15 @@ cpm_status cpm_gcd_solve(cpm_system *s, const double *b_dev, const double *Q_dev
   const Gcd &g = s->gcd;
   cpm_status rc = solve_block(s, b_dev, nullptr, f, o, q_out_dev, info, nullptr, false);
   if (rc != CPM_OK && rc != CPM_ENOTCONV) return rc;
-  double *err = nullptr;
-  CPM_HIP_CHECK(hipMallocAsync((void **)&err, sizeof(double) * f, st));
+  cpm_status rb = CPM_OK;
+  double *err = (double *)grow_buf(s, s->buf_aux, sizeof(double) * f, &rb);
+  if (rb != CPM_OK) return rb;
   hipLaunchKernelGGL(gcd_shift_kernel, dim3((unsigned)f), dim3(GT), 0, st, q_out_dev, s->n,
                      g.labels, g.m, g.A, g.mats + g.m * g.m, Q_dev, dmu_out_dev, err);
   std::vector<double> herr(f);
   const hipError_t e1 = hipGetLastError();
   const hipError_t e2 =
       hipMemcpyAsync(herr.data(), err, sizeof(double) * f, hipMemcpyDeviceToHost, st);
-  (void)hipFreeAsync(err, st);
   if (e1 != hipSuccess || e2 != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
     set_error("total-charge shift failed");
     return CPM_EDEVICE;

@@ -725,14 +725,15 @@ cpm_status warm_start_impl(cpm_system *s, bool use_mlp, const double *b, const d
   hipStream_t st = s->stream;
   const int64_t n = s->n;
   const float *y = nullptr;
-  double *mean = nullptr;
-  CPM_HIP_CHECK(hipMallocAsync((void **)&mean, sizeof(double) * f, st));
+  cpm_status rb = CPM_OK;
+  double *mean = (double *)grow_buf(s, s->buf_mean, sizeof(double) * f, &rb);
+  if (rb != CPM_OK) return rb;
+  // E q0 for the Lagrange shift
+  double *eq = (double *)grow_buf(s, s->buf_eq, sizeof(double) * f * n, &rb);
+  if (rb != CPM_OK) return rb;
   if (use_mlp) {
     cpm_status rc = ensure_rows(s, f * n);
-    if (rc != CPM_OK) {
-      (void)hipFreeAsync(mean, st);
-      return rc;
-    }
+    if (rc != CPM_OK) return rc;
     const Mlp &M = s->mlp;
     hipLaunchKernelGGL(frame_mean_kernel, dim3((unsigned)f), dim3(256), 0, st, b, n, mean);
     const float inv_layers = M.n_layers > 1 ? 1.0f / (float)(M.n_layers - 1) : 0.0f;
@@ -747,15 +748,11 @@ cpm_status warm_start_impl(cpm_system *s, bool use_mlp, const double *b, const d
   // E q0 for the Lagrange shift: FP64 when the start's residual r0 is wanted
   // too (it is then the solver's first residual), else the FP32 copy of E
   // when there is one (the shift only sets the start)
-  double *eq = nullptr;
-  CPM_HIP_CHECK(hipMallocAsync((void **)&eq, sizeof(double) * f * n, st));
   cpm_status rc =
       matvec_cols(s, (r0 == nullptr && s->E32) ? CPM_PREC_F32 : CPM_PREC_F64, x0, f, eq);
   if (rc == CPM_OK)
     hipLaunchKernelGGL(lagrange_shift_kernel, dim3((unsigned)f), dim3(256), 0, st, b, eq,
                        s->dprime, n, x0, r0);
-  (void)hipFreeAsync(eq, st);
-  (void)hipFreeAsync(mean, st);
   CPM_HIP_CHECK(hipGetLastError());
   return rc;
 }
@@ -868,10 +865,10 @@ cpm_status cpm_mlp_features(cpm_system *s, const double *b_dev, int64_t f, float
     set_error("cpm_mlp_init first");
     return CPM_ESTATE;
   }
-  double *mean = nullptr;
-  CPM_HIP_CHECK(hipMallocAsync((void **)&mean, sizeof(double) * f, s->stream));
-  cpm_status rc = features_impl(s, b_dev, f, nullptr, 0, f * s->n, feat_out_dev, mean, true);
-  (void)hipFreeAsync(mean, s->stream);
+  cpm_status rc = CPM_OK;
+  double *mean = (double *)grow_buf(s, s->buf_mean, sizeof(double) * f, &rc);
+  if (rc != CPM_OK) return rc;
+  rc = features_impl(s, b_dev, f, nullptr, 0, f * s->n, feat_out_dev, mean, true);
   if (rc == CPM_OK) CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   return rc;
 }
@@ -946,28 +943,27 @@ cpm_status cpm_mlp_train_epoch(cpm_system *s, const double *b_dev, const double 
   const int64_t rows_total = f * s->n;
   cpm_status rc = ensure_rows(s, batch);
   if (rc != CPM_OK) return rc;
+  const int64_t nb = (rows_total + batch - 1) / batch;
+  // buf_aux: the row check's flag, then the loss of each batch
+  void *aux = grow_buf(s, s->buf_aux, std::max(sizeof(int), sizeof(double) * (size_t)nb), &rc);
+  if (rc != CPM_OK) return rc;
+  double *mean = (double *)grow_buf(s, s->buf_mean, sizeof(double) * f, &rc);
+  if (rc != CPM_OK) return rc;
   {
-    int *flag = nullptr, hflag = 0;
-    CPM_HIP_CHECK(hipMallocAsync((void **)&flag, sizeof(int), st));
+    int *flag = (int *)aux, hflag = 0;
     CPM_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
     hipLaunchKernelGGL(check_rows_kernel, dim3((unsigned)((rows_total + 255) / 256)), dim3(256), 0,
                        st, perm_dev, rows_total, rows_total, flag);
     CPM_HIP_CHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    (void)hipFreeAsync(flag, st);
     CPM_HIP_CHECK(hipStreamSynchronize(st));
     if (hflag) {
       set_error("perm holds a row id outside [0, f*n)");
       return CPM_EINVAL;
     }
   }
-  double *mean = nullptr;
-  CPM_HIP_CHECK(hipMallocAsync((void **)&mean, sizeof(double) * f, st));
   hipLaunchKernelGGL(frame_mean_kernel, dim3((unsigned)f), dim3(256), 0, st, b_dev, s->n, mean);
   const double inv_qs = 1.0 / (double)s->mlp.q_scale;
-  std::vector<double> losses;
-  double *lhist = nullptr;
-  const int64_t nb = (rows_total + batch - 1) / batch;
-  CPM_HIP_CHECK(hipMallocAsync((void **)&lhist, sizeof(double) * nb, st));
+  double *lhist = (double *)aux;
   for (int64_t bi = 0; bi < nb; ++bi) {
     const int64_t r0 = bi * batch;
     const int64_t rows = std::min(batch, rows_total - r0);
@@ -983,8 +979,6 @@ cpm_status cpm_mlp_train_epoch(cpm_system *s, const double *b_dev, const double 
   std::vector<double> lh(nb);
   if (rc == CPM_OK)
     CPM_HIP_CHECK(hipMemcpyAsync(lh.data(), lhist, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
-  (void)hipFreeAsync(lhist, st);
-  (void)hipFreeAsync(mean, st);
   CPM_HIP_CHECK(hipStreamSynchronize(st));
   if (rc != CPM_OK) return rc;
   if (mean_loss) {
@@ -1006,10 +1000,11 @@ cpm_status cpm_set_warm_chi(cpm_system *s, const double *chi_dev, const cpm_solv
     s->dprime_ready = true;
   }
   // b = chi / k_e (no electrolyte), Q_sol = 0: q_chi by the two-step solve
-  double *b = nullptr, *q0 = nullptr;
   hipStream_t st = s->stream;
-  CPM_HIP_CHECK(hipMallocAsync((void **)&b, sizeof(double) * s->n, st));
-  CPM_HIP_CHECK(hipMallocAsync((void **)&q0, sizeof(double) * 2, st));
+  cpm_status rb = CPM_OK;
+  double *q0 = (double *)grow_buf(s, s->buf_aux, sizeof(double) * (s->n + 2), &rb);
+  if (rb != CPM_OK) return rb;
+  double *b = q0 + 2;
   CPM_HIP_CHECK(hipMemsetAsync(q0, 0, sizeof(double) * 2, st));
   cpm_status rc = cpm_rhs(s, nullptr, nullptr, 0, 1, chi_dev, b, q0 + 1);
   if (rc == CPM_OK) {
@@ -1017,8 +1012,6 @@ cpm_status cpm_set_warm_chi(cpm_system *s, const double *chi_dev, const cpm_solv
     o.warm_start = CPM_WARM_ZERO;
     rc = solve_block(s, b, q0, 1, o, s->qchi, nullptr, nullptr);
   }
-  (void)hipFreeAsync(b, st);
-  (void)hipFreeAsync(q0, st);
   CPM_HIP_CHECK(hipStreamSynchronize(st));
   if (rc == CPM_OK) s->qchi_ready = true;
   return rc;

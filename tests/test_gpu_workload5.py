@@ -20,6 +20,8 @@ Checks against the FP64 oracle:
     potentials, spread <= 2e-10 |b|_2; sum q + Q_sol <= 1e-12 e; the mixed
     (FP32 + PCG-DC) and FP64 solves agree to rel_2 <= 1e-8.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -43,6 +45,8 @@ def w5():
     geo, ipos, iq, chi = wl.workload(5)
     print(f"[case] workload 5, K_max {KMAX}: N={geo.n} frames={ipos.shape[0]} "
           f"ions={ipos.shape[1]}", flush=True)
+    # the assembly prints a line per k-vector chunk: a long build stays visibly alive
+    os.environ.setdefault("CPM_PROGRESS", "1")
     S = cpm.System(geo.pos, geo.box, A, BETA, RC, kmax_override=KMAX, store=("f32",))
     print(f"[case] E built: {S.describe()}", flush=True)
     t_chi = torch.tensor(chi, device=dev)
