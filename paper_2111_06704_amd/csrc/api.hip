@@ -111,6 +111,42 @@ std::vector<int32_t> spatial_order(const std::vector<double> &pos, int64_t n) {
   return idx;
 }
 
+// Distinct z of the (wrapped) positions, when there are at most kMaxPlanes
+// of them: the z / L_z of each plane and tiles of kPlaneTile atoms of one
+// plane each (atoms in spatial order within a plane, -1 pads). Empty
+// results when the atoms spread over more planes.
+void plane_tiles(const std::vector<double> &pos, int64_t n, double lz,
+                 const std::vector<int32_t> &order, std::vector<double> &uz,
+                 std::vector<int32_t> &tile_plane, std::vector<int32_t> &tile_atom) {
+  uz.clear();
+  tile_plane.clear();
+  tile_atom.clear();
+  std::vector<double> zs;
+  for (int64_t i = 0; i < n; ++i) {
+    const double z = pos[3 * i + 2];
+    if (std::find(zs.begin(), zs.end(), z) == zs.end()) {
+      if ((int)zs.size() == kMaxPlanes) return;
+      zs.push_back(z);
+    }
+  }
+  std::sort(zs.begin(), zs.end());
+  std::vector<std::vector<int32_t>> members(zs.size());
+  for (int64_t t = 0; t < n; ++t) {
+    const int32_t i = order[t];
+    const size_t p = std::lower_bound(zs.begin(), zs.end(), pos[3 * i + 2]) - zs.begin();
+    members[p].push_back(i);
+  }
+  for (size_t p = 0; p < zs.size(); ++p) {
+    uz.push_back(zs[p] / lz);
+    const std::vector<int32_t> &m = members[p];
+    for (size_t a = 0; a < m.size(); a += kPlaneTile) {
+      tile_plane.push_back((int32_t)p);
+      for (int r = 0; r < kPlaneTile; ++r)
+        tile_atom.push_back(a + r < m.size() ? m[a + r] : -1);
+    }
+  }
+}
+
 hipEvent_t Profile::get() {
   if (!pool.empty()) {
     hipEvent_t e = pool.back();
@@ -190,7 +226,8 @@ template <typename T> cpm_status dev_alloc(cpm_system *s, T **p, size_t count) {
 
 void free_system(cpm_system *s) {
   if (!s) return;
-  void *ptrs[] = {s->pos, s->width, s->kn, s->kw, s->kinfo, s->krun, s->kcol, s->atom_order, s->E64, s->E32, s->E16, s->dinv, s->dprime,
+  void *ptrs[] = {s->pos, s->width, s->kn, s->kw, s->kinfo, s->krun, s->kcol, s->atom_order,
+                  s->plane_uz, s->plane_tile, s->plane_atom, s->E64, s->E32, s->E16, s->dinv, s->dprime,
                   s->dvec, s->qchi, s->erfc_tab, s->rhs_S, s->S, s->mlp.nbr, s->mlp.nbr_r, s->mlp.layer, s->mlp.params,
                   s->mlp.adam_m, s->mlp.adam_v, s->mlp.grad, s->mlp.gpart, s->mlp.loss,
                   s->mlp.feat, s->mlp.yout};
@@ -426,6 +463,27 @@ cpm_status cpm_build_E(const double *pos_host, int64_t n, const double *box_host
   const std::vector<int32_t> order = spatial_order(pos, n);
   BUILD_CHECK(hipMemcpyAsync(s->atom_order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
                              st));
+  if (nk > 0 && s->kset.smax <= kMaxPlaneS) {
+    std::vector<double> uz;
+    std::vector<int32_t> tp, ta;
+    plane_tiles(pos, n, box_host[2], order, uz, tp, ta);
+    if (!uz.empty()) {
+      s->nplanes = (int)uz.size();
+      s->plane_ntiles = (int64_t)tp.size();
+      if ((rc = dev_alloc(s, &s->plane_uz, uz.size())) ||
+          (rc = dev_alloc(s, &s->plane_tile, tp.size())) ||
+          (rc = dev_alloc(s, &s->plane_atom, ta.size())))
+        return fail(rc);
+      BUILD_CHECK(hipMemcpyAsync(s->plane_uz, uz.data(), sizeof(double) * uz.size(),
+                                 hipMemcpyHostToDevice, st));
+      BUILD_CHECK(hipMemcpyAsync(s->plane_tile, tp.data(), sizeof(int32_t) * tp.size(),
+                                 hipMemcpyHostToDevice, st));
+      BUILD_CHECK(hipMemcpyAsync(s->plane_atom, ta.data(), sizeof(int32_t) * ta.size(),
+                                 hipMemcpyHostToDevice, st));
+      // the host vectors go out of scope: wait for the copies
+      BUILD_CHECK(hipStreamSynchronize(st));
+    }
+  }
   BUILD_CHECK(hipMemsetAsync(s->qchi, 0, sizeof(double) * ld, st));
 
   // Reciprocal part A A^T in chunks of k-vectors whose phase matrix stays

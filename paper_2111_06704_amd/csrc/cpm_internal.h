@@ -46,6 +46,12 @@ struct Kset {
 
 constexpr int kSfTile = 64;    // columns per workgroup of the structure-factor product
 
+// electrode atoms on at most kMaxPlanes exact z-planes (graphite layers)
+// take the factored back-projection; its n_z sums keep a table of
+// |n_z| <= kMaxPlaneS per plane in LDS; kPlaneTile atoms per wave tile
+constexpr int kMaxPlanes = 64;
+constexpr int kMaxPlaneS = 1023;
+constexpr int kPlaneTile = 16;
 constexpr int kRun = 24;       // longest run of consecutive n_z (phase recurrence length)
 
 // Half-space reciprocal vectors with |K| <= kmax, K != 0 (host).
@@ -182,6 +188,14 @@ struct cpm_system {
   int32_t *krun = nullptr;    // nruns*2 device (Kset::runs)
   int32_t *kcol = nullptr;    // ncols_pad*4 device (Kset::cols)
   int32_t *atom_order = nullptr;  // n device: atoms in compact spatial tiles (real-space sums)
+  // the atoms' z-planes when there are at most kMaxPlanes of them (else
+  // nplanes = 0): z / L_z per plane, and tiles of kPlaneTile atoms of one
+  // plane each (atom -1 pads a plane's last tile)
+  int nplanes = 0;
+  int64_t plane_ntiles = 0;
+  double *plane_uz = nullptr;
+  int32_t *plane_tile = nullptr;  // plane_ntiles: plane of the tile
+  int32_t *plane_atom = nullptr;  // plane_ntiles * kPlaneTile
   double *E64 = nullptr;      // ld*ld device (rows >= n and cols >= n are zero)
   float *E32 = nullptr;
   uint16_t *E16 = nullptr;

@@ -404,6 +404,116 @@ __global__ __launch_bounds__(RB) void backproject_kernel(
   }
 }
 
+// Factored back-projection for electrode atoms on few z-planes. With
+// exp(i K.r) = P_c(x, y) Z_nz(z), P_c = exp(2 pi i (n_x x / L_x + n_y y / L_y)),
+// Z_nz = exp(2 pi i n_z z / L_z), for the column c = (n_x, n_y):
+//   sum_K w_K Re(exp(-i K.r_i) S_fK) = sum_c Re(conj(P_c(r_i)) T_f(p, c)),
+//   T_f(p, c) = sum_nz w_(c, nz) conj(Z_nz(z_p)) S_f(c, nz),
+// where z_p is the z shared by every atom of plane p: the n_z sums are
+// taken once per (plane, column, frame) instead of once per atom.
+//
+// plane_table_kernel: T as Re / Im arrays [plane][column][frame] (zero for
+// the padding columns). Grid (columns * frames / PT_THREADS, planes); the
+// plane's Z_s for s = 0..smax sit in LDS (sincospi of the reduced
+// fractional phase), Z_-s = conj(Z_s).
+constexpr int PT_THREADS = 256;
+
+__global__ __launch_bounds__(PT_THREADS) void plane_table_kernel(
+    const double *__restrict__ plane_uz, const int4 *__restrict__ kcol, int64_t ncols_pad,
+    const double *__restrict__ kw, const double *__restrict__ S, int64_t f_total, int smax,
+    double *__restrict__ Tre, double *__restrict__ Tim) {
+  __shared__ double2 zt[kMaxPlaneS + 1];
+  const int p = blockIdx.y;
+  const double u = plane_uz[p];
+  for (int sv = threadIdx.x; sv <= smax; sv += PT_THREADS) {
+    double t = (double)sv * u;
+    t -= rint(t);
+    double sn, cs;
+    sincospi(2.0 * t, &sn, &cs);
+    zt[sv] = make_double2(cs, sn);
+  }
+  __syncthreads();
+  const int64_t idx = (int64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+  if (idx >= ncols_pad * f_total) return;
+  const int64_t c = idx / f_total, f = idx - c * f_total;
+  const int4 col = kcol[c];
+  double re = 0.0, im = 0.0;
+  if (col.z >= 0) {
+    // (0, 0) holds n_z = 1..m only
+    const int lo = (col.x == 0 && col.y == 0) ? 1 : -col.z;
+    for (int nz = lo; nz <= col.z; ++nz) {
+      const int64_t k = (int64_t)col.w + nz;
+      const double2 sv = *reinterpret_cast<const double2 *>(S + (k * f_total + f) * 2);
+      const double w = kw[k];
+      const double2 z = zt[nz < 0 ? -nz : nz];
+      const double zi = nz < 0 ? -z.y : z.y;   // Im Z_nz
+      // conj(Z) S = (Re Z Re S + Im Z Im S) + i (Re Z Im S - Im Z Re S)
+      re = fma(w, fma(z.x, sv.x, zi * sv.y), re);
+      im = fma(w, fma(z.x, sv.y, -zi * sv.x), im);
+    }
+  }
+  const int64_t o = ((int64_t)p * ncols_pad + c) * f_total + f;
+  Tre[o] = re;
+  Tim[o] = im;
+}
+
+// part[f][i] = sum_c cos(theta_ic) Re T_f(p, c) + sin(theta_ic) Im T_f(p, c),
+// theta_ic = 2 pi (n_x x_i / L_x + n_y y_i / L_y): the product
+// [atoms x (cos, sin) of the columns] . [(Re T, Im T) x frames] on the FP64
+// matrix cores. One wave per tile of kPlaneTile atoms of one plane and up to
+// 32 frames: per step of 4 columns, lane (r, q) forms the phase of atom r
+// and column q once (sincospi of the reduced fractional phase) and gives
+// its cosine and sine as the A operand of two v_mfma_f64_16x16x4f64 per 16
+// frames, with Re T and Im T of (column q, frame r) as the B operand.
+// Grid (tiles / PB_WAVES, frames / 32).
+constexpr int PB_WAVES = 4;
+
+__global__ __launch_bounds__(64 * PB_WAVES) void plane_backproject_kernel(
+    const double *__restrict__ pos, int64_t n, const int32_t *__restrict__ tile_plane,
+    const int32_t *__restrict__ tile_atom, int64_t ntiles, const int4 *__restrict__ kcol,
+    int64_t ncols_pad, double inv_lx, double inv_ly, const double *__restrict__ Tre,
+    const double *__restrict__ Tim, int64_t f_total, double *__restrict__ part) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * PB_WAVES + wave;
+  if (t >= ntiles) return;   // no barriers below: a wave may leave alone
+  const int lr = lane & 15, lq = lane >> 4;
+  const int p = tile_plane[t];
+  const int32_t atom = tile_atom[t * kPlaneTile + lr];
+  double ux = 0.0, uy = 0.0;
+  if (atom >= 0) {
+    ux = pos[3 * (int64_t)atom] * inv_lx;
+    uy = pos[3 * (int64_t)atom + 1] * inv_ly;
+  }
+  const int64_t fa = (int64_t)blockIdx.y * 32 + lr, fb = fa + 16;
+  const bool va = fa < f_total, vb = fb < f_total;
+  const double *tr = Tre + (int64_t)p * ncols_pad * f_total;
+  const double *ti = Tim + (int64_t)p * ncols_pad * f_total;
+  d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t c0 = 0; c0 < ncols_pad; c0 += 4) {
+    const int64_t c = c0 + lq;
+    const int4 col = kcol[c];
+    double th = (double)col.x * ux + (double)col.y * uy;
+    th -= rint(th);
+    double sn, cs;
+    sincospi(2.0 * th, &sn, &cs);
+    const int64_t o = c * f_total;
+    const double ra = va ? tr[o + fa] : 0.0, ia = va ? ti[o + fa] : 0.0;
+    const double rb = vb ? tr[o + fb] : 0.0, ib = vb ? ti[o + fb] : 0.0;
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cs, ra, acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(sn, ia, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cs, rb, acc1, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(sn, ib, acc1, 0, 0, 0);
+  }
+  // D[i][j] (atom i of the tile, frame j) in lane j + 16 (i % 4), register i / 4
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int32_t a = tile_atom[t * kPlaneTile + 4 * v + lq];
+    if (a < 0) continue;
+    if (va) part[fa * n + a] = acc0[v];
+    if (vb) part[fb * n + a] = acc1[v];
+  }
+}
+
 // b[f, i] = chi_i / k_e - sum_ks bp[ks][f][i] - sum_g rs[g][f][i] - c0 Q_f
 // (fixed order over the k splits and ion groups); slab geometry (Eq. 39 in
 // its definite form): - (4 pi / V) M1_f z_i.
@@ -832,14 +942,16 @@ namespace {
 //   S   [nk][f][2]             structure factors
 //   Sg  [sf_groups][nk][f][2]  per ion group (only when sf_groups > 1)
 //   bp  [ksplit][f][n]         back-projection partials
+//   T   [2][planes][cols][f]   per-plane n_z sums (factored back-projection)
 //   rs  [rs_groups][f][n]      real-space partials
 struct RhsPlan {
   int64_t sf_groups = 1, sf_ipg = 0, ksplit = 0, kper = 0, rs_groups = 0, rs_ipg = 0;
   bool sf_gemm = false;         // structure factors on the matrix cores (|n_z| <= 63)
+  bool bp_plane = false;        // factored back-projection over the atoms' z-planes
   bool rs_cell = false;         // real space over the cell list of the ions
   int nc[3] = {1, 1, 1};        // cells per box edge
   int64_t nchunks = 0;          // sorting chunks per frame
-  int64_t off_sg = 0, off_bp = 0, off_rs = 0, off_m1 = 0, off_sorted = 0, off_keys = 0,
+  int64_t off_sg = 0, off_bp = 0, off_tp = 0, off_rs = 0, off_m1 = 0, off_sorted = 0, off_keys = 0,
           off_hist = 0, off_cstart = 0, total = 0;
 };
 
@@ -878,7 +990,7 @@ int64_t groups_for(int64_t blocks, int64_t items, int64_t cap, int64_t &per) {
 // the back-projection and the ion groups of the real-space sum (fewer
 // partial buffers, less parallelism)
 RhsPlan rhs_plan_capped(const cpm_system *s, int64_t m, int64_t f, int64_t cap_sf,
-                        int64_t cap_ks, int64_t cap_rs) {
+                        int64_t cap_ks, int64_t cap_rs, bool planes) {
   RhsPlan p;
   const int64_t n = s->n, nk = std::max<int64_t>(s->kset.nk, 1);
   const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
@@ -897,6 +1009,11 @@ RhsPlan rhs_plan_capped(const cpm_system *s, int64_t m, int64_t f, int64_t cap_s
                             std::max<int64_t>(1, kPartialCap / (f * n)), cap_ks});
     p.kper = (nk + ks - 1) / ks;
     p.ksplit = (nk + p.kper - 1) / p.kper;
+    if (planes && s->nplanes > 0) {
+      p.bp_plane = true;
+      p.kper = nk;
+      p.ksplit = 1;
+    }
   }
   if (m >= kCellMinIons) {
     p.rs_cell = true;
@@ -909,7 +1026,8 @@ RhsPlan rhs_plan_capped(const cpm_system *s, int64_t m, int64_t f, int64_t cap_s
   const int64_t ncell = (int64_t)p.nc[0] * p.nc[1] * p.nc[2];
   p.off_sg = 2 * nk * f;
   p.off_bp = p.off_sg + (p.sf_groups > 1 ? p.sf_groups * 2 * nk * f : 0);
-  p.off_rs = p.off_bp + p.ksplit * f * n;
+  p.off_tp = p.off_bp + p.ksplit * f * n;
+  p.off_rs = p.off_tp + (p.bp_plane ? 2 * (int64_t)s->nplanes * s->kset.ncols_pad * f : 0);
   p.off_m1 = p.off_rs + p.rs_groups * f * n;
   p.off_sorted = (p.off_m1 + f + 3) / 4 * 4;   // 32-byte aligned (double4)
   p.off_keys = p.off_sorted + (p.rs_cell ? 4 * f * m : 0);
@@ -924,18 +1042,22 @@ constexpr int64_t kNoCap = (int64_t)1 << 40;
 // the default plan, or with limit > 0 the most parallel plan whose scratch
 // holds at most limit doubles (halving the largest partial count first)
 RhsPlan rhs_plan(const cpm_system *s, int64_t m, int64_t f, int64_t limit = 0) {
-  RhsPlan p = rhs_plan_capped(s, m, f, kNoCap, kNoCap, kNoCap);
-  int64_t csf = p.sf_groups, cks = std::max<int64_t>(1, p.ksplit), crs = p.rs_groups;
-  while (limit > 0 && p.total > limit && (csf > 1 || cks > 1 || crs > 1)) {
-    const int64_t nk = std::max<int64_t>(s->kset.nk, 1);
-    const int64_t wsf = csf > 1 ? csf * 2 * nk * f : 0, wks = cks > 1 ? cks * f * s->n : 0,
-                  wrs = crs > 1 ? crs * f * s->n : 0;
-    if (wsf >= wks && wsf >= wrs) csf = std::max<int64_t>(1, csf / 2);
-    else if (wks >= wrs) cks = std::max<int64_t>(1, cks / 2);
-    else crs = std::max<int64_t>(1, crs / 2);
-    p = rhs_plan_capped(s, m, f, csf, cks, crs);
+  // the factored back-projection first; without it when its per-plane sums
+  // do not fit the limit
+  for (int planes = 1;; planes = 0) {
+    RhsPlan p = rhs_plan_capped(s, m, f, kNoCap, kNoCap, kNoCap, planes != 0);
+    int64_t csf = p.sf_groups, cks = std::max<int64_t>(1, p.ksplit), crs = p.rs_groups;
+    while (limit > 0 && p.total > limit && (csf > 1 || cks > 1 || crs > 1)) {
+      const int64_t nk = std::max<int64_t>(s->kset.nk, 1);
+      const int64_t wsf = csf > 1 ? csf * 2 * nk * f : 0, wks = cks > 1 ? cks * f * s->n : 0,
+                    wrs = crs > 1 ? crs * f * s->n : 0;
+      if (wsf >= wks && wsf >= wrs) csf = std::max<int64_t>(1, csf / 2);
+      else if (wks >= wrs) cks = std::max<int64_t>(1, cks / 2);
+      else crs = std::max<int64_t>(1, crs / 2);
+      p = rhs_plan_capped(s, m, f, csf, cks, crs, planes != 0);
+    }
+    if (limit <= 0 || p.total <= limit || !p.bp_plane) return p;
   }
-  return p;
 }
 
 // ---- cpm_rhs_noalloc: the scratch in a fixed device array
@@ -1016,10 +1138,28 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
       hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
                          Sg, (int)p.sf_groups, len, S);
     }
-    const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
-    hipLaunchKernelGGL(backproject_kernel<BP_AT>, dim3((unsigned)bblocks, (unsigned)p.ksplit, (unsigned)fgroups),
-                       dim3(RB), 0, st, s->pos, n, s->kinfo, s->kw, nk, p.kper, ilx, ily, ilz, S, f,
-                       bp);
+    if (p.bp_plane) {
+      const int64_t ncp = s->kset.ncols_pad;
+      double *Tre = buf + p.off_tp, *Tim = Tre + (int64_t)s->nplanes * ncp * f;
+      hipLaunchKernelGGL(plane_table_kernel,
+                         dim3((unsigned)((ncp * f + PT_THREADS - 1) / PT_THREADS),
+                              (unsigned)s->nplanes),
+                         dim3(PT_THREADS), 0, st, (const double *)s->plane_uz,
+                         reinterpret_cast<const int4 *>(s->kcol), ncp, (const double *)s->kw,
+                         (const double *)S, f, s->kset.smax, Tre, Tim);
+      hipLaunchKernelGGL(plane_backproject_kernel,
+                         dim3((unsigned)((s->plane_ntiles + PB_WAVES - 1) / PB_WAVES),
+                              (unsigned)((f + 31) / 32)),
+                         dim3(64 * PB_WAVES), 0, st, (const double *)s->pos, n,
+                         (const int32_t *)s->plane_tile, (const int32_t *)s->plane_atom,
+                         s->plane_ntiles, reinterpret_cast<const int4 *>(s->kcol), ncp, ilx, ily,
+                         (const double *)Tre, (const double *)Tim, f, bp);
+    } else {
+      const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
+      hipLaunchKernelGGL(backproject_kernel<BP_AT>,
+                         dim3((unsigned)bblocks, (unsigned)p.ksplit, (unsigned)fgroups), dim3(RB),
+                         0, st, s->pos, n, s->kinfo, s->kw, nk, p.kper, ilx, ily, ilz, S, f, bp);
+    }
   }
   if (p.rs_cell) {
     double4 *sorted = reinterpret_cast<double4 *>(buf + p.off_sorted);
