@@ -191,86 +191,117 @@ __global__ __launch_bounds__(RB) void structure_factor_kernel(
 // ions, AZ = sum a z, BW = sum b w, AW = sum a w, BZ = sum b z:
 //   S(c, +s) = (AZ - BW) + i (AW + BZ),  S(c, -s) = (AZ + BW) + i (BZ - AW),
 // one pass over the ions for both signs of n_z. A workgroup takes 64
-// columns (a wave each 16: the A operand rows) and the s blocks of 16 its
-// largest |n_z| needs (columns sorted by it), and streams its ion group in
-// chunks: per chunk the Z_s of every ion go to LDS (sincospi of the reduced
-// fractional phase), per step of 4 ions each lane forms its (column, ion)
-// entry of q P the same way; v_mfma_f64_16x16x4f64 accumulates the four
-// products. Output: Sg as in structure_factor_kernel.
+// columns (a wave each 16: the A operand rows) and NSB blocks of 16 s (the
+// columns are sorted by their largest |n_z|, and each range of tiles with
+// the same block count has its own launch), and streams its ion group in
+// chunks of SG_CH ions through two LDS buffers:
+//   - table phase: the chunk's x / L_x, y / L_y, q and Z_s for s < 16 NSB,
+//     eight threads per ion, each a run of 2 NSB consecutive s (Z_s0 by
+//     sincospi of the reduced fractional phase, then Z_(s+1) = Z_s Z_1);
+//     the raw positions were loaded into registers one chunk ahead;
+//   - product phase: per step of 4 ions each lane forms its (column, ion)
+//     entry of q P (sincospi) and v_mfma_f64_16x16x4f64 accumulates the
+//     four products for every s block.
+// One barrier per chunk: the table of chunk c + 1 goes to the buffer that
+// the product phase of chunk c - 1 read, and every wave has left that phase
+// before the barrier of chunk c. Output: Sg as in structure_factor_kernel.
 constexpr int SG_CH = 32;      // ions per LDS chunk
 constexpr int SG_SB = 4;       // s blocks of 16 at most (|n_z| <= 63)
 
+template <int NSB>
 __global__ __launch_bounds__(256, 2) void sf_gemm_kernel(
     const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m, int64_t ipg,
-    const int4 *__restrict__ kcol, double inv_lx, double inv_ly, double inv_lz, int64_t nk,
-    int64_t f_total, double *__restrict__ Sg) {
-  __shared__ double2 zt[SG_CH][SG_SB * 16];
-  __shared__ double su[SG_CH][3];   // x / L_x, y / L_y, q
+    const int4 *__restrict__ kcol, int64_t tile0, double inv_lx, double inv_ly, double inv_lz,
+    int64_t nk, int64_t f_total, double *__restrict__ Sg) {
+  constexpr int NS = 16 * NSB;        // s values of the tables
+  constexpr int PER = NS / 8;         // s values per table thread
+  __shared__ double2 zt[2][SG_CH][NS];
+  __shared__ double su[2][SG_CH][3];   // x / L_x, y / L_y, q
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lg = lane >> 4;
-  const int64_t cbase = (int64_t)blockIdx.x * kSfTile;
+  const int64_t cbase = (tile0 + (int64_t)blockIdx.x) * kSfTile;
   const int64_t f = blockIdx.y, g = blockIdx.z;
-  // columns are sorted by their largest |n_z|: the first one sets the blocks
-  const int nsb = (kcol[cbase].z + 16) / 16;
   const int4 mycol = kcol[cbase + wave * 16 + lr];
   const double cnx = (double)mycol.x, cny = (double)mycol.y;
-  d4 acc[SG_SB][4];
+  d4 acc[NSB][4];
 #pragma unroll
-  for (int sb = 0; sb < SG_SB; ++sb)
+  for (int sb = 0; sb < NSB; ++sb)
 #pragma unroll
     for (int p = 0; p < 4; ++p) acc[sb][p] = d4{0.0, 0.0, 0.0, 0.0};
   const double *pf = ion_pos + f * m * 3;
   const double *qf = ion_q + f * m;
   const int64_t i0 = g * ipg, i1 = min(m, i0 + ipg);
-  const int ns = nsb * 16;
-  for (int64_t base = i0; base < i1; base += SG_CH) {
-    const int cnt = (int)((i1 - base) < SG_CH ? (i1 - base) : SG_CH);
-    if (tid < SG_CH) {
-      double ux = 0.0, uy = 0.0, q = 0.0;   // missing ions enter with q = 0
-      if (tid < cnt) {
-        ux = pf[3 * (base + tid)] * inv_lx;
-        uy = pf[3 * (base + tid) + 1] * inv_ly;
-        q = qf[base + tid];
+  const int nchunks = (int)((i1 - i0 + SG_CH - 1) / SG_CH);
+  // table thread: ion ti of the chunk, run tj of s values
+  const int ti = tid >> 3, tj = tid & 7;
+  double rx = 0.0, ry = 0.0, rz = 0.0, rq = 0.0;   // raw data of the next chunk
+  auto fetch = [&](int c) {
+    const int64_t I = i0 + (int64_t)c * SG_CH + ti;
+    rx = ry = rz = rq = 0.0;   // missing ions: q = 0 (and Z = 1)
+    if (I < i1) {
+      rx = pf[3 * I];
+      ry = pf[3 * I + 1];
+      rz = pf[3 * I + 2];
+      rq = qf[I];
+    }
+  };
+  auto table = [&](int buf) {
+    const double uz = rz * inv_lz;
+    if (tj == 0) {
+      su[buf][ti][0] = rx * inv_lx;
+      su[buf][ti][1] = ry * inv_ly;
+      su[buf][ti][2] = rq;
+    }
+    double t = (double)(tj * PER) * uz;
+    t -= rint(t);
+    double sn, cs;
+    sincospi(2.0 * t, &sn, &cs);
+    zt[buf][ti][tj * PER] = make_double2(cs, sn);
+    if (PER > 1) {
+      double t1 = uz - rint(uz), s1, c1;
+      sincospi(2.0 * t1, &s1, &c1);
+#pragma unroll
+      for (int u = 1; u < PER; ++u) {
+        const double c2 = cs * c1 - sn * s1;
+        sn = sn * c1 + cs * s1;
+        cs = c2;
+        zt[buf][ti][tj * PER + u] = make_double2(cs, sn);
       }
-      su[tid][0] = ux;
-      su[tid][1] = uy;
-      su[tid][2] = q;
     }
-    for (int e = tid; e < SG_CH * ns; e += 256) {
-      const int ion = e / ns, sidx = e - ion * ns;
-      double t = 0.0;
-      if (ion < cnt) t = (double)sidx * (pf[3 * (base + ion) + 2] * inv_lz);
-      t -= rint(t);
-      double sn, cs;
-      sincospi(2.0 * t, &sn, &cs);
-      zt[ion][sidx] = make_double2(cs, sn);
-    }
+  };
+  if (nchunks > 0) {
+    fetch(0);
+    table(0);
+  }
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
     __syncthreads();
+    if (c + 1 < nchunks) fetch(c + 1);   // in flight during the products
 #pragma unroll 2
     for (int ks = 0; ks < SG_CH / 4; ++ks) {
       const int ion = ks * 4 + lg;
-      double t = cnx * su[ion][0] + cny * su[ion][1];
+      double2 z[NSB];
+#pragma unroll
+      for (int sb = 0; sb < NSB; ++sb) z[sb] = zt[buf][ion][sb * 16 + lr];
+      double t = cnx * su[buf][ion][0] + cny * su[buf][ion][1];
       t -= rint(t);
       double sn, cs;
       sincospi(2.0 * t, &sn, &cs);
-      const double a = su[ion][2] * cs, b = su[ion][2] * sn;
+      const double q = su[buf][ion][2];
+      const double a = q * cs, b = q * sn;
 #pragma unroll
-      for (int sb = 0; sb < SG_SB; ++sb) {
-        if (sb < nsb) {
-          const double2 z = zt[ion][sb * 16 + lr];
-          acc[sb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z.x, acc[sb][0], 0, 0, 0);
-          acc[sb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, z.y, acc[sb][1], 0, 0, 0);
-          acc[sb][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z.y, acc[sb][2], 0, 0, 0);
-          acc[sb][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, z.x, acc[sb][3], 0, 0, 0);
-        }
+      for (int sb = 0; sb < NSB; ++sb) {
+        acc[sb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z[sb].x, acc[sb][0], 0, 0, 0);
+        acc[sb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, z[sb].y, acc[sb][1], 0, 0, 0);
+        acc[sb][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z[sb].y, acc[sb][2], 0, 0, 0);
+        acc[sb][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, z[sb].x, acc[sb][3], 0, 0, 0);
       }
     }
-    __syncthreads();
+    if (c + 1 < nchunks) table(buf ^ 1);
   }
   // D[i][j] (column i, s = j of the block) in lane j + 16 (i % 4), register i / 4
 #pragma unroll
-  for (int sb = 0; sb < SG_SB; ++sb) {
-    if (sb >= nsb) break;
+  for (int sb = 0; sb < NSB; ++sb) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int4 col = kcol[cbase + wave * 16 + 4 * v + lg];
@@ -290,6 +321,33 @@ __global__ __launch_bounds__(256, 2) void sf_gemm_kernel(
         o[1] = BZ - AW;
       }
     }
+  }
+}
+
+// launch of the tiles [t0, t1) of the structure-factor product, all with
+// NSB s blocks
+void launch_sf_gemm(hipStream_t st, int nsb, int64_t t0, int64_t t1, int64_t f, int64_t groups,
+                    const double *ion_pos, const double *ion_q, int64_t m, int64_t ipg,
+                    const int4 *kcol, double ilx, double ily, double ilz, int64_t nk, double *Sg) {
+  if (t1 <= t0) return;
+  const dim3 grid((unsigned)(t1 - t0), (unsigned)f, (unsigned)groups);
+  switch (nsb) {
+    case 1:
+      hipLaunchKernelGGL(sf_gemm_kernel<1>, grid, dim3(256), 0, st, ion_pos, ion_q, m, ipg, kcol,
+                         t0, ilx, ily, ilz, nk, f, Sg);
+      break;
+    case 2:
+      hipLaunchKernelGGL(sf_gemm_kernel<2>, grid, dim3(256), 0, st, ion_pos, ion_q, m, ipg, kcol,
+                         t0, ilx, ily, ilz, nk, f, Sg);
+      break;
+    case 3:
+      hipLaunchKernelGGL(sf_gemm_kernel<3>, grid, dim3(256), 0, st, ion_pos, ion_q, m, ipg, kcol,
+                         t0, ilx, ily, ilz, nk, f, Sg);
+      break;
+    default:
+      hipLaunchKernelGGL(sf_gemm_kernel<4>, grid, dim3(256), 0, st, ion_pos, ion_q, m, ipg, kcol,
+                         t0, ilx, ily, ilz, nk, f, Sg);
+      break;
   }
 }
 
@@ -1124,12 +1182,21 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
   if (p.ksplit > 0) {
     double *Sg = p.sf_groups > 1 ? buf + p.off_sg : S;
     const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
-    if (p.sf_gemm)
-      hipLaunchKernelGGL(sf_gemm_kernel, dim3((unsigned)(s->kset.ncols_pad / kSfTile), (unsigned)f,
-                                              (unsigned)p.sf_groups),
-                         dim3(256), 0, st, ion_pos, ion_q, m, p.sf_ipg,
-                         reinterpret_cast<const int4 *>(s->kcol), ilx, ily, ilz, nk, f, Sg);
-    else
+    if (p.sf_gemm) {
+      // tiles by their s-block count (the first column of a tile has its
+      // largest |n_z|; the count does not increase along the tiles)
+      const int64_t ntile = s->kset.ncols_pad / kSfTile;
+      int64_t t0 = 0;
+      while (t0 < ntile) {
+        const int nsb = std::max(1, (s->kset.cols[4 * t0 * kSfTile + 2] + 16) / 16);
+        int64_t t1 = t0 + 1;
+        while (t1 < ntile && std::max(1, (s->kset.cols[4 * t1 * kSfTile + 2] + 16) / 16) == nsb)
+          ++t1;
+        launch_sf_gemm(st, nsb, t0, t1, f, p.sf_groups, ion_pos, ion_q, m, p.sf_ipg,
+                       reinterpret_cast<const int4 *>(s->kcol), ilx, ily, ilz, nk, Sg);
+        t0 = t1;
+      }
+    } else
       hipLaunchKernelGGL(structure_factor_kernel, dim3((unsigned)rblocks, (unsigned)f, (unsigned)p.sf_groups),
                          dim3(RB), 0, st, ion_pos, ion_q, m, p.sf_ipg, s->kinfo, s->krun,
                          s->kset.nruns, nk, ilx, ily, ilz, f, Sg);
