@@ -192,9 +192,9 @@ __global__ __launch_bounds__(RB) void structure_factor_kernel(
 //   S(c, +s) = (AZ - BW) + i (AW + BZ),  S(c, -s) = (AZ + BW) + i (BZ - AW),
 // one pass over the ions for both signs of n_z. A workgroup takes 64
 // columns (a wave each 16: the A operand rows) and NSB blocks of 16 s (the
-// columns are sorted by their largest |n_z|, and each range of tiles with
-// the same block count has its own launch), and streams its ion group in
-// chunks of SG_CH ions through two LDS buffers:
+// columns are sorted by their largest |n_z|; the body is compiled for each
+// block count), and streams its ion group in chunks of SG_CH ions through
+// two LDS buffers:
 //   - table phase: the chunk's x / L_x, y / L_y, q and Z_s for s < 16 NSB,
 //     eight threads per ion, each a run of 2 NSB consecutive s (Z_s0 by
 //     sincospi of the reduced fractional phase, then Z_(s+1) = Z_s Z_1);
@@ -206,21 +206,26 @@ __global__ __launch_bounds__(RB) void structure_factor_kernel(
 // the product phase of chunk c - 1 read, and every wave has left that phase
 // before the barrier of chunk c. Output: Sg as in structure_factor_kernel.
 constexpr int SG_CH = 32;      // ions per LDS chunk
-constexpr int SG_SB = 4;       // s blocks of 16 at most (|n_z| <= 63)
+constexpr int SG_SB = 3;       // s blocks of 16 at most (|n_z| <= 47)
+
+// LDS of one workgroup: two chunk buffers of Z tables (SG_CH ions x 16 NSB
+// s values, sized for the largest NSB) and of x / L_x, y / L_y, q
+struct SfLds {
+  double2 zt[2][SG_CH][16 * SG_SB];
+  double su[2][SG_CH][3];
+};
 
 template <int NSB>
-__global__ __launch_bounds__(256, 2) void sf_gemm_kernel(
-    const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m, int64_t ipg,
-    const int4 *__restrict__ kcol, int64_t tile0, double inv_lx, double inv_ly, double inv_lz,
-    int64_t nk, int64_t f_total, double *__restrict__ Sg) {
+__device__ __forceinline__ void sf_gemm_body(SfLds &L, const double *__restrict__ ion_pos,
+                                             const double *__restrict__ ion_q, int64_t m,
+                                             int64_t ipg, const int4 *__restrict__ kcol,
+                                             int64_t cbase, int64_t f, int64_t g, double inv_lx,
+                                             double inv_ly, double inv_lz, int64_t nk,
+                                             int64_t f_total, double *__restrict__ Sg) {
   constexpr int NS = 16 * NSB;        // s values of the tables
   constexpr int PER = NS / 8;         // s values per table thread
-  __shared__ double2 zt[2][SG_CH][NS];
-  __shared__ double su[2][SG_CH][3];   // x / L_x, y / L_y, q
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lg = lane >> 4;
-  const int64_t cbase = (tile0 + (int64_t)blockIdx.x) * kSfTile;
-  const int64_t f = blockIdx.y, g = blockIdx.z;
   const int4 mycol = kcol[cbase + wave * 16 + lr];
   const double cnx = (double)mycol.x, cny = (double)mycol.y;
   d4 acc[NSB][4];
@@ -248,15 +253,15 @@ __global__ __launch_bounds__(256, 2) void sf_gemm_kernel(
   auto table = [&](int buf) {
     const double uz = rz * inv_lz;
     if (tj == 0) {
-      su[buf][ti][0] = rx * inv_lx;
-      su[buf][ti][1] = ry * inv_ly;
-      su[buf][ti][2] = rq;
+      L.su[buf][ti][0] = rx * inv_lx;
+      L.su[buf][ti][1] = ry * inv_ly;
+      L.su[buf][ti][2] = rq;
     }
     double t = (double)(tj * PER) * uz;
     t -= rint(t);
     double sn, cs;
     sincospi(2.0 * t, &sn, &cs);
-    zt[buf][ti][tj * PER] = make_double2(cs, sn);
+    L.zt[buf][ti][tj * PER] = make_double2(cs, sn);
     if (PER > 1) {
       double t1 = uz - rint(uz), s1, c1;
       sincospi(2.0 * t1, &s1, &c1);
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(256, 2) void sf_gemm_kernel(
         const double c2 = cs * c1 - sn * s1;
         sn = sn * c1 + cs * s1;
         cs = c2;
-        zt[buf][ti][tj * PER + u] = make_double2(cs, sn);
+        L.zt[buf][ti][tj * PER + u] = make_double2(cs, sn);
       }
     }
   };
@@ -282,12 +287,12 @@ __global__ __launch_bounds__(256, 2) void sf_gemm_kernel(
       const int ion = ks * 4 + lg;
       double2 z[NSB];
 #pragma unroll
-      for (int sb = 0; sb < NSB; ++sb) z[sb] = zt[buf][ion][sb * 16 + lr];
-      double t = cnx * su[buf][ion][0] + cny * su[buf][ion][1];
+      for (int sb = 0; sb < NSB; ++sb) z[sb] = L.zt[buf][ion][sb * 16 + lr];
+      double t = cnx * L.su[buf][ion][0] + cny * L.su[buf][ion][1];
       t -= rint(t);
       double sn, cs;
       sincospi(2.0 * t, &sn, &cs);
-      const double q = su[buf][ion][2];
+      const double q = L.su[buf][ion][2];
       const double a = q * cs, b = q * sn;
 #pragma unroll
       for (int sb = 0; sb < NSB; ++sb) {
@@ -324,31 +329,28 @@ __global__ __launch_bounds__(256, 2) void sf_gemm_kernel(
   }
 }
 
-// launch of the tiles [t0, t1) of the structure-factor product, all with
-// NSB s blocks
-void launch_sf_gemm(hipStream_t st, int nsb, int64_t t0, int64_t t1, int64_t f, int64_t groups,
-                    const double *ion_pos, const double *ion_q, int64_t m, int64_t ipg,
-                    const int4 *kcol, double ilx, double ily, double ilz, int64_t nk, double *Sg) {
-  if (t1 <= t0) return;
-  const dim3 grid((unsigned)(t1 - t0), (unsigned)f, (unsigned)groups);
-  switch (nsb) {
-    case 1:
-      hipLaunchKernelGGL(sf_gemm_kernel<1>, grid, dim3(256), 0, st, ion_pos, ion_q, m, ipg, kcol,
-                         t0, ilx, ily, ilz, nk, f, Sg);
-      break;
-    case 2:
-      hipLaunchKernelGGL(sf_gemm_kernel<2>, grid, dim3(256), 0, st, ion_pos, ion_q, m, ipg, kcol,
-                         t0, ilx, ily, ilz, nk, f, Sg);
-      break;
-    case 3:
-      hipLaunchKernelGGL(sf_gemm_kernel<3>, grid, dim3(256), 0, st, ion_pos, ion_q, m, ipg, kcol,
-                         t0, ilx, ily, ilz, nk, f, Sg);
-      break;
-    default:
-      hipLaunchKernelGGL(sf_gemm_kernel<4>, grid, dim3(256), 0, st, ion_pos, ion_q, m, ipg, kcol,
-                         t0, ilx, ily, ilz, nk, f, Sg);
-      break;
-  }
+// One launch for every tile: grid (frames, tiles, ion groups), so that the
+// dispatch order runs through the frames of the first tiles (the most s
+// blocks, the longest workgroups) first and ends with the tiles of one s
+// block; the s-block count of a tile is set by its first column (the
+// columns are sorted by their largest |n_z|) and selects the body compiled
+// for it.
+__global__ __launch_bounds__(256, 2) void sf_gemm_kernel(
+    const double *__restrict__ ion_pos, const double *__restrict__ ion_q, int64_t m, int64_t ipg,
+    const int4 *__restrict__ kcol, double inv_lx, double inv_ly, double inv_lz, int64_t nk,
+    int64_t f_total, double *__restrict__ Sg) {
+  __shared__ SfLds L;
+  const int64_t f = blockIdx.x, cbase = (int64_t)blockIdx.y * kSfTile, g = blockIdx.z;
+  const int nsb = (kcol[cbase].z + 16) / 16;
+  if (nsb >= 3)
+    sf_gemm_body<3>(L, ion_pos, ion_q, m, ipg, kcol, cbase, f, g, inv_lx, inv_ly, inv_lz, nk,
+                    f_total, Sg);
+  else if (nsb == 2)
+    sf_gemm_body<2>(L, ion_pos, ion_q, m, ipg, kcol, cbase, f, g, inv_lx, inv_ly, inv_lz, nk,
+                    f_total, Sg);
+  else
+    sf_gemm_body<1>(L, ion_pos, ion_q, m, ipg, kcol, cbase, f, g, inv_lx, inv_ly, inv_lz, nk,
+                    f_total, Sg);
 }
 
 // S[e] = sum_g Sg[g][e] over the ion groups (fixed order)
@@ -1004,7 +1006,7 @@ namespace {
 //   rs  [rs_groups][f][n]      real-space partials
 struct RhsPlan {
   int64_t sf_groups = 1, sf_ipg = 0, ksplit = 0, kper = 0, rs_groups = 0, rs_ipg = 0;
-  bool sf_gemm = false;         // structure factors on the matrix cores (|n_z| <= 63)
+  bool sf_gemm = false;         // structure factors on the matrix cores (|n_z| <= 47)
   bool bp_plane = false;        // factored back-projection over the atoms' z-planes
   bool rs_cell = false;         // real space over the cell list of the ions
   int nc[3] = {1, 1, 1};        // cells per box edge
@@ -1183,19 +1185,11 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
     double *Sg = p.sf_groups > 1 ? buf + p.off_sg : S;
     const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
     if (p.sf_gemm) {
-      // tiles by their s-block count (the first column of a tile has its
-      // largest |n_z|; the count does not increase along the tiles)
-      const int64_t ntile = s->kset.ncols_pad / kSfTile;
-      int64_t t0 = 0;
-      while (t0 < ntile) {
-        const int nsb = std::max(1, (s->kset.cols[4 * t0 * kSfTile + 2] + 16) / 16);
-        int64_t t1 = t0 + 1;
-        while (t1 < ntile && std::max(1, (s->kset.cols[4 * t1 * kSfTile + 2] + 16) / 16) == nsb)
-          ++t1;
-        launch_sf_gemm(st, nsb, t0, t1, f, p.sf_groups, ion_pos, ion_q, m, p.sf_ipg,
-                       reinterpret_cast<const int4 *>(s->kcol), ilx, ily, ilz, nk, Sg);
-        t0 = t1;
-      }
+      hipLaunchKernelGGL(sf_gemm_kernel,
+                         dim3((unsigned)f, (unsigned)(s->kset.ncols_pad / kSfTile),
+                              (unsigned)p.sf_groups),
+                         dim3(256), 0, st, ion_pos, ion_q, m, p.sf_ipg,
+                         reinterpret_cast<const int4 *>(s->kcol), ilx, ily, ilz, nk, f, Sg);
     } else
       hipLaunchKernelGGL(structure_factor_kernel, dim3((unsigned)rblocks, (unsigned)f, (unsigned)p.sf_groups),
                          dim3(RB), 0, st, ion_pos, ion_q, m, p.sf_ipg, s->kinfo, s->krun,
