@@ -13,11 +13,19 @@ Construction (Sec. III.B.2, steps 1-3): for each electrode atom tau
 Optionally the zeros of P are replaced by p_gap (Eq. 37), the mean of the
 removed entries of E^-1: p_gap = (1^T E^-1 1 - sum_ij P_ij) / n_zero.
 
+PCG-Normal and PCG-Full (Sec. III.B.2) sparsify E^-1 itself by the
+real-space distance of the two charges: p_ij = (E^-1)_ij when the pair is
+closer than a cutoff, 0 otherwise (Full: the cutoff of the neighbour list;
+Normal: a shorter preset r_cut).
+
 Readings (the paper is silent or ambiguous):
   * the neighbourhood includes atoms at exactly r_cut (Fig. 2: N_cut = 21 for
     a chain of spacing 1.5 A at r_cut = 15 A counts the atoms at 15 A); their
     Eq. 36 coupling to tau is zero;
-  * P filled column by column is not symmetric; CG uses (P + P^T) / 2.
+  * P filled column by column is not symmetric; CG uses (P + P^T) / 2;
+  * PCG-Normal / Full: the distance of a pair is that of the nearest images
+    (E^-1 has one entry per pair), pairs strictly closer than the cutoff are
+    kept, the diagonal always.
 """
 from __future__ import annotations
 
@@ -91,6 +99,23 @@ def dc_preconditioner(pos, box, a, g, rcut, symmetric=True):
 
     P = dc_columns(n, nbhd, local)
     return 0.5 * (P + P.T) if symmetric else P
+
+
+def min_image_distances(pos, box):
+    """Distance of every pair of atoms to the nearest periodic image (n x n)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    d = pos[:, None, :] - pos[None, :, :]
+    d -= box * np.round(d / box)
+    return np.linalg.norm(d, axis=2)
+
+
+def sparse_inverse(Einv, pos, box, rcut):
+    """PCG-Normal / PCG-Full P: the entries of E^-1 of the pairs closer than
+    rcut (nearest images) and the diagonal; zero elsewhere."""
+    keep = min_image_distances(pos, box) < rcut
+    np.fill_diagonal(keep, True)
+    return np.where(keep, Einv, 0.0)
 
 
 def p_gap(P, sum_einv):

@@ -128,3 +128,57 @@ def test_images_of_one_atom_add_up():
     assert math.isclose(P[1, 0], -2 * c / (1 + 3 * c), rel_tol=1e-14)
     assert math.isclose(P[0, 0], 1 - c / (1 + 3 * c), rel_tol=1e-14)
     assert math.isclose(P[0, 1], -c / (1 + 2 * c), rel_tol=1e-14)
+
+
+# ---- PCG-Normal / PCG-Full (sparsified E^-1, Sec. III.B.2)
+
+def _w1_inverse():
+    geo = wl.geometry(1)
+    km = ew.kmax_from_eps(wl.EWALD_SPLIT, wl.KSPACE_EPS)
+    E = ew.ewald_matrix(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, km)
+    return geo, E, np.linalg.inv(E)
+
+
+def test_sparse_inverse_pattern_by_brute_force():
+    """The kept pairs are those with an image closer than rcut, found here by
+    looping over the 27 neighbouring images of every pair."""
+    pos, box = _small_system(10, seed=5)
+    Einv = np.arange(100, dtype=np.float64).reshape(10, 10) + 1.0
+    P = pc.sparse_inverse(Einv, pos, box, 4.0)
+    for i in range(10):
+        for j in range(10):
+            dmin = min(np.linalg.norm(pos[j] + np.array([a, b, c]) * box - pos[i])
+                       for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1))
+            want = Einv[i, j] if (i == j or dmin < 4.0) else 0.0
+            assert P[i, j] == want
+
+
+def test_sparse_inverse_limits():
+    """A cutoff beyond every pair distance keeps E^-1 (preconditioned CG then
+    converges in one iteration); one below the nearest-neighbour distance
+    keeps its diagonal only."""
+    geo, E, Einv = _w1_inverse()
+    far = float(np.linalg.norm(geo.box))
+    P = pc.sparse_inverse(Einv, geo.pos, geo.box, far)
+    assert np.array_equal(P, Einv)
+    b = np.random.default_rng(4).standard_normal(geo.n)
+    _, it = pc.pcg(E, b, P, 1e-10)
+    assert it == 1
+    D = pc.sparse_inverse(Einv, geo.pos, geo.box, 0.5 * wl.BOND)
+    assert np.array_equal(D, np.diag(np.diag(Einv)))
+
+
+def test_sparse_inverse_gap_and_fig6_order():
+    """Eq. 37 restores the sum of E^-1; a longer cutoff needs no more
+    iterations (Fig. 6a: Full before Normal at 8, 4, 2 A), and every one of
+    them fewer than plain CG."""
+    geo, E, Einv = _w1_inverse()
+    P8 = pc.sparse_inverse(Einv, geo.pos, geo.box, 8.0)
+    s = float(Einv.sum())
+    assert abs(pc.with_gap(P8, pc.p_gap(P8, s)).sum() - s) <= 1e-10 * abs(s)
+    b = wl.electrode_potential(geo) / ew.K_E + 0.05 * np.random.default_rng(9).standard_normal(geo.n)
+    _, it_cg = pc.pcg(E, b, np.eye(geo.n), 1e-10)
+    its = [pc.pcg(E, b, pc.sparse_inverse(Einv, geo.pos, geo.box, rc), 1e-10)[1]
+           for rc in (2.0, 4.0, 8.0, 12.0)]
+    assert all(a >= c for a, c in zip(its, its[1:])), its
+    assert its[0] < it_cg, (its, it_cg)
