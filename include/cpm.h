@@ -171,8 +171,11 @@ typedef struct {
                           this factor, e.g. 1e-2                                   */
   int check_every;     /* iterations between the device-side convergence checks
                           (>= 1)                                                   */
-  int preconditioner;  /* CPM_PRECOND_JACOBI (diag E) or CPM_PRECOND_DC (the PCG-DC
-                          matrix of cpm_precond_dc, Sec. III.B.2)                   */
+  int preconditioner;  /* CPM_PRECOND_JACOBI (diag E) or CPM_PRECOND_DC (the
+                          system's sparse P, Sec. III.B.2: the PCG-DC matrix of
+                          cpm_precond_dc or the sparsified inverse of
+                          cpm_precond_sparse_inverse, whichever was built last,
+                          with the Eq. 37 fill when cpm_precond_gap enabled it)   */
 } cpm_solve_opts;
 
 typedef struct {
@@ -218,8 +221,31 @@ cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev,
 cpm_status cpm_precond_dc(cpm_system *s, double screening_g, double rcut);
 
 /* z = P r for f vectors, r_dev and z_dev (f, n) device arrays: the solver's
-   own apply kernel (tests). CPM_ESTATE before cpm_precond_dc. */
+   own apply kernel (tests), with the Eq. 37 fill when it is on. CPM_ESTATE
+   before a preconditioner is built. */
 cpm_status cpm_precond_apply(cpm_system *s, const double *r_dev, int64_t f, double *z_dev);
+
+/* ---- PCG-Normal / PCG-Full (Sec. III.B.2) ---------------------------------
+ * P = E^-1 sparsified by distance: p_ij = (E^-1)_ij for every pair whose
+ * nearest images are strictly closer than rcut, and the diagonal; 0
+ * elsewhere. E^-1 = S + d' d'^T / C_ele from the matrix-inversion path
+ * (cpm_mi_build first; S symmetrised entry by entry). PCG-Normal takes a
+ * preset rcut, PCG-Full the cutoff of the neighbour list. The result
+ * replaces the system's sparse preconditioner (the one CPM_PRECOND_DC
+ * applies) in the same ELL form. Errors: CPM_EINVAL (rcut not finite and
+ * > 0), CPM_ESTATE (no cpm_mi_build), CPM_ENOMEM, CPM_EDEVICE. */
+cpm_status cpm_precond_sparse_inverse(cpm_system *s, double rcut);
+
+/* Eq. 37: enable != 0 fills the zeros of the current sparse preconditioner
+ * with p_gap = (1^T E^-1 1 - sum_ij p_ij) / n_zero, the mean of the entries of
+ * E^-1 that the sparsification removed (1^T E^-1 1 = 1^T d' = C_ele, solved
+ * here if needed; n_zero = n^2 - the stored entries); enable = 0 removes the
+ * fill. Applied as z = (P - p_gap on the pattern of P) r + p_gap (1^T r) 1.
+ * A negative p_gap can make P indefinite: a solve then stops with
+ * CPM_ENOTSPD (r^T P r <= 0). gap_out (may be NULL) receives p_gap (0 when
+ * disabled). Errors: CPM_EINVAL, CPM_ESTATE (no preconditioner), the d'
+ * solve's errors. */
+cpm_status cpm_precond_gap(cpm_system *s, int enable, double *gap_out);
 
 /* ---- matrix-inversion path (Sec. III.B.1 MI; Eq. 33-35) -------------------
  * cpm_mi_build forms S = E^-1 (I - 1 d^T) (Eq. 33), symmetric, whose column

@@ -32,6 +32,7 @@ EXPORTS = [
     "cpm_mlp_loss_grad", "cpm_mlp_train_step", "cpm_mlp_train_epoch", "cpm_set_warm_chi",
     "cpm_warm_start",
     "cpm_profile_enable", "cpm_profile_read", "cpm_precond_dc", "cpm_precond_apply",
+    "cpm_precond_sparse_inverse", "cpm_precond_gap",
     "cpm_mi_build", "cpm_mi_solve", "cpm_gcd_build", "cpm_gcd_solve",
     "cpm_status_str", "cpm_last_error",
 ]
@@ -91,6 +92,8 @@ def lib():
     L.cpm_get_E.argtypes = [vp, C.c_int, vp, i64]
     L.cpm_get_E_block.argtypes = [vp, C.c_int, i64, i64, i64, i64, vp, i64]
     L.cpm_get_dprime.argtypes = [vp, vp, C.POINTER(dbl)]
+    L.cpm_precond_sparse_inverse.argtypes = [vp, dbl]
+    L.cpm_precond_gap.argtypes = [vp, C.c_int, C.POINTER(dbl)]
     L.cpm_matvec.argtypes = [vp, C.c_int, vp, i64, vp]
     L.cpm_mlp_init.argtypes = [vp, vp, C.c_int32, f32, f32, f32]
     L.cpm_mlp_neighbours.argtypes = [vp, vp]
@@ -303,6 +306,16 @@ class System:
         """Build the PCG-DC preconditioner (Sec. III.B.2, Eq. 36)."""
         _check(lib().cpm_precond_dc(self._h, C.c_double(screening_g), C.c_double(rcut)),
                "cpm_precond_dc")
+
+    def precond_sparse_inverse(self, rcut):
+        """PCG-Normal / PCG-Full: E^-1 (from mi_build) sparsified at rcut."""
+        _check(lib().cpm_precond_sparse_inverse(self._h, float(rcut)), "cpm_precond_sparse_inverse")
+
+    def precond_gap(self, enable=True):
+        """Eq. 37 fill of the current sparse preconditioner; returns p_gap."""
+        g = C.c_double()
+        _check(lib().cpm_precond_gap(self._h, 1 if enable else 0, C.byref(g)), "cpm_precond_gap")
+        return g.value
 
     def precond_apply(self, r):
         """z = P r for vectors r (F, N) on the device."""

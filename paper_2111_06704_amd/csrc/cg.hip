@@ -1020,6 +1020,22 @@ __global__ __launch_bounds__(RED_THREADS) void rows_kernel(const double *__restr
   }
 }
 
+// 1^T r per column (fixed order): rsum[c] = sum_i r[c * cs + i], zero for
+// c >= fc; the Eq. 37 term of the preconditioner apply
+__global__ __launch_bounds__(RED_THREADS) void colsum_kernel(const double *__restrict__ r,
+                                                            int64_t cs, int64_t n, int fc,
+                                                            double *__restrict__ rsum,
+                                                            const int *__restrict__ gate) {
+  __shared__ double red[4];
+  if (gate != nullptr && *gate == 0) return;
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  if (c < fc)
+    for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) acc += r[(int64_t)c * cs + i];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) rsum[c] = acc;
+}
+
 // PCG-DC apply (Sec. III.B.2): z = P r with P in row-major ELL form whose
 // row t is the row of atom order[t] (entry k at t * width + k), r in the
 // row-interleaved layout of rows_kernel. One wavefront per row (rows taken
@@ -1044,7 +1060,7 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
     const int32_t *__restrict__ pidx, const double *__restrict__ pval, int width,
     const int32_t *__restrict__ order, int64_t ld, int64_t n, int cols,
     const double *__restrict__ scal, int slot, double *__restrict__ bpart, int set_p,
-    const int *__restrict__ gate) {
+    double gap, const double *__restrict__ rsum, const int *__restrict__ gate) {
   __shared__ double red[PC_ROWS][kColGroup][2];
   __shared__ double sval[PC_ROWS][PC_CHUNK];
   __shared__ int32_t sidx[PC_ROWS][PC_CHUNK];
@@ -1112,7 +1128,9 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
     if (i >= 0) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const double zi = u ? a1 : a0, rv = u ? ri.y : ri.x;
+        // the Eq. 37 fill: P's zeros hold gap, its pattern P - gap
+        const double zi = (u ? a1 : a0) + (rsum != nullptr ? gap * rsum[c0 + u] : 0.0);
+        const double rv = u ? ri.y : ri.x;
         if (u ? act1 : act0) {
           const int64_t idx = (int64_t)(c0 + u) * ld + i;
           z[idx] = zi;
@@ -1152,11 +1170,13 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
 // slot ^ 1), so no workgroup reads a flag this launch writes; the control
 // step clears both.
 constexpr double kHold = 1e-3;
+// r.z = r^T P r <= 0 for r != 0 means that the preconditioner is not
+// positive definite (possible with the Eq. 37 fill): breakdown word 2.
 template <typename VT>
 __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
     VT *__restrict__ p, const double *__restrict__ z, int64_t ld, int64_t n, int cols, int nblk,
     const double *__restrict__ partial, int cmajor, double *__restrict__ scal, int slot, double tol,
-    double ru) {
+    double ru, int *__restrict__ flags) {
   __shared__ double red[3][4];
   const int c = blockIdx.y;
   const int blk = blockIdx.x;
@@ -1182,6 +1202,13 @@ __global__ __launch_bounds__(RED_THREADS) void cg_direction_kernel(
     p[idx] = (VT)(z[idx] + beta * (double)p[idx]);
   }
   if (blk == 0 && threadIdx.x == 0) {
+    if (rr > 0.0 && !(rzn > 0.0)) {
+      flags[0] = 2;   // breakdown: r^T P r <= 0
+      flags[1] = c;
+      double *dbg = reinterpret_cast<double *>(flags + 2);
+      dbg[0] = rr;
+      dbg[1] = rzn;
+    }
     scal[(S_RZ0 + (slot ^ 1)) * cols + c] = rzn;
     scal[S_RR * cols + c] = rr;
     scal[S_IT * cols + c] += 1.0;
@@ -1572,7 +1599,7 @@ hipError_t launch_matvec(hipStream_t st, const T *E, int64_t ld, int64_t cols,
 }
 
 void free_workspace(Workspace &w) {
-  void *ptrs[] = {w.x, w.r, w.rt, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.red, w.sum_err, w.bx, w.bres, w.flags,
+  void *ptrs[] = {w.x, w.r, w.rt, w.p, w.z, w.v, w.vpart, w.partial, w.scal, w.red, w.sum_err, w.rsum, w.bx, w.bres, w.flags,
                   w.xf, w.rf, w.pf, w.zf, w.vf, w.bpart};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -1613,6 +1640,7 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
             alloc((void **)&w.scal, sizeof(double) * S_NFIELDS * cols) &&
             alloc((void **)&w.red, sizeof(double) * 3 * MAX_COLS) &&
             alloc((void **)&w.sum_err, sizeof(double) * MAX_COLS) &&
+            alloc((void **)&w.rsum, sizeof(double) * MAX_COLS) &&
             alloc((void **)&w.bpart,
                   sizeof(double) * 2 * (size_t)((s->n + PC_ROWS - 1) / PC_ROWS) * cols) &&
             alloc((void **)&w.flags, sizeof(int) * F_NWORDS);
@@ -1666,14 +1694,22 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
 
 // z = P r (PCG-DC) for cols columns of the row-interleaved residual rt;
 // bpart gets one (r.r, r.z) pair per workgroup and column.
+// With the Eq. 37 fill, r (column c at r + c * rs, fc columns) gives the
+// column sums first.
 template <typename VT>
 void launch_precond(hipStream_t st, const cpm_system *s, const Precond &pc, const double *rt,
-                    double *z, VT *p, int64_t cols, const double *scal, int slot, double *bpart,
-                    bool set_p, const int *gate) {
+                    const double *r, int64_t rs, int fc, double *z, VT *p, int64_t cols,
+                    const double *scal, int slot, double *bpart, bool set_p, const int *gate) {
   const int64_t ld = s->ld, n = s->n;
+  const double *rsum = nullptr;
+  if (pc.gap != 0.0) {
+    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, r, rs, n, fc,
+                       s->ws.rsum, gate);
+    rsum = s->ws.rsum;
+  }
   hipLaunchKernelGGL(precond_kernel<VT>, dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
                      dim3(PC_THREADS), 0, st, rt, z, p, pc.idx, pc.val, pc.width, s->atom_order, ld,
-                     n, (int)cols, scal, slot, bpart, set_p ? 1 : 0, gate);
+                     n, (int)cols, scal, slot, bpart, set_p ? 1 : 0, pc.gap, rsum, gate);
 }
 
 // The solver over one block of cols columns. VT is the vector type of p and
@@ -1746,7 +1782,8 @@ template <typename T> struct Solver {
       hipLaunchKernelGGL(rows_kernel, dim3((unsigned)(ld / RT_ROWS), (unsigned)(cols / kColGroup)),
                          dim3(RED_THREADS), 0, st, (const double *)r, ld, n, (int)cols, rt, ld,
                          gate);
-    launch_precond<VT>(st, s, *pc, rt, z, p, cols, scal, slot, s->ws.bpart, set_p, gate);
+    launch_precond<VT>(st, s, *pc, rt, r, ld, (int)cols, z, p, cols, scal, slot, s->ws.bpart,
+                       set_p, gate);
   }
 
   // z = M^-1 r (and p = z when restarting); rz into the current slot
@@ -1796,7 +1833,7 @@ template <typename T> struct Solver {
       nds = 1;
     }
     hipLaunchKernelGGL(cg_direction_kernel<VT>, grid(), dim3(RED_THREADS), 0, st, p, z, ld, n,
-                       (int)cols, nds, ds, dots_cmajor(), scal, slot, tol, ru);
+                       (int)cols, nds, ds, dots_cmajor(), scal, slot, tol, ru, flags);
     slot ^= 1;
     return hipGetLastError();
   }
@@ -1805,6 +1842,13 @@ template <typename T> struct Solver {
 cpm_status breakdown_error(int it_done, const int *fl) {
   double dbg[2];
   std::memcpy(dbg, fl + 2, sizeof(dbg));
+  if (fl[F_BREAK] == 2) {
+    set_error("PCG breakdown: r^T P r <= 0 (the preconditioner is not positive definite; the "
+              "Eq. 37 gap fill can make it indefinite); column " + std::to_string(fl[F_COL]) +
+              " within the first " + std::to_string(it_done) + " iterations, r.r=" +
+              std::to_string(dbg[0]) + " r.z=" + std::to_string(dbg[1]));
+    return CPM_ENOTSPD;
+  }
   set_error("CG breakdown: p^T E p <= 0 (E is not positive definite); column " +
             std::to_string(fl[F_COL]) + " within the first " + std::to_string(it_done) +
             " iterations, p.Ep=" + std::to_string(dbg[0]) + " r.z=" + std::to_string(dbg[1]));
@@ -2164,8 +2208,8 @@ cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z
     hipLaunchKernelGGL(rows_kernel, dim3((unsigned)(ld / RT_ROWS), (unsigned)(cols / kColGroup)),
                        dim3(RED_THREADS), 0, st, r_dev + f0 * n, n, n, fc, in, ld,
                        (const int *)nullptr);
-    launch_precond<double>(st, s, s->pc, in, out, (double *)nullptr, cols, nullptr, 0, nullptr, false,
-                           nullptr);
+    launch_precond<double>(st, s, s->pc, in, r_dev + f0 * n, n, fc, out, (double *)nullptr, cols,
+                           nullptr, 0, nullptr, false, nullptr);
     CPM_HIP_CHECK(hipMemcpy2DAsync(z_dev + f0 * n, sizeof(double) * n, out, sizeof(double) * ld,
                                    sizeof(double) * n, fc, hipMemcpyDeviceToDevice, st));
   }

@@ -71,6 +71,7 @@ struct Workspace {            // CG scratch, grown on demand
   double *scal = nullptr;     // per-column scalars, see cg.hip
   double *red = nullptr;      // 3*64 doubles: reduced dot partials (p.v; r.r and r.z)
   double *sum_err = nullptr;  // MAX_COLS doubles: |sum q + Q_sol| per column after the projection
+  double *rsum = nullptr;     // MAX_COLS doubles: 1^T r per column (the Eq. 37 gap term)
   double *bx = nullptr;       // n_pad*cols double: right-hand sides / outer iterate
   double *bres = nullptr;     // n_pad*cols double: outer residual
   int *flags = nullptr;       // device status words
@@ -91,15 +92,23 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-struct Precond {              // PCG-DC preconditioner (P + P^T) / 2 in ELL form
+struct Precond {              // sparse PCG preconditioner P in ELL form
   bool ready = false;
-  double g = 0, rcut = 0;     // screening and cutoff of Eq. 36
+  int kind = 0;               // 0: PCG-DC (P + P^T) / 2 (Eq. 36); 1: E^-1 sparsified by distance
+  double g = 0, rcut = 0;     // screening and cutoff of Eq. 36 (kind 0), cutoff (kind 1)
   int width = 0;              // entries per row (padded with (i, 0))
   int max_local = 0;          // largest local matrix
   int64_t nnz = 0;
   int32_t *idx = nullptr;     // n * width: column of entry k of the row of atom atom_order[t] at t * width + k
-  double *val = nullptr;      // width * n
+  double *val = nullptr;      // width * n (minus gap on the real entries when the gap is on)
   int64_t bytes = 0;           // device memory held
+  // Eq. 37: the zeros of P filled with gap (0: off); applied as
+  // z = (P - gap on its pattern) r + gap (1^T r) 1
+  double gap = 0.0;
+  double sum_p = 0.0;         // sum of the entries of P (without the gap)
+  std::vector<int32_t> h_idx; // host copies of the ELL arrays without the gap
+  std::vector<double> h_val;
+  std::vector<int32_t> h_len; // real entries per ELL row
 };
 void free_precond(Precond &p);
 

@@ -151,6 +151,66 @@ void free_precond(Precond &p) {
   p = Precond();
 }
 
+namespace {
+
+// p's host ELL arrays to new device arrays; on success p replaces the
+// system's preconditioner (the previous one is freed)
+cpm_status install_precond(cpm_system *s, Precond &p) {
+  if (hipMalloc((void **)&p.idx, sizeof(int32_t) * p.h_idx.size()) != hipSuccess ||
+      hipMalloc((void **)&p.val, sizeof(double) * p.h_val.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    free_precond(p);
+    set_error("preconditioner allocation failed");
+    return CPM_ENOMEM;
+  }
+  CPM_HIP_CHECK(hipMemcpyAsync(p.idx, p.h_idx.data(), sizeof(int32_t) * p.h_idx.size(),
+                               hipMemcpyHostToDevice, s->stream));
+  CPM_HIP_CHECK(hipMemcpyAsync(p.val, p.h_val.data(), sizeof(double) * p.h_val.size(),
+                               hipMemcpyHostToDevice, s->stream));
+  p.bytes = (int64_t)(sizeof(int32_t) * p.h_idx.size() + sizeof(double) * p.h_val.size());
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  p.sum_p = 0.0;
+  for (size_t e = 0; e < p.h_val.size(); ++e) p.sum_p += p.h_val[e];   // padding entries are 0
+  s->device_bytes -= s->pc.bytes;
+  free_precond(s->pc);
+  p.ready = true;
+  s->pc = std::move(p);
+  s->device_bytes += s->pc.bytes;
+  return CPM_OK;
+}
+
+std::vector<int32_t> host_atom_order(cpm_system *s) {
+  std::vector<int32_t> order(s->n);
+  if (hipMemcpyAsync(order.data(), s->atom_order, sizeof(int32_t) * s->n, hipMemcpyDeviceToHost,
+                     s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    order.clear();
+  return order;
+}
+
+// entries of E^-1 = S + d' d'^T / C_ele (S of the matrix-inversion path,
+// symmetrised) at the real entries (k < len[t]) of ELL row t (atom order[t]),
+// 0 at the padding
+__global__ void sparse_inverse_values_kernel(const double *__restrict__ S, int64_t ld,
+                                             const double *__restrict__ dprime, double inv_c,
+                                             const int32_t *__restrict__ order,
+                                             const int32_t *__restrict__ idx,
+                                             const int32_t *__restrict__ len, int width, int64_t n,
+                                             double *__restrict__ val) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * width) return;
+  const int64_t t = e / width;
+  const int k = (int)(e - t * width);
+  double v = 0.0;
+  if (k < len[t]) {
+    const int64_t i = order[t], j = idx[e];
+    v = 0.5 * (S[i * ld + j] + S[j * ld + i]) + dprime[i] * dprime[j] * inv_c;
+  }
+  val[e] = v;
+}
+
+}  // namespace
+
 }  // namespace cpm
 
 using namespace cpm;
@@ -243,50 +303,164 @@ cpm_status cpm_precond_dc(cpm_system *s, double g, double rcut) {
   for (const auto &v : col) width = std::max(width, (int)v.size());
   // ELL row t holds the row of atom order[t], the order in which the apply
   // kernel takes the rows
-  std::vector<int32_t> order(n);
-  CPM_HIP_CHECK(hipMemcpyAsync(order.data(), s->atom_order, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
-                               s->stream));
-  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
-  std::vector<int32_t> idx((size_t)width * n);
-  std::vector<double> val((size_t)width * n, 0.0);
+  const std::vector<int32_t> order = host_atom_order(s);
+  if ((int64_t)order.size() != n) {
+    set_error("reading the atom order failed");
+    return CPM_EDEVICE;
+  }
+  Precond p;
+  p.h_idx.assign((size_t)width * n, 0);
+  p.h_val.assign((size_t)width * n, 0.0);
+  p.h_len.assign(n, 0);
   int64_t nnz = 0;
   for (int64_t t = 0; t < n; ++t) {
     const int64_t i = order[t];
     const auto &v = col[i];   // the neighbour relation is symmetric: row i has the atoms of column i
     for (int k = 0; k < width; ++k) {
       if (k < (int)v.size()) {
-        idx[(size_t)t * width + k] = v[k].first;
-        val[(size_t)t * width + k] = 0.5 * (v[k].second + entry(v[k].first, (int32_t)i));
+        p.h_idx[(size_t)t * width + k] = v[k].first;
+        p.h_val[(size_t)t * width + k] = 0.5 * (v[k].second + entry(v[k].first, (int32_t)i));
       } else {
-        idx[(size_t)t * width + k] = (int32_t)i;
+        p.h_idx[(size_t)t * width + k] = (int32_t)i;
       }
     }
+    p.h_len[t] = (int32_t)v.size();
     nnz += (int64_t)v.size();
   }
-  Precond p;
+  p.kind = 0;
   p.g = g;
   p.rcut = rcut;
   p.width = width;
   p.nnz = nnz;
   p.max_local = mmax;
-  if (hipMalloc((void **)&p.idx, sizeof(int32_t) * idx.size()) != hipSuccess ||
-      hipMalloc((void **)&p.val, sizeof(double) * val.size()) != hipSuccess) {
+  return install_precond(s, p);
+}
+
+cpm_status cpm_precond_sparse_inverse(cpm_system *s, double rcut) {
+  if (!s) {
+    set_error("NULL system");
+    return CPM_EINVAL;
+  }
+  if (!(rcut > 0.0) || !std::isfinite(rcut)) {
+    set_error("rcut must be finite and > 0");
+    return CPM_EINVAL;
+  }
+  if (!s->S || !s->dprime_ready || !(s->c_ele > 0.0)) {
+    set_error("cpm_mi_build first (the sparsified preconditioner takes E^-1 from it)");
+    return CPM_ESTATE;
+  }
+  const int64_t n = s->n;
+  // pairs with an image strictly closer than rcut (a neighbourhood lists
+  // every image within rcut), the atom itself first
+  const std::vector<std::vector<Image>> nb = neighbourhoods(s->pos_host, n, s->box, rcut);
+  std::vector<std::vector<int32_t>> row(n);
+  parallel_for(n, [&](int64_t i, int) {
+    std::vector<int32_t> &r = row[i];
+    r.push_back((int32_t)i);
+    const double x = s->pos_host[3 * i], y = s->pos_host[3 * i + 1], z = s->pos_host[3 * i + 2];
+    for (const Image &im : nb[i]) {
+      const double dx = im.x - x, dy = im.y - y, dz = im.z - z;
+      if (im.atom != i && dx * dx + dy * dy + dz * dz < rcut * rcut &&
+          (r.size() == 1 || r.back() != im.atom))
+        r.push_back(im.atom);   // images come ordered by atom: one entry per atom
+    }
+  });
+  int width = 1;
+  for (const auto &r : row) width = std::max(width, (int)r.size());
+  const std::vector<int32_t> order = host_atom_order(s);
+  if ((int64_t)order.size() != n) {
+    set_error("reading the atom order failed");
+    return CPM_EDEVICE;
+  }
+  Precond p;
+  p.h_idx.assign((size_t)width * n, 0);
+  p.h_val.assign((size_t)width * n, 0.0);
+  p.h_len.assign(n, 0);
+  int64_t nnz = 0;
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t i = order[t];
+    const std::vector<int32_t> &r = row[i];
+    for (int k = 0; k < width; ++k)
+      p.h_idx[(size_t)t * width + k] = k < (int)r.size() ? r[k] : (int32_t)i;
+    p.h_len[t] = (int32_t)r.size();
+    nnz += (int64_t)r.size();
+  }
+  // values on the device from S, then back for the host copy
+  int32_t *d_idx = nullptr, *d_len = nullptr, *d_order = nullptr;
+  double *d_val = nullptr;
+  auto release = [&]() {
+    if (d_idx) (void)hipFree(d_idx);
+    if (d_len) (void)hipFree(d_len);
+    if (d_val) (void)hipFree(d_val);
+  };
+  if (hipMalloc((void **)&d_idx, sizeof(int32_t) * p.h_idx.size()) != hipSuccess ||
+      hipMalloc((void **)&d_len, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc((void **)&d_val, sizeof(double) * p.h_val.size()) != hipSuccess) {
     (void)hipGetLastError();
-    free_precond(p);
+    release();
     set_error("preconditioner allocation failed");
     return CPM_ENOMEM;
   }
-  CPM_HIP_CHECK(hipMemcpyAsync(p.idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice,
-                               s->stream));
-  CPM_HIP_CHECK(hipMemcpyAsync(p.val, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice,
-                               s->stream));
-  p.bytes = (int64_t)(sizeof(int32_t) * idx.size() + sizeof(double) * val.size());
+  d_order = s->atom_order;
+  hipError_t e = hipMemcpyAsync(d_idx, p.h_idx.data(), sizeof(int32_t) * p.h_idx.size(),
+                                hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_len, p.h_len.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) {
+    const int64_t tot = (int64_t)width * n;
+    hipLaunchKernelGGL(sparse_inverse_values_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256),
+                       0, s->stream, (const double *)s->S, s->ld, (const double *)s->dprime,
+                       1.0 / s->c_ele, (const int32_t *)d_order, (const int32_t *)d_idx,
+                       (const int32_t *)d_len, width, n, d_val);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p.h_val.data(), d_val, sizeof(double) * p.h_val.size(),
+                       hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  release();
+  if (e != hipSuccess) {
+    set_error(std::string("sparsified inverse: ") + hipGetErrorString(e));
+    return CPM_EDEVICE;
+  }
+  p.kind = 1;
+  p.rcut = rcut;
+  p.width = width;
+  p.nnz = nnz;
+  return install_precond(s, p);
+}
+
+cpm_status cpm_precond_gap(cpm_system *s, int enable, double *gap_out) {
+  if (!s) {
+    set_error("NULL system");
+    return CPM_EINVAL;
+  }
+  if (!s->pc.ready) {
+    set_error("build a preconditioner first (cpm_precond_dc or cpm_precond_sparse_inverse)");
+    return CPM_ESTATE;
+  }
+  Precond &p = s->pc;
+  double gap = 0.0;
+  if (enable) {
+    if (!s->dprime_ready) {
+      cpm_status rd = solve_dprime(s, 1e-13, 20000);
+      if (rd != CPM_OK) return rd;
+      s->dprime_ready = true;
+    }
+    const double nn = (double)s->n * (double)s->n;
+    const double n_zero = nn - (double)p.nnz;
+    // 1^T E^-1 1 = 1^T d' = C_ele
+    gap = n_zero > 0.0 ? (s->c_ele - p.sum_p) / n_zero : 0.0;
+  }
+  std::vector<double> val = p.h_val;
+  if (gap != 0.0)
+    for (int64_t t = 0; t < s->n; ++t)
+      for (int k = 0; k < p.h_len[t]; ++k) val[(size_t)t * p.width + k] -= gap;
+  CPM_HIP_CHECK(hipMemcpyAsync(p.val, val.data(), sizeof(double) * val.size(),
+                               hipMemcpyHostToDevice, s->stream));
   CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
-  s->device_bytes -= s->pc.bytes;
-  free_precond(s->pc);
-  p.ready = true;
-  s->pc = p;
-  s->device_bytes += s->pc.bytes;
+  p.gap = gap;
+  if (gap_out) *gap_out = gap;
   return CPM_OK;
 }
 

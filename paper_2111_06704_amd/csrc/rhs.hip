@@ -525,15 +525,20 @@ __global__ __launch_bounds__(PT_THREADS) void plane_table_kernel(
 // and column q once (sincospi of the reduced fractional phase) and gives
 // its cosine and sine as the A operand of two v_mfma_f64_16x16x4f64 per 16
 // frames, with Re T and Im T of (column q, frame r) as the B operand.
-// Grid (tiles / PB_WAVES, frames / 32).
+// Grid (tiles / PB_WAVES, frames / 32, column splits): split z takes the
+// columns [z cper, (z + 1) cper) and writes part + z f n (summed with the
+// other splits when b is assembled).
 constexpr int PB_WAVES = 4;
 
 __global__ __launch_bounds__(64 * PB_WAVES) void plane_backproject_kernel(
     const double *__restrict__ pos, int64_t n, const int32_t *__restrict__ tile_plane,
     const int32_t *__restrict__ tile_atom, int64_t ntiles, const int4 *__restrict__ kcol,
-    int64_t ncols_pad, double inv_lx, double inv_ly, const double *__restrict__ Tre,
-    const double *__restrict__ Tim, int64_t f_total, double *__restrict__ part) {
+    int64_t ncols_pad, int64_t cper, double inv_lx, double inv_ly,
+    const double *__restrict__ Tre, const double *__restrict__ Tim, int64_t f_total,
+    double *__restrict__ part) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t cbeg = (int64_t)blockIdx.z * cper, cend = min(ncols_pad, cbeg + cper);
+  part += (int64_t)blockIdx.z * f_total * n;
   const int64_t t = (int64_t)blockIdx.x * PB_WAVES + wave;
   if (t >= ntiles) return;   // no barriers below: a wave may leave alone
   const int lr = lane & 15, lq = lane >> 4;
@@ -549,7 +554,7 @@ __global__ __launch_bounds__(64 * PB_WAVES) void plane_backproject_kernel(
   const double *tr = Tre + (int64_t)p * ncols_pad * f_total;
   const double *ti = Tim + (int64_t)p * ncols_pad * f_total;
   d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t c0 = 0; c0 < ncols_pad; c0 += 4) {
+  for (int64_t c0 = cbeg; c0 < cend; c0 += 4) {
     const int64_t c = c0 + lq;
     const int4 col = kcol[c];
     double th = (double)col.x * ux + (double)col.y * uy;
@@ -1070,9 +1075,15 @@ RhsPlan rhs_plan_capped(const cpm_system *s, int64_t m, int64_t f, int64_t cap_s
     p.kper = (nk + ks - 1) / ks;
     p.ksplit = (nk + p.kper - 1) / p.kper;
     if (planes && s->nplanes > 0) {
+      // column splits (multiples of 64 columns) until about 1024 workgroups
       p.bp_plane = true;
-      p.kper = nk;
-      p.ksplit = 1;
+      const int64_t wgs = (s->plane_ntiles + 3) / 4 * ((f + 31) / 32);
+      const int64_t units = s->kset.ncols_pad / 64;
+      int64_t cs = std::min<int64_t>({std::max<int64_t>(1, (1024 + wgs - 1) / wgs), units,
+                                      std::max<int64_t>(1, kPartialCap / (f * n)), cap_ks});
+      cs = std::max<int64_t>(1, cs);
+      p.kper = (units + cs - 1) / cs * 64;   // columns per split
+      p.ksplit = (s->kset.ncols_pad + p.kper - 1) / p.kper;
     }
   }
   if (m >= kCellMinIons) {
@@ -1210,11 +1221,11 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
                          (const double *)S, f, s->kset.smax, Tre, Tim);
       hipLaunchKernelGGL(plane_backproject_kernel,
                          dim3((unsigned)((s->plane_ntiles + PB_WAVES - 1) / PB_WAVES),
-                              (unsigned)((f + 31) / 32)),
+                              (unsigned)((f + 31) / 32), (unsigned)p.ksplit),
                          dim3(64 * PB_WAVES), 0, st, (const double *)s->pos, n,
                          (const int32_t *)s->plane_tile, (const int32_t *)s->plane_atom,
-                         s->plane_ntiles, reinterpret_cast<const int4 *>(s->kcol), ncp, ilx, ily,
-                         (const double *)Tre, (const double *)Tim, f, bp);
+                         s->plane_ntiles, reinterpret_cast<const int4 *>(s->kcol), ncp, p.kper,
+                         ilx, ily, (const double *)Tre, (const double *)Tim, f, bp);
     } else {
       const int64_t bblocks = (n + RB * BP_AT - 1) / (RB * BP_AT);
       hipLaunchKernelGGL(backproject_kernel<BP_AT>,
