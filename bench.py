@@ -74,10 +74,11 @@ def parse():
     ap.add_argument("--warm", default="mlp", choices=["zero", "chi", "mlp"])
     ap.add_argument("--precond", default="dc", choices=["jacobi", "dc"],
                     help="preconditioner of the timed solves")
-    ap.add_argument("--dc-g", type=float, default=0.15,
-                    help="PCG-DC screening g (1/A); 0.15 with r_cut 7 from a sweep on workload 2 "
-                         "(the paper: 0.083 with 8)")
-    ap.add_argument("--dc-rcut", type=float, default=7.0, help="PCG-DC cutoff (A)")
+    ap.add_argument("--dc-g", type=float, default=None,
+                    help="PCG-DC screening g (1/A); default 0.15 with r_cut 7 (a sweep on "
+                         "workload 2), 0.10 with 10 at workload 5 (a sweep there); the paper: "
+                         "0.083 with 8")
+    ap.add_argument("--dc-rcut", type=float, default=None, help="PCG-DC cutoff (A)")
     ap.add_argument("--weights", default=None,
                     help="warm-start network (default: the one for the workload's geometry)")
     ap.add_argument("--kmax-override", type=float, default=0.0,
@@ -299,6 +300,14 @@ def main():
     cfg = args.workload
     if args.check_every is None:
         args.check_every = 8 if cfg == 5 else 4
+    # PCG-DC: at workload 5 the apply costs 0.34 ms against a 12.4 ms product,
+    # so a wider P pays: a sweep of (g, r_cut) from (0.15, 7) to (0.07, 12)
+    # gave 80 FP32 iterations at (0.15, 7), 72 at 9 A, 64 at (0.10, 10) and
+    # 56 at (0.10, 12), whose host construction takes 89 s against 24 s at 10
+    if args.dc_g is None:
+        args.dc_g = 0.10 if cfg == 5 else 0.15
+    if args.dc_rcut is None:
+        args.dc_rcut = 10.0 if cfg == 5 else 7.0
     geo, ipos, iq, chi = wl.workload(cfg)
     if args.jitter > 0:
         # genericity check: the same workload with every electrode atom displaced
