@@ -6,10 +6,14 @@
 // column tau of P; entries of different images of one atom add up. CG needs
 // a symmetric preconditioner, so the device copy holds (P + P^T) / 2 in
 // row-major ELL form: entry k of row i at i * width + k (column index,
-// value), rows padded with (i, 0). The construction runs once per system on host threads (a few
-// hundred local factorisations of size ~ 200 per thread); the apply z = P r
-// of every PCG iteration runs on the device (cg.hip).
+// value), rows padded with (i, 0). The construction runs once per system:
+// the neighbourhoods on host threads, the local matrices and their batched
+// Cholesky factorisations and solves on the device; the apply z = P r of
+// every PCG iteration runs on the device (cg.hip). Also here: the
+// sparsified inverse of PCG-Normal / Full and the Eq. 37 fill.
 #include "cpm_internal.h"
+
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <atomic>
@@ -122,26 +126,6 @@ std::vector<std::vector<Image>> neighbourhoods(const std::vector<double> &pos, i
   return out;
 }
 
-// In-place Cholesky of the m x m row-major matrix M (lower triangle used);
-// false if a pivot is not positive.
-bool cholesky(double *M, int m) {
-  for (int k = 0; k < m; ++k) {
-    double d = M[(size_t)k * m + k];
-    for (int l = 0; l < k; ++l) d -= M[(size_t)k * m + l] * M[(size_t)k * m + l];
-    if (!(d > 0.0)) return false;
-    d = std::sqrt(d);
-    M[(size_t)k * m + k] = d;
-    const double inv = 1.0 / d;
-    for (int i = k + 1; i < m; ++i) {
-      double s = M[(size_t)i * m + k];
-      const double *ri = M + (size_t)i * m, *rk = M + (size_t)k * m;
-      for (int l = 0; l < k; ++l) s -= ri[l] * rk[l];
-      M[(size_t)i * m + k] = s * inv;
-    }
-  }
-  return true;
-}
-
 }  // namespace
 
 void free_precond(Precond &p) {
@@ -209,6 +193,163 @@ __global__ void sparse_inverse_values_kernel(const double *__restrict__ S, int64
   val[e] = v;
 }
 
+
+// Local matrices of Eq. 36 for a batch of atoms, column-major, each padded
+// to mm x mm with the identity (which leaves the solution for e_0
+// unchanged): img holds, per atom b, its m_b points (tau first, then its
+// neighbourhood images) as (x, y, z, a); X gets e_0.
+__global__ void dc_local_kernel(const double4 *__restrict__ img, const int32_t *__restrict__ mlen,
+                                int mm, double g, double rcut, double erfc_rc,
+                                double *__restrict__ A, double *__restrict__ X) {
+  const int64_t b = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)mm * mm) return;
+  const int row = (int)(e % mm), col = (int)(e / mm);
+  const int m = mlen[b];
+  const double4 *p = img + b * mm;
+  double v;
+  if (row >= m || col >= m) {
+    v = (row == col) ? 1.0 : 0.0;
+  } else if (row == col) {
+    v = sqrt(2.0 / M_PI) * p[row].w;
+  } else {
+    const double dx = p[row].x - p[col].x, dy = p[row].y - p[col].y, dz = p[row].z - p[col].z;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    v = (r > 0.0 && r < rcut) ? (erfc(g * r) - erfc_rc) / r : 0.0;
+  }
+  A[b * (int64_t)mm * mm + e] = v;
+  if (col == 0) X[b * (int64_t)mm + row] = (row == 0) ? 1.0 : 0.0;
+}
+
+// Column tau of P (step 2 of the construction) for every atom: the local
+// matrices are formed on the device in batches of atoms with neighbourhoods
+// of similar size, factorised and solved for e_0 by the batched Cholesky of
+// rocSOLVER (strided, FP64); images of one atom add up on the host.
+cpm_status dc_columns_device(cpm_system *s, const std::vector<std::vector<Image>> &nb, double g,
+                             double rcut, std::vector<std::vector<std::pair<int32_t, double>>> &col) {
+  const int64_t n = s->n;
+  hipStream_t st = s->stream;
+  std::vector<int64_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return nb[a].size() > nb[b].size(); });
+  const int mfirst = (int)nb[order[0]].size() + 1;
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  // one batch: at most cap atoms (every per-atom array below holds cap
+  // atoms of mfirst points, mfirst being the largest neighbourhood), and
+  // local matrices of at most 4 GiB or a quarter of the free memory (at
+  // least one matrix); a batch of atoms with mm <= mfirst points takes
+  // min(cap, a_elems / mm^2) atoms, so every array bound holds
+  const int64_t cap = std::min<int64_t>(n, 16384);
+  const size_t budget = std::min<size_t>((size_t)4 << 30, free_b / 4);
+  const int64_t a_elems = std::max<int64_t>(
+      (int64_t)mfirst * mfirst,
+      std::min<int64_t>(cap * mfirst * mfirst, (int64_t)(budget / sizeof(double))));
+  double *A = nullptr, *X = nullptr;
+  double4 *img = nullptr;
+  int32_t *mlen = nullptr, *info = nullptr;
+  rocblas_handle h = nullptr;
+  auto release = [&]() {
+    if (h) (void)rocblas_destroy_handle(h);
+    void *ptrs[] = {A, X, img, mlen, info};
+    for (void *q : ptrs)
+      if (q) (void)hipFree(q);
+  };
+  if (hipMalloc((void **)&A, sizeof(double) * (size_t)a_elems) != hipSuccess ||
+      hipMalloc((void **)&X, sizeof(double) * (size_t)cap * mfirst) != hipSuccess ||
+      hipMalloc((void **)&img, sizeof(double4) * (size_t)cap * mfirst) != hipSuccess ||
+      hipMalloc((void **)&mlen, sizeof(int32_t) * cap) != hipSuccess ||
+      hipMalloc((void **)&info, sizeof(int32_t) * cap) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    set_error("PCG-DC: allocation of the local matrices failed");
+    return CPM_ENOMEM;
+  }
+  if (rocblas_create_handle(&h) != rocblas_status_success ||
+      rocblas_set_stream(h, st) != rocblas_status_success) {
+    release();
+    set_error("PCG-DC: rocBLAS handle");
+    return CPM_EDEVICE;
+  }
+  const double erfc_rc = std::erfc(g * rcut);
+  std::vector<double4> himg((size_t)cap * mfirst);
+  std::vector<int32_t> hlen(cap), hinfo(cap);
+  std::vector<double> hx((size_t)cap * mfirst);
+  for (int64_t b0 = 0; b0 < n;) {
+    const int mm = (int)nb[order[b0]].size() + 1;   // the batch's largest (<= mfirst)
+    const int64_t nb_b =
+        std::min<int64_t>({n - b0, cap, std::max<int64_t>(1, a_elems / ((int64_t)mm * mm))});
+    for (int64_t b = 0; b < nb_b; ++b) {
+      const int64_t tau = order[b0 + b];
+      const std::vector<Image> &v = nb[tau];
+      hlen[b] = (int32_t)v.size() + 1;
+      double4 *row = himg.data() + (size_t)b * mm;
+      row[0] = make_double4(s->pos_host[3 * tau], s->pos_host[3 * tau + 1], s->pos_host[3 * tau + 2],
+                            s->width_host[tau]);
+      for (size_t k = 0; k < v.size(); ++k)
+        row[k + 1] = make_double4(v[k].x, v[k].y, v[k].z, s->width_host[v[k].atom]);
+    }
+    hipError_t e = hipMemcpyAsync(img, himg.data(), sizeof(double4) * (size_t)nb_b * mm,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(mlen, hlen.data(), sizeof(int32_t) * nb_b, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+      const int64_t ent = (int64_t)mm * mm;
+      hipLaunchKernelGGL(dc_local_kernel, dim3((unsigned)((ent + 255) / 256), (unsigned)nb_b),
+                         dim3(256), 0, st, (const double4 *)img, (const int32_t *)mlen, mm, g, rcut,
+                         erfc_rc, A, X);
+      e = hipGetLastError();
+    }
+    const rocblas_stride sa = (rocblas_stride)mm * mm, sx = mm;
+    if (e != hipSuccess ||
+        rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, mm, A, mm, sa, info,
+                                         (rocblas_int)nb_b) != rocblas_status_success ||
+        rocsolver_dpotrs_strided_batched(h, rocblas_fill_lower, mm, 1, A, mm, sa, X, mm, sx,
+                                         (rocblas_int)nb_b) != rocblas_status_success) {
+      release();
+      set_error("PCG-DC: batched factorisation failed");
+      return CPM_EDEVICE;
+    }
+    e = hipMemcpyAsync(hx.data(), X, sizeof(double) * (size_t)nb_b * mm, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hinfo.data(), info, sizeof(int32_t) * nb_b, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      release();
+      set_error(std::string("PCG-DC: ") + hipGetErrorString(e));
+      return CPM_EDEVICE;
+    }
+    for (int64_t b = 0; b < nb_b; ++b)
+      if (hinfo[b] != 0) {
+        release();
+        set_error("PCG-DC: the local matrix of atom " + std::to_string(order[b0 + b]) +
+                  " (Eq. 36) is not positive definite");
+        return CPM_ENOTSPD;
+      }
+    parallel_for(nb_b, [&](int64_t b, int) {
+      const int64_t tau = order[b0 + b];
+      const std::vector<Image> &v = nb[tau];
+      const double *x = hx.data() + (size_t)b * mm;
+      std::vector<std::pair<int32_t, double>> &c = col[tau];
+      c.push_back({(int32_t)tau, x[0]});
+      for (size_t k = 1; k <= v.size(); ++k) {
+        const int32_t j = v[k - 1].atom;
+        auto it = std::lower_bound(
+            c.begin(), c.end(), j,
+            [](const std::pair<int32_t, double> &q, int32_t a) { return q.first < a; });
+        if (it != c.end() && it->first == j)
+          it->second += x[k];
+        else
+          c.insert(it, {j, x[k]});
+      }
+    });
+    b0 += nb_b;
+  }
+  release();
+  return CPM_OK;
+}
+
 }  // namespace
 
 }  // namespace cpm
@@ -239,59 +380,8 @@ cpm_status cpm_precond_dc(cpm_system *s, double g, double rcut) {
 
   // column tau of P: (atom, value) pairs, images of one atom summed
   std::vector<std::vector<std::pair<int32_t, double>>> col(n);
-  const int nt = build_threads();
-  std::vector<std::vector<double>> scratch(nt, std::vector<double>((size_t)mmax * mmax + 2 * mmax));
-  std::atomic<int64_t> bad{-1};
-  const double erfc_rc = std::erfc(g * rcut), self = std::sqrt(2.0 / M_PI);
-  parallel_for(n, [&](int64_t tau, int tid) {
-    const std::vector<Image> &v = nb[tau];
-    const int m = (int)v.size() + 1;
-    double *M = scratch[tid].data(), *y = M + (size_t)mmax * mmax, *x = y + mmax;
-    auto px = [&](int k, int d) {
-      if (k == 0) return s->pos_host[3 * tau + d];
-      return d == 0 ? v[k - 1].x : (d == 1 ? v[k - 1].y : v[k - 1].z);
-    };
-    auto width = [&](int k) { return s->width_host[k == 0 ? tau : v[k - 1].atom]; };
-    for (int k = 0; k < m; ++k) {
-      M[(size_t)k * m + k] = self * width(k);
-      for (int l = 0; l < k; ++l) {
-        const double dx = px(k, 0) - px(l, 0), dy = px(k, 1) - px(l, 1), dz = px(k, 2) - px(l, 2);
-        const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
-        M[(size_t)k * m + l] = (r > 0.0 && r < rcut) ? (std::erfc(g * r) - erfc_rc) / r : 0.0;
-      }
-    }
-    if (!cholesky(M, m)) {
-      bad.store(tau);
-      return;
-    }
-    // M x = e_0: L y = e_0, L^T x = y
-    for (int i = 0; i < m; ++i) {
-      double t = (i == 0) ? 1.0 : 0.0;
-      for (int l = 0; l < i; ++l) t -= M[(size_t)i * m + l] * y[l];
-      y[i] = t / M[(size_t)i * m + i];
-    }
-    for (int i = m - 1; i >= 0; --i) {
-      double t = y[i];
-      for (int l = i + 1; l < m; ++l) t -= M[(size_t)l * m + i] * x[l];
-      x[i] = t / M[(size_t)i * m + i];
-    }
-    std::vector<std::pair<int32_t, double>> &c = col[tau];
-    c.push_back({(int32_t)tau, x[0]});
-    for (int k = 1; k < m; ++k) {
-      const int32_t j = v[k - 1].atom;
-      auto it = std::lower_bound(c.begin(), c.end(), j,
-                                 [](const std::pair<int32_t, double> &e, int32_t a) { return e.first < a; });
-      if (it != c.end() && it->first == j)
-        it->second += x[k];
-      else
-        c.insert(it, {j, x[k]});
-    }
-  });
-  if (bad.load() >= 0) {
-    set_error("PCG-DC: the local matrix of atom " + std::to_string(bad.load()) +
-              " (Eq. 36) is not positive definite");
-    return CPM_ENOTSPD;
-  }
+  cpm_status rcol = dc_columns_device(s, nb, g, rcut, col);
+  if (rcol != CPM_OK) return rcol;
   // symmetric part, row by row: P_s[i][j] = (C_i[j] + C_j[i]) / 2
   auto entry = [&](int64_t c, int32_t r) {
     const auto &v = col[c];
