@@ -75,8 +75,8 @@ def parse():
     ap.add_argument("--precond", default="dc", choices=["jacobi", "dc"],
                     help="preconditioner of the timed solves")
     ap.add_argument("--dc-g", type=float, default=None,
-                    help="PCG-DC screening g (1/A); default 0.15 with r_cut 7 (a sweep on "
-                         "workload 2), 0.10 with 10 at workload 5 (a sweep there); the paper: "
+                    help="PCG-DC screening g (1/A); default 0.08 with r_cut 12 / 14 / 14 A at "
+                         "workloads 2 / 3 / 5 (sweeps there), else 0.15 with 7; the paper: "
                          "0.083 with 8")
     ap.add_argument("--dc-rcut", type=float, default=None, help="PCG-DC cutoff (A)")
     ap.add_argument("--weights", default=None,
@@ -300,14 +300,17 @@ def main():
     cfg = args.workload
     if args.check_every is None:
         args.check_every = 8 if cfg == 5 else 4
-    # PCG-DC: at workload 5 the apply costs 0.34 ms against a 12.4 ms product,
-    # so a wider P pays: a sweep of (g, r_cut) from (0.15, 7) to (0.07, 12)
-    # gave 80 FP32 iterations at (0.15, 7), 72 at 9 A, 64 at (0.10, 10) and
-    # 56 at (0.10, 12), whose host construction takes 89 s against 24 s at 10
+    # PCG-DC: the apply is cheap next to the product at large N, so a wide P
+    # pays. Sweeps of (g, r_cut) over (0.15, 7) .. (0.06, 16) on each
+    # workload (FP32 iterations to 1e-11): workload 5 80 at (0.15, 7), 64 at
+    # (0.10, 10), 56 at 12 A, 48 at (0.08, 14) (solve 1132 -> 763 ms; 16 A no
+    # better); workload 3 52 -> 32 at (0.08, 14) (84.9 -> 74.1 ms); workload 2
+    # 32 -> 24 at (0.08, 12), 1.78 -> 1.74 ms (its apply is half the product's
+    # time, so 14 A is slower there)
     if args.dc_g is None:
-        args.dc_g = 0.10 if cfg == 5 else 0.15
+        args.dc_g = 0.08 if cfg in (2, 3, 5) else 0.15
     if args.dc_rcut is None:
-        args.dc_rcut = 10.0 if cfg == 5 else 7.0
+        args.dc_rcut = {2: 12.0, 3: 14.0, 5: 14.0}.get(cfg, 7.0)
     geo, ipos, iq, chi = wl.workload(cfg)
     if args.jitter > 0:
         # genericity check: the same workload with every electrode atom displaced
