@@ -213,11 +213,14 @@ cpm_status cpm_solve(cpm_system *s, const double *b_dev, const double *qsol_dev,
  * with r_ij the distance of the two images; the column of M_tau^-1 belonging
  * to tau becomes column tau of P (entries of images of one atom add up, zero
  * beyond rcut). The solver uses the symmetric part (P + P^T) / 2. Built once
- * per system (local FP64 Cholesky factorisations on host threads), kept on
- * the device in ELL form; cpm_solve applies it with CPM_PRECOND_DC. The
- * paper's choice for graphene electrodes is g = 0.083 / A, rcut = 8 A.
- * Errors: CPM_EINVAL (g or rcut not finite and > 0, point-charge atoms),
- * CPM_ENOTSPD (a local matrix is not positive definite), CPM_ENOMEM. */
+ * per system: the neighbourhoods on host threads, the local matrices and
+ * their FP64 Cholesky factorisations on the device (rocSOLVER, batched);
+ * kept on the device in a block-dense form (tiles of 64 atoms over the
+ * union of their columns) that cpm_solve applies with CPM_PRECOND_DC on the
+ * FP64 matrix cores. The paper's choice for graphene electrodes is
+ * g = 0.083 / A, rcut = 8 A. Errors: CPM_EINVAL (g or rcut not finite and
+ * > 0, point-charge atoms), CPM_ENOTSPD (a local matrix is not positive
+ * definite), CPM_ENOMEM, CPM_EDEVICE. */
 cpm_status cpm_precond_dc(cpm_system *s, double screening_g, double rcut);
 
 /* z = P r for f vectors, r_dev and z_dev (f, n) device arrays: the solver's
@@ -232,7 +235,7 @@ cpm_status cpm_precond_apply(cpm_system *s, const double *r_dev, int64_t f, doub
  * (cpm_mi_build first; S symmetrised entry by entry). PCG-Normal takes a
  * preset rcut, PCG-Full the cutoff of the neighbour list. The result
  * replaces the system's sparse preconditioner (the one CPM_PRECOND_DC
- * applies) in the same ELL form. Errors: CPM_EINVAL (rcut not finite and
+ * applies) in the same block-dense form. Errors: CPM_EINVAL (rcut not finite and
  * > 0), CPM_ESTATE (no cpm_mi_build), CPM_ENOMEM, CPM_EDEVICE. */
 cpm_status cpm_precond_sparse_inverse(cpm_system *s, double rcut);
 

@@ -92,24 +92,37 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-struct Precond {              // sparse PCG preconditioner P in ELL form
+struct Precond {              // sparse PCG preconditioner P
   bool ready = false;
   int kind = 0;               // 0: PCG-DC (P + P^T) / 2 (Eq. 36); 1: E^-1 sparsified by distance
   double g = 0, rcut = 0;     // screening and cutoff of Eq. 36 (kind 0), cutoff (kind 1)
-  int width = 0;              // entries per row (padded with (i, 0))
+  int width = 0;              // entries per ELL row (padded with (i, 0))
   int max_local = 0;          // largest local matrix
   int64_t nnz = 0;
-  int32_t *idx = nullptr;     // n * width: column of entry k of the row of atom atom_order[t] at t * width + k
-  double *val = nullptr;      // width * n (minus gap on the real entries when the gap is on)
   int64_t bytes = 0;           // device memory held
   // Eq. 37: the zeros of P filled with gap (0: off); applied as
   // z = (P - gap on its pattern) r + gap (1^T r) 1
   double gap = 0.0;
   double sum_p = 0.0;         // sum of the entries of P (without the gap)
-  std::vector<int32_t> h_idx; // host copies of the ELL arrays without the gap
+  // host ELL form without the gap: row t is the row of atom atom_order[t],
+  // entry k (column, value) at t * width + k, h_len[t] real entries
+  std::vector<int32_t> h_idx;
   std::vector<double> h_val;
-  std::vector<int32_t> h_len; // real entries per ELL row
+  std::vector<int32_t> h_len;
+  // block-dense form, what the apply reads: tile t holds the kPcTile ELL
+  // rows t kPcTile .. (atom_order positions) over U_t, the sorted union of
+  // their columns padded to a multiple of 4 with its first column:
+  // U_t = uidx[uoff[t] .. uoff[t + 1]), entry (row, k) of the tile at
+  // blk[(uoff[t] + k) * kPcTile + row] (P minus gap on its pattern, zero
+  // off it and in the padding)
+  int64_t ntiles = 0;
+  int64_t *uoff = nullptr;
+  int32_t *uidx = nullptr;
+  double *blk = nullptr;
+  std::vector<int64_t> h_uoff;
+  std::vector<int32_t> h_uidx;
 };
+constexpr int kPcTile = 64;
 void free_precond(Precond &p);
 
 struct Gcd {                 // capacitance coefficients (Supplementary Eq. S22-S24)

@@ -4,9 +4,11 @@
 // (every atom image within rcut) is formed from Eq. 36, factorised
 // (Cholesky, FP64), and the column of M_tau^-1 belonging to tau becomes
 // column tau of P; entries of different images of one atom add up. CG needs
-// a symmetric preconditioner, so the device copy holds (P + P^T) / 2 in
-// row-major ELL form: entry k of row i at i * width + k (column index,
-// value), rows padded with (i, 0). The construction runs once per system:
+// a symmetric preconditioner, so it uses (P + P^T) / 2, kept on the host in
+// row-major ELL form (entry k of row i at i * width + k, rows padded with
+// (i, 0)) and on the device in the block-dense form the apply reads (tiles
+// of 64 atoms over the union of their columns). The construction runs once
+// per system:
 // the neighbourhoods on host threads, the local matrices and their batched
 // Cholesky factorisations and solves on the device; the apply z = P r of
 // every PCG iteration runs on the device (cg.hip). Also here: the
@@ -129,7 +131,7 @@ std::vector<std::vector<Image>> neighbourhoods(const std::vector<double> &pos, i
 }  // namespace
 
 void free_precond(Precond &p) {
-  void *ptrs[] = {p.idx, p.val};
+  void *ptrs[] = {p.uoff, p.uidx, p.blk};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   p = Precond();
@@ -137,21 +139,70 @@ void free_precond(Precond &p) {
 
 namespace {
 
-// p's host ELL arrays to new device arrays; on success p replaces the
+// the tiles' column unions (host): U_t sorted, padded to a multiple of 4
+void block_pattern(Precond &p, int64_t n) {
+  p.ntiles = (n + kPcTile - 1) / kPcTile;
+  std::vector<std::vector<int32_t>> u(p.ntiles);
+  parallel_for(p.ntiles, [&](int64_t t, int) {
+    std::vector<int32_t> &v = u[t];
+    for (int64_t r = t * kPcTile; r < std::min<int64_t>(n, (t + 1) * kPcTile); ++r)
+      for (int k = 0; k < p.h_len[r]; ++k) v.push_back(p.h_idx[(size_t)r * p.width + k]);
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    if (v.empty()) v.push_back(0);
+    while (v.size() % 4 != 0) v.push_back(v[0]);
+  });
+  p.h_uoff.assign(p.ntiles + 1, 0);
+  for (int64_t t = 0; t < p.ntiles; ++t) p.h_uoff[t + 1] = p.h_uoff[t] + (int64_t)u[t].size();
+  p.h_uidx.assign(p.h_uoff[p.ntiles], 0);
+  for (int64_t t = 0; t < p.ntiles; ++t)
+    std::copy(u[t].begin(), u[t].end(), p.h_uidx.begin() + p.h_uoff[t]);
+}
+
+// the dense tile entries (host): P minus gap on its pattern
+std::vector<double> block_values(const Precond &p, int64_t n, double gap) {
+  std::vector<double> b((size_t)p.h_uoff[p.ntiles] * kPcTile, 0.0);
+  parallel_for(p.ntiles, [&](int64_t t, int) {
+    const int32_t *u0 = p.h_uidx.data() + p.h_uoff[t];
+    int64_t K = p.h_uoff[t + 1] - p.h_uoff[t];
+    // the sorted part: the padding repeats U_t[0] after it
+    for (int64_t i = 1; i < K; ++i)
+      if (u0[i] == u0[0]) {
+        K = i;
+        break;
+      }
+    double *bt = b.data() + (size_t)p.h_uoff[t] * kPcTile;
+    for (int64_t r = t * kPcTile; r < std::min<int64_t>(n, (t + 1) * kPcTile); ++r)
+      for (int k = 0; k < p.h_len[r]; ++k) {
+        const int32_t j = p.h_idx[(size_t)r * p.width + k];
+        const int64_t kk = std::lower_bound(u0, u0 + K, j) - u0;
+        bt[(size_t)kk * kPcTile + (r - t * kPcTile)] += p.h_val[(size_t)r * p.width + k] - gap;
+      }
+  });
+  return b;
+}
+
+// p's block-dense form to new device arrays; on success p replaces the
 // system's preconditioner (the previous one is freed)
 cpm_status install_precond(cpm_system *s, Precond &p) {
-  if (hipMalloc((void **)&p.idx, sizeof(int32_t) * p.h_idx.size()) != hipSuccess ||
-      hipMalloc((void **)&p.val, sizeof(double) * p.h_val.size()) != hipSuccess) {
+  block_pattern(p, s->n);
+  const std::vector<double> b = block_values(p, s->n, 0.0);
+  if (hipMalloc((void **)&p.uoff, sizeof(int64_t) * p.h_uoff.size()) != hipSuccess ||
+      hipMalloc((void **)&p.uidx, sizeof(int32_t) * p.h_uidx.size()) != hipSuccess ||
+      hipMalloc((void **)&p.blk, sizeof(double) * b.size()) != hipSuccess) {
     (void)hipGetLastError();
     free_precond(p);
     set_error("preconditioner allocation failed");
     return CPM_ENOMEM;
   }
-  CPM_HIP_CHECK(hipMemcpyAsync(p.idx, p.h_idx.data(), sizeof(int32_t) * p.h_idx.size(),
+  CPM_HIP_CHECK(hipMemcpyAsync(p.uoff, p.h_uoff.data(), sizeof(int64_t) * p.h_uoff.size(),
                                hipMemcpyHostToDevice, s->stream));
-  CPM_HIP_CHECK(hipMemcpyAsync(p.val, p.h_val.data(), sizeof(double) * p.h_val.size(),
+  CPM_HIP_CHECK(hipMemcpyAsync(p.uidx, p.h_uidx.data(), sizeof(int32_t) * p.h_uidx.size(),
                                hipMemcpyHostToDevice, s->stream));
-  p.bytes = (int64_t)(sizeof(int32_t) * p.h_idx.size() + sizeof(double) * p.h_val.size());
+  CPM_HIP_CHECK(hipMemcpyAsync(p.blk, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice,
+                               s->stream));
+  p.bytes = (int64_t)(sizeof(int64_t) * p.h_uoff.size() + sizeof(int32_t) * p.h_uidx.size() +
+                      sizeof(double) * b.size());
   CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   p.sum_p = 0.0;
   for (size_t e = 0; e < p.h_val.size(); ++e) p.sum_p += p.h_val[e];   // padding entries are 0
@@ -542,12 +593,9 @@ cpm_status cpm_precond_gap(cpm_system *s, int enable, double *gap_out) {
     // 1^T E^-1 1 = 1^T d' = C_ele
     gap = n_zero > 0.0 ? (s->c_ele - p.sum_p) / n_zero : 0.0;
   }
-  std::vector<double> val = p.h_val;
-  if (gap != 0.0)
-    for (int64_t t = 0; t < s->n; ++t)
-      for (int k = 0; k < p.h_len[t]; ++k) val[(size_t)t * p.width + k] -= gap;
-  CPM_HIP_CHECK(hipMemcpyAsync(p.val, val.data(), sizeof(double) * val.size(),
-                               hipMemcpyHostToDevice, s->stream));
+  const std::vector<double> b = block_values(p, s->n, gap);
+  CPM_HIP_CHECK(hipMemcpyAsync(p.blk, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice,
+                               s->stream));
   CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   p.gap = gap;
   if (gap_out) *gap_out = gap;
