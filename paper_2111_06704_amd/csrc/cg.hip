@@ -1036,6 +1036,131 @@ __global__ __launch_bounds__(RED_THREADS) void colsum_kernel(const double *__res
   if (threadIdx.x == 0) rsum[c] = acc;
 }
 
+// Preconditioner apply for small systems (fewer than kPcBlockTiles tiles of
+// the block-dense form, whose few workgroups would leave most of the chip
+// idle): z = P r with P in row-major ELL form whose
+// row t is the row of atom order[t] (entry k at t * width + k), r in the
+// row-interleaved layout of rows_kernel. One wavefront per row (rows taken
+// in the spatial order) and column group (grid.y); lane = 8 e + h takes
+// entries k = e, e + 8, ... and the column pair (2h, 2h + 1), so every
+// gather of the wavefront reads eight whole 128-byte lines. Each wavefront
+// stages its row of P in LDS with all its loads in flight at once (the ELL
+// row does not depend on order[t], so that load overlaps them), and the
+// vector memory path then serves only the gathers. The eight entry lanes of
+// each pair are summed by shuffles in a fixed order. Active columns only
+// (scal == nullptr: all); set_p: p = z. bpart (may be null): per workgroup
+// and column (r.r, r.z), column-major (bpart[(c * gridDim.x + block) * 2 +
+// {0, 1}]) so that the kernels summing one column read it contiguously.
+constexpr int PC_ROWS = 4;                  // rows (waves) per workgroup
+constexpr int PC_THREADS = 64 * PC_ROWS;
+constexpr int PC_CHUNK = 256;               // entries per row staged at a time
+constexpr int PC_PER_LANE = PC_CHUNK / 64;
+
+template <typename VT>
+__global__ __launch_bounds__(PC_THREADS) void precond_kernel(
+    const double *__restrict__ rt, double *__restrict__ z, VT *__restrict__ p,
+    const int32_t *__restrict__ pidx, const double *__restrict__ pval, int width,
+    const int32_t *__restrict__ order, int64_t ld, int64_t n, int cols,
+    const double *__restrict__ scal, int slot, double *__restrict__ bpart, int set_p,
+    double gap, const double *__restrict__ rsum, const int *__restrict__ gate) {
+  __shared__ double red[PC_ROWS][kColGroup][2];
+  __shared__ double sval[PC_ROWS][PC_CHUNK];
+  __shared__ int32_t sidx[PC_ROWS][PC_CHUNK];
+  if (gate != nullptr && *gate == 0) return;
+  const int g = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = lane >> 3, h = lane & 7;
+  const int64_t t = (int64_t)blockIdx.x * PC_ROWS + wave;
+  const bool live = t < n;
+  const int64_t i = live ? (int64_t)order[t] : -1;
+  const int32_t *ix = pidx + (live ? t : 0) * width;
+  const double *vx = pval + (live ? t : 0) * width;
+  const double *rg = rt + (int64_t)g * ld * kColGroup;
+  const int c0 = g * kColGroup + 2 * h;
+  const bool act0 = scal == nullptr || (scal[S_ACT * cols + c0] != 0.0 &&
+                                         scal[(S_HOLD0 + slot) * cols + c0] == 0.0);
+  const bool act1 = scal == nullptr || (scal[S_ACT * cols + c0 + 1] != 0.0 &&
+                                         scal[(S_HOLD0 + slot) * cols + c0 + 1] == 0.0);
+  double2 ri = make_double2(0.0, 0.0);
+  double a0 = 0.0, a1 = 0.0;
+  for (int k0 = 0; k0 < width; k0 += PC_CHUNK) {
+    const int cw = min(PC_CHUNK, width - k0);
+    int32_t li[PC_PER_LANE];
+    double lv[PC_PER_LANE];
+#pragma unroll
+    for (int u = 0; u < PC_PER_LANE; ++u) {
+      const int k = lane + 64 * u;
+      li[u] = 0;
+      lv[u] = 0.0;
+      if (live && k < cw) {
+        li[u] = ix[k0 + k];
+        lv[u] = vx[k0 + k];
+      }
+    }
+    if (k0 == 0 && i >= 0) ri = *reinterpret_cast<const double2 *>(rg + i * kColGroup + 2 * h);
+    if (k0 > 0) __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PC_PER_LANE; ++u) {
+      const int k = lane + 64 * u;
+      if (k < cw) {
+        sidx[wave][k] = li[u];
+        sval[wave][k] = lv[u];
+      }
+    }
+    __syncthreads();
+    if (i >= 0) {
+#pragma unroll 4
+      for (int k = e; k < cw; k += 8) {
+        const int64_t j = sidx[wave][k];
+        const double v = sval[wave][k];
+        const double2 x = *reinterpret_cast<const double2 *>(rg + j * kColGroup + 2 * h);
+        a0 += v * x.x;
+        a1 += v * x.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 8; off < 64; off <<= 1) {
+    a0 += __shfl_xor(a0, off, 64);
+    a1 += __shfl_xor(a1, off, 64);
+  }
+  // lanes 0..7 hold columns (2h, 2h + 1)
+  if (lane < 8) {
+    double d[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    if (i >= 0) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        // the Eq. 37 fill: P's zeros hold gap, its pattern P - gap
+        const double zi = (u ? a1 : a0) + (rsum != nullptr ? gap * rsum[c0 + u] : 0.0);
+        const double rv = u ? ri.y : ri.x;
+        if (u ? act1 : act0) {
+          const int64_t idx = (int64_t)(c0 + u) * ld + i;
+          z[idx] = zi;
+          if (set_p || (scal != nullptr && scal[S_RST * cols + c0 + u] != 0.0)) p[idx] = (VT)zi;
+          d[u][0] = rv * rv;
+          d[u][1] = rv * zi;
+        }
+      }
+    }
+    if (bpart != nullptr) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        red[wave][2 * h + u][0] = d[u][0];
+        red[wave][2 * h + u][1] = d[u][1];
+      }
+    }
+  }
+  if (bpart == nullptr) return;
+  __syncthreads();
+  if (threadIdx.x < 2 * kColGroup) {
+    const int c = threadIdx.x >> 1, s2 = threadIdx.x & 1;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < PC_ROWS; ++w) v += red[w][c][s2];
+    bpart[((int64_t)(g * kColGroup + c) * gridDim.x + blockIdx.x) * 2 + s2] = v;
+  }
+}
+
 // Preconditioner apply (Sec. III.B.2): z = P r with P in its block-dense
 // form: tile t (one workgroup) holds the kPcTile rows of atoms
 // order[t kPcTile ..] over U_t, the union of their columns, so z of the tile
@@ -1604,7 +1729,7 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
             alloc((void **)&w.sum_err, sizeof(double) * MAX_COLS) &&
             alloc((void **)&w.rsum, sizeof(double) * MAX_COLS) &&
             alloc((void **)&w.bpart,
-                  sizeof(double) * 2 * (size_t)((s->n + kPcTile - 1) / kPcTile) * cols) &&
+                  sizeof(double) * 2 * (size_t)((s->n + PC_ROWS - 1) / PC_ROWS) * cols) &&
             alloc((void **)&w.flags, sizeof(int) * F_NWORDS);
   if (ok && (hipHostMalloc((void **)&w.hstat, sizeof(int) * F_NWORDS * kStatusSlots,
                            hipHostMallocDefault) != hipSuccess ||
@@ -1668,6 +1793,14 @@ void launch_precond(hipStream_t st, const cpm_system *s, const Precond &pc, cons
     hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, r, rs, n, fc,
                        s->ws.rsum, gate);
     rsum = s->ws.rsum;
+  }
+  if (pc.blk == nullptr) {
+    hipLaunchKernelGGL(precond_kernel<VT>,
+                       dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
+                       dim3(PC_THREADS), 0, st, rt, z, p, (const int32_t *)pc.idx,
+                       (const double *)pc.val, pc.width, s->atom_order, ld, n, (int)cols, scal,
+                       slot, bpart, set_p ? 1 : 0, pc.gap, rsum, gate);
+    return;
   }
   const dim3 grid((unsigned)pc.ntiles);
 #define CPM_PB(NGV)                                                                            \
@@ -1742,7 +1875,7 @@ template <typename T> struct Solver {
   // partial sums of r.r / r.z per column that the direction and set_scalars
   // kernels add up: one per vector block (Jacobi) or per preconditioner
   // workgroup (DC)
-  int npc() const { return (int)pc->ntiles; }
+  int npc() const { return pc->blk ? (int)pc->ntiles : (int)((n + PC_ROWS - 1) / PC_ROWS); }
   int nred() const { return pc ? npc() : nblk; }
   const double *dots() const { return pc ? s->ws.bpart : partial; }
   int dots_cmajor() const { return pc ? 1 : 0; }

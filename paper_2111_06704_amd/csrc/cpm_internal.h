@@ -99,6 +99,11 @@ struct Precond {              // sparse PCG preconditioner P
   int width = 0;              // entries per ELL row (padded with (i, 0))
   int max_local = 0;          // largest local matrix
   int64_t nnz = 0;
+  // device ELL form (systems below kPcBlockTiles tiles): column of entry k
+  // of the row of atom atom_order[t] at t * width + k, value (minus gap on
+  // the real entries when the gap is on)
+  int32_t *idx = nullptr;
+  double *val = nullptr;
   int64_t bytes = 0;           // device memory held
   // Eq. 37: the zeros of P filled with gap (0: off); applied as
   // z = (P - gap on its pattern) r + gap (1^T r) 1
@@ -109,7 +114,7 @@ struct Precond {              // sparse PCG preconditioner P
   std::vector<int32_t> h_idx;
   std::vector<double> h_val;
   std::vector<int32_t> h_len;
-  // block-dense form, what the apply reads: tile t holds the kPcTile ELL
+  // block-dense form (from kPcBlockTiles tiles on): tile t holds the kPcTile ELL
   // rows t kPcTile .. (atom_order positions) over U_t, the sorted union of
   // their columns padded to a multiple of 4 with its first column:
   // U_t = uidx[uoff[t] .. uoff[t + 1]), entry (row, k) of the tile at
@@ -123,6 +128,9 @@ struct Precond {              // sparse PCG preconditioner P
   std::vector<int32_t> h_uidx;
 };
 constexpr int kPcTile = 64;
+// the block-dense form from this many tiles on (N >= 16384); below, the ELL
+// form (one wavefront per row) keeps more of the chip busy
+constexpr int64_t kPcBlockTiles = 256;
 void free_precond(Precond &p);
 
 struct Gcd {                 // capacitance coefficients (Supplementary Eq. S22-S24)

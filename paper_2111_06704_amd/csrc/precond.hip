@@ -6,9 +6,9 @@
 // column tau of P; entries of different images of one atom add up. CG needs
 // a symmetric preconditioner, so it uses (P + P^T) / 2, kept on the host in
 // row-major ELL form (entry k of row i at i * width + k, rows padded with
-// (i, 0)) and on the device in the block-dense form the apply reads (tiles
-// of 64 atoms over the union of their columns). The construction runs once
-// per system:
+// (i, 0)) and on the device in the form the apply reads: block-dense (tiles
+// of 64 atoms over the union of their columns) for large systems, the ELL
+// rows for small ones. The construction runs once per system:
 // the neighbourhoods on host threads, the local matrices and their batched
 // Cholesky factorisations and solves on the device; the apply z = P r of
 // every PCG iteration runs on the device (cg.hip). Also here: the
@@ -131,7 +131,7 @@ std::vector<std::vector<Image>> neighbourhoods(const std::vector<double> &pos, i
 }  // namespace
 
 void free_precond(Precond &p) {
-  void *ptrs[] = {p.uoff, p.uidx, p.blk};
+  void *ptrs[] = {p.idx, p.val, p.uoff, p.uidx, p.blk};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   p = Precond();
@@ -182,27 +182,49 @@ std::vector<double> block_values(const Precond &p, int64_t n, double gap) {
   return b;
 }
 
-// p's block-dense form to new device arrays; on success p replaces the
-// system's preconditioner (the previous one is freed)
+// p's device form (block-dense from kPcBlockTiles tiles on, else ELL) to
+// new device arrays; on success p replaces the system's preconditioner (the
+// previous one is freed)
 cpm_status install_precond(cpm_system *s, Precond &p) {
   block_pattern(p, s->n);
-  const std::vector<double> b = block_values(p, s->n, 0.0);
-  if (hipMalloc((void **)&p.uoff, sizeof(int64_t) * p.h_uoff.size()) != hipSuccess ||
-      hipMalloc((void **)&p.uidx, sizeof(int32_t) * p.h_uidx.size()) != hipSuccess ||
-      hipMalloc((void **)&p.blk, sizeof(double) * b.size()) != hipSuccess) {
+  // CPM_PRECOND_BLOCK=1 / 0 in the environment forces the form (tests run
+  // both at small sizes)
+  bool blocks = p.ntiles >= kPcBlockTiles;
+  if (const char *e = std::getenv("CPM_PRECOND_BLOCK"))
+    if (e[0] == '0' || e[0] == '1') blocks = e[0] == '1';
+  std::vector<double> b;
+  bool ok = true;
+  if (blocks) {
+    b = block_values(p, s->n, 0.0);
+    ok = hipMalloc((void **)&p.uoff, sizeof(int64_t) * p.h_uoff.size()) == hipSuccess &&
+         hipMalloc((void **)&p.uidx, sizeof(int32_t) * p.h_uidx.size()) == hipSuccess &&
+         hipMalloc((void **)&p.blk, sizeof(double) * b.size()) == hipSuccess;
+  } else {
+    ok = hipMalloc((void **)&p.idx, sizeof(int32_t) * p.h_idx.size()) == hipSuccess &&
+         hipMalloc((void **)&p.val, sizeof(double) * p.h_val.size()) == hipSuccess;
+  }
+  if (!ok) {
     (void)hipGetLastError();
     free_precond(p);
     set_error("preconditioner allocation failed");
     return CPM_ENOMEM;
   }
-  CPM_HIP_CHECK(hipMemcpyAsync(p.uoff, p.h_uoff.data(), sizeof(int64_t) * p.h_uoff.size(),
-                               hipMemcpyHostToDevice, s->stream));
-  CPM_HIP_CHECK(hipMemcpyAsync(p.uidx, p.h_uidx.data(), sizeof(int32_t) * p.h_uidx.size(),
-                               hipMemcpyHostToDevice, s->stream));
-  CPM_HIP_CHECK(hipMemcpyAsync(p.blk, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice,
-                               s->stream));
-  p.bytes = (int64_t)(sizeof(int64_t) * p.h_uoff.size() + sizeof(int32_t) * p.h_uidx.size() +
-                      sizeof(double) * b.size());
+  if (blocks) {
+    CPM_HIP_CHECK(hipMemcpyAsync(p.uoff, p.h_uoff.data(), sizeof(int64_t) * p.h_uoff.size(),
+                                 hipMemcpyHostToDevice, s->stream));
+    CPM_HIP_CHECK(hipMemcpyAsync(p.uidx, p.h_uidx.data(), sizeof(int32_t) * p.h_uidx.size(),
+                                 hipMemcpyHostToDevice, s->stream));
+    CPM_HIP_CHECK(hipMemcpyAsync(p.blk, b.data(), sizeof(double) * b.size(),
+                                 hipMemcpyHostToDevice, s->stream));
+    p.bytes = (int64_t)(sizeof(int64_t) * p.h_uoff.size() + sizeof(int32_t) * p.h_uidx.size() +
+                        sizeof(double) * b.size());
+  } else {
+    CPM_HIP_CHECK(hipMemcpyAsync(p.idx, p.h_idx.data(), sizeof(int32_t) * p.h_idx.size(),
+                                 hipMemcpyHostToDevice, s->stream));
+    CPM_HIP_CHECK(hipMemcpyAsync(p.val, p.h_val.data(), sizeof(double) * p.h_val.size(),
+                                 hipMemcpyHostToDevice, s->stream));
+    p.bytes = (int64_t)(sizeof(int32_t) * p.h_idx.size() + sizeof(double) * p.h_val.size());
+  }
   CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   p.sum_p = 0.0;
   for (size_t e = 0; e < p.h_val.size(); ++e) p.sum_p += p.h_val[e];   // padding entries are 0
@@ -593,9 +615,18 @@ cpm_status cpm_precond_gap(cpm_system *s, int enable, double *gap_out) {
     // 1^T E^-1 1 = 1^T d' = C_ele
     gap = n_zero > 0.0 ? (s->c_ele - p.sum_p) / n_zero : 0.0;
   }
-  const std::vector<double> b = block_values(p, s->n, gap);
-  CPM_HIP_CHECK(hipMemcpyAsync(p.blk, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice,
-                               s->stream));
+  if (p.blk != nullptr) {
+    const std::vector<double> b = block_values(p, s->n, gap);
+    CPM_HIP_CHECK(hipMemcpyAsync(p.blk, b.data(), sizeof(double) * b.size(),
+                                 hipMemcpyHostToDevice, s->stream));
+  } else {
+    std::vector<double> val = p.h_val;
+    if (gap != 0.0)
+      for (int64_t t = 0; t < s->n; ++t)
+        for (int k = 0; k < p.h_len[t]; ++k) val[(size_t)t * p.width + k] -= gap;
+    CPM_HIP_CHECK(hipMemcpyAsync(p.val, val.data(), sizeof(double) * val.size(),
+                                 hipMemcpyHostToDevice, s->stream));
+  }
   CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   p.gap = gap;
   if (gap_out) *gap_out = gap;

@@ -92,6 +92,42 @@ def test_solve_dc(which, prec_name, request):
     assert st["iterations"] < 0.8 * st0["iterations"]
 
 
+@pytest.mark.parametrize("which", ["d1", "d2"])
+def test_block_form_matches_oracle(which, request):
+    """The block-dense apply (tiles of 64 atoms over the union of their
+    columns, on the FP64 matrix cores; the form of systems with 256 tiles or
+    more) forced at these sizes: z = P r against the oracle's P (1e-12), with
+    the Eq. 37 fill against with_gap(P, p_gap) (the oracle's sum of E^-1),
+    and the FP32 solve against the oracle's charges."""
+    c = request.getfixturevalue(which)
+    cpm = c.cpm
+    os.environ["CPM_PRECOND_BLOCK"] = "1"
+    try:
+        c.S.precond_dc(G, RDC)
+    finally:
+        del os.environ["CPM_PRECOND_BLOCK"]
+    try:
+        rng = np.random.default_rng(8)
+        for nf in (1, 16, 40):
+            r = rng.standard_normal((nf, c.geo.n))
+            z = c.S.precond_apply(torch.tensor(r, device=c.dev)).cpu().numpy()
+            zo = r @ c.P.T
+            assert np.max(np.abs(z - zo)) <= 1e-12 * np.max(np.abs(zo))
+        q, st = c.S.solve(c.b, c.qsol, tol=1e-11, precision=cpm.PREC_F32, inner_tol=1e-2,
+                          check_every=4, preconditioner=cpm.PRECOND_DC)
+        r2, _ = ocpm.rel_errors(q.cpu().numpy(), c.qo)
+        assert r2.max() <= 1e-8 and st["max_abs_sum_q"] <= 1e-12
+        gap = c.S.precond_gap(True)
+        gap_o = pc.p_gap(c.P, float(np.linalg.inv(c.E).sum()))
+        assert abs(gap - gap_o) <= 1e-9 * abs(gap_o)
+        r = rng.standard_normal((3, c.geo.n))
+        z = c.S.precond_apply(torch.tensor(r, device=c.dev)).cpu().numpy()
+        zo = r @ pc.with_gap(c.P, gap_o).T
+        assert np.max(np.abs(z - zo)) <= 1e-9 * np.max(np.abs(zo))
+    finally:
+        c.S.precond_dc(G, RDC)   # the default form for the other tests
+
+
 def test_dc_requires_build():
     from paper_2111_06704_amd import cpm
     cpm.lib()
