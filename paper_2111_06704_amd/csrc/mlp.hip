@@ -30,8 +30,6 @@ constexpr int NIN = CPM_MLP_IN;
 constexpr int NH = CPM_MLP_HIDDEN;
 constexpr int NP = CPM_MLP_NPARAM;
 constexpr int NNB = 12;
-constexpr int TR = 32;          // rows per tile (LDS footprint < 64 KB)
-constexpr int RPG = TR / 16;    // rows per thread group in the layer products
 constexpr int TT = 256;         // threads per tile block
 // parameter offsets
 constexpr int OW1 = 0, OB1 = OW1 + NIN * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
@@ -80,196 +78,213 @@ __global__ void features_kernel(const double *__restrict__ b, const double *__re
   }
 }
 
-struct TileLds {
-  float x[TR][NIN + 1];
-  float a1[TR][NH + 1];
-  float a2[TR][NH + 1];
-  float g2[TR][NH + 1];   // dL/da2
-  float g1[TR][NH + 1];   // dL/da1
-  float w1[NIN][NH];
-  float w2[NH][NH];
-  float w3[NH];
-  float b1[NH], b2[NH];
-  float y[TR], dy[TR];
-  float b3;
+// Training gradient on the FP32 matrix cores (v_mfma_f32_16x16x4f32 with
+// the operand layout of the inference kernel below: lane (lr, lg) supplies
+// A[row lr][k + lg] and B[k + lg][column lr] and receives
+// D[row 4 lg + v][column lr]). One workgroup per tile of GR rows; writes
+// the tile's gradient (sum over its rows of d/dtheta of (y - t)^2 /
+// rows_total) and its loss sum. Products per tile:
+//   a1 = X W1 (+ b1), a2 = silu(a1) W2 (+ b2): wave w takes rows 16 w ..;
+//   dW2 = silu(a1)^T G2 and dW1 = X^T G1: contractions over the tile's rows;
+//   G1 = (G2 W2^T) o silu'(a1): wave w takes rows 16 w ..;
+// the output layer (one unit) and the bias sums on the vector units, in a
+// fixed order. Rows past the end enter with zero error, so they add nothing.
+constexpr int GR = 64;                    // rows per gradient tile (16 per wavefront)
+constexpr int NINP = (NIN + 3) / 4 * 4;   // input width padded for the k-steps of 4
+constexpr int NHT = NH / 16;              // 16-wide tiles of a hidden layer
+static_assert(NH == 64 && NIN <= 32 && TT == 256 && GR == 4 * 16, "gradient tiling");
+typedef float mf4 __attribute__((ext_vector_type(4)));
+struct GradLds {
+  alignas(16) float w1[NINP][NH];
+  alignas(16) float w2[NH][NH];
+  float b1[NH], b2[NH], w3[NH];
+  float x[GR][33];          // inputs, zero beyond NIN (two 16-wide blocks for dW1)
+  float h1[GR][NH + 1];     // silu(a1)
+  float d1[GR][NH + 1];     // silu'(a1), then G1 = dL/da1
+  float g2[GR][NH + 1];     // G2 = dL/da2
+  float red[4][NH + 1];     // per-wave sums: dW3, db3
+  double lred[4];           // per-wave loss sums
 };
 
-__device__ inline void load_params(TileLds &L, const float *__restrict__ prm) {
-  for (int t = threadIdx.x; t < NIN * NH; t += TT) L.w1[t / NH][t % NH] = prm[OW1 + t];
-  for (int t = threadIdx.x; t < NH * NH; t += TT) L.w2[t / NH][t % NH] = prm[OW2 + t];
-  for (int t = threadIdx.x; t < NH; t += TT) {
-    L.w3[t] = prm[OW3 + t];
-    L.b1[t] = prm[OB1 + t];
-    L.b2[t] = prm[OB2 + t];
-  }
-  if (threadIdx.x == 0) L.b3 = prm[OB3];
-}
-
-// forward pass of one tile: a1, a2 pre-activations and y
-__device__ inline void tile_forward(TileLds &L, int nrows) {
-  const int t = threadIdx.x;
-  const int rg = t >> 4, ug = t & 15;   // rows rg*RPG.., units ug*4..+3
-  {
-    float acc[RPG][4];
-#pragma unroll
-    for (int a = 0; a < RPG; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = L.b1[ug * 4 + c];
-    for (int k = 0; k < NIN; ++k) {
-      float xv[RPG], wv[4];
-#pragma unroll
-      for (int a = 0; a < RPG; ++a) xv[a] = L.x[rg * RPG + a][k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) wv[c] = L.w1[k][ug * 4 + c];
-#pragma unroll
-      for (int a = 0; a < RPG; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xv[a], wv[c], acc[a][c]);
-    }
-#pragma unroll
-    for (int a = 0; a < RPG; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) L.a1[rg * RPG + a][ug * 4 + c] = acc[a][c];
-  }
-  __syncthreads();
-  {
-    float acc[RPG][4];
-#pragma unroll
-    for (int a = 0; a < RPG; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = L.b2[ug * 4 + c];
-    for (int k = 0; k < NH; ++k) {
-      float hv[RPG], wv[4];
-#pragma unroll
-      for (int a = 0; a < RPG; ++a) {
-        const float z = L.a1[rg * RPG + a][k];
-        hv[a] = z * sigm(z);
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) wv[c] = L.w2[k][ug * 4 + c];
-#pragma unroll
-      for (int a = 0; a < RPG; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(hv[a], wv[c], acc[a][c]);
-    }
-#pragma unroll
-    for (int a = 0; a < RPG; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) L.a2[rg * RPG + a][ug * 4 + c] = acc[a][c];
-  }
-  __syncthreads();
-  // y[r] = sum_j silu(a2[r][j]) w3[j] + b3: 4 threads per row, fixed order
-  if (t < 4 * TR) {
-    const int r = t >> 2, part = t & 3;
-    float s = 0.0f;
-    for (int j = part * 16; j < part * 16 + 16; ++j) {
-      const float z = L.a2[r][j];
-      s = fmaf(z * sigm(z), L.w3[j], s);
-    }
-    L.g1[r][part] = s;   // scratch
-  }
-  __syncthreads();
-  if (t < TR) {
-    L.y[t] = ((L.g1[t][0] + L.g1[t][1]) + (L.g1[t][2] + L.g1[t][3])) + L.b3;
-  }
-  __syncthreads();
-  (void)nrows;
-}
-
-__device__ inline void load_rows(TileLds &L, const float *__restrict__ feat, int64_t r0,
-                                 int nrows) {
-  for (int t = threadIdx.x; t < TR * NIN; t += TT) {
-    const int r = t / NIN, k = t % NIN;
-    L.x[r][k] = (r < nrows) ? feat[(r0 + r) * NIN + k] : 0.0f;
-  }
-}
-
-// Forward + backward of one tile; writes the tile's gradient (sum over its
-// rows of d/dtheta of (y - t)^2 / rows_total) and its loss sum.
 __global__ __launch_bounds__(TT) void mlp_grad_kernel(const float *__restrict__ prm,
                                                       const float *__restrict__ feat,
                                                       const float *__restrict__ target,
                                                       int64_t rows, float inv_rows,
                                                       float *__restrict__ gpart,
                                                       double *__restrict__ lpart) {
-  extern __shared__ unsigned char smem[];
-  TileLds &L = *reinterpret_cast<TileLds *>(smem);
-  const int64_t r0 = (int64_t)blockIdx.x * TR;
-  const int nrows = (int)std::min<int64_t>(TR, rows - r0);
-  const int t = threadIdx.x;
-  load_params(L, prm);
-  load_rows(L, feat, r0, nrows);
+  __shared__ GradLds L;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int rw = 16 * wave;
+  const int64_t r0 = (int64_t)blockIdx.x * GR;
+  for (int q = t; q < NINP * NH; q += TT) {
+    const int k = q / NH, j = q % NH;
+    L.w1[k][j] = k < NIN ? prm[OW1 + k * NH + j] : 0.0f;
+  }
+  for (int q = t; q < NH * NH; q += TT) L.w2[q / NH][q % NH] = prm[OW2 + q];
+  if (t < NH) {
+    L.b1[t] = prm[OB1 + t];
+    L.b2[t] = prm[OB2 + t];
+    L.w3[t] = prm[OW3 + t];
+  }
+  const float b3 = prm[OB3];
+  for (int q = t; q < GR * 32; q += TT) {
+    const int r = q / 32, k = q % 32;
+    L.x[r][k] = (r0 + r < rows && k < NIN) ? feat[(r0 + r) * NIN + k] : 0.0f;
+  }
   __syncthreads();
-  tile_forward(L, nrows);
-  if (t < TR) {
-    const float e = (t < nrows) ? (L.y[t] - target[r0 + t]) : 0.0f;
-    L.dy[t] = 2.0f * e * inv_rows;
-    L.y[t] = e * e;   // squared error for the loss
+  // layer 1
+  mf4 acc[NHT];
+#pragma unroll
+  for (int u = 0; u < NHT; ++u) acc[u] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < NINP; k += 4) {
+    const float a = L.x[rw + lr][k + lg];
+#pragma unroll
+    for (int u = 0; u < NHT; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L.w1[k + lg][16 * u + lr], acc[u], 0, 0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < NHT; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rw + 4 * lg + v, unit = 16 * u + lr;
+      const float z = acc[u][v] + L.b1[unit];
+      const float sg = sigm(z);
+      L.h1[row][unit] = z * sg;
+      L.d1[row][unit] = sg * (1.0f + z * (1.0f - sg));
+    }
+  __syncthreads();
+  // layer 2, the output, G2 = dy w3 silu'(a2)
+#pragma unroll
+  for (int u = 0; u < NHT; ++u) acc[u] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+  for (int k = 0; k < NH; k += 4) {
+    const float a = L.h1[rw + lr][k + lg];
+#pragma unroll
+    for (int u = 0; u < NHT; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L.w2[k + lg][16 * u + lr], acc[u], 0, 0, 0);
+  }
+  float dw3[NHT];
+#pragma unroll
+  for (int u = 0; u < NHT; ++u) dw3[u] = 0.0f;
+  float db3 = 0.0f;
+  double loss = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = rw + 4 * lg + v;
+    float h2[NHT], s2[NHT], sp = 0.0f;
+#pragma unroll
+    for (int u = 0; u < NHT; ++u) {
+      const int unit = 16 * u + lr;
+      const float z = acc[u][v] + L.b2[unit];
+      const float sg = sigm(z);
+      h2[u] = z * sg;
+      s2[u] = sg * (1.0f + z * (1.0f - sg));
+      sp = fmaf(h2[u], L.w3[unit], sp);
+    }
+    // every lane of the row group gets the sum over the 64 units
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) sp += __shfl_xor(sp, off, 16);
+    const float e = (r0 + row < rows) ? (sp + b3 - target[r0 + row]) : 0.0f;
+    const float dy = 2.0f * e * inv_rows;
+#pragma unroll
+    for (int u = 0; u < NHT; ++u) {
+      const int unit = 16 * u + lr;
+      L.g2[row][unit] = dy * L.w3[unit] * s2[u];
+      dw3[u] = fmaf(h2[u], dy, dw3[u]);
+    }
+    if (lr == 0) {
+      db3 += dy;
+      loss += (double)(e * e);
+    }
+  }
+  // over the wave's four row groups (lanes lr, lr + 16, lr + 32, lr + 48)
+#pragma unroll
+  for (int u = 0; u < NHT; ++u) {
+    dw3[u] += __shfl_xor(dw3[u], 16, 64);
+    dw3[u] += __shfl_xor(dw3[u], 32, 64);
+  }
+  db3 += __shfl_xor(db3, 16, 64);
+  db3 += __shfl_xor(db3, 32, 64);
+  loss += __shfl_xor(loss, 16, 64);
+  loss += __shfl_xor(loss, 32, 64);
+  if (lg == 0)
+#pragma unroll
+    for (int u = 0; u < NHT; ++u) L.red[wave][16 * u + lr] = dw3[u];
+  if (lane == 0) {
+    L.red[wave][NH] = db3;
+    L.lred[wave] = loss;
   }
   __syncthreads();
   float *g = gpart + (int64_t)blockIdx.x * NP;
+  if (t < NH) g[OW3 + t] = ((L.red[0][t] + L.red[1][t]) + L.red[2][t]) + L.red[3][t];
   if (t == 0) {
-    double ls = 0.0;
-    float db3 = 0.0f;
-    for (int r = 0; r < TR; ++r) {
-      ls += (double)L.y[r];
-      db3 += L.dy[r];
-    }
-    lpart[blockIdx.x] = ls;
-    g[OB3] = db3;
+    g[OB3] = ((L.red[0][NH] + L.red[1][NH]) + L.red[2][NH]) + L.red[3][NH];
+    lpart[blockIdx.x] = ((L.lred[0] + L.lred[1]) + L.lred[2]) + L.lred[3];
   }
-  // dW3[j] = sum_r silu(a2[r][j]) dy[r]; g2[r][j] = dy[r] w3[j] silu'(a2[r][j])
+  // dW2 = silu(a1)^T G2: wave w takes input units 16 w .., every output block
+#pragma unroll
+  for (int u = 0; u < NHT; ++u) acc[u] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+  for (int k = 0; k < GR; k += 4) {
+    const float a = L.h1[k + lg][rw + lr];
+#pragma unroll
+    for (int u = 0; u < NHT; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L.g2[k + lg][16 * u + lr], acc[u], 0, 0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < NHT; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) g[OW2 + (rw + 4 * lg + v) * NH + 16 * u + lr] = acc[u][v];
+  // G1 = (G2 W2^T) o silu'(a1): wave w takes rows 16 w .., B = W2^T
+#pragma unroll
+  for (int u = 0; u < NHT; ++u) acc[u] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+  for (int k = 0; k < NH; k += 4) {
+    const float a = L.g2[rw + lr][k + lg];
+#pragma unroll
+    for (int u = 0; u < NHT; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L.w2[16 * u + lr][k + lg], acc[u], 0, 0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < NHT; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rw + 4 * lg + v, unit = 16 * u + lr;
+      L.d1[row][unit] = acc[u][v] * L.d1[row][unit];
+    }
   if (t < NH) {
-    float s = 0.0f;
-    for (int r = 0; r < TR; ++r) {
-      const float z = L.a2[r][t];
-      s = fmaf(z * sigm(z), L.dy[r], s);
-    }
-    g[OW3 + t] = s;
-  }
-  for (int q = t; q < TR * NH; q += TT) {
-    const int r = q / NH, j = q % NH;
-    const float z = L.a2[r][j];
-    const float sg = sigm(z);
-    L.g2[r][j] = L.dy[r] * L.w3[j] * (sg * (1.0f + z * (1.0f - sg)));
+    float sb = 0.0f;
+    for (int r = 0; r < GR; ++r) sb += L.g2[r][t];
+    g[OB2 + t] = sb;
   }
   __syncthreads();
-  // dW2[k][j] = sum_r silu(a1[r][k]) g2[r][j]; db2[j] = sum_r g2[r][j]
-  for (int q = t; q < NH * NH; q += TT) {
-    const int k = q / NH, j = q % NH;
-    float s = 0.0f;
-    for (int r = 0; r < TR; ++r) {
-      const float z = L.a1[r][k];
-      s = fmaf(z * sigm(z), L.g2[r][j], s);
+  // dW1 = X^T G1: wave w takes inputs 16 (w / 2) .. and output blocks
+  // 2 (w % 2), 2 (w % 2) + 1
+  {
+    const int ib = wave >> 1, ob = 2 * (wave & 1);
+    mf4 a2[2] = {mf4{0.0f, 0.0f, 0.0f, 0.0f}, mf4{0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll 4
+    for (int k = 0; k < GR; k += 4) {
+      const float a = L.x[k + lg][16 * ib + lr];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        a2[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L.d1[k + lg][16 * (ob + q) + lr], a2[q],
+                                                     0, 0, 0);
     }
-    g[OW2 + q] = s;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int in = 16 * ib + 4 * lg + v;
+        if (in < NIN) g[OW1 + in * NH + 16 * (ob + q) + lr] = a2[q][v];
+      }
   }
   if (t < NH) {
-    float s = 0.0f;
-    for (int r = 0; r < TR; ++r) s += L.g2[r][t];
-    g[OB2 + t] = s;
-  }
-  // g1[r][k] = (sum_j g2[r][j] w2[k][j]) silu'(a1[r][k])
-  for (int q = t; q < TR * NH; q += TT) {
-    const int r = q / NH, k = q % NH;
-    float s = 0.0f;
-    for (int j = 0; j < NH; ++j) s = fmaf(L.g2[r][j], L.w2[k][j], s);
-    const float z = L.a1[r][k];
-    const float sg = sigm(z);
-    L.g1[r][k] = s * (sg * (1.0f + z * (1.0f - sg)));
-  }
-  __syncthreads();
-  // dW1[m][k] = sum_r x[r][m] g1[r][k]; db1[k] = sum_r g1[r][k]
-  for (int q = t; q < NIN * NH; q += TT) {
-    const int m = q / NH, k = q % NH;
-    float s = 0.0f;
-    for (int r = 0; r < TR; ++r) s = fmaf(L.x[r][m], L.g1[r][k], s);
-    g[OW1 + q] = s;
-  }
-  if (t < NH) {
-    float s = 0.0f;
-    for (int r = 0; r < TR; ++r) s += L.g1[r][t];
-    g[OB1 + t] = s;
+    float sb = 0.0f;
+    for (int r = 0; r < GR; ++r) sb += L.d1[r][t];
+    g[OB1 + t] = sb;
   }
 }
 
@@ -376,7 +391,6 @@ __global__ __launch_bounds__(256) void lagrange_shift_kernel(const double *__res
     for (int64_t i = threadIdx.x; i < n; i += 256) r0[f * n + i] = (b[f * n + i] - eq[f * n + i]) - mu;
 }
 
-size_t tile_lds_bytes() { return sizeof(TileLds); }
 
 // Host 12-neighbour list: order by distance, then azimuth about +z from +x,
 // then index; distance and angle compared after rounding to 1e-6.
@@ -476,14 +490,11 @@ cpm_status build_neighbours(const cpm_system *s, std::vector<int32_t> &nbr,
 // shuffles in a fixed order. FROM_B: the inputs are formed from b in the
 // kernel (same definition as features_kernel), otherwise read from feat.
 constexpr int IR = 64;                       // rows per inference tile (16 per wavefront)
-constexpr int NINP = (NIN + 3) / 4 * 4;      // input width padded for the k-steps of 4
-constexpr int NHT = NH / 16;                 // output tiles per layer
 static_assert(NH % 16 == 0 && TT == 4 * 64 && IR == 16 * (TT / 64) && TT == 4 * IR &&
                   NNB % 4 == 0 && NIN == 2 + 2 * NNB, "inference tiling");
 static_assert(OW1 % 4 == 0 && OB1 % 4 == 0 && OW2 % 4 == 0 && OB2 % 4 == 0 && OW3 % 4 == 0 &&
                   (NH * NH / 4) % TT == 0 && 3 * (NH / 4) <= TT,
               "parameter offsets and sizes in whole float4 pieces");
-typedef float mf4 __attribute__((ext_vector_type(4)));
 struct InferLds {
   alignas(16) float w1[NINP][NH];
   alignas(16) float w2[NH][NH];
@@ -679,11 +690,11 @@ static double *lpart_of(cpm_system *s) {
 
 static cpm_status loss_grad_impl(cpm_system *s, const float *feat, const float *target,
                                  int64_t rows, float *grad_out) {
-  const int64_t tiles = (rows + TR - 1) / TR;
+  const int64_t tiles = (rows + GR - 1) / GR;
   cpm_status rc = ensure_gpart(s, tiles);
   if (rc != CPM_OK) return rc;
   hipStream_t st = s->stream;
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)tiles), dim3(TT), tile_lds_bytes(), st,
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)tiles), dim3(TT), 0, st,
                      s->mlp.params, feat, target, rows, (float)(1.0 / (double)rows), s->mlp.gpart,
                      lpart_of(s));
   hipLaunchKernelGGL(grad_reduce_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, s->mlp.gpart,
