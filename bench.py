@@ -51,6 +51,14 @@ def kernel_name(kind, ng):
 CG_SOURCE = os.path.join(ROOT, "paper_2111_06704_amd", "csrc", "cg.hip")
 PROFILE_STRIDE = 5   # timed launches of the block product: every 5th (coprime to the check batches)
 MODE_STEPS = 5       # timed steps of every comparison mode (at most --steps)
+# in-plane patch edge (A) of the coarse-space correction per workload (0: off).
+# Sweeps of the FP32 solve to 1e-11 over edges 18 .. 5 A and checks every 8 / 4
+# / 2 iterations: workload 5 704 ms (48 iterations, P alone) -> 255 ms at 9 A
+# (4080 patches, 10 iterations, checks every 2); workload 3 74 -> 38 ms at 14 A
+# (480 patches, 12 iterations, checks every 4); workload 2 (N = 4608) is
+# faster without it (1.64 ms against 2.1 ms: the seven extra launches per
+# iteration cost more than the 8 iterations they save)
+COARSE_EDGE = {3: 14.0, 5: 9.0}
 
 
 def log(*a):
@@ -79,6 +87,9 @@ def parse():
                          "workloads 2 / 3 / 5 (sweeps there), else 0.15 with 7; the paper: "
                          "0.083 with 8")
     ap.add_argument("--dc-rcut", type=float, default=None, help="PCG-DC cutoff (A)")
+    ap.add_argument("--coarse-edge", type=float, default=None,
+                    help="in-plane patch edge (A) of the coarse-space correction of the sparse "
+                         "preconditioner; 0 turns it off (default: per workload, from sweeps)")
     ap.add_argument("--weights", default=None,
                     help="warm-start network (default: the one for the workload's geometry)")
     ap.add_argument("--kmax-override", type=float, default=0.0,
@@ -298,8 +309,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cfg = args.workload
+    if args.coarse_edge is None:
+        args.coarse_edge = COARSE_EDGE.get(cfg, 0.0)
+    # checks every 8 iterations suit workload 5 with P alone (48 iterations);
+    # with the coarse space the residual falls about tenfold per iteration and
+    # the recursive FP32 residual must be checked (and replaced) every 2
+    ce_plain = 8 if cfg == 5 else 4
     if args.check_every is None:
-        args.check_every = 8 if cfg == 5 else 4
+        args.check_every = (2 if args.coarse_edge > 0 else 8) if cfg == 5 else 4
     # PCG-DC: the apply is cheap next to the product at large N, so a wide P
     # pays. Sweeps of (g, r_cut) over (0.15, 7) .. (0.06, 16) on each
     # workload (FP32 iterations to 1e-11): workload 5 80 at (0.15, 7), 64 at
@@ -350,6 +367,13 @@ def main():
     S.precond_dc(args.dc_g, args.dc_rcut)
     precond_build_s = time.perf_counter() - t0
     log(f"PCG-DC preconditioner built in {precond_build_s:.2f} s")
+    coarse_m, coarse_build_s = 0, 0.0
+    if args.coarse_edge > 0:
+        t0 = time.perf_counter()
+        coarse_m = S.precond_coarse(args.coarse_edge)
+        torch.cuda.synchronize()
+        coarse_build_s = time.perf_counter() - t0
+        log(f"coarse space: {coarse_m} patches of edge {args.coarse_edge} A in {coarse_build_s:.2f} s")
     t0 = time.perf_counter()
     S.set_warm_chi(t_chi, preconditioner=cpm.PRECOND_DC)
     torch.cuda.synchronize()
@@ -462,7 +486,12 @@ def main():
     # per-mode solver settings: the BF16 variant of workload 5 restarts its
     # inner CG on true residuals; a sweep (inner 1e-1 .. 1e-2, checks every
     # 4 / 8 iterations) gave the shortest solve at 1e-2 with checks every 4
-    mode_opts = {}
+    mode_opts = {"f64_jacobi_zero": dict(check_every=ce_plain)}
+    if coarse_m:
+        # the same mode as the headline with P alone (and its own check
+        # interval): what the coarse space gains
+        mode_list.append((f"{hname}_without_coarse", prec, wmode, pcmode, None))
+        mode_opts[f"{hname}_without_coarse"] = dict(coarse=False, check_every=ce_plain)
     if cfg == 5 and "bf16" in store:
         mode_list.append(("bf16_dc_mlp", cpm.PREC_BF16, cpm.WARM_MLP, cpm.PRECOND_DC, None))
         mode_opts["bf16_dc_mlp"] = dict(inner=1e-2, check_every=4)
@@ -470,12 +499,18 @@ def main():
     qm = torch.empty_like(b)
     for name, pm, wm, pcm, qout in mode_list:
         log(f"mode {name}: {nmode} timed steps")
+        opts = dict(mode_opts.get(name, {}))
+        coarse_off = not opts.pop("coarse", True)
+        if coarse_off:
+            S.precond_coarse(0.0)
         torch.cuda.synchronize()
         tm = time.perf_counter()
-        _, sm = run_steps(nmode, solver(pm, wm, qout if qout is not None else qm, pcm,
-                                        **mode_opts.get(name, {})), name)
+        _, sm = run_steps(nmode, solver(pm, wm, qout if qout is not None else qm, pcm, **opts),
+                          name)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - tm) / nmode
+        if coarse_off:
+            S.precond_coarse(args.coarse_edge)
         modes[name] = {"solves_per_s": nf / dt, "ms_per_step": dt * 1e3,
                        "solve_only_solves_per_s": nf / (dt - rhs_ms * 1e-3),
                        "iterations": sm["iterations"], "true_residual_updates": sm["outer"],
@@ -546,6 +581,7 @@ def main():
                    "overlap_rhs": bool(args.overlap), "jitter_A": args.jitter,
                    "warm_start": args.warm, "warm_start_weights": os.path.basename(weights),
                    "preconditioner": args.precond, "dc_g": args.dc_g, "dc_rcut": args.dc_rcut,
+                   "coarse_edge": args.coarse_edge or None, "coarse_patches": coarse_m,
                    "kmax_override": args.kmax_override or None,
                    "E_stored": ["f64"] + list(store), "device_bytes": desc["device_bytes"]},
         "fp64_cg_solves_per_s": fp64["solves_per_s"],
@@ -563,6 +599,7 @@ def main():
         "e_assembly_gflops": asm_gflops, "e_assembly_ms": prof_build["ms"],
         "e_assembly_frac_fp64_peak": (asm_gflops / 1e3 / FP64_PEAK_TFLOPS) if asm_gflops else None,
         "e_build_s": build_s, "precond_build_s": precond_build_s,
+        "coarse_build_s": coarse_build_s,
         "roofline": roofline,
     }
     out.update(extras)
@@ -646,6 +683,8 @@ def run_extras(S, cpm, wl, geo, args, b, qsol, q64, dev, t_ipos, t_iq, t_chi, nf
     S2 = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT,
                     wl.KSPACE_EPS, store=("f32",), slab=True)
     S2.precond_dc(args.dc_g, args.dc_rcut)
+    if args.coarse_edge > 0:
+        S2.precond_coarse(args.coarse_edge)
     torch.cuda.synchronize()
     slab_build_s = time.perf_counter() - t0
     b2, qs2, q2 = torch.empty_like(b), torch.empty_like(qsol), torch.empty_like(b)

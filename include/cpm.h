@@ -175,7 +175,8 @@ typedef struct {
                           system's sparse P, Sec. III.B.2: the PCG-DC matrix of
                           cpm_precond_dc or the sparsified inverse of
                           cpm_precond_sparse_inverse, whichever was built last,
-                          with the Eq. 37 fill when cpm_precond_gap enabled it)   */
+                          with the Eq. 37 fill when cpm_precond_gap enabled it,
+                          and the coarse correction of cpm_precond_coarse)      */
 } cpm_solve_opts;
 
 typedef struct {
@@ -249,6 +250,30 @@ cpm_status cpm_precond_sparse_inverse(cpm_system *s, double rcut);
  * disabled). Errors: CPM_EINVAL, CPM_ESTATE (no preconditioner), the d'
  * solve's errors. */
 cpm_status cpm_precond_gap(cpm_system *s, int enable, double *gap_out);
+
+/* ---- coarse-space correction of the sparse preconditioner -----------------
+ * Not in the paper: a second level on top of the sparse P of Sec. III.B.2
+ * (the balancing Neumann-Neumann form of two-level preconditioning; Mandel,
+ * Commun. Numer. Methods Eng. 9, 233 (1993)). Z (n x m) holds the indicator
+ * columns of m patches of atoms: the atoms are split into z-slabs (sorted z,
+ * a new slab wherever two consecutive values differ by more than 1 A) and
+ * each slab into nx x ny in-plane bins of the box, nx = max(1, floor(L_x /
+ * edge + 1/2)) and likewise ny; empty bins are dropped. With E_c = Z^T E Z,
+ * Q = Z E_c^-1 Z^T and P_D = I - E Q, CPM_PRECOND_DC then applies
+ *   z = P_D^T P P_D r + Q r,
+ * which is symmetric positive definite for every SPD P, maps E Z exactly to
+ * Z (the coarse modes converge in one step) and equals E^-1 when P does.
+ * A local P leaves the long-wavelength modes of E at large eigenvalues;
+ * the coarse solve removes them. E Z is kept in FP32 (m x n_pad floats)
+ * and E_c^-1 in FP64 (m_pad^2 doubles); each apply adds two products with
+ * E Z on the FP32 matrix cores and two with E_c^-1 on the FP64 ones.
+ * edge > 0: builds the space for that in-plane patch edge (A) and keeps it
+ * until replaced or disabled (it does not depend on P, so rebuilding P
+ * keeps it); edge <= 0: disables it. m_out (may be NULL) receives m.
+ * Errors: CPM_EINVAL (edge not finite, more than 8192 patches), CPM_ESTATE
+ * (no sparse preconditioner built), CPM_ENOTSPD (E_c not positive
+ * definite), CPM_ENOMEM, CPM_EDEVICE. */
+cpm_status cpm_precond_coarse(cpm_system *s, double edge, int64_t *m_out);
 
 /* ---- matrix-inversion path (Sec. III.B.1 MI; Eq. 33-35) -------------------
  * cpm_mi_build forms S = E^-1 (I - 1 d^T) (Eq. 33), symmetric, whose column

@@ -18,6 +18,15 @@ real-space distance of the two charges: p_ij = (E^-1)_ij when the pair is
 closer than a cutoff, 0 otherwise (Full: the cutoff of the neighbour list;
 Normal: a shorter preset r_cut).
 
+Not in the paper: a coarse-space (two-level) correction of any of these P,
+in the balancing Neumann-Neumann form (Mandel, Commun. Numer. Methods Eng.
+9, 233 (1993)): with Z the indicator columns of patches of atoms, E_c =
+Z^T E Z, Q = Z E_c^-1 Z^T and P_D = I - E Q, the preconditioner is
+P_D^T P P_D + Q. Patches: z-slabs (sorted z, a new slab where two
+consecutive values differ by more than 1 A) split into nx x ny in-plane
+bins, nx = max(1, floor(L_x / edge + 1/2)). Its pins are closed forms
+(exact on the coarse space, E^-1 from an exact P or from one patch per atom).
+
 Readings (the paper is silent or ambiguous):
   * the neighbourhood includes atoms at exactly r_cut (Fig. 2: N_cut = 21 for
     a chain of spacing 1.5 A at r_cut = 15 A counts the atoms at 15 A); their
@@ -153,3 +162,40 @@ def pcg(E, b, P, tol, max_iter=10000):
         p = z + (rz_new / rz) * p
         rz = rz_new
     return x, max_iter
+
+
+def coarse_patches(pos, box, edge, slab_gap=1.0):
+    """Patch index of every atom (numbered by slab, x bin, y bin; empty bins
+    dropped): z-slabs from the sorted z (a new slab where two consecutive
+    values differ by more than slab_gap), each split into nx x ny bins of
+    the box, nx = max(1, floor(L_x / edge + 1/2)). Positions are wrapped
+    into the box first (fmod, then one shift)."""
+    box = np.asarray(box, dtype=np.float64)
+    w = np.fmod(np.asarray(pos, dtype=np.float64), box)
+    w = np.where(w < 0, w + box, w)
+    w = np.where(w >= box, w - box, w)
+    n = len(w)
+    order = np.argsort(w[:, 2], kind="stable")
+    slab = np.zeros(n, dtype=np.int64)
+    slab[order] = np.concatenate([[0], np.cumsum(np.diff(w[order, 2]) > slab_gap)])
+    nx = max(1, int(math.floor(box[0] / edge + 0.5)))
+    ny = max(1, int(math.floor(box[1] / edge + 0.5)))
+    bx = np.minimum(nx - 1, np.floor(w[:, 0] / box[0] * nx).astype(np.int64))
+    by = np.minimum(ny - 1, np.floor(w[:, 1] / box[1] * ny).astype(np.int64))
+    key = (slab * nx + bx) * ny + by
+    _, pid = np.unique(key, return_inverse=True)
+    return pid.astype(np.int64)
+
+
+def two_level(P, E, pid):
+    """Balancing Neumann-Neumann two-level preconditioner on top of P:
+    Z = indicator columns of the patches pid, E_c = Z^T E Z,
+    Q = Z E_c^-1 Z^T, P_D = I - E Q; returns P_D^T P P_D + Q (dense)."""
+    n = E.shape[0]
+    m = int(pid.max()) + 1
+    Z = np.zeros((n, m))
+    Z[np.arange(n), pid] = 1.0
+    Ec = Z.T @ E @ Z
+    Q = Z @ np.linalg.solve(Ec, Z.T)
+    PD = np.eye(n) - E @ Q
+    return PD.T @ P @ PD + Q

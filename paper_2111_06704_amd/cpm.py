@@ -32,7 +32,7 @@ EXPORTS = [
     "cpm_mlp_loss_grad", "cpm_mlp_train_step", "cpm_mlp_train_epoch", "cpm_set_warm_chi",
     "cpm_warm_start",
     "cpm_profile_enable", "cpm_profile_read", "cpm_precond_dc", "cpm_precond_apply",
-    "cpm_precond_sparse_inverse", "cpm_precond_gap",
+    "cpm_precond_sparse_inverse", "cpm_precond_gap", "cpm_precond_coarse",
     "cpm_mi_build", "cpm_mi_solve", "cpm_gcd_build", "cpm_gcd_solve",
     "cpm_status_str", "cpm_last_error",
 ]
@@ -94,6 +94,7 @@ def lib():
     L.cpm_get_dprime.argtypes = [vp, vp, C.POINTER(dbl)]
     L.cpm_precond_sparse_inverse.argtypes = [vp, dbl]
     L.cpm_precond_gap.argtypes = [vp, C.c_int, C.POINTER(dbl)]
+    L.cpm_precond_coarse.argtypes = [vp, dbl, C.POINTER(C.c_int64)]
     L.cpm_matvec.argtypes = [vp, C.c_int, vp, i64, vp]
     L.cpm_mlp_init.argtypes = [vp, vp, C.c_int32, f32, f32, f32]
     L.cpm_mlp_neighbours.argtypes = [vp, vp]
@@ -316,6 +317,14 @@ class System:
         g = C.c_double()
         _check(lib().cpm_precond_gap(self._h, 1 if enable else 0, C.byref(g)), "cpm_precond_gap")
         return g.value
+
+    def precond_coarse(self, edge):
+        """Coarse-space correction of the sparse preconditioner: patches of
+        in-plane edge `edge` (A) per z-slab; edge <= 0 disables it. Returns
+        the number of patches."""
+        m = C.c_int64()
+        _check(lib().cpm_precond_coarse(self._h, float(edge), C.byref(m)), "cpm_precond_coarse")
+        return m.value
 
     def precond_apply(self, r):
         """z = P r for vectors r (F, N) on the device."""

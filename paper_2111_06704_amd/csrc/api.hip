@@ -240,6 +240,7 @@ void free_system(cpm_system *s) {
     if (e) (void)hipEventDestroy(e);
   release_workspace(s);
   free_precond(s->pc);
+  free_coarse(s->cz);
   free_gcd(s->gcd);
   s->prof.reset();
   for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);

@@ -1062,7 +1062,8 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
     const int32_t *__restrict__ pidx, const double *__restrict__ pval, int width,
     const int32_t *__restrict__ order, int64_t ld, int64_t n, int cols,
     const double *__restrict__ scal, int slot, double *__restrict__ bpart, int set_p,
-    double gap, const double *__restrict__ rsum, const int *__restrict__ gate) {
+    double gap, const double *__restrict__ rsum, const int *__restrict__ gate,
+    double *__restrict__ zt) {
   __shared__ double red[PC_ROWS][kColGroup][2];
   __shared__ double sval[PC_ROWS][PC_CHUNK];
   __shared__ int32_t sidx[PC_ROWS][PC_CHUNK];
@@ -1125,6 +1126,18 @@ __global__ __launch_bounds__(PC_THREADS) void precond_kernel(
     a1 += __shfl_xor(a1, off, 64);
   }
   // lanes 0..7 hold columns (2h, 2h + 1)
+  if (zt != nullptr) {
+    // raw output (the coarse correction's inner apply): every column, in the
+    // row-interleaved layout, no dots
+    if (lane < 8 && i >= 0) {
+      const double add0 = rsum != nullptr ? gap * rsum[c0] : 0.0;
+      const double add1 = rsum != nullptr ? gap * rsum[c0 + 1] : 0.0;
+      double *o = zt + ((int64_t)g * ld + i) * kColGroup + 2 * h;
+      o[0] = a0 + add0;
+      o[1] = a1 + add1;
+    }
+    return;
+  }
   if (lane < 8) {
     double d[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
     if (i >= 0) {
@@ -1180,7 +1193,8 @@ __global__ __launch_bounds__(256) void precond_block_kernel(
     const int64_t *__restrict__ uoff, const int32_t *__restrict__ uidx,
     const double *__restrict__ blk, const int32_t *__restrict__ order, int64_t ld, int64_t n,
     int cols, const double *__restrict__ scal, int slot, double *__restrict__ bpart, int set_p,
-    double gap, const double *__restrict__ rsum, const int *__restrict__ gate) {
+    double gap, const double *__restrict__ rsum, const int *__restrict__ gate,
+    double *__restrict__ zt) {
   __shared__ double red[4][16 * NG][2];
   if (gate != nullptr && *gate == 0) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1204,6 +1218,20 @@ __global__ __launch_bounds__(256) void precond_block_kernel(
   }
   // D[i][j] (row i of the wave's 16, column j of the group) in lane
   // j + 16 (i % 4), register i / 4
+  if (zt != nullptr) {
+    // raw output (the coarse correction's inner apply): every column, in the
+    // row-interleaved layout, no dots
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const double add = rsum != nullptr ? gap * rsum[g * 16 + lr] : 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t t = tile * kPcTile + wave * 16 + 4 * v + lg;
+        if (t < n) zt[((int64_t)g * ld + order[t]) * kColGroup + lr] = acc[g][v] + add;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     const int c = g * 16 + lr;
@@ -1243,6 +1271,255 @@ __global__ __launch_bounds__(256) void precond_block_kernel(
     const int c = threadIdx.x >> 1, s2 = threadIdx.x & 1;
     const double v = ((red[0][c][s2] + red[1][c][s2]) + red[2][c][s2]) + red[3][c][s2];
     bpart[((int64_t)c * gridDim.x + tile) * 2 + s2] = v;
+  }
+}
+
+// ---- coarse-space correction (two-level, balancing Neumann-Neumann form)
+// z = P_D^T P P_D r + Q r with Q = Z E_c^-1 Z^T, P_D = I - E Q, Z the
+// indicator columns of the patches, applied as
+//   g1 = E_c^-1 Z^T r,  u = r - (E Z) g1,  w = P u,
+//   g2 = E_c^-1 (E Z)^T w,  z = w + Z (g1 - g2).
+// Z^T r and Z y are sums and broadcasts over the patches' atoms; the two
+// products with E Z (kept as FP32 (E Z)^T, patch-major, atoms contiguous)
+// run on the FP32 matrix cores, the two with E_c^-1 on the FP64 ones.
+
+// c1[c * mp + t] = sum of r over the atoms of patch t (fixed order), from the
+// row-interleaved rt: one wavefront per patch; lane (lr, lg) takes column lr
+// of every group and the patch's atoms lg, lg + 4, ...
+template <int NG>
+__global__ __launch_bounds__(256) void coarse_restrict_kernel(
+    const double *__restrict__ rt, int64_t ld, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ off, int64_t mp, double *__restrict__ c1,
+    const int *__restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t t = (int64_t)blockIdx.x * 4 + wave;
+  const int32_t k1 = off[t + 1];
+  double acc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) acc[g] = 0.0;
+  for (int32_t k = off[t] + lg; k < k1; k += 4) {
+    const int64_t i = perm[k];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[g] += rt[((int64_t)g * ld + i) * kColGroup + lr];
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    acc[g] += __shfl_xor(acc[g], 16, 64);
+    acc[g] += __shfl_xor(acc[g], 32, 64);
+    if (lg == 0) c1[(int64_t)(g * kColGroup + lr) * mp + t] = acc[g];
+  }
+}
+
+// out = E_c^-1 in for 16 NG columns on the FP64 matrix cores: out[c * mp + t]
+// = sum_s eci[s * mp + t] in[c * mp + s] (E_c^-1 is symmetric). Workgroup:
+// 16 patches t and every column; its four waves split s in quarters and add
+// their results in LDS in a fixed order. Lane (lr, lg) gives A = eci(s + lg,
+// t0 + lr) and, per group, B = in(column 16 g + lr, s + lg). mode 0: g1 = out
+// and its FP32 copy g1f; mode 1: dg = g1 - out.
+template <int NG>
+__global__ __launch_bounds__(256) void coarse_solve_kernel(
+    const double *__restrict__ eci, int64_t mp, const double *__restrict__ in,
+    double *__restrict__ g1, float *__restrict__ g1f, double *__restrict__ dg, int mode,
+    const int *__restrict__ gate) {
+  __shared__ double red[4][NG][4][64];
+  if (gate != nullptr && *gate == 0) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t t0 = (int64_t)blockIdx.x * 16;
+  const int64_t q = mp / 4, s0 = wave * q;
+  d4 acc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) acc[g] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int64_t s = s0 + lg; s < s0 + q; s += 4) {
+    const double a = eci[s * mp + t0 + lr];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+      acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, in[(int64_t)(g * 16 + lr) * mp + s], acc[g],
+                                                    0, 0, 0);
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][g][v][lane] = acc[g][v];
+  __syncthreads();
+  for (int e = threadIdx.x; e < NG * 256; e += 256) {
+    const int g = e >> 8, v = (e >> 6) & 3, l = e & 63;
+    const double val =
+        ((red[0][g][v][l] + red[1][g][v][l]) + red[2][g][v][l]) + red[3][g][v][l];
+    // D[i][j] in lane j + 16 (i % 4), register i / 4
+    const int64_t t = t0 + 4 * v + (l >> 4);
+    const int64_t o = (int64_t)(g * 16 + (l & 15)) * mp + t;
+    if (mode == 0) {
+      g1[o] = val;
+      g1f[o] = (float)val;
+    } else {
+      dg[o] = g1[o] - val;
+    }
+  }
+}
+
+// u = r - (E Z) g1 into the row-interleaved ut, on the FP32 matrix cores:
+// wave w of workgroup b takes the atoms i0 = 64 b + 16 w .. i0 + 15 and every
+// column group; per step of 4 patches lane (lr, lg) gives A = az(patch t +
+// lg, atom i0 + lr) and B = g1f(column 16 g + lr, patch t + lg), and holds
+// D[row 4 lg + v][column lr] in register v. Rows past n stay 0 (az and rt
+// are 0 there).
+template <int NG>
+__global__ __launch_bounds__(256) void coarse_prolong_kernel(
+    const float *__restrict__ az, const float *__restrict__ g1f, int64_t mp,
+    const double *__restrict__ rt, int64_t ld, double *__restrict__ ut,
+    const int *__restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  f4 acc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+  const float *A = az + i0 + lr;
+#pragma unroll 4
+  for (int64_t t = lg; t < mp; t += 4) {
+    const float a = A[t * ld];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+      acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g1f[(int64_t)(g * 16 + lr) * mp + t],
+                                                    acc[g], 0, 0, 0);
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t o = ((int64_t)g * ld + i0 + 4 * lg + v) * kColGroup + lr;
+      ut[o] = rt[o] - (double)acc[g][v];
+    }
+}
+
+// Slice partials of (E Z)^T w on the FP32 matrix cores: c2p[(k * cols + c) *
+// mp + t] = sum over the atoms i of slice k of az(t, i) w(i, c), w from the
+// row-interleaved wt. Workgroup: kCoarseAlign patches (wave w: 64 of them,
+// four row blocks of 16) and one slice of kslice atoms (a multiple of 16).
+// Per 16 atoms lane (lr, lg) loads az(patch tb + 16 rb + lr, atoms i + 4 lg
+// .. + 3) as one float4; step j (0..3) takes k = lg as the atom i + 4 lg + j,
+// with B = w(i + 4 lg + j, column 16 g + lr).
+template <int NG>
+__global__ __launch_bounds__(256) void coarse_gather_kernel(
+    const float *__restrict__ az, const double *__restrict__ wt, int64_t ld, int64_t mp,
+    int64_t kslice, int cols, float *__restrict__ c2p, const int *__restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t tb = (int64_t)blockIdx.x * kCoarseAlign + wave * 64;
+  const int64_t i0 = (int64_t)blockIdx.y * kslice;
+  const int64_t i1 = min(ld, i0 + kslice);
+  f4 acc[4][NG];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[rb][g] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t i = i0; i < i1; i += 16) {
+    f4 a[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+      a[rb] = *reinterpret_cast<const f4 *>(az + (tb + 16 * rb + lr) * ld + i + 4 * lg);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const float b = (float)wt[((int64_t)g * ld + i + 4 * lg + j) * kColGroup + lr];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          acc[rb][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], b, acc[rb][g], 0, 0, 0);
+      }
+  }
+  float *out = c2p + (int64_t)blockIdx.y * cols * mp;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(int64_t)(g * 16 + lr) * mp + tb + 16 * rb + 4 * lg + v] = acc[rb][g][v];
+}
+
+// c[e] = sum over the ks slices of c2p (FP64, in slice order), e < count
+__global__ __launch_bounds__(256) void coarse_sum_kernel(const float *__restrict__ c2p, int ks,
+                                                         int64_t count, double *__restrict__ c,
+                                                         const int *__restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= count) return;
+  double v = 0.0;
+  for (int k = 0; k < ks; ++k) v += (double)c2p[(int64_t)k * count + e];
+  c[e] = v;
+}
+
+// 1^T u per column of the row-interleaved ut (fixed order): the Eq. 37 term
+// of the inner apply
+__global__ __launch_bounds__(RED_THREADS) void colsum_rt_kernel(const double *__restrict__ ut,
+                                                               int64_t ld, int64_t n,
+                                                               double *__restrict__ rsum,
+                                                               const int *__restrict__ gate) {
+  __shared__ double red[4];
+  if (gate != nullptr && *gate == 0) return;
+  const int c = blockIdx.x, g = c / kColGroup, cc = c % kColGroup;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += RED_THREADS)
+    acc += ut[((int64_t)g * ld + i) * kColGroup + cc];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) rsum[c] = acc;
+}
+
+// z = w + Z dg (dg = g1 - g2) for the active columns, p = z where a column
+// restarts (or set_p), and per workgroup of 64 atoms and column the partial
+// (r.r, r.z) into bpart, column-major like the local apply kernels (r from
+// the row-interleaved rt). Wave q takes the columns 4 q .. 4 q + 3 of every
+// group, lane = atom; the wave sums of the dots run in a fixed order.
+template <typename VT>
+__global__ __launch_bounds__(256) void coarse_finish_kernel(
+    const double *__restrict__ wt, const double *__restrict__ dg,
+    const int32_t *__restrict__ pid, const double *__restrict__ rt, int64_t ld, int64_t n,
+    int cols, int64_t mp, double *__restrict__ z, VT *__restrict__ p,
+    const double *__restrict__ scal, int slot, double *__restrict__ bpart, int set_p,
+    const int *__restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = i < n;
+  const int64_t t = live ? pid[i] : 0;
+  for (int c0 = 4 * q; c0 < cols; c0 += 16) {
+    const int g = c0 / kColGroup;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u;
+      const bool act = scal == nullptr || (scal[S_ACT * cols + c] != 0.0 &&
+                                           scal[(S_HOLD0 + slot) * cols + c] == 0.0);
+      const bool rst = set_p || (scal != nullptr && scal[S_RST * cols + c] != 0.0);
+      double rr = 0.0, rz = 0.0;
+      if (live && act) {
+        const int64_t o = ((int64_t)g * ld + i) * kColGroup + (c % kColGroup);
+        const double zi = wt[o] + dg[(int64_t)c * mp + t];
+        const int64_t idx = (int64_t)c * ld + i;
+        z[idx] = zi;
+        if (rst && p != nullptr) p[idx] = (VT)zi;
+        const double ri = rt[o];
+        rr = ri * ri;
+        rz = ri * zi;
+      }
+      if (bpart != nullptr) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          rr += __shfl_xor(rr, off, 64);
+          rz += __shfl_xor(rz, off, 64);
+        }
+        if (lane == 0) {
+          bpart[((int64_t)c * gridDim.x + blockIdx.x) * 2] = rr;
+          bpart[((int64_t)c * gridDim.x + blockIdx.x) * 2 + 1] = rz;
+        }
+      }
+    }
   }
 }
 
@@ -1779,27 +2056,22 @@ cpm_status ensure_workspace(cpm_system *s, int64_t cols) {
   return CPM_OK;
 }
 
-// z = P r (PCG-DC) for cols columns of the row-interleaved residual rt;
-// bpart gets one (r.r, r.z) pair per workgroup and column.
-// With the Eq. 37 fill, r (column c at r + c * rs, fc columns) gives the
-// column sums first.
+// the local apply z = P r of the sparse P for cols columns of the
+// row-interleaved rt; bpart gets one (r.r, r.z) pair per workgroup and
+// column; rsum (may be null): the column sums of r for the Eq. 37 fill.
+// zt != null: raw output of every column into the row-interleaved zt
+// instead of z, p and the dots.
 template <typename VT>
-void launch_precond(hipStream_t st, const cpm_system *s, const Precond &pc, const double *rt,
-                    const double *r, int64_t rs, int fc, double *z, VT *p, int64_t cols,
-                    const double *scal, int slot, double *bpart, bool set_p, const int *gate) {
+void launch_local(hipStream_t st, const cpm_system *s, const Precond &pc, const double *rt,
+                  double *z, VT *p, int64_t cols, const double *scal, int slot, double *bpart,
+                  bool set_p, const double *rsum, const int *gate, double *zt) {
   const int64_t ld = s->ld, n = s->n;
-  const double *rsum = nullptr;
-  if (pc.gap != 0.0) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, r, rs, n, fc,
-                       s->ws.rsum, gate);
-    rsum = s->ws.rsum;
-  }
   if (pc.blk == nullptr) {
     hipLaunchKernelGGL(precond_kernel<VT>,
                        dim3((unsigned)((n + PC_ROWS - 1) / PC_ROWS), (unsigned)(cols / kColGroup)),
                        dim3(PC_THREADS), 0, st, rt, z, p, (const int32_t *)pc.idx,
                        (const double *)pc.val, pc.width, s->atom_order, ld, n, (int)cols, scal,
-                       slot, bpart, set_p ? 1 : 0, pc.gap, rsum, gate);
+                       slot, bpart, set_p ? 1 : 0, pc.gap, rsum, gate, zt);
     return;
   }
   const dim3 grid((unsigned)pc.ntiles);
@@ -1807,7 +2079,7 @@ void launch_precond(hipStream_t st, const cpm_system *s, const Precond &pc, cons
   hipLaunchKernelGGL((precond_block_kernel<VT, NGV>), grid, dim3(256), 0, st, rt, z, p,       \
                      (const int64_t *)pc.uoff, (const int32_t *)pc.uidx, (const double *)pc.blk, \
                      s->atom_order, ld, n, (int)cols, scal, slot, bpart, set_p ? 1 : 0, pc.gap,  \
-                     rsum, gate)
+                     rsum, gate, zt)
   switch (cols / kColGroup) {
     case 1: CPM_PB(1); break;
     case 2: CPM_PB(2); break;
@@ -1815,6 +2087,81 @@ void launch_precond(hipStream_t st, const cpm_system *s, const Precond &pc, cons
     default: CPM_PB(4); break;
   }
 #undef CPM_PB
+}
+
+// the coarse-correction kernels that depend on the number of column groups
+template <int NG>
+void launch_coarse_ng(hipStream_t st, const cpm_system *s, const double *rt, const int *gate,
+                      int stage) {
+  const Coarse &cz = s->cz;
+  const int64_t ld = s->ld, mp = cz.mp;
+  if (stage == 0) {
+    hipLaunchKernelGGL(coarse_restrict_kernel<NG>, dim3((unsigned)(mp / 4)), dim3(256), 0, st, rt,
+                       ld, (const int32_t *)cz.perm, (const int32_t *)cz.off, mp, cz.c1, gate);
+    hipLaunchKernelGGL(coarse_solve_kernel<NG>, dim3((unsigned)(mp / 16)), dim3(256), 0, st,
+                       (const double *)cz.eci, mp, (const double *)cz.c1, cz.g1, cz.g1f,
+                       (double *)nullptr, 0, gate);
+    hipLaunchKernelGGL(coarse_prolong_kernel<NG>, dim3((unsigned)(ld / 64)), dim3(256), 0, st,
+                       (const float *)cz.az, (const float *)cz.g1f, mp, rt, ld, cz.ut, gate);
+  } else {
+    hipLaunchKernelGGL(coarse_gather_kernel<NG>, dim3((unsigned)(mp / kCoarseAlign), (unsigned)cz.ks),
+                       dim3(256), 0, st, (const float *)cz.az, (const double *)cz.wt, ld, mp,
+                       cz.kslice, NG * 16, cz.c2p, gate);
+    const int64_t count = (int64_t)NG * 16 * mp;
+    hipLaunchKernelGGL(coarse_sum_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       (const float *)cz.c2p, cz.ks, count, cz.c1, gate);
+    hipLaunchKernelGGL(coarse_solve_kernel<NG>, dim3((unsigned)(mp / 16)), dim3(256), 0, st,
+                       (const double *)cz.eci, mp, (const double *)cz.c1, cz.g1, (float *)nullptr,
+                       cz.dg, 1, gate);
+  }
+}
+
+// z = P r (PCG-DC, the sparsified inverse, with the Eq. 37 fill and the
+// coarse correction where they are on) for cols columns of the
+// row-interleaved residual rt; bpart gets one (r.r, r.z) pair per workgroup
+// and column. With the Eq. 37 fill, r (column c at r + c * rs, fc columns)
+// gives the column sums first.
+template <typename VT>
+void launch_precond(hipStream_t st, const cpm_system *s, const Precond &pc, const double *rt,
+                    const double *r, int64_t rs, int fc, double *z, VT *p, int64_t cols,
+                    const double *scal, int slot, double *bpart, bool set_p, const int *gate) {
+  const int64_t ld = s->ld, n = s->n;
+  if (!s->cz.ready) {
+    const double *rsum = nullptr;
+    if (pc.gap != 0.0) {
+      hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st, r, rs, n,
+                         fc, s->ws.rsum, gate);
+      rsum = s->ws.rsum;
+    }
+    launch_local<VT>(st, s, pc, rt, z, p, cols, scal, slot, bpart, set_p, rsum, gate, nullptr);
+    return;
+  }
+  const Coarse &cz = s->cz;
+  auto by_ng = [&](int stage) {
+    switch (cols / kColGroup) {
+      case 1: launch_coarse_ng<1>(st, s, rt, gate, stage); break;
+      case 2: launch_coarse_ng<2>(st, s, rt, gate, stage); break;
+      case 3: launch_coarse_ng<3>(st, s, rt, gate, stage); break;
+      default: launch_coarse_ng<4>(st, s, rt, gate, stage); break;
+    }
+  };
+  // g1 = E_c^-1 Z^T r, u = r - (E Z) g1
+  by_ng(0);
+  // w = P u (raw, every column)
+  const double *rsum = nullptr;
+  if (pc.gap != 0.0) {
+    hipLaunchKernelGGL(colsum_rt_kernel, dim3((unsigned)cols), dim3(RED_THREADS), 0, st,
+                       (const double *)cz.ut, ld, n, s->ws.rsum, gate);
+    rsum = s->ws.rsum;
+  }
+  launch_local<VT>(st, s, pc, cz.ut, (double *)nullptr, (VT *)nullptr, cols, nullptr, 0, nullptr,
+                   false, rsum, gate, cz.wt);
+  // dg = g1 - E_c^-1 (E Z)^T w
+  by_ng(1);
+  // z = w + Z dg, p, dots
+  hipLaunchKernelGGL(coarse_finish_kernel<VT>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st,
+                     (const double *)cz.wt, (const double *)cz.dg, (const int32_t *)cz.pid, rt, ld,
+                     n, (int)cols, cz.mp, z, p, scal, slot, bpart, set_p ? 1 : 0, gate);
 }
 
 // The solver over one block of cols columns. VT is the vector type of p and
@@ -1875,7 +2222,10 @@ template <typename T> struct Solver {
   // partial sums of r.r / r.z per column that the direction and set_scalars
   // kernels add up: one per vector block (Jacobi) or per preconditioner
   // workgroup (DC)
-  int npc() const { return pc->blk ? (int)pc->ntiles : (int)((n + PC_ROWS - 1) / PC_ROWS); }
+  int npc() const {
+    if (s->cz.ready) return (int)((n + 63) / 64);   // coarse_finish_kernel's workgroups
+    return pc->blk ? (int)pc->ntiles : (int)((n + PC_ROWS - 1) / PC_ROWS);
+  }
   int nred() const { return pc ? npc() : nblk; }
   const double *dots() const { return pc ? s->ws.bpart : partial; }
   int dots_cmajor() const { return pc ? 1 : 0; }
@@ -2133,6 +2483,16 @@ cpm_status solve_columns(cpm_system *s, int fc, const cpm_solve_opts &o, cpm_sol
 }
 
 }  // namespace
+
+// slices of the Z^T-side coarse product: about 1024 workgroups of
+// kCoarseAlign patches, at least 64 atoms and a multiple of 16 per slice
+void coarse_slices(int64_t ld, int64_t mp, int &ks, int64_t &kslice) {
+  const int64_t pw = std::max<int64_t>(1, mp / kCoarseAlign);
+  int64_t want = std::max<int64_t>(1, (1024 + pw - 1) / pw);
+  want = std::min<int64_t>(want, std::max<int64_t>(1, ld / 64));
+  kslice = round_up((ld + want - 1) / want, 16);
+  ks = (int)((ld + kslice - 1) / kslice);
+}
 
 void release_workspace(cpm_system *s) {
   s->device_bytes -= (int64_t)s->ws.bytes;

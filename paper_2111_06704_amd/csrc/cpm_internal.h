@@ -133,6 +133,38 @@ constexpr int kPcTile = 64;
 constexpr int64_t kPcBlockTiles = 256;
 void free_precond(Precond &p);
 
+// Coarse-space correction of the sparse preconditioner P (two-level,
+// balancing Neumann-Neumann form): Z holds the indicator columns of m
+// patches of atoms (z-slabs split into in-plane bins), E_c = Z^T E Z, and
+// the apply is z = P_D^T P P_D r + Z E_c^-1 Z^T r with P_D = I - E Z E_c^-1 Z^T.
+// The local P resolves the short-range response, the coarse solve the
+// long-wavelength modes that a local P leaves at large eigenvalues.
+struct Coarse {
+  bool ready = false;
+  double edge = 0.0;            // in-plane patch edge (A)
+  int64_t m = 0, mp = 0;        // patches, and padded to kCoarseAlign
+  int nslab = 0;
+  int32_t *pid = nullptr;       // n: patch of atom i
+  int32_t *perm = nullptr;      // n: atoms grouped by patch, increasing index in a patch
+  int32_t *off = nullptr;       // mp + 1: patch t is perm[off[t] .. off[t + 1]) (empty past m)
+  float *az = nullptr;          // mp x ld: az[t * ld + i] = (E Z)_it (zero padding)
+  double *eci = nullptr;        // mp x mp: E_c^-1 (zero padding)
+  int ks = 0;                   // atom slices of the Z^T-side product
+  int64_t kslice = 0;
+  // scratch for up to 64 columns: row-interleaved u = P_D r and w = P u
+  // (layout of the residual copy rt), coarse vectors (cols x mp), the
+  // slice partials of (E Z)^T w
+  double *ut = nullptr, *wt = nullptr;
+  double *c1 = nullptr, *g1 = nullptr, *dg = nullptr;
+  float *g1f = nullptr, *c2p = nullptr;
+  int64_t bytes = 0;
+};
+constexpr int kCoarseAlign = 256;     // patches per workgroup of the Z^T-side product
+constexpr int kCoarseCols = 64;       // columns of the coarse scratch (the solver's most)
+constexpr int64_t kMaxCoarse = 8192;  // most patches (E_c^-1: 512 MB)
+constexpr double kSlabGap = 1.0;      // z gap (A) that starts a new slab
+void free_coarse(Coarse &c);
+
 struct Gcd {                 // capacitance coefficients (Supplementary Eq. S22-S24)
   bool ready = false;
   int m = 0;                  // electrodes
@@ -244,6 +276,7 @@ struct cpm_system {
   cpm::Workspace ws;
   cpm::Mlp mlp;
   cpm::Precond pc;
+  cpm::Coarse cz;
   cpm::Gcd gcd;
   std::vector<double> width_host;   // n Gaussian inverse widths (host copy)
   cpm::Profile prof;
@@ -319,6 +352,8 @@ cpm_status matvec_cols_with(cpm_system *s, int precision, const double *M64, con
                             int64_t f, double *v_dev);
 // z = P r (PCG-DC preconditioner) for f vectors (f, n), the CG's own apply kernel
 cpm_status precond_cols(cpm_system *s, const double *r_dev, int64_t f, double *z_dev);
+// slices of the coarse Z^T-side product for mp padded patches
+void coarse_slices(int64_t ld, int64_t mp, int &ks, int64_t &kslice);
 hipError_t launch_diag_inverse(hipStream_t st, const double *E, int64_t n, int64_t ld,
                                double *dinv);
 

@@ -137,6 +137,13 @@ void free_precond(Precond &p) {
   p = Precond();
 }
 
+void free_coarse(Coarse &c) {
+  void *ptrs[] = {c.pid, c.perm, c.off, c.az, c.eci, c.ut, c.wt, c.c1, c.g1, c.dg, c.g1f, c.c2p};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  c = Coarse();
+}
+
 namespace {
 
 // the tiles' column unions (host): U_t sorted, padded to a multiple of 4
@@ -423,6 +430,223 @@ cpm_status dc_columns_device(cpm_system *s, const std::vector<std::vector<Image>
   return CPM_OK;
 }
 
+
+// ---- coarse space of the two-level preconditioner
+
+// Patches (host): z-slabs from the sorted z of the atoms (a new slab where
+// two consecutive values differ by more than kSlabGap, so a jittered layer
+// stays one slab), each split into nx x ny in-plane bins of the box, nx =
+// max(1, floor(L_x / edge + 1/2)); empty patches dropped, the rest numbered
+// in (slab, x bin, y bin) order. pos: wrapped positions.
+std::vector<int32_t> coarse_patch_ids(const std::vector<double> &pos, int64_t n,
+                                      const double box[3], double edge, int64_t &m, int &nslab) {
+  std::vector<int64_t> by_z(n);
+  for (int64_t i = 0; i < n; ++i) by_z[i] = i;
+  std::stable_sort(by_z.begin(), by_z.end(),
+                   [&](int64_t a, int64_t b) { return pos[3 * a + 2] < pos[3 * b + 2]; });
+  std::vector<int64_t> slab(n, 0);
+  int64_t sl = 0;
+  for (int64_t k = 1; k < n; ++k) {
+    if (pos[3 * by_z[k] + 2] - pos[3 * by_z[k - 1] + 2] > kSlabGap) ++sl;
+    slab[by_z[k]] = sl;
+  }
+  nslab = (int)(sl + 1);
+  const int64_t nx = std::max<int64_t>(1, (int64_t)std::floor(box[0] / edge + 0.5));
+  const int64_t ny = std::max<int64_t>(1, (int64_t)std::floor(box[1] / edge + 0.5));
+  std::vector<int64_t> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t bx = std::min<int64_t>(nx - 1, (int64_t)std::floor(pos[3 * i] / box[0] * nx));
+    const int64_t by = std::min<int64_t>(ny - 1, (int64_t)std::floor(pos[3 * i + 1] / box[1] * ny));
+    key[i] = (slab[i] * nx + bx) * ny + by;
+  }
+  std::vector<int64_t> keys(key);
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  m = (int64_t)keys.size();
+  std::vector<int32_t> pid(n);
+  for (int64_t i = 0; i < n; ++i)
+    pid[i] = (int32_t)(std::lower_bound(keys.begin(), keys.end(), key[i]) - keys.begin());
+  return pid;
+}
+
+// rows t0 .. t0 + gridDim.y - 1 of (E Z)^T in FP64: out[(t - t0) * ld + i] =
+// sum over the atoms j of patch t of E_ij (column j of the symmetric E, read
+// coalesced in i); zero for i >= n
+__global__ __launch_bounds__(256) void coarse_az_kernel(const double *__restrict__ E, int64_t ld,
+                                                        int64_t n, const int32_t *__restrict__ perm,
+                                                        const int32_t *__restrict__ off,
+                                                        int64_t t0, double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= ld) return;
+  const int64_t t = t0 + blockIdx.y;
+  double v = 0.0;
+  if (i < n)
+    for (int32_t k = off[t]; k < off[t + 1]; ++k) v += E[(int64_t)perm[k] * ld + i];
+  out[(int64_t)blockIdx.y * ld + i] = v;
+}
+
+// rows t0 .. of E_c = Z^T E Z: ec[t * mp + u] = sum over the atoms of patch u
+// of row t of (E Z)^T (FP64)
+__global__ __launch_bounds__(256) void coarse_ec_kernel(const double *__restrict__ az64, int64_t ld,
+                                                        const int32_t *__restrict__ perm,
+                                                        const int32_t *__restrict__ off, int64_t m,
+                                                        int64_t mp, int64_t t0,
+                                                        double *__restrict__ ec) {
+  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (u >= m) return;
+  const double *row = az64 + (int64_t)blockIdx.y * ld;
+  double v = 0.0;
+  for (int32_t k = off[u]; k < off[u + 1]; ++k) v += row[perm[k]];
+  ec[(t0 + blockIdx.y) * mp + u] = v;
+}
+
+__global__ __launch_bounds__(256) void f64_to_f32_rows_kernel(const double *__restrict__ in,
+                                                              float *__restrict__ out,
+                                                              int64_t count) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < count) out[e] = (float)in[e];
+}
+
+// E_c (mp x mp, symmetric up to rounding): the mean of (t, u) and (u, t) in
+// both, 1 on the diagonal of the padding and 0 elsewhere in it (an SPD
+// matrix for the factorisation)
+__global__ __launch_bounds__(256) void coarse_ec_sym_kernel(double *__restrict__ ec, int64_t m,
+                                                            int64_t mp) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= mp * mp) return;
+  const int64_t t = e / mp, u = e - t * mp;
+  if (t < m && u < m) {
+    if (u > t) {
+      const double a = 0.5 * (ec[t * mp + u] + ec[u * mp + t]);
+      ec[t * mp + u] = a;
+      ec[u * mp + t] = a;
+    }
+  } else {
+    ec[e] = (t == u) ? 1.0 : 0.0;
+  }
+}
+
+// after the inversion (lower triangle of the column-major matrix, i.e.
+// ec[t * mp + u] with u >= t): mirror into the other triangle and zero the
+// padding, so that E_c^-1 is applied to padded vectors as 0
+__global__ __launch_bounds__(256) void coarse_eci_fill_kernel(double *__restrict__ a, int64_t m,
+                                                              int64_t mp) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= mp * mp) return;
+  const int64_t t = e / mp, u = e - t * mp;
+  if (t >= m || u >= m)
+    a[e] = 0.0;
+  else if (u < t)
+    a[e] = a[u * mp + t];
+}
+
+// temporaries of the coarse-space construction, released on every path
+struct CoarseTmp {
+  double *az64 = nullptr;
+  int32_t *info = nullptr;
+  rocblas_handle h = nullptr;
+  ~CoarseTmp() {
+    if (h) (void)rocblas_destroy_handle(h);
+    if (az64) (void)hipFree(az64);
+    if (info) (void)hipFree(info);
+  }
+};
+
+// the coarse space for patches pid (host, n): device arrays, E Z (FP32) and
+// E_c^-1; on failure the caller frees c
+cpm_status build_coarse(cpm_system *s, const std::vector<int32_t> &pid, int64_t m, Coarse &c) {
+  hipStream_t st = s->stream;
+  const int64_t n = s->n, ld = s->ld;
+  const int64_t mp = (m + kCoarseAlign - 1) / kCoarseAlign * kCoarseAlign;
+  c.m = m;
+  c.mp = mp;
+  // atoms by patch (counting sort: increasing index within a patch)
+  std::vector<int32_t> off(mp + 1, 0), perm(n);
+  for (int64_t i = 0; i < n; ++i) ++off[pid[i] + 1];
+  for (int64_t t = 0; t < mp; ++t) off[t + 1] += off[t];
+  {
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int64_t i = 0; i < n; ++i) perm[fill[pid[i]]++] = (int32_t)i;
+  }
+  coarse_slices(ld, mp, c.ks, c.kslice);
+  const size_t vec = sizeof(double) * (size_t)ld * kCoarseCols;
+  const size_t cv = (size_t)kCoarseCols * mp;
+  const int64_t CH = std::min<int64_t>(256, m);   // rows of E Z per pass
+  const size_t sizes[] = {sizeof(int32_t) * (size_t)n, sizeof(int32_t) * (size_t)n,
+                          sizeof(int32_t) * (size_t)(mp + 1), sizeof(float) * (size_t)mp * ld,
+                          sizeof(double) * (size_t)mp * mp, vec, vec, sizeof(double) * cv,
+                          sizeof(double) * cv, sizeof(double) * cv, sizeof(float) * cv,
+                          sizeof(float) * cv * (size_t)c.ks};
+  void **dst[] = {(void **)&c.pid, (void **)&c.perm, (void **)&c.off, (void **)&c.az,
+                  (void **)&c.eci, (void **)&c.ut, (void **)&c.wt, (void **)&c.c1,
+                  (void **)&c.g1, (void **)&c.dg, (void **)&c.g1f, (void **)&c.c2p};
+  CoarseTmp tmp;
+  bool ok = true;
+  for (size_t k = 0; k < sizeof(sizes) / sizeof(sizes[0]); ++k) {
+    ok = ok && hipMalloc(dst[k], sizes[k]) == hipSuccess;
+    if (ok) c.bytes += (int64_t)sizes[k];
+  }
+  ok = ok && hipMalloc((void **)&tmp.az64, sizeof(double) * (size_t)CH * ld) == hipSuccess &&
+       hipMalloc((void **)&tmp.info, sizeof(int32_t)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    set_error("coarse space: allocation failed");
+    return CPM_ENOMEM;
+  }
+  CPM_HIP_CHECK(hipMemcpyAsync(c.pid, pid.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+  CPM_HIP_CHECK(hipMemcpyAsync(c.perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+  CPM_HIP_CHECK(hipMemcpyAsync(c.off, off.data(), sizeof(int32_t) * (mp + 1), hipMemcpyHostToDevice,
+                               st));
+  CPM_HIP_CHECK(hipMemsetAsync(c.az, 0, sizeof(float) * (size_t)mp * ld, st));
+  CPM_HIP_CHECK(hipMemsetAsync(c.ut, 0, vec, st));
+  CPM_HIP_CHECK(hipMemsetAsync(c.wt, 0, vec, st));
+  CPM_HIP_CHECK(hipMemsetAsync(c.eci, 0, sizeof(double) * (size_t)mp * mp, st));
+  // E_c is formed and inverted in place in c.eci
+  for (int64_t t0 = 0; t0 < m; t0 += CH) {
+    const int64_t rows = std::min<int64_t>(CH, m - t0);
+    hipLaunchKernelGGL(coarse_az_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)rows),
+                       dim3(256), 0, st, (const double *)s->E64, ld, n, (const int32_t *)c.perm,
+                       (const int32_t *)c.off, t0, tmp.az64);
+    hipLaunchKernelGGL(coarse_ec_kernel, dim3((unsigned)((m + 255) / 256), (unsigned)rows),
+                       dim3(256), 0, st, (const double *)tmp.az64, ld, (const int32_t *)c.perm,
+                       (const int32_t *)c.off, m, mp, t0, c.eci);
+    hipLaunchKernelGGL(f64_to_f32_rows_kernel, dim3((unsigned)((rows * ld + 255) / 256)),
+                       dim3(256), 0, st, (const double *)tmp.az64, c.az + t0 * ld, rows * ld);
+  }
+  const unsigned gm = (unsigned)((mp * mp + 255) / 256);
+  hipLaunchKernelGGL(coarse_ec_sym_kernel, dim3(gm), dim3(256), 0, st, c.eci, m, mp);
+  CPM_HIP_CHECK(hipGetLastError());
+  if (rocblas_create_handle(&tmp.h) != rocblas_status_success ||
+      rocblas_set_stream(tmp.h, st) != rocblas_status_success) {
+    set_error("coarse space: rocBLAS handle");
+    return CPM_EDEVICE;
+  }
+  int32_t hinfo[2] = {0, 0};
+  if (rocsolver_dpotrf(tmp.h, rocblas_fill_lower, (rocblas_int)mp, c.eci, (rocblas_int)mp,
+                       tmp.info) != rocblas_status_success ||
+      hipMemcpyAsync(hinfo, tmp.info, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    set_error("coarse space: factorisation of Z^T E Z failed");
+    return CPM_EDEVICE;
+  }
+  if (hinfo[0] != 0) {
+    set_error("coarse space: Z^T E Z is not positive definite");
+    return CPM_ENOTSPD;
+  }
+  if (rocsolver_dpotri(tmp.h, rocblas_fill_lower, (rocblas_int)mp, c.eci, (rocblas_int)mp,
+                       tmp.info) != rocblas_status_success ||
+      hipMemcpyAsync(hinfo + 1, tmp.info, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess || hinfo[1] != 0) {
+    set_error("coarse space: inversion of Z^T E Z failed");
+    return CPM_EDEVICE;
+  }
+  hipLaunchKernelGGL(coarse_eci_fill_kernel, dim3(gm), dim3(256), 0, st, c.eci, m, mp);
+  CPM_HIP_CHECK(hipGetLastError());
+  CPM_HIP_CHECK(hipStreamSynchronize(st));
+  return CPM_OK;
+}
+
 }  // namespace
 
 }  // namespace cpm
@@ -630,6 +854,53 @@ cpm_status cpm_precond_gap(cpm_system *s, int enable, double *gap_out) {
   CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
   p.gap = gap;
   if (gap_out) *gap_out = gap;
+  return CPM_OK;
+}
+
+cpm_status cpm_precond_coarse(cpm_system *s, double edge, int64_t *m_out) {
+  if (m_out) *m_out = 0;
+  if (!s) {
+    set_error("NULL system");
+    return CPM_EINVAL;
+  }
+  if (!std::isfinite(edge)) {
+    set_error("the patch edge must be finite");
+    return CPM_EINVAL;
+  }
+  if (edge <= 0.0) {
+    CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+    s->device_bytes -= s->cz.bytes;
+    free_coarse(s->cz);
+    return CPM_OK;
+  }
+  if (!s->pc.ready) {
+    set_error("build a preconditioner first (cpm_precond_dc or cpm_precond_sparse_inverse)");
+    return CPM_ESTATE;
+  }
+  int64_t m = 0;
+  int nslab = 0;
+  const std::vector<int32_t> pid = coarse_patch_ids(s->pos_host, s->n, s->box, edge, m, nslab);
+  if (m > kMaxCoarse) {
+    set_error("coarse space: " + std::to_string(m) + " patches, more than " +
+              std::to_string(kMaxCoarse) + " (take a larger patch edge)");
+    return CPM_EINVAL;
+  }
+  // no enqueued solve still reads the previous coarse space
+  CPM_HIP_CHECK(hipStreamSynchronize(s->stream));
+  s->device_bytes -= s->cz.bytes;
+  free_coarse(s->cz);
+  Coarse c;
+  c.edge = edge;
+  c.nslab = nslab;
+  const cpm_status rc = build_coarse(s, pid, m, c);
+  if (rc != CPM_OK) {
+    free_coarse(c);
+    return rc;
+  }
+  c.ready = true;
+  s->cz = c;
+  s->device_bytes += c.bytes;
+  if (m_out) *m_out = m;
   return CPM_OK;
 }
 

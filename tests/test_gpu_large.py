@@ -145,3 +145,30 @@ def test_pcg_dc_at_full_size(big):
     assert st["iterations"] < big["st"]["iterations"]
     spread = _stationarity_spread(big, q[5], 5)
     assert spread <= 2e-10 * np.linalg.norm(big["b"][5])
+
+
+def test_bench_step_settings(big):
+    """The combination bench.py times at this workload: FP32 E, the committed
+    four-layer network's start, PCG-DC with g = 0.08 / A and r_cut = 14 A
+    (the block-dense apply on the matrix cores) with the coarse space of
+    14 A patches, reliable-update factor 1e-3, checks every 4 iterations.
+    All 64 frames within rel_2 1e-8 of the FP64 solve, stationarity at every
+    atom of frame 17, sum q + Q_sol <= 1e-12 e."""
+    from paper_2111_06704_amd import warmstart
+    cpm, S, geo = big["cpm"], big["S"], big["geo"]
+    S.precond_dc(0.08, 14.0)
+    assert S.precond_coarse(14.0) == 480
+    warmstart.load_into(S, geo, warmstart.weights_for(3))
+    b = torch.tensor(big["b"], device="cuda")
+    qsol = torch.tensor(big["qsol"], device="cuda")
+    q, st = S.solve(b, qsol, tol=1e-11, precision=cpm.PREC_F32, warm_start=cpm.WARM_MLP,
+                    inner_tol=1e-3, check_every=4, preconditioner=cpm.PRECOND_DC)
+    q = q.cpu().numpy()
+    print(f"[bench settings] workload 3: {st['iterations']} iterations, "
+          f"{st['outer']} true residuals, fell back: {st['fell_back']}", flush=True)
+    rel = np.linalg.norm(q - big["q64"], axis=1) / np.linalg.norm(big["q64"], axis=1)
+    assert rel.max() <= 1e-8
+    assert np.max(np.abs(q.sum(axis=1) + big["qsol"])) <= 1e-12
+    S.precond_coarse(0.0)
+    spread = _stationarity_spread(big, q[17], 17)
+    assert spread <= 2e-10 * np.linalg.norm(big["b"][17])

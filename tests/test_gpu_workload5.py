@@ -120,3 +120,34 @@ def test_mixed_matches_fp64(w5):
     rel = np.linalg.norm(q - q64, axis=1) / np.linalg.norm(q64, axis=1)
     assert rel.max() <= 1e-8
     assert w5["st"]["iterations"] < w5["st64"]["iterations"]
+
+
+def test_bench_step_settings(w5):
+    """The solver settings bench.py times at this size: FP32 E, the committed
+    workload-5 network's start, PCG-DC with g = 0.08 / A and r_cut = 14 A
+    (device construction, block-dense apply) with the coarse space of 9 A
+    patches (4080 of them), reliable-update factor 3e-3, checks every 2
+    iterations. All 32 frames within rel_2 1e-8 of the FP64 solve,
+    stationarity at sampled atoms of frame 12, sum q + Q_sol <= 1e-12 e."""
+    from paper_2111_06704_amd import warmstart
+    cpm, S, geo = w5["cpm"], w5["S"], w5["geo"]
+    S.precond_dc(0.08, 14.0)
+    assert S.precond_coarse(9.0) == 4080
+    warmstart.load_into(S, geo, warmstart.weights_for(5))
+    b = torch.tensor(w5["b"], device="cuda")
+    qsol = torch.tensor(w5["qsol"], device="cuda")
+    q, st = S.solve(b, qsol, tol=1e-11, precision=cpm.PREC_F32, warm_start=cpm.WARM_MLP,
+                    inner_tol=3e-3, check_every=2, preconditioner=cpm.PRECOND_DC)
+    S.precond_coarse(0.0)
+    q = q.cpu().numpy()
+    print(f"[bench settings] workload 5: {st['iterations']} iterations, "
+          f"{st['outer']} true residuals, fell back: {st['fell_back']}", flush=True)
+    rel = np.linalg.norm(q - w5["q64"], axis=1) / np.linalg.norm(w5["q64"], axis=1)
+    assert rel.max() <= 1e-8
+    assert np.max(np.abs(q.sum(axis=1) + w5["qsol"])) <= 1e-12
+    at = _samples(geo.n, 8, 56)
+    u = ew.potentials(geo.pos, A, q[12], geo.box, BETA, RC, KMAX, at=at)
+    bo, _ = ew.rhs(geo.pos[at], A, w5["ipos"][12], w5["iq"][12], w5["chi"][at], geo.box,
+                   BETA, RC, KMAX)
+    dev = u - bo
+    assert np.max(np.abs(dev - np.mean(dev))) <= 2e-10 * np.linalg.norm(w5["b"][12])

@@ -182,3 +182,88 @@ def test_sparse_inverse_gap_and_fig6_order():
            for rc in (2.0, 4.0, 8.0, 12.0)]
     assert all(a >= c for a, c in zip(its, its[1:])), its
     assert its[0] < it_cg, (its, it_cg)
+
+
+# ---- coarse-space (two-level) correction: not in the paper; pinned by its
+# closed forms
+
+
+def test_coarse_patches_of_workload1():
+    """Two sheets of 6 x 6 four-atom cells in a 25.56 x 14.757 A box: an edge
+    of 8 A gives 3 x 2 bins per sheet (floor(L / 8 + 1/2)), 12 patches of 24
+    atoms; displacing every atom by up to 0.01 A keeps each sheet one slab
+    (12 patches, none across the sheets) and moves only atoms within 0.01 A
+    of a bin edge; one bin per slab gives the two sheets."""
+    geo = wl.geometry(1)
+    pid = pc.coarse_patches(geo.pos, geo.box, 8.0)
+    assert pid.max() + 1 == 12
+    assert np.all(np.bincount(pid) == 24)
+    # one patch never spans both sheets
+    for t in range(12):
+        assert len(np.unique(geo.layer[pid == t])) == 1
+    jit = wl.jitter(geo, 0.01, 5)
+    pj = pc.coarse_patches(jit.pos, jit.box, 8.0)
+    assert pj.max() + 1 == 12
+    for t in range(12):
+        assert len(np.unique(geo.layer[pj == t])) == 1
+    moved = np.nonzero(pid != pj)[0]
+    assert len(moved) > 0   # the lattice has atoms on the bin edges
+    w = np.mod(geo.pos[moved, :2], geo.box[:2])
+    edges = [geo.box[0] / 3, geo.box[1] / 2]
+    near = np.zeros(len(moved), dtype=bool)
+    for d, e in enumerate(edges):
+        frac = w[:, d] / e
+        near |= np.abs(frac - np.round(frac)) * e <= 0.0101
+    assert near.all()
+    one = pc.coarse_patches(geo.pos, geo.box, 1e3)
+    assert np.array_equal(one, geo.layer.astype(np.int64))
+
+
+def _w1_dc():
+    geo = wl.geometry(1)
+    km = ew.kmax_from_eps(wl.EWALD_SPLIT, wl.KSPACE_EPS)
+    E = ew.ewald_matrix(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, km)
+    prm = GOLD["pcg_dc_parameters"]
+    P = pc.dc_preconditioner(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, prm["g"], prm["rcut"])
+    return geo, E, P
+
+
+def test_two_level_exact_on_coarse_space_and_definite():
+    """M = P_D^T P P_D + Q maps E Z to Z exactly (M E Z = Z: the coarse modes
+    converge in one step), is symmetric and positive definite."""
+    geo, E, P = _w1_dc()
+    pid = pc.coarse_patches(geo.pos, geo.box, 8.0)
+    M = pc.two_level(P, E, pid)
+    Z = np.zeros((geo.n, pid.max() + 1))
+    Z[np.arange(geo.n), pid] = 1.0
+    assert np.max(np.abs(M @ E @ Z - Z)) <= 1e-10
+    assert np.max(np.abs(M - M.T)) <= 1e-12 * np.max(np.abs(M))
+    assert np.linalg.eigvalsh(M).min() > 0.0
+
+
+def test_two_level_limits():
+    """An exact local solve (P = E^-1) stays exact, and one patch per atom
+    (Z = I) gives Q = E^-1 whatever P is."""
+    geo, E, P = _w1_dc()
+    Einv = np.linalg.inv(E)
+    pid = pc.coarse_patches(geo.pos, geo.box, 8.0)
+    assert np.max(np.abs(pc.two_level(Einv, E, pid) - Einv)) <= 1e-9 * np.max(np.abs(Einv))
+    each = np.arange(geo.n)
+    assert np.max(np.abs(pc.two_level(P, E, each) - Einv)) <= 1e-9 * np.max(np.abs(Einv))
+
+
+def test_two_level_reaches_cholesky_solution_faster():
+    """PCG with the two-level P reaches the Cholesky solution (1e-9) in fewer
+    iterations than with P alone."""
+    geo, ipos, iq, chi = wl.workload(1, frames=1)
+    _, E, P = _w1_dc()
+    km = ew.kmax_from_eps(wl.EWALD_SPLIT, wl.KSPACE_EPS)
+    b, _ = ew.rhs(geo.pos, wl.GAUSS_INV_WIDTH, ipos, iq, chi, geo.box, wl.EWALD_SPLIT, wl.RCUT, km)
+    b = b[0]
+    import scipy.linalg as sla
+    xo = sla.cho_solve(ocpm.cholesky(E), b)
+    M = pc.two_level(P, E, pc.coarse_patches(geo.pos, geo.box, 8.0))
+    x1, k1 = pc.pcg(E, b, M, 1e-12)
+    _, k0 = pc.pcg(E, b, P, 1e-12)
+    assert np.linalg.norm(x1 - xo) <= 1e-9 * np.linalg.norm(xo)
+    assert k1 < k0, (k1, k0)
