@@ -46,9 +46,22 @@ KERNEL_OF_KIND_WIDE = {"matvec_f64": "block_matvec_f64s_kernel<{ng}>",
                        "matvec_bf16": "block_matvec_split_kernel<unsigned short, {ng}>"}
 
 
+# the ion structure factors of the right-hand side (|n_z| <= 47: every workload here)
+SF_KERNEL = "sf_gemm_kernel"
+
+
 def kernel_name(kind, ng):
+    if kind == "sf":
+        return SF_KERNEL
     return (KERNEL_OF_KIND_WIDE if ng >= 2 else KERNEL_OF_KIND)[kind].format(ng=ng)
-CG_SOURCE = os.path.join(ROOT, "paper_2111_06704_amd", "csrc", "cg.hip")
+
+
+CSRC = os.path.join(ROOT, "paper_2111_06704_amd", "csrc")
+
+
+def kernel_source(name):
+    """The source file that defines a kernel of the traffic record."""
+    return os.path.join(CSRC, "rhs.hip" if name.startswith(SF_KERNEL) else "cg.hip")
 PROFILE_STRIDE = 5   # timed launches of the block product: every 5th (coprime to the check batches)
 MODE_STEPS = 5       # timed steps of every comparison mode (at most --steps)
 # in-plane patch edge (A) of the coarse-space correction per workload (0: off).
@@ -159,17 +172,30 @@ def summarize_pmc(fetch_dir, write_dir, out_path):
 
     kf, cf = calib(fetch)
     kw, cw = calib(write)
+    # the counter run's own bench line (written beside its directory): the
+    # structure factors' traffic depends on its k-set
+    run_cfg = {}
+    run_json = fetch_dir.rstrip("/") + ".json"
+    if os.path.exists(run_json):
+        with open(run_json) as fh:
+            c = json.loads(fh.read().strip().splitlines()[-1])["config"]
+        run_cfg = {"n_kvec": c.get("n_kvec"), "kmax_override": c.get("kmax_override")}
     rec = {"counter_unit": "KiB per dispatch",
            "calibration": {"kernel_fetch": kf, "kernel_write": kw, "bytes": CALIB_BYTES,
                            "fetch_kib": cf, "write_kib": cw,
                            "fetch_factor": CALIB_BYTES / (cf * 1024.0),
                            "write_factor": CALIB_BYTES / (cw * 1024.0)},
-           "cg_source_sha256": _sha256(CG_SOURCE), "kernels": {}}
+           "source_sha256": {os.path.basename(f): _sha256(os.path.join(CSRC, f))
+                             for f in ("cg.hip", "rhs.hip")},
+           "run_config": run_cfg, "kernels": {}}
     for name in sorted(set(fetch) | set(write)):
         m = re.search(r"(block_matvec(?:_split|_rows|_f64s)?_kernel)<([^>]*)>", name)
-        if not m:
+        if m:
+            key = m.group(1) + "<" + m.group(2) + ">"
+        elif re.search(r"\b" + SF_KERNEL + r"\b", name):
+            key = SF_KERNEL
+        else:
             continue
-        key = m.group(1) + "<" + m.group(2) + ">"
         # median over dispatches: launches that the device-side control
         # turned into no-ops move no data and are not typical
         rec["kernels"][key] = {"dispatches": len(fetch.get(name, [])),
@@ -181,16 +207,22 @@ def summarize_pmc(fetch_dir, write_dir, out_path):
     print(json.dumps(rec))
 
 
-def traffic_bytes(record_path, kind, ng):
-    """HBM bytes per launch of the dominant kernel from a committed traffic
-    record; None if there is none or the block-product source has changed."""
+def traffic_bytes(record_path, kind, ng, n_kvec=None):
+    """HBM bytes per launch of a kernel from a committed traffic record; None
+    if there is none, the source file of that kernel has changed since the
+    counters were taken, or (structure factors) the counter run used another
+    k-set than this one."""
     if not record_path or not os.path.exists(record_path):
         return None
     with open(record_path) as fh:
         rec = json.load(fh)
-    if rec.get("cg_source_sha256") != _sha256(CG_SOURCE):
+    name = kernel_name(kind, ng)
+    if kind == "sf" and rec.get("run_config", {}).get("n_kvec") != n_kvec:
         return None
-    k = rec["kernels"].get(kernel_name(kind, ng))
+    src = kernel_source(name)
+    if rec.get("source_sha256", {}).get(os.path.basename(src)) != _sha256(src):
+        return None
+    k = rec["kernels"].get(name)
     if not k or k.get("fetch_kib") is None or k.get("write_kib") is None:
         return None
     c = rec["calibration"]
@@ -527,22 +559,39 @@ def main():
         extras = run_extras(S, cpm, wl, geo, args, b, qsol, q64, dev, t_ipos, t_iq, t_chi, nf,
                             prec, pcmode, inner_tol_for, run_steps)
 
-    # dominant kernel of the timed region: the block matrix product with the most time
-    kinds = ["matvec_f64", "matvec_f32", "matvec_bf16"]
-    k = int(np.argmax([prof[i]["ms"] for i in range(3)]))
-    avg_ms = prof[k]["ms"] / max(1, prof[k]["launches"])
-    bytes_per_launch = prof[k]["work"] / max(1, prof[k]["launches"])
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    # rooflines from the live HIP-event timing of the timed region (every
+    # PROFILE_STRIDE-th launch of each kind): the block matrix product with
+    # the most time (HBM-bound: algorithmic bytes) and the ion structure
+    # factors of the right-hand side (FP64 matrix cores: algorithmic flops);
+    # `roofline` is whichever of the two takes more of the step
+    kinds = {0: "matvec_f64", 1: "matvec_f32", 2: "matvec_bf16", 4: "sf"}
     ng = min(4, (nf + 15) // 16)
     rec_path = args.traffic_record or os.path.join(ROOT, "profiles", f"traffic_workload{cfg}.json")
-    traffic = traffic_bytes(rec_path, kinds[k], ng)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
-                "kernel": kernel_name(kinds[k], ng),
-                "avg_launch_us": avg_ms * 1e3, "launches": prof[k]["launches"],
-                "timed_every": PROFILE_STRIDE,
-                "bytes_per_launch": bytes_per_launch,
-                "kernel_share_of_step": PROFILE_STRIDE * prof[k]["ms"] / (elapsed * 1e3)}
+
+    def roofline_of(k):
+        launches = max(1, prof[k]["launches"])
+        avg_ms = prof[k]["ms"] / launches
+        work = prof[k]["work"] / launches
+        r = {"traffic": traffic_bytes(rec_path, kinds[k], ng, desc["n_kvec"]),
+             "traffic_unit": "bytes per launch",
+             "kernel": kernel_name(kinds[k], ng), "avg_launch_us": avg_ms * 1e3,
+             "launches": prof[k]["launches"], "timed_every": PROFILE_STRIDE,
+             "kernel_share_of_step": PROFILE_STRIDE * prof[k]["ms"] / (elapsed * 1e3)}
+        if k == 4:
+            achieved = work / (avg_ms * 1e-3) / 1e12
+            r.update({"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                      "flops_per_launch": work})
+        else:
+            achieved = work / (avg_ms * 1e-3) / 1e9
+            r.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": work})
+        return {key: r[key] for key in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | r
+
+    kmv = max((0, 1, 2), key=lambda i: prof[i]["ms"])
+    roofline_mv = roofline_of(kmv)
+    roofline_sf = roofline_of(4) if prof[4]["launches"] else None
+    roofline = roofline_sf if roofline_sf and prof[4]["ms"] > prof[kmv]["ms"] else roofline_mv
 
     # counter calibration: a plain copy of CALIB_BYTES (outside the timed region)
     src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
@@ -558,8 +607,8 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     copy_gbs = 2.0 * CALIB_BYTES * 5 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
-    roofline["copy_kernel_GBps"] = copy_gbs
-    roofline["frac_of_copy"] = achieved / copy_gbs
+    roofline_mv["copy_kernel_GBps"] = copy_gbs
+    roofline_mv["frac_of_copy"] = roofline_mv["achieved"] / copy_gbs
     del src, dst
 
     qg = q.cpu().numpy()
@@ -601,6 +650,8 @@ def main():
         "e_build_s": build_s, "precond_build_s": precond_build_s,
         "coarse_build_s": coarse_build_s,
         "roofline": roofline,
+        "roofline_block_product": roofline_mv,
+        "roofline_structure_factors": roofline_sf,
     }
     out.update(extras)
     if not args.no_cpu_baseline:

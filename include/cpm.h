@@ -426,21 +426,25 @@ cpm_status cpm_warm_start(cpm_system *s, int warm_start, const double *b_dev,
 
 /* ---- live kernel timing ----------------------------------------------------
  * While enabled, the library brackets launches of the block matrix product
- * (per storage precision of E) and of the assembly contraction with HIP
- * events on its stream and records each launch's algorithmic work:
+ * (per storage precision of E), of the assembly contraction and of the ion
+ * structure factors of cpm_rhs with HIP events on its stream and records
+ * each launch's algorithmic work:
  *   matvec: bytes s*n*n (E) + 2 * s_v * n * cols (P read, V written),
  *           s = 8/4/2 for FP64/FP32/BF16 E, s_v = 8 (FP64) or 4 (FP32 vectors);
- *   assembly: flops 4 * n_k * n (n + 1) / 2 for a chunk of n_k k-vectors.
+ *   assembly: flops 4 * n_k * n (n + 1) / 2 for a chunk of n_k k-vectors;
+ *   structure factors: flops 4 * n_k * m * f (one complex multiply-add of
+ *           q e^{iK.r} per k-vector, ion and frame) for f frames of m ions.
  * cpm_profile_enable(s, on) starts a new window (clears earlier records):
  * on = 0 stops timing, on = 1 times every launch, on = k > 1 times every
- * k-th launch of the block product of each precision (the bracketing
+ * k-th launch of each kind (the bracketing
  * launch costs the host ~10 us more than a plain one; sampling keeps that
  * out of the throughput being measured); cpm_profile_read synchronises the
  * stream and sums each kind over the timed launches. */
 typedef struct {
-  int64_t launches[4];   /* index: CPM_PREC_F64, CPM_PREC_F32, CPM_PREC_BF16, 3 = assembly */
-  double ms[4];          /* summed kernel time (ms) between the events                    */
-  double work[4];        /* summed algorithmic bytes (matvec) or flops (assembly)         */
+  int64_t launches[5];   /* index: CPM_PREC_F64, CPM_PREC_F32, CPM_PREC_BF16, 3 = assembly,
+                            4 = structure factors                                         */
+  double ms[5];          /* summed kernel time (ms) between the events                    */
+  double work[5];        /* summed algorithmic bytes (matvec) or flops (the others)       */
 } cpm_profile_info;
 
 cpm_status cpm_profile_enable(cpm_system *s, int on);

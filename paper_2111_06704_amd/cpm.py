@@ -66,7 +66,7 @@ class SolveInfo(C.Structure):
 
 
 class ProfileInfo(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 4), ("ms", C.c_double * 4), ("work", C.c_double * 4)]
+    _fields_ = [("launches", C.c_int64 * 5), ("ms", C.c_double * 5), ("work", C.c_double * 5)]
 
 
 _lib = None
@@ -197,15 +197,17 @@ class System:
             pass
 
     def profile_enable(self, on=True, stride=1):
-        """Time launches of the block product (every stride-th of each kind)."""
+        """Time launches of the block product, the assembly contraction and the
+        structure factors (every stride-th of each kind)."""
         _check(lib().cpm_profile_enable(self._h, max(1, int(stride)) if on else 0),
                "cpm_profile_enable")
 
     def profile_read(self):
-        """Per kind (0 FP64, 1 FP32, 2 BF16 matvec, 3 assembly): launches, ms, work."""
+        """Per kind (0 FP64, 1 FP32, 2 BF16 matvec, 3 assembly, 4 structure
+        factors): launches, ms, work."""
         pi = ProfileInfo()
         _check(lib().cpm_profile_read(self._h, C.byref(pi)), "cpm_profile_read")
-        return [dict(launches=pi.launches[k], ms=pi.ms[k], work=pi.work[k]) for k in range(4)]
+        return [dict(launches=pi.launches[k], ms=pi.ms[k], work=pi.work[k]) for k in range(5)]
 
     def describe(self):
         n, nk, dev = C.c_int64(), C.c_int64(), C.c_int64()

@@ -1361,40 +1361,63 @@ __global__ __launch_bounds__(256) void coarse_solve_kernel(
   }
 }
 
-// u = r - (E Z) g1 into the row-interleaved ut, on the FP32 matrix cores:
-// wave w of workgroup b takes the atoms i0 = 64 b + 16 w .. i0 + 15 and every
-// column group; per step of 4 patches lane (lr, lg) gives A = az(patch t +
-// lg, atom i0 + lr) and B = g1f(column 16 g + lr, patch t + lg), and holds
-// D[row 4 lg + v][column lr] in register v. Rows past n stay 0 (az and rt
-// are 0 there).
+// u = r - (E Z) g1 into the row-interleaved ut, on the FP32 matrix cores,
+// as the product g1^T (E Z)^T: workgroup = 64 atoms, its four waves split
+// the patches in quarters and add their sums in LDS in a fixed order. Per
+// step of 4 patches lane (lr, lg) loads (E Z)^T(patch t + lg, atoms i0 + 4 lr
+// .. + 3) as one float4 and gives A = g1f(column 16 g + lr, patch t + lg);
+// product j of a group takes B = the j-th of those atoms, so it holds
+// D[row 4 lg + v][column lr] = column 16 g + 4 lg + v of atom i0 + 4 lr + j
+// in register v. Rows past n stay 0 (az and rt are 0 there).
 template <int NG>
 __global__ __launch_bounds__(256) void coarse_prolong_kernel(
     const float *__restrict__ az, const float *__restrict__ g1f, int64_t mp,
     const double *__restrict__ rt, int64_t ld, double *__restrict__ ut,
     const int *__restrict__ gate) {
+  __shared__ float red[3][NG][4][4][64];
   if (gate != nullptr && *gate == 0) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lr = lane & 15, lg = lane >> 4;
-  const int64_t i0 = (int64_t)blockIdx.x * 64 + wave * 16;
-  f4 acc[NG];
-#pragma unroll
-  for (int g = 0; g < NG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
-  const float *A = az + i0 + lr;
-#pragma unroll 4
-  for (int64_t t = lg; t < mp; t += 4) {
-    const float a = A[t * ld];
-#pragma unroll
-    for (int g = 0; g < NG; ++g)
-      acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g1f[(int64_t)(g * 16 + lr) * mp + t],
-                                                    acc[g], 0, 0, 0);
-  }
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t q = mp / 4, t0 = wave * q;
+  f4 acc[NG][4];
 #pragma unroll
   for (int g = 0; g < NG; ++g)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t o = ((int64_t)g * ld + i0 + 4 * lg + v) * kColGroup + lr;
-      ut[o] = rt[o] - (double)acc[g][v];
+    for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const float *B = az + i0 + 4 * lr;
+#pragma unroll 2
+  for (int64_t t = t0 + lg; t < t0 + q; t += 4) {
+    const f4 b4 = *reinterpret_cast<const f4 *>(B + t * ld);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const float a = g1f[(int64_t)(g * 16 + lr) * mp + t];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[g][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b4[j], acc[g][j], 0, 0, 0);
     }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wave - 1][g][j][v][lane] = acc[g][j][v];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float sum = ((acc[g][j][v] + red[0][g][j][v][lane]) + red[1][g][j][v][lane]) +
+                          red[2][g][j][v][lane];
+        const int64_t o = ((int64_t)g * ld + i0 + 4 * lr + j) * kColGroup + 4 * lg + v;
+        ut[o] = rt[o] - (double)sum;
+      }
 }
 
 // Slice partials of (E Z)^T w on the FP32 matrix cores: c2p[(k * cols + c) *

@@ -201,11 +201,12 @@ struct Mlp {
 struct Profile {
   bool enabled = false;
   int stride = 1;            // time every stride-th block-product launch of each kind
-  int64_t seen[3] = {0, 0, 0};
+  int64_t seen[5] = {0, 0, 0, 0, 0};
   // whether this launch of the block product (kind 0..2) is to be timed
   bool sample(int kind) { return enabled && (seen[kind]++ % stride) == 0; }
   struct Rec {
-    int kind;              // 0..2: matvec FP64/FP32/BF16, 3: assembly contraction
+    int kind;              // 0..2: matvec FP64/FP32/BF16, 3: assembly contraction,
+                           // 4: ion structure factors of the right-hand side
     double work;           // algorithmic bytes (matvec) or flops (assembly) of the launch
     hipEvent_t a, b;
     int mark = -1;         // slot in marks: 1 if the launch did its work, 0 if it was gated off
@@ -279,7 +280,7 @@ struct cpm_system {
   cpm::Coarse cz;
   cpm::Gcd gcd;
   std::vector<double> width_host;   // n Gaussian inverse widths (host copy)
-  cpm::Profile prof;
+  mutable cpm::Profile prof;   // timing only: recorded from const paths too
   hipEvent_t warm_ev[2] = {nullptr, nullptr};   // brackets of the warm start (its time)
   // per-call scratch, grown on demand and kept: the warm start and its
   // residual (2 f n), E q0 of its neutral shift (f n), per-frame means (f),

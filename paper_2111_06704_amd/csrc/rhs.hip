@@ -1195,16 +1195,24 @@ hipError_t launch_rhs(hipStream_t st, const cpm_system *s, const double *ion_pos
   if (p.ksplit > 0) {
     double *Sg = p.sf_groups > 1 ? buf + p.off_sg : S;
     const int64_t rblocks = (s->kset.nruns + RB - 1) / RB;
+    // live timing (cpm_profile_enable): algorithmic flops 4 n_k m f
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (s->prof.sample(4)) {
+      Profile::Rec &r = s->prof.add(4, 4.0 * (double)nk * (double)m * (double)f);
+      ea = r.a;
+      eb = r.b;
+    }
     if (p.sf_gemm) {
-      hipLaunchKernelGGL(sf_gemm_kernel,
-                         dim3((unsigned)f, (unsigned)(s->kset.ncols_pad / kSfTile),
-                              (unsigned)p.sf_groups),
-                         dim3(256), 0, st, ion_pos, ion_q, m, p.sf_ipg,
-                         reinterpret_cast<const int4 *>(s->kcol), ilx, ily, ilz, nk, f, Sg);
+      hipExtLaunchKernelGGL(sf_gemm_kernel,
+                            dim3((unsigned)f, (unsigned)(s->kset.ncols_pad / kSfTile),
+                                 (unsigned)p.sf_groups),
+                            dim3(256), 0, st, ea, eb, 0, ion_pos, ion_q, m, p.sf_ipg,
+                            reinterpret_cast<const int4 *>(s->kcol), ilx, ily, ilz, nk, f, Sg);
     } else
-      hipLaunchKernelGGL(structure_factor_kernel, dim3((unsigned)rblocks, (unsigned)f, (unsigned)p.sf_groups),
-                         dim3(RB), 0, st, ion_pos, ion_q, m, p.sf_ipg, s->kinfo, s->krun,
-                         s->kset.nruns, nk, ilx, ily, ilz, f, Sg);
+      hipExtLaunchKernelGGL(structure_factor_kernel,
+                            dim3((unsigned)rblocks, (unsigned)f, (unsigned)p.sf_groups), dim3(RB),
+                            0, st, ea, eb, 0, ion_pos, ion_q, m, p.sf_ipg, s->kinfo, s->krun,
+                            s->kset.nruns, nk, ilx, ily, ilz, f, Sg);
     if (p.sf_groups > 1) {
       const int64_t len = 2 * nk * f;
       hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
