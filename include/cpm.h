@@ -170,7 +170,11 @@ typedef struct {
                           replaces the recursive one once the latter has fallen by
                           this factor, e.g. 1e-2                                   */
   int check_every;     /* iterations between the device-side convergence checks
-                          (>= 1)                                                   */
+                          (>= 1). FP32 / BF16 replace the recursive residual only
+                          at a check: with the coarse correction (about tenfold
+                          per iteration) keep it at 2-4, as longer intervals let
+                          the recursion run orders past the reliable-update
+                          point and can cost many iterations                  */
   int preconditioner;  /* CPM_PRECOND_JACOBI (diag E) or CPM_PRECOND_DC (the
                           system's sparse P, Sec. III.B.2: the PCG-DC matrix of
                           cpm_precond_dc or the sparsified inverse of
