@@ -193,8 +193,8 @@ def test_solver_warm_start_matches_oracle():
 
 def test_learned_start_gain_workload2():
     """What the trained network gains over the method without it, at the
-    settings bench.py times at workload 2 (FP32 E, PCG-DC g = 0.15 / A with
-    r_cut 7 A, reliable-update factor 1e-4, checks every 4 iterations, tol
+    settings bench.py times at workload 2 (FP32 E, PCG-DC g = 0.08 / A with
+    r_cut 12 A, reliable-update factor 1e-4, checks every 4 iterations, tol
     1e-11), on the 16 evaluation frames (seeds disjoint from the training
     frames): a smaller initial residual and strictly fewer iterations than
     both the zero start and the free q_chi start."""
@@ -202,7 +202,7 @@ def test_learned_start_gain_workload2():
     from paper_2111_06704_amd import warmstart
     geo, ipos, iq, chi = wl.workload(2)
     S = cpm.System(geo.pos, geo.box, A, BETA, RC, EPS, store=("f32",))
-    S.precond_dc(0.15, 7.0)
+    S.precond_dc(0.08, 12.0)
     t_chi = torch.tensor(chi, device="cuda")
     S.set_warm_chi(t_chi, preconditioner=cpm.PRECOND_DC)
     warmstart.load_into(S, geo, warmstart.DEFAULT_PATH)

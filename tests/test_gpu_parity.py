@@ -184,13 +184,13 @@ def test_solve_mixed_workload2(c2, prec_name):
 
 def test_bench_step_workload2(c2):
     """The step bench.py times at workload 2 with its exact settings: FP32 E,
-    the committed network's start, PCG-DC (g = 0.15 / A, r_cut 7 A),
+    the committed network's start, PCG-DC (g = 0.08 / A, r_cut 12 A),
     reliable-update factor 1e-4, checks every 4 iterations, tol 1e-11;
     charges of all 16 frames against the oracle's Cholesky solution."""
     cpm = _cpm()
     from paper_2111_06704_amd import warmstart
     S = cpm.System(c2.geo.pos, c2.geo.box, A, BETA, RC, EPS, store=("f32",))
-    S.precond_dc(0.15, 7.0)
+    S.precond_dc(0.08, 12.0)
     warmstart.load_into(S, c2.geo, warmstart.weights_for(2))
     b, qsol = S.rhs(c2.t_ipos, c2.t_iq, c2.t_chi)
     q, st = S.solve(b, qsol, tol=1e-11, precision=cpm.PREC_F32, warm_start=cpm.WARM_MLP,
