@@ -8,8 +8,10 @@
 //   real space  sum_I q_I sum_{images, d < rcut} [erfc(beta d) - erfc(a_i d)] / d
 //   background  -pi / (V beta^2) Q_sol,  Q_sol = sum_I q_I.
 // Phases are evaluated from the fractional coordinate t = n . (r / L)
-// reduced to [-1/2, 1/2] and sincospi(2t), all in FP64; every sum runs in a
-// fixed order (no atomics), so results are bitwise reproducible.
+// reduced to [-1/2, 1/2] and sincospi(2t), all in FP64 (the structure
+// factors' (n_x, n_y) phases by a table of 128 roots of unity and a short
+// Taylor series, phase_cs); every sum runs in a fixed order (no atomics), so
+// results are bitwise reproducible.
 #include "cpm_internal.h"
 
 #include <algorithm>
@@ -200,8 +202,9 @@ __global__ __launch_bounds__(RB) void structure_factor_kernel(
 //     sincospi of the reduced fractional phase, then Z_(s+1) = Z_s Z_1);
 //     the raw positions were loaded into registers one chunk ahead;
 //   - product phase: per step of 4 ions each lane forms its (column, ion)
-//     entry of q P (sincospi) and v_mfma_f64_16x16x4f64 accumulates the
-//     four products for every s block.
+//     entry of q P (phase_cs: a table of exp(2 pi i j / 128) and a short
+//     Taylor series) and v_mfma_f64_16x16x4f64 accumulates the four
+//     products for every s block.
 // One barrier per chunk: the table of chunk c + 1 goes to the buffer that
 // the product phase of chunk c - 1 read, and every wave has left that phase
 // before the barrier of chunk c. Output: Sg as in structure_factor_kernel.
@@ -210,10 +213,38 @@ constexpr int SG_SB = 3;       // s blocks of 16 at most (|n_z| <= 47)
 
 // LDS of one workgroup: two chunk buffers of Z tables (SG_CH ions x 16 NSB
 // s values, sized for the largest NSB) and of x / L_x, y / L_y, q
+constexpr int kTw = 128;        // entries of the table of exp(2 pi i j / kTw)
 struct SfLds {
   double2 zt[2][SG_CH][16 * SG_SB];
   double su[2][SG_CH][3];
+  double2 tw[kTw];
 };
+
+// (cos, sin) of 2 pi t without a library sincos: t = j / kTw + d with
+// j = rint(kTw t) and |d| <= 1 / (2 kTw), and exp(2 pi i t) = exp(2 pi i j /
+// kTw) exp(2 pi i d), the first factor from the table tw, the second from
+// the Taylor series of cos(2 pi d) and sin(2 pi d) in d up to d^6 and d^7
+// (|2 pi d| <= pi / 128: the first terms left out are below 4e-18). About
+// a dozen FP64 operations, against about three times as many for sincospi;
+// on this chip the FP64 vector work does not overlap the FP64 matrix-core
+// products, so it adds to the kernel's time one for one.
+constexpr double kTwoPi = 6.283185307179586;
+constexpr double kC1 = -kTwoPi * kTwoPi / 2.0;
+constexpr double kC2 = -kC1 * kTwoPi * kTwoPi / 12.0;
+constexpr double kC3 = -kC2 * kTwoPi * kTwoPi / 30.0;
+constexpr double kS1 = -kTwoPi * kTwoPi * kTwoPi / 6.0;
+constexpr double kS2 = -kS1 * kTwoPi * kTwoPi / 20.0;
+constexpr double kS3 = -kS2 * kTwoPi * kTwoPi / 42.0;
+__device__ __forceinline__ void phase_cs(const double2 *tw, double t, double &c, double &s) {
+  const double j = rint(t * kTw);
+  const double d = fma(j, -1.0 / kTw, t);
+  const double d2 = d * d;
+  const double cd = fma(d2, fma(d2, fma(d2, kC3, kC2), kC1), 1.0);
+  const double sd = d * fma(d2, fma(d2, fma(d2, kS3, kS2), kS1), kTwoPi);
+  const double2 w = tw[(int)(int64_t)j & (kTw - 1)];
+  c = fma(w.x, cd, -w.y * sd);
+  s = fma(w.y, cd, w.x * sd);
+}
 
 template <int NSB>
 __device__ __forceinline__ void sf_gemm_body(SfLds &L, const double *__restrict__ ion_pos,
@@ -274,6 +305,12 @@ __device__ __forceinline__ void sf_gemm_body(SfLds &L, const double *__restrict_
       }
     }
   };
+  // the exp(2 pi i j / kTw) table (read after the first barrier below)
+  if (tid < kTw) {
+    double sj, cj;
+    sincospi(2.0 * (double)tid / kTw, &sj, &cj);
+    L.tw[tid] = make_double2(cj, sj);
+  }
   if (nchunks > 0) {
     fetch(0);
     table(0);
@@ -288,10 +325,8 @@ __device__ __forceinline__ void sf_gemm_body(SfLds &L, const double *__restrict_
       double2 z[NSB];
 #pragma unroll
       for (int sb = 0; sb < NSB; ++sb) z[sb] = L.zt[buf][ion][sb * 16 + lr];
-      double t = cnx * L.su[buf][ion][0] + cny * L.su[buf][ion][1];
-      t -= rint(t);
       double sn, cs;
-      sincospi(2.0 * t, &sn, &cs);
+      phase_cs(L.tw, cnx * L.su[buf][ion][0] + cny * L.su[buf][ion][1], cs, sn);
       const double q = L.su[buf][ion][2];
       const double a = q * cs, b = q * sn;
 #pragma unroll
