@@ -330,7 +330,7 @@ def main():
                       args.out or os.path.join(ROOT, "profiles", f"traffic_workload{args.workload}.json"))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the path runs on one GPU; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (single-GPU build)")
         sys.exit(2)
     # one line per assembled k chunk on stderr (workload 5 assembles for minutes)

@@ -14,7 +14,7 @@ library.
         --out paper_2111_06704_amd/weights/warmstart_4layer.npz
 
     python -m paper_2111_06704_amd.warmstart --workload 5 --frames 1024 \
-        --out paper_2111_06704_amd/weights/warmstart_cfg5.npz
+        --out paper_2111_06704_amd/weights/warmstart_graphite4_131072.npz
 
 The second network serves workload 3 (trained at workload 5's ion density,
 50000 ions in workload 3's slit), the third workload 5 itself (its inputs
@@ -36,11 +36,11 @@ from . import cpm, workloads as wl
 
 NIN, NH = cpm.MLP_IN, cpm.MLP_HIDDEN
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
-                            "warmstart_cfg2.npz")
+                            "warmstart_graphite3_4608.npz")
 FOUR_LAYER_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
                                "warmstart_4layer.npz")
 WORKLOAD5_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
-                              "warmstart_cfg5.npz")
+                              "warmstart_graphite4_131072.npz")
 
 
 def weights_for(cfg: int) -> str:
@@ -152,7 +152,7 @@ def main(argv=None):
 
     dev = torch.device("cuda:0")
     geo = wl.geometry(args.workload)
-    m = args.ions or wl.CONFIGS[args.workload]["m"]
+    m = args.ions or wl.WORKLOAD_SIZES[args.workload]["m"]
     S = cpm.System(geo.pos, geo.box, wl.GAUSS_INV_WIDTH, wl.EWALD_SPLIT, wl.RCUT, wl.KSPACE_EPS,
                    store=("f32",))
     chi = torch.tensor(wl.electrode_potential(geo), device=dev)

@@ -13,7 +13,7 @@ layer by R along the armchair direction; graphite interlayer spacing 3.35 A.
 
 Workload sizes follow the constant-potential electrode study of the paper
 (graphene electrodes, 1 V, slit filled with electrolyte; Sec. IV) at the
-sizes listed in ``CONFIGS``; the paper's equilibrated water/NaCl frames are
+sizes listed in ``WORKLOAD_SIZES``; the paper's equilibrated water/NaCl frames are
 replaced by uniform random +-1 e point charges.
 """
 from __future__ import annotations
@@ -113,24 +113,24 @@ def geometry(cfg: int) -> Geometry:
        157.41 x 272.64 x 120 A, 50 A gap.
     """
     if cfg == 1:
-        return electrode_geometry("cfg1", 6, 6, True, [10.0], [50.0], 60.0)
+        return electrode_geometry("graphene_2x144", 6, 6, True, [10.0], [50.0], 60.0)
     if cfg in (2, 4):
         lz = 100.0
-        return electrode_geometry("cfg2", 12, 16, False,
+        return electrode_geometry("graphite_2x3x768", 12, 16, False,
                                   _stack(lz / 2 - 25.0, 3, -1), _stack(lz / 2 + 25.0, 3, +1), lz)
     if cfg == 3:
         lz = 120.0
-        return electrode_geometry("cfg3", 32, 32, False,
+        return electrode_geometry("graphite_2x4x4096", 32, 32, False,
                                   _stack(lz / 2 - 25.0, 4, -1), _stack(lz / 2 + 25.0, 4, +1), lz)
     if cfg == 5:
         lz = 120.0
-        return electrode_geometry("cfg5", 64, 64, False,
+        return electrode_geometry("graphite_2x4x16384", 64, 64, False,
                                   _stack(lz / 2 - 25.0, 4, -1), _stack(lz / 2 + 25.0, 4, +1), lz)
     raise ValueError(f"unknown workload {cfg}")
 
 
 # ions per frame and frames per workload
-CONFIGS = {
+WORKLOAD_SIZES = {
     1: dict(m=200, frames=16),
     2: dict(m=2000, frames=16),
     3: dict(m=20000, frames=64),
@@ -185,7 +185,7 @@ def workload(cfg: int, frames: int | None = None, first_frame: int = 0):
     """Geometry, ion positions (F, M, 3), ion charges (F, M) and electrode
     potentials (N,) in volts for workload ``cfg``."""
     geo = geometry(cfg)
-    c = CONFIGS[cfg]
+    c = WORKLOAD_SIZES[cfg]
     nf = c["frames"] if frames is None else frames
     seed_cfg = 2 if cfg == 4 else cfg
     ipos, iq = ion_frames(geo, c["m"], [frame_seed(seed_cfg, first_frame + f) for f in range(nf)])
