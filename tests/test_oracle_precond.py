@@ -267,3 +267,23 @@ def test_two_level_reaches_cholesky_solution_faster():
     _, k0 = pc.pcg(E, b, P, 1e-12)
     assert np.linalg.norm(x1 - xo) <= 1e-9 * np.linalg.norm(xo)
     assert k1 < k0, (k1, k0)
+
+
+def test_coarse_patch_counts_of_the_large_workloads():
+    """The patch counts the parity tests and the bench rely on, from the rule's
+    closed form: 8 graphite layers (one slab each) times nx x ny bins with
+    nx = floor(L_x / edge + 1/2): 6 x 10 bins of 14 A at N = 32768 (480
+    patches) and 17 x 30 bins of 9 A at N = 131072 (4080 patches), none
+    empty, each within one layer."""
+    for cfg, edge, nx, ny in ((3, 14.0, 6, 10), (5, 9.0, 17, 30)):
+        geo = wl.geometry(cfg)
+        assert int(math.floor(geo.box[0] / edge + 0.5)) == nx
+        assert int(math.floor(geo.box[1] / edge + 0.5)) == ny
+        pid = pc.coarse_patches(geo.pos, geo.box, edge)
+        m = int(pid.max()) + 1
+        assert m == geo.n_layers * nx * ny
+        counts = np.bincount(pid, minlength=m)
+        assert counts.min() > 0 and counts.sum() == geo.n
+        first = np.zeros(m, dtype=np.int64)
+        first[pid] = geo.layer
+        assert np.all(first[pid] == geo.layer)   # one layer per patch
