@@ -417,11 +417,12 @@ def main():
     def inner_tol_for(precision, pcm, override=None):
         # reliable-update factor: 1e-4 for FP32 with PCG-DC at workload 2
         # (from a sweep: one true residual fewer at the same 32 iterations),
-        # 3e-3 with checks every 8 iterations at workload 5 (a sweep of
-        # 1e-1 .. 3e-3 and 4 / 8: 80 iterations at every factor, the fewest
-        # true residuals, 4, at 3e-3 with 8; factors of 1e-4 and below need
-        # more iterations, 1e-5 nearly three times as many), 1e-3 elsewhere
-        # (BF16, Jacobi and workload 3 need more iterations at 1e-4)
+        # 3e-3 at workload 5 (with P alone a sweep of 1e-1 .. 3e-3 and checks
+        # every 4 / 8 gave the fewest true residuals at 3e-3 with 8; factors
+        # of 1e-4 and below need more iterations, 1e-5 nearly three times as
+        # many; with the coarse space 3e-3 and 1e-2 need the same 10-12
+        # iterations and true residuals), 1e-3 elsewhere (BF16, Jacobi and
+        # workload 3 need more iterations at 1e-4)
         if override is not None:
             return override
         if args.inner_tol is not None:
