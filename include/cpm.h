@@ -273,8 +273,10 @@ cpm_status cpm_precond_gap(cpm_system *s, int enable, double *gap_out);
  * E Z on the FP32 matrix cores and two with E_c^-1 on the FP64 ones.
  * edge > 0: builds the space for that in-plane patch edge (A) and keeps it
  * until replaced or disabled (it does not depend on P, so rebuilding P
- * keeps it); edge <= 0: disables it. m_out (may be NULL) receives m. A
- * failed build leaves the system without a coarse space.
+ * keeps it); edge <= 0: disables it. m_out (may be NULL) receives m.
+ * CPM_EINVAL and CPM_ESTATE leave the current coarse space as it was; a
+ * build that fails later (CPM_ENOMEM, CPM_EDEVICE, CPM_ENOTSPD) leaves the
+ * system without one.
  * Errors: CPM_EINVAL (edge not finite, more than 8192 patches), CPM_ESTATE
  * (no sparse preconditioner built), CPM_ENOTSPD (E_c not positive
  * definite), CPM_ENOMEM, CPM_EDEVICE. */
