@@ -331,7 +331,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "the path runs on one GPU; --gpus must be 1"}))
-        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        log("bench.py: only --gpus 1 is supported (the library runs on one GPU)")
         sys.exit(2)
     # one line per assembled k chunk on stderr (workload 5 assembles for minutes)
     os.environ.setdefault("CPM_PROGRESS", "1")
